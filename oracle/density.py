@@ -1,0 +1,84 @@
+"""Electron density, Hartree potential and exchange (oracle side).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Density (eq. density_expression, Section 2.2.5): rho = 2 sum_i f_i |psi_i|^2,
+computed by inverse transforms to the grid, pointwise squares, and a forward
+transform for the coefficients tau (dualing: the same basis, Section 2.2.5).
+
+Hartree (Section 2.3.1, eqs. Laplace_expansion, hartree_calc1, zeta_definition):
+V_H(x) = sum tau_lmn (4 pi / (2l+1)) Y_lm(x) Z_ln(r), with Z_ln the radial
+integral of r_<^l / r_>^{l+1} against R_ln(s) s^2, evaluated here by direct
+Gauss quadrature of that definition (split at s = r).  In the real layout the
+same sum runs over the real harmonics S_lm (the addition theorem is basis
+independent).
+
+Exchange: Slater (LDA exchange only), V_x = -(3 rho / pi)^{1/3}.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import special
+
+from .basis import Basis, index, radial_function, real_harmonic
+from .hamiltonian import from_grid_real, to_grid_real
+
+
+def density_grid(bs: Basis, X: np.ndarray, occ: np.ndarray) -> np.ndarray:
+    """rho(x_g) = 2 sum_i f_i psi_i(x_g)^2, psi_i the inverse transform of x_i;
+    returns (n_r, n_theta, n_phi)."""
+    psi = to_grid_real(bs, X)
+    return 2.0 * np.einsum("rtpi,i->rtp", psi * psi, np.asarray(occ, dtype=np.float64))
+
+
+def density_coefficients(bs: Basis, rho: np.ndarray) -> np.ndarray:
+    """tau = forward transform of rho (same basis as the orbitals)."""
+    return from_grid_real(bs, rho[..., None])[:, 0]
+
+
+def integrate_grid(bs: Basis, f: np.ndarray) -> float:
+    """sum_g W_g f(x_g)  ~  int over the ball."""
+    return float(np.sum(bs.weights() * f))
+
+
+def zeta_table(bs: Basis, n_quad: int = 160) -> np.ndarray:
+    """Z[l, n, k] = int_0^R (r_<^l / r_>^{l+1}) R_ln(s) s^2 ds at r = r_k,
+    by Gauss-Legendre quadrature on [0, r] and [r, R] (eq. zeta_definition)."""
+    x, w = special.roots_legendre(n_quad)
+    Z = np.zeros((bs.L, bs.N, bs.n_r))
+    R = bs.R
+    for kk, r in enumerate(bs.r):
+        s1 = 0.5 * r * (x + 1.0)
+        w1 = 0.5 * r * w
+        s2 = r + 0.5 * (R - r) * (x + 1.0)
+        w2 = 0.5 * (R - r) * w
+        for l in range(bs.L):
+            f1 = radial_function(l, bs.b[l], s1, R)       # [n, q]
+            f2 = radial_function(l, bs.b[l], s2, R)
+            inner = (f1 * (s1 ** (l + 2))[None, :]) @ w1 / r ** (l + 1)
+            outer = (f2 * (s2 ** (1 - l))[None, :]) @ w2 * r ** l
+            Z[l, :, kk] = inner + outer
+    return Z
+
+
+def hartree_grid(bs: Basis, tau: np.ndarray, zeta: np.ndarray | None = None) -> np.ndarray:
+    """V_H on the grid from real-layout density coefficients tau, eq. hartree_calc1."""
+    if zeta is None:
+        zeta = zeta_table(bs)
+    TH, PH = np.meshgrid(bs.theta, bs.phi, indexing="ij")
+    V = np.zeros((bs.n_r, bs.n_theta, bs.n_phi))
+    for l in range(bs.L):
+        pref = 4.0 * math.pi / (2 * l + 1)
+        for m in range(-l, l + 1):
+            S = real_harmonic(l, m, TH, PH)
+            a0 = index(l, m, 0, bs.N)
+            radial = pref * (tau[a0:a0 + bs.N] @ zeta[l])   # [r]
+            V += radial[:, None, None] * S[None]
+    return V
+
+
+def slater_exchange(rho: np.ndarray) -> np.ndarray:
+    """V_x = -(3 rho / pi)^{1/3} (LDA exchange)."""
+    return -np.cbrt(3.0 * np.maximum(rho, 0.0) / math.pi)
