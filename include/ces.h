@@ -1,0 +1,189 @@
+/*
+ * ces.h -- C interface of the MI355X (gfx950) implementation of the spectral
+ * Kohn-Sham hot path: applying the discretised Hamiltonian H to a block of
+ * orbitals in the spherical-Bessel x spherical-harmonic basis on a ball, and
+ * Chebyshev-filtered subspace iteration around it.
+ *
+ * Method: A. S. Banerjee, R. S. Elliott, R. D. James, "A spectral scheme for
+ * Kohn-Sham density functional theory of clusters" (J. Comput. Phys.).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Basis.  F_lmn = R_ln(r) S_lm(theta, phi), 0 <= l < L (L = lmax + 1),
+ *    -l <= m <= l, 0 <= n < N, with R_ln the Dirichlet spherical-Bessel radial
+ *    functions of Section 2.2.1 (eq. spherical_bessel_1) and S_lm the REAL
+ *    orthonormal harmonics
+ *        S_lm     = sqrt2 c_lm P_l^m(cos theta) cos(m phi)   (m > 0)
+ *        S_l0     =       c_l0 P_l(cos theta)
+ *        S_{l,-m} = sqrt2 c_lm P_l^m(cos theta) sin(m phi)   (m > 0)
+ *    without the Condon-Shortley phase (Section 2.2.1).  This basis is a
+ *    unitary recombination of the paper's complex Y_l^m within each (l, n):
+ *    s_m = (f_m + f_{-m})/sqrt2, s_{-m} = i (f_m - f_{-m})/sqrt2; eigenvalues,
+ *    densities and residual norms are the same in both.
+ *  Index.  Coefficient alpha = (l*l + l + m) * N + n (0-based form of the
+ *    paper's indexing map, Section 2.2.3).  d = L*L*N.
+ *  Blocks.  Orbitals are columns; column-major; leading dimension ld >= d.
+ *    All values crossing this interface are FP64.
+ *  Grid.  n_r radial nodes (ascending r) x n_theta Gauss-Legendre nodes in
+ *    cos(theta) (ascending theta) x n_phi uniform phi_p = 2 pi p / n_phi
+ *    (Section 2.2.2).  Grid arrays are C-order [r][theta][phi].
+ *  Pointers.  d_* are device pointers, h_* host pointers.  The caller owns
+ *    every buffer, the workspace and the stream; handles own their tables.
+ *  Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  Calls are asynchronous on it unless stated otherwise.
+ *  Workspace.  Calls that take (d_work, work_bytes) use only that device
+ *    memory for scratch; query the size with ces_workspace_size.  Calls that
+ *    run concurrently on different streams need distinct workspaces.
+ *  Errors.  Every call returns a ces_status; arguments are validated on the
+ *    host before any launch.  Device faults surface as CES_ERR_DEVICE at the
+ *    next synchronising call.  ces_last_error() gives a thread-local detail.
+ */
+#ifndef CES_H
+#define CES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CES_OK = 0,
+  CES_ERR_INVALID_ARG = 1,
+  CES_ERR_DEVICE = 2,
+  CES_ERR_ALLOC = 3,
+  CES_ERR_WORKSPACE = 4,
+  CES_ERR_NOT_POSITIVE_DEFINITE = 5,
+  CES_ERR_EIGENSOLVER = 6
+} ces_status;
+
+/* FP64: every stage in double.  MIXED: the transforms, kinetic term,
+ * projector GEMMs and Chebyshev recurrence in FP32 with FP32 accumulation
+ * (converted from/to FP64 once per call); orthonormalisation and
+ * Rayleigh-Ritz stay FP64. */
+typedef enum { CES_PREC_FP64 = 0, CES_PREC_MIXED = 1 } ces_precision;
+
+/* Radial rule: Gauss-Jacobi nodes for the weight r^2 on [0,R] (the paper's
+ * choice, Section 2.2.2) or Gauss-Legendre nodes with r^2 in the weights. */
+typedef enum {
+  CES_RADIAL_GAUSS_JACOBI_R2 = 0,
+  CES_RADIAL_GAUSS_LEGENDRE = 1
+} ces_radial_rule;
+
+typedef struct ces_basis_s* ces_basis;
+typedef struct ces_ham_s* ces_ham;
+
+/* ------------------------------------------------------------------ basis */
+
+/* Build the basis tables (Section 2.2.1-2.2.2): Bessel zeros b_ln by Halley
+ * iteration, Lambda_ln = (b_ln/R)^2, radial and angular Gauss nodes and
+ * weights by Golub-Welsch, R_ln(r_k), normalised P_l^m(t_j), and their FP32
+ * copies, uploaded to the current device.  Synchronous.
+ * lmax >= 0, n_rad >= 1, R > 0, n_r >= 1, n_theta >= 1, n_phi >= 2*lmax+1. */
+ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
+                            int n_phi, int radial_rule, ces_basis* out);
+ces_status ces_basis_destroy(ces_basis b);
+/* d = L*L*N and n_grid = n_r*n_theta*n_phi. */
+ces_status ces_basis_info(ces_basis b, int64_t* d, int64_t* n_grid);
+/* Host copies of the grid: h_r[n_r], h_wr[n_r] (weights include r^2),
+ * h_theta[n_theta], h_wtheta[n_theta] (Gauss weights in cos theta),
+ * h_phi[n_phi].  Any pointer may be NULL. */
+ces_status ces_basis_grid(ces_basis b, double* h_r, double* h_wr, double* h_theta,
+                          double* h_wtheta, double* h_phi);
+/* Host copies of the setup tables, for checking: h_zeros[L*N] = b_ln
+ * (row l), h_radial[L*n_r*N] = R_ln(r_k) at [l][k][n], h_legendre
+ * [n_theta*L*(L+1)/2] = c_lm P_l^m(t_j) at [j][l(l+1)/2 + m] (m >= 0, no
+ * sqrt2 factor).  Any pointer may be NULL. */
+ces_status ces_basis_tables(ces_basis b, double* h_zeros, double* h_radial,
+                            double* h_legendre);
+
+/* ------------------------------------------------------------ hamiltonian */
+
+/* H = 1/2 diag(Lambda) + B^T W diag(V_eff) B [+ P diag(h) P^T]
+ * (Section 2.2.4, eq. matvec_final; Section 2.3.2 for the projector term).
+ * d_veff: n_grid doubles, [r][theta][phi], copied.  d_proj: d x n_proj
+ * column-major (ld = d) real-layout projector coefficients, or NULL with
+ * n_proj = 0; copied in FP64 and FP32.  h_proj_energy: n_proj host doubles.
+ * Synchronous on `stream`. */
+ces_status ces_ham_create(ces_basis b, const double* d_veff, int n_proj,
+                          const double* d_proj, const double* h_proj_energy,
+                          void* stream, ces_ham* out);
+/* Replace V_eff (same layout); asynchronous on `stream`. */
+ces_status ces_ham_set_veff(ces_ham h, const double* d_veff, void* stream);
+ces_status ces_ham_destroy(ces_ham h);
+
+/* Device bytes that any call below with k columns and precision `prec`
+ * needs in d_work. */
+ces_status ces_workspace_size(ces_ham h, int k, int prec, size_t* bytes);
+
+/* Y = H X for a d x k block (eq. matvec_final): inverse radial sum
+ * (eq. G_lmr), inverse Legendre sums, phi synthesis, V_eff, phi analysis,
+ * Legendre quadrature (eq. Ar_lm), radial quadrature (eq. Arlm_to_coeff),
+ * plus 1/2 Lambda X and the projector term.  X and Y must not overlap. */
+ces_status ces_apply_H(ces_ham h, int k, const double* d_X, int64_t ldx, double* d_Y,
+                       int64_t ldy, int prec, void* d_work, size_t work_bytes,
+                       void* stream);
+
+/* X <- p_m(H) X in place, p_m(t) = T_m((t-c)/e) / T_m((a0-c)/e), e = (b-a)/2,
+ * c = (b+a)/2 (the scaled Chebyshev filter of Section 3.2), by the three-term
+ * recurrence with per-step scaling.  Requires degree >= 1, a < b, a0 < a. */
+ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degree,
+                           double a, double b, double a0, int prec, void* d_work,
+                           size_t work_bytes, void* stream);
+
+/* Cholesky-QR with column scaling (Section 3.1.1, 3.2), then Rayleigh-Ritz
+ * (Section 3.2), all FP64: Q = X D R^{-1}; theta, S = eig(Q^T H Q) ascending;
+ * X <- Q S; HX <- (H Q) S; r_i = ||H x_i - theta_i x_i||.  d_HX (d x k, ld =
+ * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles.  hx_prec selects
+ * the precision of the H*Q product.  Synchronises `stream`; returns
+ * CES_ERR_NOT_POSITIVE_DEFINITE if the scaled Gram matrix is not positive
+ * definite after a shifted retry (X is then left scaled but not rotated). */
+ces_status ces_rayleigh_ritz(ces_ham h, int k, double* d_X, int64_t ldx, double* d_HX,
+                             double* d_eval, double* d_resnorm, int hx_prec,
+                             void* d_work, size_t work_bytes, void* stream);
+
+/* Upper bound of the spectrum of H: `steps` Lanczos steps from the start
+ * vector d_v0 (d doubles, not modified); bound = (largest Ritz value +
+ * final residual norm) * 1.01 (1/1.01 if negative).  Synchronous. */
+ces_status ces_lanczos_bound(ces_ham h, const double* d_v0, int steps, double* h_bound,
+                             void* d_work, size_t work_bytes, void* stream);
+
+/* Chebyshev-filtered subspace iteration from the block in d_X (Section 3.2,
+ * started from random vectors): Rayleigh-Ritz; then repeat filter(prec, a =
+ * theta_k, a0 = theta_1, b) + Rayleigh-Ritz (FP64 H*X) until, for i <
+ * n_check, r_i <= res_tol*max(1,|theta_i|) and |delta theta_i| < dtheta_tol,
+ * or max_iter; fixed_iter > 0 runs exactly that many iterations.  On return
+ * d_X holds the Ritz vectors, d_eval/d_resnorm their values and residuals,
+ * *h_iters the outer iterations.  Synchronous. */
+ces_status ces_chefsi(ces_ham h, int k, double* d_X, int64_t ldx, int degree, double b,
+                      int n_check, int max_iter, int fixed_iter, double res_tol,
+                      double dtheta_tol, int prec, double* d_eval, double* d_resnorm,
+                      int* h_iters, void* d_work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------- density */
+
+/* rho(x_g) = 2 sum_i f_i psi_i(x_g)^2 with psi_i the inverse transform of
+ * column i (Section 2.2.5); d_occ[k] device doubles f_i; d_rho_grid[n_grid]
+ * ([r][theta][phi]); d_rho_coef[d] (may be NULL) = forward transform of rho
+ * (same basis, the dualing choice of Section 2.2.5). */
+ces_status ces_density(ces_ham h, int k, const double* d_X, int64_t ldx,
+                       const double* d_occ, double* d_rho_grid, double* d_rho_coef,
+                       int prec, void* d_work, size_t work_bytes, void* stream);
+
+/* Inverse transform of k columns to the grid: d_f[n_grid * k], column i at
+ * offset i*n_grid, each [r][theta][phi] (Section 2.2.2, eq. G_lmr). */
+ces_status ces_to_grid(ces_ham h, int k, const double* d_X, int64_t ldx, double* d_f,
+                       void* d_work, size_t work_bytes, void* stream);
+/* Forward transform of k grid functions (eqs. Ar_lm, Arlm_to_coeff). */
+ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64_t ldx,
+                         void* d_work, size_t work_bytes, void* stream);
+
+/* ----------------------------------------------------------------- misc */
+const char* ces_status_string(ces_status s);
+const char* ces_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CES_H */

@@ -39,7 +39,7 @@ def bessel_zeros(L: int, N: int) -> np.ndarray:
     0.1 step cannot skip a pair) and refined with Brent's method."""
     out = np.empty((L, N))
     for l in range(L):
-        hi = l + (N + 2) * math.pi + 10.0
+        hi = (N + 0.5 * l + 4) * math.pi + 10.0   # z_{l,n} ~ (n + l/2 + 1) pi
         xs = np.arange(0.1, hi, 0.1)
         ys = special.spherical_jn(l, xs)
         idx = np.nonzero(np.sign(ys[:-1]) * np.sign(ys[1:]) < 0)[0]

@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libces (include/ces.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.
+
+Block convention: a d x k column-major block with leading dimension ld is a
+torch tensor of shape (k, ld) (row i = orbital i), float64, on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libces.so")
+
+CES_PREC_FP64 = 0
+CES_PREC_MIXED = 1
+CES_RADIAL_GAUSS_JACOBI_R2 = 0
+CES_RADIAL_GAUSS_LEGENDRE = 1
+
+EXPORTS = [
+    "ces_basis_create", "ces_basis_destroy", "ces_basis_info", "ces_basis_grid",
+    "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
+    "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
+    "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
+    "ces_status_string", "ces_last_error",
+]
+
+_lib = None
+
+
+class CesError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Load libces.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libces.so not built at {LIB_PATH}; run "
+                          "`python -m paper_1404_3773_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                        ctypes.c_size_t)
+    sig = {
+        "ces_basis_create": [I, I, D, I, I, I, I, ctypes.POINTER(P)],
+        "ces_basis_destroy": [P],
+        "ces_basis_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+        "ces_basis_grid": [P, P, P, P, P, P],
+        "ces_basis_tables": [P, P, P, P],
+        "ces_ham_create": [P, P, I, P, P, P, ctypes.POINTER(P)],
+        "ces_ham_set_veff": [P, P, P],
+        "ces_ham_destroy": [P],
+        "ces_workspace_size": [P, I, I, ctypes.POINTER(SZ)],
+        "ces_apply_H": [P, I, P, I64, P, I64, I, P, SZ, P],
+        "ces_cheb_filter": [P, I, P, I64, I, D, D, D, I, P, SZ, P],
+        "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, I, P, SZ, P],
+        "ces_lanczos_bound": [P, P, I, ctypes.POINTER(D), P, SZ, P],
+        "ces_chefsi": [P, I, P, I64, I, D, I, I, I, D, D, I, P, P, ctypes.POINTER(I), P, SZ, P],
+        "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
+        "ces_to_grid": [P, I, P, I64, P, P, SZ, P],
+        "ces_from_grid": [P, I, P, P, I64, P, SZ, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ces_status_string.argtypes = [ctypes.c_int]
+    lib.ces_status_string.restype = ctypes.c_char_p
+    lib.ces_last_error.argtypes = []
+    lib.ces_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        lib = load()
+        raise CesError(status, where, lib.ces_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ld(X):
+    """Leading dimension of a (k, ld) block tensor."""
+    assert X.dtype.is_floating_point and X.dim() == 2 and X.stride(1) == 1
+    return X.stride(0)
+
+
+class Basis:
+    """Handle of ces_basis (host tables; device upload on first Ham)."""
+
+    def __init__(self, lmax, n_rad, R, n_r, n_theta, n_phi, rule=CES_RADIAL_GAUSS_JACOBI_R2):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.ces_basis_create(int(lmax), int(n_rad), float(R), int(n_r), int(n_theta),
+                                    int(n_phi), int(rule), ctypes.byref(h)), "ces_basis_create")
+        self._h = h
+        self.L, self.N = lmax + 1, n_rad
+        self.R = R
+        self.n_r, self.n_theta, self.n_phi = n_r, n_theta, n_phi
+        d, g = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.ces_basis_info(h, ctypes.byref(d), ctypes.byref(g)), "ces_basis_info")
+        self.d, self.n_grid = d.value, g.value
+
+    @classmethod
+    def for_workload(cls, w):
+        return cls(w.L - 1, w.N, w.R, w.n_r, w.n_theta, w.n_phi, w.radial_rule)
+
+    def grid(self):
+        r, wr = np.zeros(self.n_r), np.zeros(self.n_r)
+        th, wt = np.zeros(self.n_theta), np.zeros(self.n_theta)
+        ph = np.zeros(self.n_phi)
+        args = [a.ctypes.data_as(ctypes.c_void_p) for a in (r, wr, th, wt, ph)]
+        _check(load().ces_basis_grid(self._h, *args), "ces_basis_grid")
+        return r, wr, th, wt, ph
+
+    def tables(self):
+        z = np.zeros(self.L * self.N)
+        rad = np.zeros(self.L * self.n_r * self.N)
+        leg = np.zeros(self.n_theta * self.L * (self.L + 1) // 2)
+        _check(load().ces_basis_tables(self._h, *[a.ctypes.data_as(ctypes.c_void_p)
+                                                  for a in (z, rad, leg)]), "ces_basis_tables")
+        return (z.reshape(self.L, self.N), rad.reshape(self.L, self.n_r, self.N),
+                leg.reshape(self.n_theta, -1))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ces_basis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ham:
+    """Handle of ces_ham: V_eff on the grid (torch float64, n_grid), optional
+    projector coefficients (torch float64 of shape (n_proj, d)) and energies."""
+
+    def __init__(self, basis: Basis, veff, proj=None, energies=None, stream=None):
+        lib = load()
+        self.basis = basis
+        n_proj = 0 if proj is None else int(proj.shape[0])
+        if proj is not None:
+            assert proj.is_contiguous() and proj.shape[1] == basis.d
+        e = None
+        if n_proj:
+            e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+        h = ctypes.c_void_p()
+        _check(lib.ces_ham_create(basis._h, _ptr(veff.contiguous()), n_proj, _ptr(proj),
+                                  None if e is None else e.ctypes.data_as(ctypes.c_void_p),
+                                  _stream(stream), ctypes.byref(h)), "ces_ham_create")
+        self._h = h
+        self.n_proj = n_proj
+
+    def set_veff(self, veff, stream=None):
+        _check(load().ces_ham_set_veff(self._h, _ptr(veff.contiguous()), _stream(stream)),
+               "ces_ham_set_veff")
+
+    def workspace_size(self, k, prec=CES_PREC_FP64) -> int:
+        n = ctypes.c_size_t()
+        _check(load().ces_workspace_size(self._h, int(k), int(prec), ctypes.byref(n)),
+               "ces_workspace_size")
+        return n.value
+
+    def workspace(self, k, prec=CES_PREC_FP64):
+        import torch
+        n = self.workspace_size(k, prec)
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def apply_H(self, X, Y, prec, work, stream=None):
+        k = X.shape[0]
+        _check(load().ces_apply_H(self._h, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y), int(prec),
+                                  _ptr(work), work.numel(), _stream(stream)), "ces_apply_H")
+
+    def cheb_filter(self, X, degree, a, b, a0, prec, work, stream=None):
+        _check(load().ces_cheb_filter(self._h, X.shape[0], _ptr(X), _ld(X), int(degree),
+                                      float(a), float(b), float(a0), int(prec), _ptr(work),
+                                      work.numel(), _stream(stream)), "ces_cheb_filter")
+
+    def rayleigh_ritz(self, X, evals, res, work, HX=None, hx_prec=CES_PREC_FP64, stream=None):
+        _check(load().ces_rayleigh_ritz(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(HX),
+                                        _ptr(evals), _ptr(res), int(hx_prec), _ptr(work),
+                                        work.numel(), _stream(stream)), "ces_rayleigh_ritz")
+
+    def lanczos_bound(self, v0, work, steps=20, stream=None) -> float:
+        out = ctypes.c_double()
+        _check(load().ces_lanczos_bound(self._h, _ptr(v0), int(steps), ctypes.byref(out),
+                                        _ptr(work), work.numel(), _stream(stream)),
+               "ces_lanczos_bound")
+        return out.value
+
+    def chefsi(self, X, degree, b, n_check, evals, res, work, prec, max_iter=60,
+               fixed_iter=0, res_tol=1e-4, dtheta_tol=1e-7, stream=None) -> int:
+        it = ctypes.c_int()
+        _check(load().ces_chefsi(self._h, X.shape[0], _ptr(X), _ld(X), int(degree), float(b),
+                                 int(n_check), int(max_iter), int(fixed_iter), float(res_tol),
+                                 float(dtheta_tol), int(prec), _ptr(evals), _ptr(res),
+                                 ctypes.byref(it), _ptr(work), work.numel(), _stream(stream)),
+               "ces_chefsi")
+        return it.value
+
+    def density(self, X, occ, rho_grid, rho_coef, prec, work, stream=None):
+        _check(load().ces_density(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(occ),
+                                  _ptr(rho_grid), _ptr(rho_coef), int(prec), _ptr(work),
+                                  work.numel(), _stream(stream)), "ces_density")
+
+    def to_grid(self, X, f, work, stream=None):
+        _check(load().ces_to_grid(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(f), _ptr(work),
+                                  work.numel(), _stream(stream)), "ces_to_grid")
+
+    def from_grid(self, f, X, work, stream=None):
+        _check(load().ces_from_grid(self._h, X.shape[0], _ptr(f), _ptr(X), _ld(X), _ptr(work),
+                                    work.numel(), _stream(stream)), "ces_from_grid")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ces_ham_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

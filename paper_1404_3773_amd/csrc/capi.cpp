@@ -1,0 +1,954 @@
+// C interface of libces (declared in include/ces.h): handle lifecycle,
+// argument validation, workspace carving and the host-side sequencing of the
+// device kernels for H*X, the Chebyshev filter, Cholesky-QR + Rayleigh-Ritz,
+// Lanczos bounds, the CheFSI driver, density and grid transforms.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ces_internal.h"
+#include "setup_tables.h"
+
+struct ces_basis_s {
+  ces::Basis b;
+};
+struct ces_ham_s {
+  ces::Ham h;
+};
+
+namespace ces {
+namespace {
+
+thread_local std::string g_err;
+
+ces_status fail(ces_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define CES_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(CES_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CES_BLAS(call)                                                             \
+  do {                                                                             \
+    rocblas_status e_ = (call);                                                    \
+    if (e_ != rocblas_status_success)                                              \
+      return fail(CES_ERR_DEVICE, std::string(#call) + ": " + rocblas_status_to_string(e_)); \
+  } while (0)
+
+#define CES_TRY(expr)                 \
+  do {                                \
+    ces_status s_ = (expr);           \
+    if (s_ != CES_OK) return s_;      \
+  } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Host tables of the basis (Section 2.2.1-2.2.2).
+void build_host_tables(Basis& b) {
+  const int L = b.L, N = b.N;
+  b.zeros = bessel_zeros(L, N);
+  std::vector<double> x, w;
+  if (b.rule == CES_RADIAL_GAUSS_JACOBI_R2) {
+    gauss_jacobi(b.n_r, 0.0, 2.0, x, w);  // weight (1+x)^2 on [-1,1]
+    b.r.resize(b.n_r);
+    b.wr.resize(b.n_r);
+    for (int i = 0; i < b.n_r; ++i) {
+      b.r[i] = b.R * (1.0 + x[i]) / 2.0;
+      b.wr[i] = w[i] * std::pow(b.R / 2.0, 3);
+    }
+  } else {
+    gauss_jacobi(b.n_r, 0.0, 0.0, x, w);
+    b.r.resize(b.n_r);
+    b.wr.resize(b.n_r);
+    for (int i = 0; i < b.n_r; ++i) {
+      b.r[i] = b.R * (1.0 + x[i]) / 2.0;
+      b.wr[i] = w[i] * (b.R / 2.0) * b.r[i] * b.r[i];
+    }
+  }
+  gauss_jacobi(b.n_theta, 0.0, 0.0, x, w);  // ascending t
+  b.t.resize(b.n_theta);
+  b.wt.resize(b.n_theta);
+  b.theta.resize(b.n_theta);
+  for (int j = 0; j < b.n_theta; ++j) {  // order by increasing theta
+    b.t[j] = x[b.n_theta - 1 - j];
+    b.wt[j] = w[b.n_theta - 1 - j];
+    b.theta[j] = std::acos(b.t[j]);
+  }
+  // exact symmetry t_{n-1-j} = -t_j (the kernels rely on it)
+  for (int j = 0; j < b.n_theta / 2; ++j) {
+    const int jn = b.n_theta - 1 - j;
+    const double tt = 0.5 * (b.t[j] - b.t[jn]);
+    const double ww = 0.5 * (b.wt[j] + b.wt[jn]);
+    b.t[j] = tt;
+    b.t[jn] = -tt;
+    b.wt[j] = b.wt[jn] = ww;
+    b.theta[j] = std::acos(tt);
+    b.theta[jn] = std::acos(-tt);
+  }
+  if (b.n_theta % 2 == 1) {
+    b.t[b.n_theta / 2] = 0.0;
+    b.theta[b.n_theta / 2] = M_PI / 2;
+  }
+  b.phi.resize(b.n_phi);
+  for (int p = 0; p < b.n_phi; ++p) b.phi[p] = 2.0 * M_PI * p / b.n_phi;
+  // R_ln(r_k) = sqrt(2/R^3) j_l(b_ln r_k / R) / j_{l+1}(b_ln)
+  b.radial.assign(static_cast<size_t>(L) * b.n_r * N, 0.0);
+  const double c0 = std::sqrt(2.0 / (b.R * b.R * b.R));
+  for (int l = 0; l < L; ++l)
+    for (int n = 0; n < N; ++n) {
+      const double z = b.zeros[static_cast<size_t>(l) * N + n];
+      const double den = sph_bessel_j(l + 1, z);
+      for (int kk = 0; kk < b.n_r; ++kk)
+        b.radial[(static_cast<size_t>(l) * b.n_r + kk) * N + n] =
+            c0 * sph_bessel_j(l, z * b.r[kk] / b.R) / den;
+    }
+  const int LP = L * (L + 1) / 2;
+  b.legendre.assign(static_cast<size_t>(b.n_theta) * LP, 0.0);
+  for (int j = 0; j < b.n_theta; ++j) legendre_normalized(L, b.t[j], &b.legendre[size_t(j) * LP]);
+}
+
+template <typename T>
+void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std::vector<T>& Pleg,
+                 std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& trig) {
+  const int L = b.L, N = b.N, LP = L * (L + 1) / 2, S = 2 * L - 1;
+  Rinv.resize(b.radial.size());
+  Rfwd.resize(b.radial.size());
+  for (int l = 0; l < L; ++l)
+    for (int kk = 0; kk < b.n_r; ++kk)
+      for (int n = 0; n < N; ++n) {
+        const double v = b.radial[(static_cast<size_t>(l) * b.n_r + kk) * N + n];
+        Rinv[(static_cast<size_t>(l) * b.n_r + kk) * N + n] = static_cast<T>(v);
+        Rfwd[(static_cast<size_t>(l) * N + n) * b.n_r + kk] = static_cast<T>(b.wr[kk] * v);
+      }
+  const int npairs = (b.n_theta + 1) / 2;
+  Pleg.resize(static_cast<size_t>(npairs) * LP);
+  for (int jp = 0; jp < npairs; ++jp)
+    for (int l = 0; l < L; ++l)
+      for (int m = 0; m <= l; ++m)
+        Pleg[size_t(jp) * LP + l * (l + 1) / 2 + m] = static_cast<T>(
+            b.legendre[size_t(jp) * LP + l * (l + 1) / 2 + m] * (m > 0 ? std::sqrt(2.0) : 1.0));
+  lamh.resize(static_cast<size_t>(L) * N);
+  for (int l = 0; l < L; ++l)
+    for (int n = 0; n < N; ++n) {
+      const double k = b.zeros[size_t(l) * N + n] / b.R;
+      lamh[size_t(l) * N + n] = static_cast<T>(0.5 * k * k);
+    }
+  wt.resize(b.n_theta);
+  for (int j = 0; j < b.n_theta; ++j) wt[j] = static_cast<T>(b.wt[j]);
+  trig.resize(static_cast<size_t>(S) * b.n_phi);
+  for (int s = 0; s < S; ++s)
+    for (int p = 0; p < b.n_phi; ++p) {
+      const int m = s < L ? s : s - L + 1;
+      const long long u = (static_cast<long long>(m) * p) % b.n_phi;
+      const double ang = 2.0 * M_PI * static_cast<double>(u) / b.n_phi;
+      trig[size_t(s) * b.n_phi + p] = static_cast<T>(s < L ? std::cos(ang) : std::sin(ang));
+    }
+}
+
+// Upload device tables once (on the device current at first use).
+ces_status ensure_device(Basis& b) {
+  int dev = 0;
+  CES_HIP(hipGetDevice(&dev));
+  if (b.dev_block) {
+    if (dev != b.device) return fail(CES_ERR_INVALID_ARG, "basis tables live on another device");
+    return CES_OK;
+  }
+  std::vector<double> R64, F64, P64, l64, w64, t64;
+  std::vector<float> R32, F32, P32, l32, w32, t32;
+  fill_tables(b, R64, F64, P64, l64, w64, t64);
+  fill_tables(b, R32, F32, P32, l32, w32, t32);
+  std::vector<double> cs(2 * static_cast<size_t>(b.n_phi));
+  for (int u = 0; u < b.n_phi; ++u) {
+    cs[u] = std::cos(2.0 * M_PI * u / b.n_phi);
+    cs[b.n_phi + u] = std::sin(2.0 * M_PI * u / b.n_phi);
+  }
+  struct Piece {
+    const void* src;
+    size_t bytes;
+    void** dst;
+  };
+  std::vector<Piece> pieces = {
+      {R64.data(), R64.size() * 8, (void**)&b.t64.Rinv}, {F64.data(), F64.size() * 8, (void**)&b.t64.Rfwd},
+      {P64.data(), P64.size() * 8, (void**)&b.t64.Pleg}, {l64.data(), l64.size() * 8, (void**)&b.t64.lamh},
+      {w64.data(), w64.size() * 8, (void**)&b.t64.wt},   {t64.data(), t64.size() * 8, (void**)&b.t64.trig},
+      {R32.data(), R32.size() * 4, (void**)&b.t32.Rinv}, {F32.data(), F32.size() * 4, (void**)&b.t32.Rfwd},
+      {P32.data(), P32.size() * 4, (void**)&b.t32.Pleg}, {l32.data(), l32.size() * 4, (void**)&b.t32.lamh},
+      {w32.data(), w32.size() * 4, (void**)&b.t32.wt},   {t32.data(), t32.size() * 4, (void**)&b.t32.trig},
+      {cs.data(), cs.size() * 8, (void**)&b.dev_cs}};
+  size_t total = 0;
+  for (auto& p : pieces) total += align256(p.bytes);
+  void* blk = nullptr;
+  if (hipMalloc(&blk, total) != hipSuccess) return fail(CES_ERR_ALLOC, "hipMalloc of basis tables failed");
+  size_t off = 0;
+  for (auto& p : pieces) {
+    *p.dst = static_cast<char*>(blk) + off;
+    if (hipMemcpy(*p.dst, p.src, p.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(blk);
+      return fail(CES_ERR_DEVICE, "upload of basis tables failed");
+    }
+    off += align256(p.bytes);
+  }
+  b.dev_block = blk;
+  b.device = dev;
+  return CES_OK;
+}
+
+// ------------------------------------------------------------- workspace
+
+struct Layout {
+  size_t G = 0, A = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0, vec = 0,
+         info = 0, solver = 0, total = 0;
+  size_t solver_bytes = 0;
+  int64_t kp = 0;
+};
+
+size_t solver_bytes_for(Ham& h, int k) {
+  if (h.solver_ws_k == k) return h.solver_ws;
+  size_t sz = 0;
+  // Size query: no kernel runs while the handle is in query mode; the
+  // functions only need non-null placeholders to pass argument checks.
+  if (rocblas_start_device_memory_size_query(h.blas) == rocblas_status_success) {
+    if (rocblas_is_device_memory_size_query(h.blas)) {
+      double* fake = reinterpret_cast<double*>(uintptr_t(4096));
+      rocblas_int* ifake = reinterpret_cast<rocblas_int*>(uintptr_t(4096));
+      (void)rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, fake, k, ifake);
+      (void)rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, fake, k,
+                             fake, fake, ifake);
+    }
+    (void)rocblas_stop_device_memory_size_query(h.blas, &sz);
+  }
+  h.solver_ws = align256(sz) + (16u << 20);  // margin for the BLAS-3 calls
+  h.solver_ws_k = k;
+  return h.solver_ws;
+}
+
+Layout layout_for(Ham& h, int k, int prec) {
+  const Basis& b = *h.basis;
+  Layout L;
+  L.kp = round_up(k, kColPad);
+  const size_t LL = size_t(b.L) * b.L;
+  const size_t gbytes = size_t(b.n_r) * LL * L.kp * sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align256(off);
+    const size_t at = off;
+    off += bytes;
+    return at;
+  };
+  L.G = take(gbytes);
+  L.A = take(gbytes);
+  L.B1 = take(size_t(b.d) * k * sizeof(double));
+  L.B2 = take(size_t(b.d) * k * sizeof(double));
+  L.V3 = take(size_t(b.d) * 3 * sizeof(double));
+  if (prec == CES_PREC_MIXED) {
+    L.F0 = take(size_t(b.d) * L.kp * sizeof(float));
+    L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
+  }
+  L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * sizeof(double));
+  L.S1 = take(size_t(k) * k * sizeof(double));
+  L.S2 = take(size_t(k) * k * sizeof(double));
+  L.vec = take(size_t(8) * std::max(k, 64) * sizeof(double));
+  L.info = take(256);
+  L.solver_bytes = solver_bytes_for(h, k);
+  L.solver = take(L.solver_bytes);
+  L.total = align256(off);
+  return L;
+}
+
+template <typename T>
+struct Ptr {
+  static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+};
+
+// -------------------------------------------------------------- one H step
+
+template <typename T>
+const DevTables<T>& tables(const Basis& b);
+template <>
+const DevTables<double>& tables<double>(const Basis& b) { return b.t64; }
+template <>
+const DevTables<float>& tables<float>(const Basis& b) { return b.t32; }
+
+template <typename T>
+const T* ab_of(const Ham& h);
+template <>
+const double* ab_of<double>(const Ham& h) { return h.ab64; }
+template <>
+const float* ab_of<float>(const Ham& h) { return h.ab32; }
+
+inline rocblas_status gemm_t(rocblas_handle hb, rocblas_operation ta, rocblas_operation tb, int m,
+                             int n, int kk, const double* alpha, const double* A, int lda,
+                             const double* B, int ldb, const double* beta, double* C, int ldc) {
+  return rocblas_dgemm(hb, ta, tb, m, n, kk, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+inline rocblas_status gemm_t(rocblas_handle hb, rocblas_operation ta, rocblas_operation tb, int m,
+                             int n, int kk, const float* alpha, const float* A, int lda,
+                             const float* B, int ldb, const float* beta, float* C, int ldc) {
+  return rocblas_sgemm(hb, ta, tb, m, n, kk, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+// out = alpha * (H Yin - c Yin) + beta * Yold  (kinetic and projector terms
+// included).  Uses the G, A and C regions of the workspace.
+template <typename T>
+ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int64_t ldin,
+                  const T* Yold, int64_t ldold, T* out, int64_t ldout, T alpha, T c, T beta,
+                  hipStream_t s) {
+  const Basis& b = *h.basis;
+  const DevTables<T>& tb = tables<T>(b);
+  T* G = Ptr<T>::at(work, ly.G);
+  T* A = Ptr<T>::at(work, ly.A);
+  T* C = Ptr<T>::at(work, ly.C);
+  const int kp = static_cast<int>(ly.kp);
+  const T* P = nullptr;
+  if (h.n_proj > 0) {
+    // C = diag(h) P^T Yin  (n_proj x kp)
+    const T one = 1, zero = 0;
+    CES_BLAS(rocblas_set_stream(h.blas, s));
+    CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
+    const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
+    const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
+    CES_BLAS(gemm_t(h.blas, rocblas_operation_transpose, rocblas_operation_none, h.n_proj, k,
+                    static_cast<int>(b.d), &one, Pd, static_cast<int>(b.d), Yin,
+                    static_cast<int>(ldin), &zero, C, kp));
+    launch_scale_rows<T>(C, h.n_proj, kp, hd, s);
+    P = Pd;
+  }
+  launch_radial_inverse<T>(b, tb, Yin, ldin, G, k, kp, s);
+  launch_angular<T>(b, tb, ab_of<T>(h), G, A, kp, s);
+  launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true, P,
+                           h.n_proj, C, k, kp, s);
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status check_ham(ces_ham hh) {
+  if (!hh) return fail(CES_ERR_INVALID_ARG, "null ham");
+  int dev = 0;
+  CES_HIP(hipGetDevice(&dev));
+  if (dev != hh->h.basis->device) return fail(CES_ERR_INVALID_ARG, "ham lives on another device");
+  return CES_OK;
+}
+
+ces_status check_block(const Ham& h, int k, const void* X, int64_t ldx, const char* what) {
+  if (k < 1) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": k must be >= 1");
+  if (!X) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": null block");
+  if (ldx < h.basis->d) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": ld < d");
+  return CES_OK;
+}
+
+ces_status check_work(Ham& h, int k, int prec, void* work, size_t bytes, Layout& ly) {
+  if (prec != CES_PREC_FP64 && prec != CES_PREC_MIXED)
+    return fail(CES_ERR_INVALID_ARG, "unknown precision");
+  ly = layout_for(h, k, prec);
+  if (!work) return fail(CES_ERR_WORKSPACE, "null workspace");
+  if (bytes < ly.total)
+    return fail(CES_ERR_WORKSPACE, "workspace too small: need " + std::to_string(ly.total) +
+                                       " bytes, got " + std::to_string(bytes));
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(CES_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return CES_OK;
+}
+
+// Chebyshev filter on an internal block; Y0 (ld ld0) in place.
+template <typename T>
+ces_status cheb_run(Ham& h, const Layout& ly, void* work, int k, T* Y0, int64_t ld0, T* Yb,
+                    int64_t ldb, int degree, double a, double bnd, double a0, hipStream_t s,
+                    T** result, int64_t* ldres) {
+  const double e = (bnd - a) / 2.0, c = (bnd + a) / 2.0;
+  const double sigma1 = e / (a0 - c);
+  // step 1: Yb = (sigma1/e) (H Y0 - c Y0)
+  CES_TRY(h_step<T>(h, ly, work, k, Y0, ld0, nullptr, 0, Yb, ldb, T(sigma1 / e), T(c), T(0), s));
+  T* cur = Yb;
+  int64_t ldc = ldb;
+  T* prev = Y0;
+  int64_t ldp = ld0;
+  double sigma = sigma1;
+  for (int j = 2; j <= degree; ++j) {
+    const double sn = 1.0 / (2.0 / sigma1 - sigma);
+    // Y_j = (2 sn / e)(H Y_{j-1} - c Y_{j-1}) - sigma sn Y_{j-2}, written over Y_{j-2}
+    CES_TRY(h_step<T>(h, ly, work, k, cur, ldc, prev, ldp, prev, ldp, T(2.0 * sn / e), T(c),
+                      T(-sigma * sn), s));
+    std::swap(cur, prev);
+    std::swap(ldc, ldp);
+    sigma = sn;
+  }
+  *result = cur;
+  *ldres = ldc;
+  return CES_OK;
+}
+
+// Largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection).
+double tridiag_max(const std::vector<double>& a, const std::vector<double>& bb) {
+  const int n = static_cast<int>(a.size());
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double rad = (i > 0 ? std::fabs(bb[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(bb[i]) : 0.0);
+    lo = std::min(lo, a[i] - rad);
+    hi = std::max(hi, a[i] + rad);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double dd = 1.0;
+    for (int i = 0; i < n; ++i) {
+      dd = (a[i] - x) - (i > 0 ? bb[i - 1] * bb[i - 1] / dd : 0.0);
+      if (dd == 0.0) dd = -1e-300;
+      if (dd < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx, double* HX,
+                   int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s) {
+  const Basis& b = *h.basis;
+  const int64_t d = b.d;
+  double* S1 = Ptr<double>::at(work, ly.S1);
+  double* S2 = Ptr<double>::at(work, ly.S2);
+  double* vec = Ptr<double>::at(work, ly.vec);
+  double* dinv = vec;
+  double* evals = vec + k;
+  double* Ework = vec + 2 * k;
+  rocblas_int* info = Ptr<rocblas_int>::at(work, ly.info);
+  double* B1 = Ptr<double>::at(work, ly.B1);
+  CES_BLAS(rocblas_set_stream(h.blas, s));
+  CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
+  const double one = 1.0, zero = 0.0;
+  // S = X^T X, column scaling, Cholesky (Section 3.1.1: scale before factorising)
+  CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
+                         static_cast<int>(d), &one, X, static_cast<int>(ldx), X,
+                         static_cast<int>(ldx), &zero, S1, k));
+  launch_symmetrize(S1, k, s);
+  launch_scale_gram(S1, k, dinv, s);
+  CES_HIP(hipMemcpyAsync(S2, S1, size_t(k) * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+  rocblas_int hinfo = 0;
+  CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  CES_HIP(hipStreamSynchronize(s));
+  if (hinfo != 0) {
+    // shifted retry: factor D S D + eps I (shifted Cholesky-QR), then a
+    // second Cholesky-QR pass below restores orthonormality.
+    CES_HIP(hipMemcpyAsync(S1, S2, size_t(k) * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_add_diag(S1, k, 1e-12 * k, s);
+    CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+    CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    CES_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky of the scaled Gram matrix failed");
+    launch_scale_cols(X, ldx, d, k, dinv, s);
+    CES_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, static_cast<int>(d), k, &one, S1, k, X,
+                           static_cast<int>(ldx)));
+    // second pass
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
+                           static_cast<int>(d), &one, X, static_cast<int>(ldx), X,
+                           static_cast<int>(ldx), &zero, S1, k));
+    launch_symmetrize(S1, k, s);
+    launch_scale_gram(S1, k, dinv, s);
+    CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+    CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    CES_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky-QR2 failed");
+  }
+  // Q = X D R^{-1}
+  launch_scale_cols(X, ldx, d, k, dinv, s);
+  CES_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, static_cast<int>(d), k, &one, S1, k, X,
+                         static_cast<int>(ldx)));
+  // HQ
+  double* HQ = HX ? HX : B1;
+  const int64_t ldhq = HX ? ldhx : d;
+  if (hx_prec == CES_PREC_FP64) {
+    CES_TRY(h_step<double>(h, ly, work, k, X, ldx, nullptr, 0, HQ, ldhq, 1.0, 0.0, 0.0, s));
+  } else {
+    float* F0 = Ptr<float>::at(work, ly.F0);
+    float* F1 = Ptr<float>::at(work, ly.F1);
+    launch_convert<double, float>(X, ldx, F0, d, d, k, s);
+    CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
+    launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
+  }
+  // Hs = Q^T H Q, eigen-decomposition (ascending)
+  CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
+                         static_cast<int>(d), &one, X, static_cast<int>(ldx), HQ,
+                         static_cast<int>(ldhq), &zero, S1, k));
+  launch_symmetrize(S1, k, s);
+  CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k, evals,
+                            Ework, info));
+  // X <- Q S ; HX <- HQ S  (through B1 when HX is given, else B1 holds HQ)
+  if (HX) {
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                           static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
+                           B1, static_cast<int>(d)));
+    launch_copy2d(B1, d, X, ldx, d, k, s);
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                           static_cast<int>(d), k, k, &one, HX, static_cast<int>(ldhx), S1, k,
+                           &zero, B1, static_cast<int>(d)));
+    launch_copy2d(B1, d, HX, ldhx, d, k, s);
+    launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, s);
+  } else {
+    // B1 holds HQ; rotate X through B2, then HQ S into B2 for the residuals
+    double* T2 = Ptr<double>::at(work, ly.B2);
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                           static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
+                           T2, static_cast<int>(d)));
+    launch_copy2d(T2, d, X, ldx, d, k, s);
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                           static_cast<int>(d), k, k, &one, B1, static_cast<int>(d), S1, k, &zero,
+                           T2, static_cast<int>(d)));
+    launch_residuals(T2, d, X, ldx, evals, res, d, k, s);
+  }
+  CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  CES_HIP(hipStreamSynchronize(s));
+  if (hinfo != 0) return fail(CES_ERR_EIGENSOLVER, "syevd did not converge");
+  return CES_OK;
+}
+
+}  // namespace
+}  // namespace ces
+
+using namespace ces;
+
+extern "C" {
+
+const char* ces_status_string(ces_status s) {
+  switch (s) {
+    case CES_OK: return "CES_OK";
+    case CES_ERR_INVALID_ARG: return "CES_ERR_INVALID_ARG";
+    case CES_ERR_DEVICE: return "CES_ERR_DEVICE";
+    case CES_ERR_ALLOC: return "CES_ERR_ALLOC";
+    case CES_ERR_WORKSPACE: return "CES_ERR_WORKSPACE";
+    case CES_ERR_NOT_POSITIVE_DEFINITE: return "CES_ERR_NOT_POSITIVE_DEFINITE";
+    case CES_ERR_EIGENSOLVER: return "CES_ERR_EIGENSOLVER";
+  }
+  return "unknown ces_status";
+}
+
+const char* ces_last_error(void) { return g_err.c_str(); }
+
+ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
+                            int radial_rule, ces_basis* out) {
+  if (!out) return fail(CES_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (lmax < 0 || n_rad < 1 || !(R > 0) || n_r < 1 || n_theta < 1)
+    return fail(CES_ERR_INVALID_ARG, "basis sizes must be positive");
+  if (n_phi < 2 * lmax + 1) return fail(CES_ERR_INVALID_ARG, "n_phi must be >= 2*lmax+1");
+  if (radial_rule != CES_RADIAL_GAUSS_JACOBI_R2 && radial_rule != CES_RADIAL_GAUSS_LEGENDRE)
+    return fail(CES_ERR_INVALID_ARG, "unknown radial rule");
+  if (lmax > 200 || n_rad > 4000 || n_r > 8000 || n_theta > 4000 || n_phi > 2048)
+    return fail(CES_ERR_INVALID_ARG, "basis sizes beyond supported limits");
+  ces_basis_s* bb = new (std::nothrow) ces_basis_s();
+  if (!bb) return fail(CES_ERR_ALLOC, "out of host memory");
+  Basis& b = bb->b;
+  b.L = lmax + 1;
+  b.N = n_rad;
+  b.R = R;
+  b.n_r = n_r;
+  b.n_theta = n_theta;
+  b.n_phi = n_phi;
+  b.rule = radial_rule;
+  b.d = int64_t(b.L) * b.L * b.N;
+  b.n_grid = int64_t(n_r) * n_theta * n_phi;
+  try {
+    build_host_tables(b);
+  } catch (const std::exception& e) {
+    delete bb;
+    return fail(CES_ERR_INVALID_ARG, e.what());
+  }
+  *out = bb;
+  return CES_OK;
+}
+
+ces_status ces_basis_destroy(ces_basis bb) {
+  if (!bb) return CES_OK;
+  if (bb->b.dev_block) (void)hipFree(bb->b.dev_block);
+  delete bb;
+  return CES_OK;
+}
+
+ces_status ces_basis_info(ces_basis bb, int64_t* d, int64_t* n_grid) {
+  if (!bb) return fail(CES_ERR_INVALID_ARG, "null basis");
+  if (d) *d = bb->b.d;
+  if (n_grid) *n_grid = bb->b.n_grid;
+  return CES_OK;
+}
+
+ces_status ces_basis_grid(ces_basis bb, double* h_r, double* h_wr, double* h_theta,
+                          double* h_wtheta, double* h_phi) {
+  if (!bb) return fail(CES_ERR_INVALID_ARG, "null basis");
+  const Basis& b = bb->b;
+  if (h_r) std::memcpy(h_r, b.r.data(), b.r.size() * 8);
+  if (h_wr) std::memcpy(h_wr, b.wr.data(), b.wr.size() * 8);
+  if (h_theta) std::memcpy(h_theta, b.theta.data(), b.theta.size() * 8);
+  if (h_wtheta) std::memcpy(h_wtheta, b.wt.data(), b.wt.size() * 8);
+  if (h_phi) std::memcpy(h_phi, b.phi.data(), b.phi.size() * 8);
+  return CES_OK;
+}
+
+ces_status ces_basis_tables(ces_basis bb, double* h_zeros, double* h_radial, double* h_legendre) {
+  if (!bb) return fail(CES_ERR_INVALID_ARG, "null basis");
+  const Basis& b = bb->b;
+  if (h_zeros) std::memcpy(h_zeros, b.zeros.data(), b.zeros.size() * 8);
+  if (h_radial) std::memcpy(h_radial, b.radial.data(), b.radial.size() * 8);
+  if (h_legendre) std::memcpy(h_legendre, b.legendre.data(), b.legendre.size() * 8);
+  return CES_OK;
+}
+
+ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const double* d_proj,
+                          const double* h_proj_energy, void* stream, ces_ham* out) {
+  if (!out) return fail(CES_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!bb || !d_veff) return fail(CES_ERR_INVALID_ARG, "null basis or V_eff");
+  if (n_proj < 0 || (n_proj > 0 && (!d_proj || !h_proj_energy)))
+    return fail(CES_ERR_INVALID_ARG, "bad projector arguments");
+  Basis& b = bb->b;
+  CES_TRY(ensure_device(b));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ces_ham_s* hh = new (std::nothrow) ces_ham_s();
+  if (!hh) return fail(CES_ERR_ALLOC, "out of host memory");
+  Ham& h = hh->h;
+  h.basis = &b;
+  h.n_proj = n_proj;
+  const size_t S = 2 * size_t(b.L) - 1;
+  const size_t nab = size_t(b.n_r) * b.n_theta * 2 * S;
+  const size_t sz_v = align256(size_t(b.n_grid) * 8), sz_ab64 = align256(nab * 8),
+               sz_ab32 = align256(nab * 4), sz_p64 = align256(size_t(b.d) * n_proj * 8),
+               sz_p32 = align256(size_t(b.d) * n_proj * 4), sz_h = align256(size_t(n_proj) * 12 + 16);
+  void* blk = nullptr;
+  if (hipMalloc(&blk, sz_v + sz_ab64 + sz_ab32 + sz_p64 + sz_p32 + sz_h) != hipSuccess) {
+    delete hh;
+    return fail(CES_ERR_ALLOC, "hipMalloc of hamiltonian storage failed");
+  }
+  h.dev_block = blk;
+  char* p = static_cast<char*>(blk);
+  h.veff = reinterpret_cast<double*>(p);
+  h.ab64 = reinterpret_cast<double*>(p + sz_v);
+  h.ab32 = reinterpret_cast<float*>(p + sz_v + sz_ab64);
+  char* pp = p + sz_v + sz_ab64 + sz_ab32;
+  if (n_proj > 0) {
+    h.proj64 = reinterpret_cast<double*>(pp);
+    h.proj32 = reinterpret_cast<float*>(pp + sz_p64);
+    h.hproj64 = reinterpret_cast<double*>(pp + sz_p64 + sz_p32);
+    h.hproj32 = reinterpret_cast<float*>(pp + sz_p64 + sz_p32 + align256(size_t(n_proj) * 8));
+  }
+  auto cleanup = [&](ces_status st) {
+    if (h.blas) rocblas_destroy_handle(h.blas);
+    (void)hipFree(blk);
+    delete hh;
+    return st;
+  };
+  if (rocblas_create_handle(&h.blas) != rocblas_status_success)
+    return cleanup(fail(CES_ERR_DEVICE, "rocblas_create_handle failed"));
+  if (hipMemcpyAsync(h.veff, d_veff, size_t(b.n_grid) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return cleanup(fail(CES_ERR_DEVICE, "copy of V_eff failed"));
+  launch_veff_fourier(b, h.veff, h.ab64, h.ab32, s);
+  if (n_proj > 0) {
+    if (hipMemcpyAsync(h.proj64, d_proj, size_t(b.d) * n_proj * 8, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return cleanup(fail(CES_ERR_DEVICE, "copy of projectors failed"));
+    launch_convert<double, float>(h.proj64, b.d, h.proj32, b.d, b.d, n_proj, s);
+    std::vector<float> e32(n_proj);
+    for (int q = 0; q < n_proj; ++q) e32[q] = static_cast<float>(h_proj_energy[q]);
+    if (hipMemcpyAsync(h.hproj64, h_proj_energy, size_t(n_proj) * 8, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(h.hproj32, e32.data(), size_t(n_proj) * 4, hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+      return cleanup(fail(CES_ERR_DEVICE, "copy of projector energies failed"));
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
+    return cleanup(fail(CES_ERR_DEVICE, "hamiltonian setup failed on the device"));
+  *out = hh;
+  return CES_OK;
+}
+
+ces_status ces_ham_set_veff(ces_ham hh, const double* d_veff, void* stream) {
+  CES_TRY(check_ham(hh));
+  if (!d_veff) return fail(CES_ERR_INVALID_ARG, "null V_eff");
+  Ham& h = hh->h;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CES_HIP(hipMemcpyAsync(h.veff, d_veff, size_t(h.basis->n_grid) * 8, hipMemcpyDeviceToDevice, s));
+  launch_veff_fourier(*h.basis, h.veff, h.ab64, h.ab32, s);
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_ham_destroy(ces_ham hh) {
+  if (!hh) return CES_OK;
+  if (hh->h.blas) rocblas_destroy_handle(hh->h.blas);
+  if (hh->h.dev_block) (void)hipFree(hh->h.dev_block);
+  delete hh;
+  return CES_OK;
+}
+
+ces_status ces_workspace_size(ces_ham hh, int k, int prec, size_t* bytes) {
+  if (!hh || !bytes) return fail(CES_ERR_INVALID_ARG, "null argument");
+  if (k < 1) return fail(CES_ERR_INVALID_ARG, "k must be >= 1");
+  if (prec != CES_PREC_FP64 && prec != CES_PREC_MIXED)
+    return fail(CES_ERR_INVALID_ARG, "unknown precision");
+  *bytes = layout_for(hh->h, k, prec).total;
+  return CES_OK;
+}
+
+ces_status ces_apply_H(ces_ham hh, int k, const double* d_X, int64_t ldx, double* d_Y,
+                       int64_t ldy, int prec, void* d_work, size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  CES_TRY(check_block(h, k, d_Y, ldy, "Y"));
+  Layout ly;
+  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t d = h.basis->d;
+  if (prec == CES_PREC_FP64)
+    return h_step<double>(h, ly, d_work, k, d_X, ldx, nullptr, 0, d_Y, ldy, 1.0, 0.0, 0.0, s);
+  float* F0 = Ptr<float>::at(d_work, ly.F0);
+  float* F1 = Ptr<float>::at(d_work, ly.F1);
+  launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
+  CES_TRY(h_step<float>(h, ly, d_work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
+  launch_convert<float, double>(F1, d, d_Y, ldy, d, k, s);
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, double a,
+                           double b, double a0, int prec, void* d_work, size_t work_bytes,
+                           void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (degree < 1) return fail(CES_ERR_INVALID_ARG, "degree must be >= 1");
+  if (!(a < b) || !(a0 < a) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(a0))
+    return fail(CES_ERR_INVALID_ARG, "filter bounds must satisfy a0 < a < b");
+  Layout ly;
+  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t d = h.basis->d;
+  if (prec == CES_PREC_FP64) {
+    double* B1 = Ptr<double>::at(d_work, ly.B1);
+    double* res = nullptr;
+    int64_t ldr = 0;
+    CES_TRY(cheb_run<double>(h, ly, d_work, k, d_X, ldx, B1, d, degree, a, b, a0, s, &res, &ldr));
+    if (res != d_X) launch_copy2d(res, ldr, d_X, ldx, d, k, s);
+  } else {
+    float* F0 = Ptr<float>::at(d_work, ly.F0);
+    float* F1 = Ptr<float>::at(d_work, ly.F1);
+    launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
+    float* res = nullptr;
+    int64_t ldr = 0;
+    CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, d, F1, d, degree, a, b, a0, s, &res, &ldr));
+    launch_convert<float, double>(res, ldr, d_X, ldx, d, k, s);
+  }
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_rayleigh_ritz(ces_ham hh, int k, double* d_X, int64_t ldx, double* d_HX,
+                             double* d_eval, double* d_resnorm, int hx_prec, void* d_work,
+                             size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (!d_eval || !d_resnorm) return fail(CES_ERR_INVALID_ARG, "null eigenvalue/residual output");
+  if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
+  Layout ly;
+  CES_TRY(check_work(h, k, hx_prec, d_work, work_bytes, ly));
+  return rr_impl(h, ly, d_work, k, d_X, ldx, d_HX, ldx, d_eval, d_resnorm, hx_prec,
+                 static_cast<hipStream_t>(stream));
+}
+
+ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* h_bound,
+                             void* d_work, size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  if (!d_v0 || !h_bound || steps < 1) return fail(CES_ERR_INVALID_ARG, "bad Lanczos arguments");
+  const int64_t d = h.basis->d;
+  if (steps > d) steps = static_cast<int>(d);
+  Layout ly;
+  CES_TRY(check_work(h, 1, CES_PREC_FP64, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* v = Ptr<double>::at(d_work, ly.V3);
+  double* vp = v + d;
+  double* w = v + 2 * d;
+  double* sc = Ptr<double>::at(d_work, ly.vec);
+  CES_HIP(hipMemsetAsync(vp, 0, size_t(d) * 8, s));
+  launch_dot(d_v0, d_v0, d, sc, s);
+  double nrm2 = 0;
+  CES_HIP(hipMemcpyAsync(&nrm2, sc, 8, hipMemcpyDeviceToHost, s));
+  CES_HIP(hipStreamSynchronize(s));
+  if (!(nrm2 > 0) || !std::isfinite(nrm2)) return fail(CES_ERR_INVALID_ARG, "bad Lanczos start vector");
+  launch_axpby(1.0 / std::sqrt(nrm2), d_v0, 0.0, v, d, s);
+  std::vector<double> al, be;
+  double beta = 0.0;
+  for (int j = 0; j < steps; ++j) {
+    CES_TRY(h_step<double>(h, ly, d_work, 1, v, d, nullptr, 0, w, d, 1.0, 0.0, 0.0, s));
+    launch_dot(v, w, d, sc, s);
+    double alpha = 0;
+    CES_HIP(hipMemcpyAsync(&alpha, sc, 8, hipMemcpyDeviceToHost, s));
+    CES_HIP(hipStreamSynchronize(s));
+    launch_axpby(-alpha, v, 1.0, w, d, s);
+    if (j > 0) launch_axpby(-beta, vp, 1.0, w, d, s);
+    launch_dot(w, w, d, sc, s);
+    double b2 = 0;
+    CES_HIP(hipMemcpyAsync(&b2, sc, 8, hipMemcpyDeviceToHost, s));
+    CES_HIP(hipStreamSynchronize(s));
+    beta = std::sqrt(std::max(b2, 0.0));
+    al.push_back(alpha);
+    if (j + 1 < steps) {
+      be.push_back(beta);
+      if (!(beta > 0)) break;  // invariant subspace found
+      launch_copy2d(v, d, vp, d, d, 1, s);
+      launch_axpby(1.0 / beta, w, 0.0, v, d, s);
+    }
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  const double ub = tridiag_max(al, be) + beta;
+  *h_bound = ub > 0 ? ub * 1.01 : ub / 1.01;
+  return CES_OK;
+}
+
+ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, double b,
+                      int n_check, int max_iter, int fixed_iter, double res_tol,
+                      double dtheta_tol, int prec, double* d_eval, double* d_resnorm,
+                      int* h_iters, void* d_work, size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (!d_eval || !d_resnorm || !h_iters) return fail(CES_ERR_INVALID_ARG, "null output");
+  if (degree < 1 || n_check < 1 || n_check > k || max_iter < 1 || fixed_iter < 0)
+    return fail(CES_ERR_INVALID_ARG, "bad iteration parameters");
+  if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
+  Layout ly;
+  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t d = h.basis->d;
+  std::vector<double> theta(k), theta_old(k), res(k);
+  CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s));
+  CES_HIP(hipMemcpy(theta.data(), d_eval, size_t(k) * 8, hipMemcpyDeviceToHost));
+  int it = 0;
+  while (true) {
+    ++it;
+    const double a0 = theta[0], a = theta[k - 1];
+    if (!(a < b)) return fail(CES_ERR_INVALID_ARG, "upper bound b is below the Ritz values");
+    const double a0u = (a0 < a) ? a0 : a - 1e-6 * std::max(1.0, std::fabs(a));
+    if (prec == CES_PREC_FP64) {
+      double* B1 = Ptr<double>::at(d_work, ly.B1);
+      double* out = nullptr;
+      int64_t ldr = 0;
+      CES_TRY(cheb_run<double>(h, ly, d_work, k, d_X, ldx, B1, d, degree, a, b, a0u, s, &out, &ldr));
+      if (out != d_X) launch_copy2d(out, ldr, d_X, ldx, d, k, s);
+    } else {
+      float* F0 = Ptr<float>::at(d_work, ly.F0);
+      float* F1 = Ptr<float>::at(d_work, ly.F1);
+      launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
+      float* out = nullptr;
+      int64_t ldr = 0;
+      CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, d, F1, d, degree, a, b, a0u, s, &out, &ldr));
+      launch_convert<float, double>(out, ldr, d_X, ldx, d, k, s);
+    }
+    theta_old = theta;
+    CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s));
+    CES_HIP(hipMemcpy(theta.data(), d_eval, size_t(k) * 8, hipMemcpyDeviceToHost));
+    CES_HIP(hipMemcpy(res.data(), d_resnorm, size_t(k) * 8, hipMemcpyDeviceToHost));
+    if (fixed_iter > 0) {
+      if (it >= fixed_iter) break;
+      continue;
+    }
+    bool ok = true;
+    for (int i = 0; i < n_check; ++i) {
+      if (!(res[i] <= res_tol * std::max(1.0, std::fabs(theta[i])))) ok = false;
+      if (!(std::fabs(theta[i] - theta_old[i]) < dtheta_tol)) ok = false;
+    }
+    if (ok || it >= max_iter) break;
+  }
+  *h_iters = it;
+  return CES_OK;
+}
+
+ces_status ces_to_grid(ces_ham hh, int k, const double* d_X, int64_t ldx, double* d_f,
+                       void* d_work, size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (!d_f) return fail(CES_ERR_INVALID_ARG, "null grid output");
+  Layout ly;
+  CES_TRY(check_work(h, k, CES_PREC_FP64, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Basis& b = *h.basis;
+  double* G = Ptr<double>::at(d_work, ly.G);
+  launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, static_cast<int>(ly.kp), s);
+  launch_angular_synth<double>(b, b.t64, G, d_f, k, static_cast<int>(ly.kp), s);
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_from_grid(ces_ham hh, int k, const double* d_f, double* d_X, int64_t ldx,
+                         void* d_work, size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (!d_f) return fail(CES_ERR_INVALID_ARG, "null grid input");
+  Layout ly;
+  CES_TRY(check_work(h, k, CES_PREC_FP64, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Basis& b = *h.basis;
+  double* A = Ptr<double>::at(d_work, ly.A);
+  const int kp = static_cast<int>(ly.kp);
+  launch_angular_analysis<double>(b, b.t64, d_f, A, k, kp, s);
+  launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_X, ldx, 1.0, 0.0, 0.0,
+                                false, nullptr, 0, nullptr, k, kp, s);
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_density(ces_ham hh, int k, const double* d_X, int64_t ldx, const double* d_occ,
+                       double* d_rho_grid, double* d_rho_coef, int prec, void* d_work,
+                       size_t work_bytes, void* stream) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  CES_TRY(check_block(h, k, d_X, ldx, "X"));
+  if (!d_occ || !d_rho_grid) return fail(CES_ERR_INVALID_ARG, "null occupations or density");
+  Layout ly;
+  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Basis& b = *h.basis;
+  const int kp = static_cast<int>(ly.kp);
+  if (prec == CES_PREC_FP64) {
+    double* G = Ptr<double>::at(d_work, ly.G);
+    launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, kp, s);
+    launch_density_synth<double>(b, b.t64, G, d_occ, d_rho_grid, k, kp, s);
+  } else {
+    float* F0 = Ptr<float>::at(d_work, ly.F0);
+    float* G = Ptr<float>::at(d_work, ly.G);
+    launch_convert<double, float>(d_X, ldx, F0, b.d, b.d, k, s);
+    launch_radial_inverse<float>(b, b.t32, F0, b.d, G, k, kp, s);
+    launch_density_synth<float>(b, b.t32, G, d_occ, d_rho_grid, k, kp, s);
+  }
+  if (d_rho_coef) {
+    double* A = Ptr<double>::at(d_work, ly.A);
+    launch_angular_analysis<double>(b, b.t64, d_rho_grid, A, 1, kp, s);
+    launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_rho_coef, b.d, 1.0, 0.0,
+                                  0.0, false, nullptr, 0, nullptr, 1, kp, s);
+  }
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+}  // extern "C"

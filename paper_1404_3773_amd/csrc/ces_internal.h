@@ -1,0 +1,126 @@
+// Internal declarations of libces: handle structs, device table layouts and
+// kernel launchers.  Device layouts (all row-major, innermost index last):
+//   X blocks   [i][alpha]            column-major d x k, ld >= d
+//   G, A       [r][lm][i]            per radial node and (l,m), i padded to kp
+//   Rinv       [l][r][n]             R_ln(r_k)
+//   Rfwd       [l][n][r]             w_k R_ln(r_k)
+//   Pleg       [jp][l(l+1)/2 + m]    c_lm P_l^m(t_jp) * (sqrt2 for m > 0),
+//                                    jp over the nodes with t >= 0
+//   ab         [r][j][2][S]          halved phi-Fourier cosine / sine sums of
+//                                    V_eff at each (r, theta_j), S = 2L - 1
+//   V          [r][j][p]
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ces.h"
+
+typedef struct _rocblas_handle* rocblas_handle;
+
+namespace ces {
+
+constexpr int kColPad = 16;  // internal column padding of G/A and mixed blocks
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+template <typename T>
+struct DevTables {
+  T* Rinv = nullptr;
+  T* Rfwd = nullptr;
+  T* Pleg = nullptr;
+  T* lamh = nullptr;   // [l][n] Lambda_ln / 2
+  T* wt = nullptr;     // [n_theta]
+  T* trig = nullptr;   // [S][n_phi]: slot s < L cos(s phi_p), else sin((s-L+1) phi_p)
+};
+
+struct Basis {
+  int L = 0, N = 0, n_r = 0, n_theta = 0, n_phi = 0, rule = 0;
+  double R = 0;
+  int64_t d = 0, n_grid = 0;
+  std::vector<double> zeros, r, wr, theta, t, wt, phi;
+  std::vector<double> radial;    // [l][k][n]
+  std::vector<double> legendre;  // [j][l(l+1)/2 + m]
+  int device = -1;
+  double* dev_cs = nullptr;      // [2][n_phi] cos, sin(2 pi u / n_phi)
+  DevTables<double> t64;
+  DevTables<float> t32;
+  void* dev_block = nullptr;     // single allocation holding all device tables
+};
+
+struct Ham {
+  Basis* basis = nullptr;
+  double* veff = nullptr;   // [n_grid]
+  double* ab64 = nullptr;   // [n_r*n_theta*2*S]
+  float* ab32 = nullptr;
+  int n_proj = 0;
+  double* proj64 = nullptr; // d x n_proj
+  float* proj32 = nullptr;
+  double* hproj64 = nullptr;
+  float* hproj32 = nullptr;
+  rocblas_handle blas = nullptr;
+  size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
+  int solver_ws_k = 0;
+  void* dev_block = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers are asynchronous on `s` and assume validated arguments.
+
+template <typename T>
+void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
+                           T* G, int k, int kp, hipStream_t s);
+
+// out = alpha * (Z + lamh o Yin + KB - c * Yin) + beta * Yold, with
+// Z = Rfwd^T A (per lm).  Yold may be null when beta == 0.  kbP/kbC may be
+// null (no projector term); kbC is n_proj x kp (ld kp) already scaled by h.
+template <typename T>
+void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
+                           int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
+                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
+                           const T* kbC, int k, int kp, hipStream_t s);
+
+template <typename T>
+void launch_angular(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* A,
+                    int kp, hipStream_t s);
+
+void launch_veff_fourier(const Basis& b, const double* V, double* ab64, float* ab32,
+                         hipStream_t s);
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t rows,
+                    int cols, hipStream_t s);
+
+// C[q][i] *= h[q] for q < rows, i < ld.
+template <typename T>
+void launch_scale_rows(T* C, int rows, int ld, const T* h, hipStream_t s);
+
+// Transforms for grids of k functions (column i at offset i*n_grid).
+template <typename T>
+void launch_angular_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* f, int k,
+                          int kp, hipStream_t s);
+template <typename T>
+void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f, T* A, int k,
+                             int kp, hipStream_t s);
+// rho[g] = 2 sum_i occ_i psi_i(g)^2 from G (inverse-radial output).
+template <typename T>
+void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, const double* occ,
+                          double* rho, int k, int kp, hipStream_t s);
+
+// Small FP64 helpers for Cholesky-QR / Rayleigh-Ritz / Lanczos.
+void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s);
+void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double* dinv,
+                       hipStream_t s);
+void launch_symmetrize(double* S, int k, hipStream_t s);
+void launch_add_diag(double* S, int k, double shift, hipStream_t s);
+void launch_residuals(const double* HX, int64_t ldh, const double* X, int64_t ldx,
+                      const double* theta, double* res, int64_t rows, int k, hipStream_t s);
+void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                   int cols, hipStream_t s);
+void launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+
+}  // namespace ces

@@ -1,0 +1,709 @@
+// HIP kernels (gfx950) for H*X in the spherical-Bessel x spherical-harmonic
+// basis: the separable transform pair of Section 2.2.2 around the pointwise
+// V_eff product of Section 2.2.4, plus the kinetic term, the projector term
+// and the Chebyshev recurrence fused into the last stage.
+//
+// Stages of one H*X (layouts in ces_internal.h):
+//   radial_inverse  G[r][lm][i] = sum_n R_ln(r) X[lm*N+n][i]          eq. G_lmr
+//   angular         A[r][lm][i] = sum_j w_j Pbar_lm(t_j) Vphi_rj(Pbar G)   eq. Ar_lm
+//                   with the phi synthesis / V_eff / phi analysis done as
+//                   one exact contraction with V's phi-Fourier sums (below)
+//   radial_forward  out = alpha (sum_r w_r R_ln(r) A + Lambda/2 Y + P C
+//                   - c Y) + beta Yold                              eq. Arlm_to_coeff
+//
+// phi stage.  With f(phi) = sum_m g^c_m cos(m phi) + g^s_m sin(m phi), the
+// analysis of V f over the uniform phi grid is, exactly,
+//   gh^c_m' = sum_m (a_{|m-m'|} + a_{m+m'}) g^c_m + (b_{m+m'} + b_{m-m'}) g^s_m
+//   gh^s_m' = sum_m (b_{m'+m} + b_{m'-m}) g^c_m + (a_{|m-m'|} - a_{m+m'}) g^s_m
+// with a_q, b_q = (pi / N_phi) sum_p V_p {cos, sin}(q phi_p), b_{-q} = -b_q
+// (product-to-sum identities; |q| <= 2L-2 < N_phi).  a, b depend on V only,
+// so they are computed once per V_eff and the per-orbital work needs no FFT.
+#include <hip/hip_runtime.h>
+
+#include "ces_internal.h"
+
+namespace ces {
+
+namespace {
+
+__device__ __forceinline__ int isqrt_lm(int lm) {
+  int l = static_cast<int>(sqrtf(static_cast<float>(lm)));
+  while (l * l > lm) --l;
+  while ((l + 1) * (l + 1) <= lm) ++l;
+  return l;
+}
+
+// ------------------------------------------------------------ radial GEMMs
+
+constexpr int RT_M = 64, RT_N = 64, RT_K = 16;
+
+// G[r][lm][i] = sum_n Rinv[l][r][n] X[lm*N + n + i*ldx]; zero for k <= i < kp.
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_inverse(const T* __restrict__ Rinv,
+                                                        const T* __restrict__ X, int64_t ldx,
+                                                        T* __restrict__ G, int L, int N, int n_r,
+                                                        int k, int kp) {
+  const int lm = blockIdx.z;
+  const int l = isqrt_lm(lm);
+  const int LL = L * L;
+  const int r0 = blockIdx.x * RT_M, i0 = blockIdx.y * RT_N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ T As[RT_K][RT_M + 1];
+  __shared__ T Bs[RT_K][RT_N + 1];
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
+  const T* Rl = Rinv + static_cast<int64_t>(l) * n_r * N;
+  const T* Xl = X + static_cast<int64_t>(lm) * N;
+  for (int n0 = 0; n0 < N; n0 += RT_K) {
+    for (int e = tid; e < RT_K * RT_M; e += 256) {
+      const int kk = e % RT_K, rr = e / RT_K;
+      const int r = r0 + rr, n = n0 + kk;
+      As[kk][rr] = (r < n_r && n < N) ? Rl[static_cast<int64_t>(r) * N + n] : T(0);
+    }
+    for (int e = tid; e < RT_K * RT_N; e += 256) {
+      const int kk = e % RT_K, ii = e / RT_K;
+      const int i = i0 + ii, n = n0 + kk;
+      Bs[kk][ii] = (i < k && n < N) ? Xl[static_cast<int64_t>(i) * ldx + n] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < RT_K; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = r0 + ty + 16 * a;
+    if (r >= n_r) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + tx + 16 * c;
+      if (i < kp) G[(static_cast<int64_t>(r) * LL + lm) * kp + i] = acc[a][c];
+    }
+  }
+}
+
+// out[lm*N+n][i] = alpha * (Z + lamh*Yin - c*Yin) + beta*Yold,
+// Z = sum_r Rfwd[l][n][r] A[r][lm][i] + sum_q P[lm*N+n][q] C[q][i].
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_forward(
+    const T* __restrict__ Rfwd, const T* __restrict__ A, const T* __restrict__ lamh,
+    const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
+    T* __restrict__ out, int64_t ldout, T alpha, T cshift, T beta, int kinetic,
+    const T* __restrict__ P, int n_proj, const T* __restrict__ C, int64_t d, int L, int N,
+    int n_r, int k, int kp) {
+  const int lm = blockIdx.z;
+  const int l = isqrt_lm(lm);
+  const int LL = L * L;
+  const int n0b = blockIdx.x * RT_M, i0 = blockIdx.y * RT_N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ T As[RT_K][RT_M + 1];
+  __shared__ T Bs[RT_K][RT_N + 1];
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
+  const T* Rl = Rfwd + static_cast<int64_t>(l) * N * n_r;
+  // radial quadrature, K = n_r
+  for (int q0 = 0; q0 < n_r; q0 += RT_K) {
+    for (int e = tid; e < RT_K * RT_M; e += 256) {
+      const int kk = e % RT_K, nn = e / RT_K;
+      const int n = n0b + nn, r = q0 + kk;
+      As[kk][nn] = (n < N && r < n_r) ? Rl[static_cast<int64_t>(n) * n_r + r] : T(0);
+    }
+    for (int e = tid; e < RT_K * RT_N; e += 256) {
+      const int ii = e % RT_N, kk = e / RT_N;
+      const int i = i0 + ii, r = q0 + kk;
+      Bs[kk][ii] = (i < kp && r < n_r) ? A[(static_cast<int64_t>(r) * LL + lm) * kp + i] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < RT_K; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+    __syncthreads();
+  }
+  // projector term, K = n_proj
+  for (int q0 = 0; q0 < n_proj; q0 += RT_K) {
+    for (int e = tid; e < RT_K * RT_M; e += 256) {
+      const int nn = e % RT_M, kk = e / RT_M;
+      const int n = n0b + nn, q = q0 + kk;
+      As[kk][nn] = (n < N && q < n_proj)
+                       ? P[static_cast<int64_t>(q) * d + static_cast<int64_t>(lm) * N + n]
+                       : T(0);
+    }
+    for (int e = tid; e < RT_K * RT_N; e += 256) {
+      const int ii = e % RT_N, kk = e / RT_N;
+      const int i = i0 + ii, q = q0 + kk;
+      Bs[kk][ii] = (i < kp && q < n_proj) ? C[static_cast<int64_t>(q) * kp + i] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < RT_K; ++kk) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int i = i0 + ty + 16 * c;
+    if (i >= k) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int n = n0b + tx + 16 * a;
+      if (n >= N) continue;
+      const int64_t row = static_cast<int64_t>(lm) * N + n;
+      T z = acc[a][c];
+      if (kinetic) {
+        const T y = Yin[static_cast<int64_t>(i) * ldin + row];
+        z += (lamh[static_cast<int64_t>(l) * N + n] - cshift) * y;
+      }
+      T v = alpha * z;
+      if (beta != T(0)) v += beta * Yold[static_cast<int64_t>(i) * ldold + row];
+      out[static_cast<int64_t>(i) * ldout + row] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------ angular stage
+
+// Coefficient of input slot s in output slot so of the phi stage (see the
+// file header); slots s < L are cos(m phi) with m = s, slots s >= L are
+// sin(m phi) with m = s - L + 1.  ha, hb hold a_q, b_q for q in [0, S).
+template <typename T>
+__device__ __forceinline__ T phi_coupling(const T* ha, const T* hb, int L, int so, int s) {
+  const bool so_sin = so >= L, s_sin = s >= L;
+  const int mo = so_sin ? so - L + 1 : so;
+  const int m = s_sin ? s - L + 1 : s;
+  const int dm = m - mo;
+  const int adm = dm < 0 ? -dm : dm;
+  const T bdif = dm >= 0 ? hb[adm] : -hb[adm];  // b_{m-m'}
+  if (!so_sin && !s_sin) return ha[adm] + ha[m + mo];
+  if (!so_sin && s_sin) return hb[m + mo] + bdif;
+  if (so_sin && !s_sin) return hb[m + mo] - bdif;
+  return ha[adm] - ha[m + mo];
+}
+
+// One workgroup per (radial node r, batch of KB columns).  G and the A
+// accumulators for the batch sit in LDS; the loop runs over pairs of theta
+// nodes t, -t (P_l^m(-t) = (-1)^{l+m} P_l^m(t)), for each pair:
+//   1. g(+-t) = E +- O, E/O the sums over even/odd l-m of Pbar G,
+//   2. gh = T_{r,t} g for both nodes (phi stage with V),
+//   3. A += w_t Pbar (gh(t) +- gh(-t)) with the sign of (-1)^{l-m}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_angular(const T* __restrict__ G, T* __restrict__ A,
+                                                 const T* __restrict__ Pleg,
+                                                 const T* __restrict__ ab,
+                                                 const T* __restrict__ wt, int L, int n_r,
+                                                 int n_theta, int kp, int KB) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int r = blockIdx.x;
+  const int i0 = blockIdx.y * KB;
+  const int LL = L * L, S = 2 * L - 1;
+  const int LP = L * (L + 1) / 2;
+  T* Gs = smem;
+  T* As = Gs + LL * KB;
+  T* gp = As + LL * KB;
+  T* gm = gp + S * KB;
+  T* hp = gm + S * KB;
+  T* hm = hp + S * KB;
+  T* abp = hm + S * KB;
+  T* abm = abp + 2 * S;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < LL * KB; e += blockDim.x) {
+    const int lm = e / KB, ii = e % KB;
+    Gs[e] = G[(static_cast<int64_t>(r) * LL + lm) * kp + i0 + ii];
+    As[e] = T(0);
+  }
+  __syncthreads();
+  const int npairs = (n_theta + 1) / 2;
+  for (int jp = 0; jp < npairs; ++jp) {
+    const int j = jp, jn = n_theta - 1 - jp;
+    const T wfac = wt[j] * (j == jn ? T(0.5) : T(1));
+    for (int q = tid; q < 2 * S; q += blockDim.x) {
+      abp[q] = ab[(static_cast<int64_t>(r) * n_theta + j) * 2 * S + q];
+      abm[q] = ab[(static_cast<int64_t>(r) * n_theta + jn) * 2 * S + q];
+    }
+    const T* Pj = Pleg + static_cast<int64_t>(jp) * LP;
+    for (int e = tid; e < S * KB; e += blockDim.x) {
+      const int s = e / KB, ii = e % KB;
+      const bool sn = s >= L;
+      const int m = sn ? s - L + 1 : s;
+      T E = T(0), O = T(0);
+      for (int l = m; l < L; ++l) {
+        const T p = Pj[l * (l + 1) / 2 + m];
+        const T g = Gs[(l * l + l + (sn ? -m : m)) * KB + ii];
+        if ((l - m) & 1)
+          O += p * g;
+        else
+          E += p * g;
+      }
+      gp[e] = E + O;
+      gm[e] = E - O;
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * S * KB; e += blockDim.x) {
+      const int which = e / (S * KB), rem = e % (S * KB);
+      const int so = rem / KB, ii = rem % KB;
+      const T* abx = which ? abm : abp;
+      const T* gx = which ? gm : gp;
+      T acc = T(0);
+      for (int s = 0; s < S; ++s) acc += phi_coupling(abx, abx + S, L, so, s) * gx[s * KB + ii];
+      (which ? hm : hp)[rem] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < LL * KB; e += blockDim.x) {
+      const int lm = e / KB, ii = e % KB;
+      const int l = isqrt_lm(lm);
+      const int ms = lm - l * l - l;
+      const int m = ms < 0 ? -ms : ms;
+      const int s = ms >= 0 ? m : L - 1 + m;
+      const T p = Pj[l * (l + 1) / 2 + m];
+      const T a = hp[s * KB + ii], b = hm[s * KB + ii];
+      As[e] += wfac * p * (((l - m) & 1) ? (a - b) : (a + b));
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < LL * KB; e += blockDim.x) {
+    const int lm = e / KB, ii = e % KB;
+    A[(static_cast<int64_t>(r) * LL + lm) * kp + i0 + ii] = As[e];
+  }
+}
+
+// ab[r][j][0][q] = (pi/N_phi) sum_p V cos(q phi_p), ab[..][1][q] the sine sums;
+// cs holds cos / sin(2 pi u / N_phi), u < N_phi, indexed by (q p) mod N_phi.
+__global__ void k_veff_fourier(const double* __restrict__ V, const double* __restrict__ cs,
+                               double* __restrict__ ab64, float* __restrict__ ab32, int n_phi,
+                               int S, double scale) {
+  const int64_t rj = blockIdx.x;
+  const double* v = V + rj * n_phi;
+  for (int q = threadIdx.x; q < 2 * S; q += blockDim.x) {
+    const bool sn = q >= S;
+    const int qq = sn ? q - S : q;
+    const double* tab = cs + (sn ? n_phi : 0);
+    double acc = 0.0;
+    int u = 0;
+    for (int p = 0; p < n_phi; ++p) {
+      acc += v[p] * tab[u];
+      u += qq;
+      if (u >= n_phi) u -= n_phi;
+    }
+    ab64[rj * 2 * S + q] = scale * acc;
+    ab32[rj * 2 * S + q] = static_cast<float>(scale * acc);
+  }
+}
+
+// ---------------------------------------------------- grid synthesis/analysis
+
+template <typename T>
+__device__ __forceinline__ T pleg_at(const T* Pleg, int n_theta, int LP, int j, int l, int m) {
+  const int jn = n_theta - 1 - j;
+  if (j <= jn) return Pleg[static_cast<int64_t>(j) * LP + l * (l + 1) / 2 + m];
+  const T v = Pleg[static_cast<int64_t>(jn) * LP + l * (l + 1) / 2 + m];
+  return ((l + m) & 1) ? -v : v;
+}
+
+// f[i][r][j][p] from G, one workgroup per (r, j), loop over columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_angular_synth(const T* __restrict__ G, T* __restrict__ f,
+                                                       const T* __restrict__ Pleg,
+                                                       const T* __restrict__ trig, int L,
+                                                       int n_theta, int n_phi, int64_t n_grid,
+                                                       int k, int kp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* gs = reinterpret_cast<T*>(smem_raw);
+  const int r = blockIdx.x, j = blockIdx.y;
+  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
+  for (int i = 0; i < k; ++i) {
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+      const bool sn = s >= L;
+      const int m = sn ? s - L + 1 : s;
+      T acc = T(0);
+      for (int l = m; l < L; ++l)
+        acc += pleg_at(Pleg, n_theta, LP, j, l, m) *
+               G[(static_cast<int64_t>(r) * LL + l * l + l + (sn ? -m : m)) * kp + i];
+      gs[s] = acc;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n_phi; p += blockDim.x) {
+      T acc = T(0);
+      for (int s = 0; s < S; ++s) acc += gs[s] * trig[static_cast<int64_t>(s) * n_phi + p];
+      f[static_cast<int64_t>(i) * n_grid + (static_cast<int64_t>(r) * n_theta + j) * n_phi + p] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// A[r][lm][i] = sum_j w_j Pbar_lm(t_j) (2 pi / N_phi) sum_p f trig, one
+// workgroup per (r, column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_angular_analysis(const T* __restrict__ f,
+                                                          T* __restrict__ A,
+                                                          const T* __restrict__ Pleg,
+                                                          const T* __restrict__ trig,
+                                                          const T* __restrict__ wt, int L,
+                                                          int n_theta, int n_phi,
+                                                          int64_t n_grid, int kp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  const int r = blockIdx.x, i = blockIdx.y;
+  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
+  T* gh = As + LL;
+  const T dphi = T(2.0 * M_PI / n_phi);
+  for (int e = threadIdx.x; e < LL; e += blockDim.x) As[e] = T(0);
+  const T* fi = f + static_cast<int64_t>(i) * n_grid;
+  for (int j = 0; j < n_theta; ++j) {
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+      T acc = T(0);
+      const T* row = fi + (static_cast<int64_t>(r) * n_theta + j) * n_phi;
+      for (int p = 0; p < n_phi; ++p) acc += row[p] * trig[static_cast<int64_t>(s) * n_phi + p];
+      gh[s] = acc * dphi;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+      const int l = isqrt_lm(e);
+      const int ms = e - l * l - l;
+      const int m = ms < 0 ? -ms : ms;
+      const int s = ms >= 0 ? m : L - 1 + m;
+      As[e] += wt[j] * pleg_at(Pleg, n_theta, LP, j, l, m) * gh[s];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < LL; e += blockDim.x)
+    A[(static_cast<int64_t>(r) * LL + e) * kp + i] = As[e];
+}
+
+// rho[r][j][p] = 2 sum_i occ_i psi_i^2, psi from G, one workgroup per (r, j).
+template <typename T>
+__global__ __launch_bounds__(256) void k_density_synth(const T* __restrict__ G,
+                                                       const double* __restrict__ occ,
+                                                       double* __restrict__ rho,
+                                                       const T* __restrict__ Pleg,
+                                                       const T* __restrict__ trig, int L,
+                                                       int n_theta, int n_phi, int k, int kp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* gs = reinterpret_cast<T*>(smem_raw);
+  const int r = blockIdx.x, j = blockIdx.y;
+  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
+  constexpr int MAXP = 8;  // n_phi <= 8 * blockDim
+  double acc[MAXP];
+#pragma unroll
+  for (int u = 0; u < MAXP; ++u) acc[u] = 0.0;
+  for (int i = 0; i < k; ++i) {
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+      const bool sn = s >= L;
+      const int m = sn ? s - L + 1 : s;
+      T a = T(0);
+      for (int l = m; l < L; ++l)
+        a += pleg_at(Pleg, n_theta, LP, j, l, m) *
+             G[(static_cast<int64_t>(r) * LL + l * l + l + (sn ? -m : m)) * kp + i];
+      gs[s] = a;
+    }
+    __syncthreads();
+    const double o = 2.0 * occ[i];
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+      const int p = threadIdx.x + u * blockDim.x;
+      if (p < n_phi) {
+        T psi = T(0);
+        for (int s = 0; s < S; ++s) psi += gs[s] * trig[static_cast<int64_t>(s) * n_phi + p];
+        acc[u] += o * static_cast<double>(psi) * static_cast<double>(psi);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < MAXP; ++u) {
+    const int p = threadIdx.x + u * blockDim.x;
+    if (p < n_phi) rho[(static_cast<int64_t>(r) * n_theta + j) * n_phi + p] = acc[u];
+  }
+}
+
+// --------------------------------------------------------------- utilities
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ src, int64_t lds, Tout* __restrict__ dst,
+                          int64_t ldd, int64_t rows, int cols) {
+  const int c = blockIdx.y;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[c * ldd + e] = static_cast<Tout>(src[c * lds + e]);
+  (void)cols;
+}
+
+__global__ void k_scale_gram(double* S, int k, double* dinv) {
+  // one block; dinv_i = 1/sqrt(S_ii), S_ij *= dinv_i dinv_j
+  for (int i = threadIdx.x; i < k; i += blockDim.x) dinv[i] = 1.0 / sqrt(S[i * (int64_t)k + i]);
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < int64_t(k) * k; e += blockDim.x) {
+    const int i = e % k, j = e / k;
+    S[e] *= dinv[i] * dinv[j];
+  }
+}
+
+__global__ void k_scale_cols(double* X, int64_t ldx, int64_t rows, const double* dinv) {
+  const int c = blockIdx.y;
+  const double s = dinv[c];
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    X[c * ldx + e] *= s;
+}
+
+__global__ void k_symmetrize(double* S, int k) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+       e < int64_t(k) * k; e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = e % k, j = e / k;
+    if (i < j) {
+      const double v = 0.5 * (S[e] + S[int64_t(i) * k + j]);
+      S[e] = v;
+      S[int64_t(i) * k + j] = v;
+    }
+  }
+}
+
+__global__ void k_add_diag(double* S, int k, double shift) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    S[int64_t(i) * k + i] += shift;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int u = 0; u < (int)(blockDim.x + 63) / 64; ++u) t += red[u];
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_residuals(const double* HX, int64_t ldh,
+                                                   const double* X, int64_t ldx,
+                                                   const double* theta, double* res,
+                                                   int64_t rows) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  const double th = theta[c];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < rows; e += blockDim.x) {
+    const double v = HX[c * ldh + e] - th * X[c * ldx + e];
+    acc += v * v;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) res[c] = sqrt(t);
+}
+
+__global__ void k_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd,
+                         int64_t rows) {
+  const int c = blockIdx.y;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[c * ldd + e] = src[c * lds + e];
+}
+
+__global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, int64_t n,
+                                             double* out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) acc += x[e] * y[e];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+__global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[e] = a * x[e] + b * y[e];
+}
+
+template <typename T>
+__global__ void k_scale_rows(T* C, int rows, int ld, const T* h) {
+  const int q = blockIdx.x;
+  for (int i = threadIdx.x; i < ld; i += blockDim.x) C[static_cast<int64_t>(q) * ld + i] *= h[q];
+}
+
+inline int grid1d(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return static_cast<int>(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
+                           T* G, int k, int kp, hipStream_t s) {
+  dim3 grid((b.n_r + RT_M - 1) / RT_M, (kp + RT_N - 1) / RT_N, b.L * b.L);
+  k_radial_inverse<T><<<grid, 256, 0, s>>>(tb.Rinv, X, ldx, G, b.L, b.N, b.n_r, k, kp);
+}
+
+template <typename T>
+void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
+                           int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
+                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
+                           const T* kbC, int k, int kp, hipStream_t s) {
+  dim3 grid((b.N + RT_M - 1) / RT_M, (k + RT_N - 1) / RT_N, b.L * b.L);
+  k_radial_forward<T><<<grid, 256, 0, s>>>(tb.Rfwd, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                           ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
+                                           kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k, kp);
+}
+
+int angular_batch(int L, size_t elem) {
+  // Largest power-of-two column batch whose LDS footprint stays within 80 KB
+  // (two workgroups per CU), capped at 16 (the column padding).
+  const size_t LL = size_t(L) * L, S = 2 * size_t(L) - 1;
+  for (int kb = 16; kb > 1; kb >>= 1)
+    if ((2 * LL + 4 * S) * kb * elem + 4 * S * elem <= 80 * 1024) return kb;
+  return 1;
+}
+
+size_t angular_lds(int L, int kb, size_t elem) {
+  const size_t LL = size_t(L) * L, S = 2 * size_t(L) - 1;
+  return ((2 * LL + 4 * S) * kb + 4 * S) * elem;
+}
+
+template <typename T>
+void launch_angular(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* A,
+                    int kp, hipStream_t s) {
+  const int kb = angular_batch(b.L, sizeof(T));
+  const size_t lds = angular_lds(b.L, kb, sizeof(T));
+  static size_t lds_set = 0;
+  if (lds > lds_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    lds_set = lds;
+  }
+  dim3 grid(b.n_r, kp / kb);
+  k_angular<T><<<grid, 256, lds, s>>>(G, A, tb.Pleg, ab, tb.wt, b.L, b.n_r, b.n_theta, kp, kb);
+}
+
+void launch_veff_fourier(const Basis& b, const double* V, double* ab64, float* ab32,
+                         hipStream_t s) {
+  const int S = 2 * b.L - 1;
+  k_veff_fourier<<<b.n_r * b.n_theta, 128, 0, s>>>(V, b.dev_cs, ab64, ab32, b.n_phi, S,
+                                                   M_PI / b.n_phi);
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t rows,
+                    int cols, hipStream_t s) {
+  dim3 grid(grid1d(rows), cols);
+  k_convert<Tin, Tout><<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows, cols);
+}
+
+template <typename T>
+void launch_angular_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* f, int k,
+                          int kp, hipStream_t s) {
+  dim3 grid(b.n_r, b.n_theta);
+  k_angular_synth<T><<<grid, 256, (2 * b.L - 1) * sizeof(T), s>>>(
+      G, f, tb.Pleg, tb.trig, b.L, b.n_theta, b.n_phi, b.n_grid, k, kp);
+}
+
+template <typename T>
+void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f, T* A, int k,
+                             int kp, hipStream_t s) {
+  dim3 grid(b.n_r, k);
+  const size_t lds = (size_t(b.L) * b.L + 2 * b.L - 1) * sizeof(T);
+  k_angular_analysis<T><<<grid, 256, lds, s>>>(f, A, tb.Pleg, tb.trig, tb.wt, b.L, b.n_theta,
+                                               b.n_phi, b.n_grid, kp);
+}
+
+template <typename T>
+void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, const double* occ,
+                          double* rho, int k, int kp, hipStream_t s) {
+  dim3 grid(b.n_r, b.n_theta);
+  k_density_synth<T><<<grid, 256, (2 * b.L - 1) * sizeof(T), s>>>(
+      G, occ, rho, tb.Pleg, tb.trig, b.L, b.n_theta, b.n_phi, k, kp);
+}
+
+template <typename T>
+void launch_scale_rows(T* C, int rows, int ld, const T* h, hipStream_t s) {
+  k_scale_rows<T><<<rows, 256, 0, s>>>(C, rows, ld, h);
+}
+
+void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s) {
+  k_scale_gram<<<1, 256, 0, s>>>(S, k, dinv);
+}
+void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double* dinv,
+                       hipStream_t s) {
+  dim3 grid(grid1d(rows), k);
+  k_scale_cols<<<grid, 256, 0, s>>>(X, ldx, rows, dinv);
+}
+void launch_symmetrize(double* S, int k, hipStream_t s) {
+  k_symmetrize<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k);
+}
+void launch_add_diag(double* S, int k, double shift, hipStream_t s) {
+  k_add_diag<<<grid1d(k), 256, 0, s>>>(S, k, shift);
+}
+void launch_residuals(const double* HX, int64_t ldh, const double* X, int64_t ldx,
+                      const double* theta, double* res, int64_t rows, int k, hipStream_t s) {
+  k_residuals<<<k, 256, 0, s>>>(HX, ldh, X, ldx, theta, res, rows);
+}
+void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                   int cols, hipStream_t s) {
+  dim3 grid(grid1d(rows), cols);
+  k_copy2d<<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows);
+}
+void launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
+  k_dot<<<1, 256, 0, s>>>(x, y, n, out);
+}
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  k_axpby<<<grid1d(n), 256, 0, s>>>(a, x, b, y, n);
+}
+
+#define CES_INST(T)                                                                           \
+  template void launch_radial_inverse<T>(const Basis&, const DevTables<T>&, const T*, int64_t, \
+                                         T*, int, int, hipStream_t);                          \
+  template void launch_radial_forward<T>(const Basis&, const DevTables<T>&, const T*, const T*, \
+                                         int64_t, const T*, int64_t, T*, int64_t, T, T, T, bool, \
+                                         const T*, int, const T*, int, int, hipStream_t);      \
+  template void launch_angular<T>(const Basis&, const DevTables<T>&, const T*, const T*, T*,  \
+                                  int, hipStream_t);                                          \
+  template void launch_angular_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
+                                        int, hipStream_t);                                    \
+  template void launch_angular_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
+                                           int, int, hipStream_t);                            \
+  template void launch_density_synth<T>(const Basis&, const DevTables<T>&, const T*,          \
+                                        const double*, double*, int, int, hipStream_t);        \
+  template void launch_scale_rows<T>(T*, int, int, const T*, hipStream_t);
+CES_INST(float)
+CES_INST(double)
+#undef CES_INST
+
+template void launch_convert<double, float>(const double*, int64_t, float*, int64_t, int64_t,
+                                            int, hipStream_t);
+template void launch_convert<float, double>(const float*, int64_t, double*, int64_t, int64_t,
+                                            int, hipStream_t);
+
+}  // namespace ces

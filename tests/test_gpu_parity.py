@@ -1,0 +1,321 @@
+"""Parity of the HIP path (through the C interface) with the FP64 oracle.
+
+Tolerances.  FP64: the GPU reorders the same sums, so results agree to a few
+hundred ulps of the largest term: 1e-11 relative to max|result|.  MIXED:
+FP32 storage and accumulation (unit roundoff 6e-8) over at most
+N + n_r + (2L-1) + L terms per output and four chained stages; 5e-5
+relative to max|result| per column.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import basis as ob
+from oracle import density as od
+from oracle import eigensolver as oe
+from oracle import hamiltonian as oh
+from conftest import golden_path
+
+torch = pytest.importorskip("torch")
+from paper_1404_3773_amd import ces  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = ces.CES_PREC_FP64, ces.CES_PREC_MIXED
+TOL64 = 1e-11
+TOL32 = 5e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def dev(X, ld=None):
+    """d x k numpy block -> (k, ld) cuda tensor."""
+    d, k = X.shape
+    ld = ld or d
+    T = torch.zeros((k, ld), dtype=torch.float64)
+    T[:, :d] = torch.from_numpy(np.ascontiguousarray(X.T))
+    return T.cuda()
+
+
+def host(T, d):
+    return T[:, :d].cpu().numpy().T.copy()
+
+
+class Setup:
+    def __init__(self, w, with_kb=False):
+        self.w = w
+        self.B = ces.Basis.for_workload(w)
+        r, wr, th, wt, ph = self.B.grid()
+        V = si.potential_on_grid(w, r, th, ph)
+        self.bs = ob.basis_for(w)
+        self.Vo = si.potential_on_grid(w, self.bs.r, self.bs.theta, self.bs.phi)
+        self.P = self.h = None
+        proj_t = None
+        if with_kb:
+            pts = si.spherical_to_cartesian(self.bs.r, self.bs.theta, self.bs.phi)
+            pg, self.h = si.kb_projector_values(pts, si.atoms_for(w))
+            self.P = oh.kb_projectors(self.bs, pg.reshape(*self.Vo.shape, -1))
+            proj_t = torch.from_numpy(np.ascontiguousarray(self.P.T)).cuda()
+        self.H = ces.Ham(self.B, torch.from_numpy(V.reshape(-1)).cuda(), proj=proj_t,
+                         energies=self.h)
+
+    def oracle_apply(self, X):
+        return oh.apply_H_real(self.bs, self.Vo, X, proj=self.P, h=self.h)
+
+
+_cache = {}
+
+
+def setup(w, with_kb=False):
+    key = (w, with_kb)
+    if key not in _cache:
+        _cache[key] = Setup(w, with_kb)
+    return _cache[key]
+
+
+SMALL = si.small(6, 8, R=9.0, k=5)
+ODD_THETA = si.small(5, 7, R=8.0, n_theta=11, n_phi=21, k=3)
+LONG_RADIAL = si.small(3, 70, R=12.0, n_r=100, k=4)
+
+
+def rel_err(got, ref):
+    return np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("w,k", [(SMALL, 1), (SMALL, 5), (SMALL, 17), (SMALL, 70),
+                                 (ODD_THETA, 3), (LONG_RADIAL, 4)],
+                         ids=["small_k1", "small_k5", "small_k17", "small_k70",
+                              "odd_theta", "N70"])
+def test_apply_H_fp64_and_mixed(w, k):
+    _say(f"case apply_H {w.name} k={k}")
+    s = setup(w)
+    X = si.random_block(s.B.d, k, 11 + k)
+    Z = s.oracle_apply(X)
+    for prec, tol in ((FP64, TOL64), (MIXED, TOL32)):
+        work = s.H.workspace(k, prec)
+        Xt = dev(X, ld=s.B.d + 3)           # ld > d
+        Yt = torch.full((k, s.B.d + 5), float("nan"), dtype=torch.float64, device="cuda")
+        s.H.apply_H(Xt, Yt, prec, work)
+        torch.cuda.synchronize()
+        Y = host(Yt, s.B.d)
+        assert np.all(np.isfinite(Y))
+        assert rel_err(Y, Z) < tol, (prec, rel_err(Y, Z))
+        assert torch.all(torch.isnan(Yt[:, s.B.d:]))   # padding untouched
+
+
+def test_apply_H_harmonic_oscillator_workload():
+    w = si.C1
+    _say(f"case apply_H {w.name}")
+    s = setup(w)
+    X = si.x0_block(w)
+    Z = s.oracle_apply(X)
+    work = s.H.workspace(w.k, FP64)
+    Xt, Yt = dev(X), torch.empty((w.k, s.B.d), dtype=torch.float64, device="cuda")
+    s.H.apply_H(Xt, Yt, FP64, work)
+    torch.cuda.synchronize()
+    assert rel_err(host(Yt, s.B.d), Z) < TOL64
+
+
+def test_apply_H_kb_projectors():
+    w = si.small(6, 8, R=10.0, k=6)
+    _say(f"case apply_H KB {w.name}")
+    s = setup(w, with_kb=True)
+    X = si.random_block(s.B.d, w.k, 5)
+    Z = s.oracle_apply(X)
+    for prec, tol in ((FP64, TOL64), (MIXED, TOL32)):
+        work = s.H.workspace(w.k, prec)
+        Xt, Yt = dev(X), torch.empty((w.k, s.B.d), dtype=torch.float64, device="cuda")
+        s.H.apply_H(Xt, Yt, prec, work)
+        torch.cuda.synchronize()
+        assert rel_err(host(Yt, s.B.d), Z) < tol, prec
+
+
+def test_apply_H_13_atom_cluster_full_size():
+    """L_max = 30, N = 60, 90 x 62 x 124 grid, k = 32, in the launch shape the
+    benchmark uses; columns sampled for the oracle."""
+    w = si.C2
+    _say(f"case apply_H full size {w.name}")
+    s = setup(w)
+    X = si.x0_block(w)
+    cols = [0, 13, 31]
+    Z = s.oracle_apply(X[:, cols])
+    for prec, tol in ((FP64, TOL64), (MIXED, TOL32)):
+        work = s.H.workspace(w.k, prec)
+        Xt, Yt = dev(X), torch.empty((w.k, s.B.d), dtype=torch.float64, device="cuda")
+        s.H.apply_H(Xt, Yt, prec, work)
+        torch.cuda.synchronize()
+        Y = host(Yt, s.B.d)[:, cols]
+        for c in range(len(cols)):
+            assert rel_err(Y[:, c], Z[:, c]) < tol, (prec, cols[c], rel_err(Y[:, c], Z[:, c]))
+
+
+def test_cheb_filter_matches_oracle():
+    w = SMALL
+    _say("case cheb_filter")
+    s = setup(w)
+    X = si.random_block(s.B.d, 7, 3)
+    app = lambda Y: s.oracle_apply(Y)  # noqa: E731
+    theta = np.linalg.eigvalsh(oh.dense_H_real(s.bs, s.Vo))
+    a0, a, b = theta[0], theta[12], theta[-1] * 1.01
+    for deg in (1, 2, 9):
+        ref = oe.chebyshev_filter(app, X, deg, a, b, a0)
+        for prec, tol in ((FP64, 1e-10), (MIXED, 1e-4)):
+            work = s.H.workspace(7, prec)
+            Xt = dev(X)
+            s.H.cheb_filter(Xt, deg, a, b, a0, prec, work)
+            torch.cuda.synchronize()
+            assert rel_err(host(Xt, s.B.d), ref) < tol, (deg, prec)
+
+
+def test_rayleigh_ritz_matches_oracle():
+    w = SMALL
+    _say("case rayleigh_ritz")
+    s = setup(w)
+    k = 6
+    X = si.random_block(s.B.d, k, 21) * np.linspace(0.1, 10.0, k)
+    theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
+    work = s.H.workspace(k, FP64)
+    Xt = dev(X)
+    HXt = torch.empty_like(Xt)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    s.H.rayleigh_ritz(Xt, ev, rs, work, HX=HXt)
+    Xg = host(Xt, s.B.d)
+    assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * np.max(np.abs(theta_ref))
+    assert np.max(np.abs(Xg.T @ Xg - np.eye(k))) < 1e-12
+    # vectors are unique up to sign (eigenvalues simple here)
+    sg = np.sign(np.sum(Xg * Xr, axis=0))
+    assert np.max(np.abs(Xg * sg - Xr)) < 1e-9
+    assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-10 * np.max(np.abs(theta_ref))
+    assert rel_err(host(HXt, s.B.d) * sg, HXr) < 1e-10
+    # without HX output
+    Xt = dev(X)
+    s.H.rayleigh_ritz(Xt, ev, rs, work)
+    assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * np.max(np.abs(theta_ref))
+
+
+def test_rayleigh_ritz_rank_deficient_block_reports_error():
+    w = SMALL
+    s = setup(w)
+    X = si.random_block(s.B.d, 4, 2)
+    X[:, 3] = X[:, 1]                 # duplicated column
+    work = s.H.workspace(4, FP64)
+    Xt = dev(X)
+    ev = torch.empty(4, dtype=torch.float64, device="cuda")
+    rs = torch.empty(4, dtype=torch.float64, device="cuda")
+    # either reported as not positive definite, or recovered by the shifted
+    # Cholesky-QR2 fallback into an orthonormal block
+    try:
+        s.H.rayleigh_ritz(Xt, ev, rs, work)
+    except ces.CesError as e:
+        assert e.value.status == 5
+        return
+    Xg = host(Xt, s.B.d)
+    assert np.max(np.abs(Xg.T @ Xg - np.eye(4))) < 1e-10
+
+
+def test_lanczos_bound_is_upper_bound():
+    w = SMALL
+    s = setup(w)
+    lam = np.linalg.eigvalsh(oh.dense_H_real(s.bs, s.Vo))
+    work = s.H.workspace(1, FP64)
+    v0 = torch.from_numpy(si.lanczos_start(s.B.d)).cuda()
+    b = s.H.lanczos_bound(v0, work)
+    assert b >= lam[-1]
+    assert b < 1.3 * lam[-1]
+
+
+def test_chefsi_harmonic_oscillator_levels():
+    """R = 10, L_max = 8, 12 radial/l, 24 x 18 x 36 grid, 10 orbitals, degree 12,
+    30 iterations: omega (n + 3/2) levels with their degeneracies."""
+    w = si.C1
+    _say(f"case chefsi {w.name}")
+    s = setup(w)
+    ref = []
+    for n, e, deg in np.loadtxt(golden_path("harmonic_oscillator_w0.5.txt"), comments="#"):
+        ref += [e] * int(deg)
+    ref = np.array(ref)
+    v0 = torch.from_numpy(si.lanczos_start(s.B.d)).cuda()
+    for prec, tol in ((FP64, 1e-8), (MIXED, 1e-6)):
+        work = s.H.workspace(w.k, prec)
+        b = s.H.lanczos_bound(v0, work)
+        Xt = dev(si.x0_block(w))
+        ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
+        rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
+        it = s.H.chefsi(Xt, w.degree, b, w.n_check, ev, rs, work, prec,
+                        fixed_iter=w.fixed_iter)
+        assert it == w.fixed_iter
+        assert np.max(np.abs(ev.cpu().numpy() - ref)) < tol, (prec, ev.cpu().numpy() - ref)
+
+
+@pytest.mark.skipif(not os.path.exists(golden_path("ico13_L31_N60_eigenvalues.txt")),
+                    reason="golden eigenvalues not generated")
+def test_chefsi_13_atom_cluster_mixed_and_fp64():
+    """13-atom cluster, k = 32, degree 16: the lowest 28 eigenvalues match the
+    oracle's converged values to 1e-6 Ha in FP64 and in mixed precision."""
+    w = si.C2
+    _say(f"case chefsi {w.name}")
+    s = setup(w)
+    ref = np.loadtxt(golden_path("ico13_L31_N60_eigenvalues.txt"), comments="#")[:, 1]
+    v0 = torch.from_numpy(si.lanczos_start(s.B.d)).cuda()
+    for prec in (MIXED, FP64):
+        work = s.H.workspace(w.k, prec)
+        b = s.H.lanczos_bound(v0, work)
+        Xt = dev(si.x0_block(w))
+        ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
+        rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
+        it = s.H.chefsi(Xt, w.degree, b, w.n_check, ev, rs, work, prec, max_iter=w.max_iter)
+        err = np.max(np.abs(ev.cpu().numpy()[:w.n_check] - ref))
+        _say(f"  prec={prec} iterations={it} max eigenvalue error={err:.3e}")
+        assert err < 1e-6, (prec, err)
+
+
+def test_density_and_transforms_match_oracle():
+    w = SMALL
+    _say("case density / to_grid / from_grid")
+    s = setup(w)
+    k = 5
+    X = si.random_block(s.B.d, k, 8)
+    occ = np.array([1.0, 1.0, 0.5, 0.25, 0.0])
+    rho_ref = od.density_grid(s.bs, X, occ)
+    tau_ref = od.density_coefficients(s.bs, rho_ref)
+    for prec, tol in ((FP64, 1e-11), (MIXED, 5e-5)):
+        work = s.H.workspace(k, prec)
+        rho = torch.empty(s.B.n_grid, dtype=torch.float64, device="cuda")
+        tau = torch.empty(s.B.d, dtype=torch.float64, device="cuda")
+        s.H.density(dev(X), torch.from_numpy(occ).cuda(), rho, tau, prec, work)
+        torch.cuda.synchronize()
+        assert rel_err(rho.cpu().numpy().reshape(rho_ref.shape), rho_ref) < tol
+        if prec == FP64:
+            assert rel_err(tau.cpu().numpy(), tau_ref) < 1e-11
+    work = s.H.workspace(k, FP64)
+    f = torch.empty((k, s.B.n_grid), dtype=torch.float64, device="cuda")
+    s.H.to_grid(dev(X), f, work)
+    fref = oh.to_grid_real(s.bs, X)
+    assert rel_err(f.cpu().numpy().reshape(k, *fref.shape[:3]),
+                   np.moveaxis(fref, 3, 0)) < 1e-11
+    Xb = torch.empty((k, s.B.d), dtype=torch.float64, device="cuda")
+    s.H.from_grid(f, Xb, work)
+    torch.cuda.synchronize()
+    assert rel_err(host(Xb, s.B.d), oh.from_grid_real(s.bs, fref)) < 1e-11
+
+
+def test_invalid_arguments_rejected_before_launch():
+    s = setup(SMALL)
+    work = s.H.workspace(3, FP64)
+    X = dev(si.random_block(s.B.d, 3, 1))
+    Y = torch.empty_like(X)
+    with pytest.raises(ces.CesError) as e:       # workspace too small
+        s.H.apply_H(X, Y, FP64, work[:1024])
+    assert e.value.status == 4
+    with pytest.raises(ces.CesError) as e:       # bad filter bounds
+        s.H.cheb_filter(X, 4, 1.0, 0.5, 0.0, FP64, work)
+    assert e.value.status == 1
+    with pytest.raises(ces.CesError) as e:       # degree 0
+        s.H.cheb_filter(X, 0, 0.0, 1.0, -1.0, FP64, work)
+    assert e.value.status == 1

@@ -1,0 +1,75 @@
+"""CPU-side checks of libces: exported symbols, host setup tables against the
+oracle's SciPy tables, argument validation.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import basis as ob
+from paper_1404_3773_amd import ces
+from conftest import ROOT
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ces.load()
+    header = open(os.path.join(ROOT, "include", "ces.h")).read()
+    declared = set(re.findall(r"\b(ces_[a-z_A-Z0-9]+)\s*\(", header))
+    assert declared, "no declarations parsed"
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(ces.EXPORTS)
+
+
+@pytest.mark.parametrize("w", [si.C1, si.small(7, 9, R=11.0, n_theta=13),
+                               si.small(12, 20, R=14.0)], ids=lambda w: w.name)
+def test_host_tables_match_oracle(w):
+    B = ces.Basis.for_workload(w)
+    bs = ob.basis_for(w)
+    r, wr, th, wt, ph = B.grid()
+    assert np.max(np.abs(r - bs.r)) < 1e-13 * w.R
+    assert np.max(np.abs(wr - bs.wr) / bs.wr) < 1e-8        # SciPy's own rule is ~1e-11
+    assert np.max(np.abs(th - bs.theta)) < 1e-13
+    assert np.max(np.abs(wt - bs.wt) / bs.wt) < 1e-10
+    assert np.max(np.abs(ph - bs.phi)) < 1e-15
+    # the library's radial rule integrates r^2 polynomials exactly
+    for p in range(0, 2 * w.n_r - 1, 3):
+        exact = w.R ** (p + 3) / (p + 3)
+        assert abs(np.sum(wr * r ** p) - exact) < 1e-12 * exact
+    z, rad, leg = B.tables()
+    assert np.max(np.abs(z - bs.b) / bs.b) < 1e-14
+    ref = np.transpose(bs.Rtab, (0, 2, 1))          # [l][k][n]
+    assert np.max(np.abs(rad - ref)) < 1e-11 * np.max(np.abs(ref))
+    L = w.L
+    for l in range(L):
+        for m in range(l + 1):
+            got = leg[:, l * (l + 1) // 2 + m]
+            assert np.max(np.abs(got - bs.Ptab[l, m])) < 1e-12, (l, m)
+
+
+def test_basis_argument_validation():
+    lib = ces.load()
+    h = ctypes.c_void_p()
+    # n_phi < 2*lmax + 1
+    assert lib.ces_basis_create(8, 12, 10.0, 24, 18, 16, 0, ctypes.byref(h)) == 1
+    assert b"n_phi" in lib.ces_last_error()
+    assert lib.ces_basis_create(-1, 12, 10.0, 24, 18, 36, 0, ctypes.byref(h)) == 1
+    assert lib.ces_basis_create(8, 12, -1.0, 24, 18, 36, 0, ctypes.byref(h)) == 1
+    assert lib.ces_basis_create(8, 12, 10.0, 24, 18, 36, 7, ctypes.byref(h)) == 1
+    assert lib.ces_basis_create(8, 12, 10.0, 24, 18, 36, 0, None) == 1
+    n = ctypes.c_size_t()
+    assert lib.ces_workspace_size(None, 4, 0, ctypes.byref(n)) == 1
+    assert lib.ces_apply_H(None, 4, None, 0, None, 0, 0, None, 0, None) == 1
+    assert lib.ces_status_string(5) == b"CES_ERR_NOT_POSITIVE_DEFINITE"
+
+
+def test_large_basis_tables_are_finite():
+    # L_max = 80, 150 radial functions: the deepest tables of the workloads
+    B = ces.Basis(80, 150, 30.0, 225, 162, 324)
+    z, rad, leg = B.tables()
+    assert np.all(np.isfinite(rad)) and np.all(np.isfinite(leg))
+    assert np.all(np.diff(z, axis=1) > 0)
+    bs_z = ob.bessel_zeros(81, 150)
+    assert np.max(np.abs(z - bs_z) / bs_z) < 1e-14
