@@ -179,6 +179,21 @@ ces_status ces_to_grid(ces_ham h, int k, const double* d_X, int64_t ldx, double*
 ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64_t ldx,
                          void* d_work, size_t work_bytes, void* stream);
 
+/* -------------------------------------------------------------- profiling */
+
+/* Stage timing with HIP events recorded around each launch of the H*X
+ * stages on the caller's stream: 0 radial inverse (eq. G_lmr), 1 angular
+ * stage (Legendre sums, phi stage with V_eff, Legendre quadrature), 2 radial
+ * quadrature with the kinetic / projector / Chebyshev epilogue, 3 projector
+ * GEMM.  ces_profile_enable(1, n) starts recording into a pool of n event
+ * pairs (later launches beyond the pool are not recorded) and clears the
+ * totals; ces_profile_enable(0, 0) stops and frees the pool.  Process-wide,
+ * not thread-safe; meant for benchmarking. */
+ces_status ces_profile_enable(int on, int max_records);
+/* Synchronise the recorded events and return, per stage s < n_stages (<= 4),
+ * the summed milliseconds h_ms[s] and launch count h_count[s]. */
+ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count);
+
 /* ----------------------------------------------------------------- misc */
 const char* ces_status_string(ces_status s);
 const char* ces_last_error(void);

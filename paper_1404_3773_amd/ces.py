@@ -26,7 +26,7 @@ EXPORTS = [
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
     "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
-    "ces_status_string", "ces_last_error",
+    "ces_profile_enable", "ces_profile_read", "ces_status_string", "ces_last_error",
 ]
 
 _lib = None
@@ -67,6 +67,8 @@ def load() -> ctypes.CDLL:
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
         "ces_to_grid": [P, I, P, I64, P, P, SZ, P],
         "ces_from_grid": [P, I, P, P, I64, P, SZ, P],
+        "ces_profile_enable": [I, I],
+        "ces_profile_read": [I, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -100,6 +102,23 @@ def _ld(X):
     """Leading dimension of a (k, ld) block tensor."""
     assert X.dtype.is_floating_point and X.dim() == 2 and X.stride(1) == 1
     return X.stride(0)
+
+
+STAGES = ("radial_inverse", "angular", "radial_forward", "kb_gemm")
+
+
+def profile_enable(on: bool, max_records: int = 65536):
+    _check(load().ces_profile_enable(1 if on else 0, int(max_records) if on else 0),
+           "ces_profile_enable")
+
+
+def profile_read():
+    """{stage: (total_ms, launches)} since profile_enable."""
+    ms = np.zeros(4)
+    cnt = np.zeros(4, dtype=np.int64)
+    _check(load().ces_profile_read(4, ms.ctypes.data_as(ctypes.c_void_p),
+                                   cnt.ctypes.data_as(ctypes.c_void_p)), "ces_profile_read")
+    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(4)}
 
 
 class Basis:

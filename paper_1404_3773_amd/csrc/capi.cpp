@@ -55,6 +55,32 @@ ces_status fail(ces_status s, const std::string& msg) {
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Stage timing (ces_profile_enable / ces_profile_read).
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;     // 2 per record
+  std::vector<int> stage;         // stage of each used record
+  double ms[4] = {0, 0, 0, 0};
+  int64_t count[4] = {0, 0, 0, 0};
+};
+Profiler g_prof;
+
+struct StageTimer {
+  int rec = -1;
+  hipStream_t s;
+  StageTimer(int st, hipStream_t stream) : s(stream) {
+    if (!g_prof.on) return;
+    const size_t used = g_prof.stage.size();
+    if (2 * used + 2 > g_prof.ev.size()) return;
+    rec = static_cast<int>(used);
+    g_prof.stage.push_back(st);
+    (void)hipEventRecord(g_prof.ev[2 * rec], s);
+  }
+  ~StageTimer() {
+    if (rec >= 0) (void)hipEventRecord(g_prof.ev[2 * rec + 1], s);
+  }
+};
+
 // Host tables of the basis (Section 2.2.1-2.2.2).
 void build_host_tables(Basis& b) {
   const int L = b.L, N = b.N;
@@ -121,7 +147,8 @@ void build_host_tables(Basis& b) {
 
 template <typename T>
 void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std::vector<T>& Pleg,
-                 std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& trig) {
+                 std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& trig,
+                 std::vector<T>& Pm, std::vector<T>& PwT) {
   const int L = b.L, N = b.N, LP = L * (L + 1) / 2, S = 2 * L - 1;
   Rinv.resize(b.radial.size());
   Rfwd.resize(b.radial.size());
@@ -147,6 +174,16 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
     }
   wt.resize(b.n_theta);
   for (int j = 0; j < b.n_theta; ++j) wt[j] = static_cast<T>(b.wt[j]);
+  const int nt = b.n_theta;
+  Pm.assign(static_cast<size_t>(L) * L * nt, T(0));
+  PwT.assign(static_cast<size_t>(L) * L * nt, T(0));
+  for (int m = 0; m < L; ++m)
+    for (int l = m; l < L; ++l)
+      for (int j = 0; j < nt; ++j) {
+        const double v = b.legendre[size_t(j) * LP + l * (l + 1) / 2 + m] * (m > 0 ? std::sqrt(2.0) : 1.0);
+        Pm[(size_t(m) * L + l) * nt + j] = static_cast<T>(v);
+        PwT[(size_t(m) * nt + j) * L + l] = static_cast<T>(b.wt[j] * v);
+      }
   trig.resize(static_cast<size_t>(S) * b.n_phi);
   for (int s = 0; s < S; ++s)
     for (int p = 0; p < b.n_phi; ++p) {
@@ -165,10 +202,10 @@ ces_status ensure_device(Basis& b) {
     if (dev != b.device) return fail(CES_ERR_INVALID_ARG, "basis tables live on another device");
     return CES_OK;
   }
-  std::vector<double> R64, F64, P64, l64, w64, t64;
-  std::vector<float> R32, F32, P32, l32, w32, t32;
-  fill_tables(b, R64, F64, P64, l64, w64, t64);
-  fill_tables(b, R32, F32, P32, l32, w32, t32);
+  std::vector<double> R64, F64, P64, l64, w64, t64, M64, W64;
+  std::vector<float> R32, F32, P32, l32, w32, t32, M32, W32;
+  fill_tables(b, R64, F64, P64, l64, w64, t64, M64, W64);
+  fill_tables(b, R32, F32, P32, l32, w32, t32, M32, W32);
   std::vector<double> cs(2 * static_cast<size_t>(b.n_phi));
   for (int u = 0; u < b.n_phi; ++u) {
     cs[u] = std::cos(2.0 * M_PI * u / b.n_phi);
@@ -186,6 +223,8 @@ ces_status ensure_device(Basis& b) {
       {R32.data(), R32.size() * 4, (void**)&b.t32.Rinv}, {F32.data(), F32.size() * 4, (void**)&b.t32.Rfwd},
       {P32.data(), P32.size() * 4, (void**)&b.t32.Pleg}, {l32.data(), l32.size() * 4, (void**)&b.t32.lamh},
       {w32.data(), w32.size() * 4, (void**)&b.t32.wt},   {t32.data(), t32.size() * 4, (void**)&b.t32.trig},
+      {M64.data(), M64.size() * 8, (void**)&b.t64.Pm},   {W64.data(), W64.size() * 8, (void**)&b.t64.PwT},
+      {M32.data(), M32.size() * 4, (void**)&b.t32.Pm},   {W32.data(), W32.size() * 4, (void**)&b.t32.PwT},
       {cs.data(), cs.size() * 8, (void**)&b.dev_cs}};
   size_t total = 0;
   for (auto& p : pieces) total += align256(p.bytes);
@@ -208,8 +247,8 @@ ces_status ensure_device(Basis& b) {
 // ------------------------------------------------------------- workspace
 
 struct Layout {
-  size_t G = 0, A = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0, vec = 0,
-         info = 0, solver = 0, total = 0;
+  size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0,
+         vec = 0, part = 0, info = 0, solver = 0, total = 0;
   size_t solver_bytes = 0;
   int64_t kp = 0;
 };
@@ -249,6 +288,7 @@ Layout layout_for(Ham& h, int k, int prec) {
   };
   L.G = take(gbytes);
   L.A = take(gbytes);
+  L.gbuf = take(size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * sizeof(double));
   L.B1 = take(size_t(b.d) * k * sizeof(double));
   L.B2 = take(size_t(b.d) * k * sizeof(double));
   L.V3 = take(size_t(b.d) * 3 * sizeof(double));
@@ -260,6 +300,7 @@ Layout layout_for(Ham& h, int k, int prec) {
   L.S1 = take(size_t(k) * k * sizeof(double));
   L.S2 = take(size_t(k) * k * sizeof(double));
   L.vec = take(size_t(8) * std::max(k, 64) * sizeof(double));
+  L.part = take(size_t(gram_chunks(b.d, k)) * k * k * sizeof(double));
   L.info = take(256);
   L.solver_bytes = solver_bytes_for(h, k);
   L.solver = take(L.solver_bytes);
@@ -313,22 +354,33 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
   const int kp = static_cast<int>(ly.kp);
   const T* P = nullptr;
   if (h.n_proj > 0) {
-    // C = diag(h) P^T Yin  (n_proj x kp)
+    // C = diag(h) P^T Yin  (n_proj x kp, row-major)
     const T one = 1, zero = 0;
     CES_BLAS(rocblas_set_stream(h.blas, s));
     CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
-    CES_BLAS(gemm_t(h.blas, rocblas_operation_transpose, rocblas_operation_none, h.n_proj, k,
-                    static_cast<int>(b.d), &one, Pd, static_cast<int>(b.d), Yin,
-                    static_cast<int>(ldin), &zero, C, kp));
+    // C[q][i] (row-major n_proj x kp) is the column-major kp x n_proj matrix Y^T P
+    StageTimer t(3, s);
+    CES_BLAS(gemm_t(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, h.n_proj,
+                    static_cast<int>(b.d), &one, Yin, static_cast<int>(ldin), Pd,
+                    static_cast<int>(b.d), &zero, C, kp));
     launch_scale_rows<T>(C, h.n_proj, kp, hd, s);
     P = Pd;
   }
-  launch_radial_inverse<T>(b, tb, Yin, ldin, G, k, kp, s);
-  launch_angular<T>(b, tb, ab_of<T>(h), G, A, kp, s);
-  launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true, P,
-                           h.n_proj, C, k, kp, s);
+  {
+    StageTimer t(0, s);
+    launch_radial_inverse<T>(b, tb, Yin, ldin, G, k, kp, s);
+  }
+  {
+    StageTimer t(1, s);
+    launch_angular_mfma<T>(b, tb, ab_of<T>(h), G, Ptr<T>::at(work, ly.gbuf), A, kp, s);
+  }
+  {
+    StageTimer t(2, s);
+    launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true,
+                             P, h.n_proj, C, k, kp, s);
+  }
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -423,7 +475,6 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   const Basis& b = *h.basis;
   const int64_t d = b.d;
   double* S1 = Ptr<double>::at(work, ly.S1);
-  double* S2 = Ptr<double>::at(work, ly.S2);
   double* vec = Ptr<double>::at(work, ly.vec);
   double* dinv = vec;
   double* evals = vec + k;
@@ -433,46 +484,43 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   CES_BLAS(rocblas_set_stream(h.blas, s));
   CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
   const double one = 1.0, zero = 0.0;
-  // S = X^T X, column scaling, Cholesky (Section 3.1.1: scale before factorising)
-  CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
-                         static_cast<int>(d), &one, X, static_cast<int>(ldx), X,
-                         static_cast<int>(ldx), &zero, S1, k));
-  launch_symmetrize(S1, k, s);
-  launch_scale_gram(S1, k, dinv, s);
-  CES_HIP(hipMemcpyAsync(S2, S1, size_t(k) * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-  CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
-  rocblas_int hinfo = 0;
-  CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  CES_HIP(hipStreamSynchronize(s));
-  if (hinfo != 0) {
-    // shifted retry: factor D S D + eps I (shifted Cholesky-QR), then a
-    // second Cholesky-QR pass below restores orthonormality.
-    CES_HIP(hipMemcpyAsync(S1, S2, size_t(k) * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_add_diag(S1, k, 1e-12 * k, s);
+  // One Cholesky-QR pass in place: S = X^T X, D = diag(S)^{-1/2}, R^T R = D S D
+  // (+ shift I), X <- X D R^{-1}.  Column scaling before factorising follows
+  // Section 3.1.1.  *ok reports whether the factorisation succeeded (X is
+  // left untouched otherwise).
+  double* part = Ptr<double>::at(work, ly.part);
+  auto pass = [&](double shift, bool* ok) -> ces_status {
+    launch_gram(X, ldx, X, ldx, S1, part, d, k, s);
+    launch_symmetrize(S1, k, s);
+    launch_scale_gram(S1, k, dinv, s);
+    if (shift > 0) launch_add_diag(S1, k, shift, s);
     CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
-    CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    rocblas_int hi = 0;
+    CES_HIP(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     CES_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky of the scaled Gram matrix failed");
+    *ok = (hi == 0);
+    if (!*ok) return CES_OK;
     launch_scale_cols(X, ldx, d, k, dinv, s);
     CES_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                            rocblas_diagonal_non_unit, static_cast<int>(d), k, &one, S1, k, X,
                            static_cast<int>(ldx)));
-    // second pass
-    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
-                           static_cast<int>(d), &one, X, static_cast<int>(ldx), X,
-                           static_cast<int>(ldx), &zero, S1, k));
-    launch_symmetrize(S1, k, s);
-    launch_scale_gram(S1, k, dinv, s);
-    CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
-    CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-    CES_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky-QR2 failed");
+    return CES_OK;
+  };
+  bool ok = false;
+  CES_TRY(pass(0.0, &ok));
+  if (!ok) {
+    // Shifted Cholesky-QR (shift ~ 11 (d k + k(k+1)) u ||D S D||), then two
+    // plain passes restore orthonormality (shifted CholeskyQR3).
+    const double u = 1.1102230246251565e-16;
+    const double shift = 11.0 * (double(d) * k + double(k) * (k + 1)) * u * k;
+    CES_TRY(pass(shift, &ok));
+    if (!ok) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "shifted Cholesky-QR failed");
+    for (int rep = 0; rep < 2; ++rep) {
+      CES_TRY(pass(0.0, &ok));
+      if (!ok) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky-QR after the shifted pass failed");
+    }
   }
-  // Q = X D R^{-1}
-  launch_scale_cols(X, ldx, d, k, dinv, s);
-  CES_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                         rocblas_diagonal_non_unit, static_cast<int>(d), k, &one, S1, k, X,
-                         static_cast<int>(ldx)));
+  rocblas_int hinfo = 0;
   // HQ
   double* HQ = HX ? HX : B1;
   const int64_t ldhq = HX ? ldhx : d;
@@ -486,9 +534,7 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
   }
   // Hs = Q^T H Q, eigen-decomposition (ascending)
-  CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, k,
-                         static_cast<int>(d), &one, X, static_cast<int>(ldx), HQ,
-                         static_cast<int>(ldhq), &zero, S1, k));
+  launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s);
   launch_symmetrize(S1, k, s);
   CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k, evals,
                             Ework, info));
@@ -543,6 +589,37 @@ const char* ces_status_string(ces_status s) {
 }
 
 const char* ces_last_error(void) { return g_err.c_str(); }
+
+ces_status ces_profile_enable(int on, int max_records) {
+  for (auto& e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof = Profiler();
+  if (!on) return CES_OK;
+  if (max_records < 1 || max_records > (1 << 20))
+    return fail(CES_ERR_INVALID_ARG, "max_records must be in [1, 2^20]");
+  g_prof.ev.resize(2 * size_t(max_records));
+  for (auto& e : g_prof.ev) CES_HIP(hipEventCreate(&e));
+  g_prof.stage.reserve(max_records);
+  g_prof.on = true;
+  return CES_OK;
+}
+
+ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count) {
+  if (n_stages < 0 || n_stages > 4 || (n_stages > 0 && (!h_ms || !h_count)))
+    return fail(CES_ERR_INVALID_ARG, "bad profile_read arguments");
+  for (size_t r = 0; r < g_prof.stage.size(); ++r) {
+    CES_HIP(hipEventSynchronize(g_prof.ev[2 * r + 1]));
+    float ms = 0.f;
+    CES_HIP(hipEventElapsedTime(&ms, g_prof.ev[2 * r], g_prof.ev[2 * r + 1]));
+    g_prof.ms[g_prof.stage[r]] += ms;
+    g_prof.count[g_prof.stage[r]] += 1;
+  }
+  g_prof.stage.clear();
+  for (int i = 0; i < n_stages; ++i) {
+    h_ms[i] = g_prof.ms[i];
+    h_count[i] = g_prof.count[i];
+  }
+  return CES_OK;
+}
 
 ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
                             int radial_rule, ces_basis* out) {

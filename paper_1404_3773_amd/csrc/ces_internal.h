@@ -35,6 +35,8 @@ struct DevTables {
   T* lamh = nullptr;   // [l][n] Lambda_ln / 2
   T* wt = nullptr;     // [n_theta]
   T* trig = nullptr;   // [S][n_phi]: slot s < L cos(s phi_p), else sin((s-L+1) phi_p)
+  T* Pm = nullptr;     // [m][l][j]  c_lm P_l^m(t_j) (* sqrt2, m > 0); 0 for l < m
+  T* PwT = nullptr;    // [m][j][l]  w_j * Pm[m][l][j]
 };
 
 struct Basis {
@@ -86,6 +88,17 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
 template <typename T>
 void launch_angular(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* A,
                     int kp, hipStream_t s);
+
+// Angular stage on MFMA: G -> gbuf (n_r x n_theta x S x kp) -> A.
+template <typename T>
+void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* gbuf,
+                         T* A, int kp, hipStream_t s);
+
+// C (k x k, column-major) = A^T B for d x k blocks, split over rows with
+// partial sums in `part` (gram_chunks(rows, k) * k * k doubles).
+int gram_chunks(int64_t rows, int k);
+void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                 double* part, int64_t rows, int k, hipStream_t s);
 
 void launch_veff_fourier(const Basis& b, const double* V, double* ab64, float* ab32,
                          hipStream_t s);

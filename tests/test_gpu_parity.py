@@ -241,16 +241,31 @@ def test_chefsi_harmonic_oscillator_levels():
         ref += [e] * int(deg)
     ref = np.array(ref)
     v0 = torch.from_numpy(si.lanczos_start(s.B.d)).cuda()
-    for prec, tol in ((FP64, 1e-8), (MIXED, 1e-6)):
-        work = s.H.workspace(w.k, prec)
+    # k = 10 exactly closes three shells: the state at the block edge sits at
+    # the start a = theta_k of the damped interval and converges slowly
+    # (1.7e-5 Ha after 30 iterations, identically in the oracle).  The GPU run
+    # must reproduce the oracle's 30-iteration values; one guard state (k = 11)
+    # brings all ten levels to the textbook values.
+    H = oh.dense_H_real(s.bs, s.Vo)
+    app = lambda Y: H @ Y  # noqa: E731
+    b_or = oe.lanczos_upper_bound(app, si.lanczos_start(s.B.d))
+    th_or, _, _, _ = oe.chefsi(app, si.x0_block(w), w.degree, b_or, w.n_check,
+                               fixed_iter=w.fixed_iter)
+    work = s.H.workspace(11, MIXED)
+    for k, prec, check in ((10, FP64, "oracle"), (11, FP64, 1e-8), (11, MIXED, 1e-6)):
         b = s.H.lanczos_bound(v0, work)
-        Xt = dev(si.x0_block(w))
-        ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
-        rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
-        it = s.H.chefsi(Xt, w.degree, b, w.n_check, ev, rs, work, prec,
-                        fixed_iter=w.fixed_iter)
+        assert abs(b - b_or) < 1e-9 * b_or
+        Xt = dev(si.x0_block(w, k=k))
+        ev = torch.empty(k, dtype=torch.float64, device="cuda")
+        rs = torch.empty(k, dtype=torch.float64, device="cuda")
+        it = s.H.chefsi(Xt, w.degree, b, 10, ev, rs, work, prec, fixed_iter=w.fixed_iter)
         assert it == w.fixed_iter
-        assert np.max(np.abs(ev.cpu().numpy() - ref)) < tol, (prec, ev.cpu().numpy() - ref)
+        e = ev.cpu().numpy()[:10]
+        if check == "oracle":
+            assert np.max(np.abs(e - th_or)) < 1e-9, e - th_or
+            assert np.max(np.abs(e[:9] - ref[:9])) < 1e-7
+        else:
+            assert np.max(np.abs(e - ref)) < check, (k, prec, e - ref)
 
 
 @pytest.mark.skipif(not os.path.exists(golden_path("ico13_L31_N60_eigenvalues.txt")),
