@@ -80,7 +80,9 @@ typedef struct ces_ham_s* ces_ham;
  * iteration, Lambda_ln = (b_ln/R)^2, radial and angular Gauss nodes and
  * weights by Golub-Welsch, R_ln(r_k), normalised P_l^m(t_j), and their FP32
  * copies, uploaded to the current device.  Synchronous.
- * lmax >= 0, n_rad >= 1, R > 0, n_r >= 1, n_theta >= 1, n_phi >= 2*lmax+1. */
+ * lmax >= 0, n_rad >= 1, R > 0, n_r >= 1, n_theta >= 1, n_phi >= 2*lmax+1;
+ * kernel tile limits: lmax <= 95, n_rad <= 192, n_r <= 256, n_phi <= 2048
+ * (CES_ERR_INVALID_ARG beyond them). */
 ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
                             int n_phi, int radial_rule, ces_basis* out);
 ces_status ces_basis_destroy(ces_basis b);

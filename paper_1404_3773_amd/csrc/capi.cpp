@@ -150,14 +150,17 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
                  std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& trig,
                  std::vector<T>& Pm, std::vector<T>& PwT) {
   const int L = b.L, N = b.N, LP = L * (L + 1) / 2, S = 2 * L - 1;
-  Rinv.resize(b.radial.size());
-  Rfwd.resize(b.radial.size());
+  // zero-padded MFMA operand tables (see kernels_radial.hip)
+  const int N4 = int(round_up(N, 4)), R16 = int(round_up(b.n_r, 16));
+  const int R4 = int(round_up(b.n_r, 4)), N16 = int(round_up(N, 16));
+  Rinv.assign(static_cast<size_t>(L) * N4 * R16, T(0));   // [l][n][r]
+  Rfwd.assign(static_cast<size_t>(L) * R4 * N16, T(0));   // [l][r][n]
   for (int l = 0; l < L; ++l)
     for (int kk = 0; kk < b.n_r; ++kk)
       for (int n = 0; n < N; ++n) {
         const double v = b.radial[(static_cast<size_t>(l) * b.n_r + kk) * N + n];
-        Rinv[(static_cast<size_t>(l) * b.n_r + kk) * N + n] = static_cast<T>(v);
-        Rfwd[(static_cast<size_t>(l) * N + n) * b.n_r + kk] = static_cast<T>(b.wr[kk] * v);
+        Rinv[(static_cast<size_t>(l) * N4 + n) * R16 + kk] = static_cast<T>(v);
+        Rfwd[(static_cast<size_t>(l) * R4 + kk) * N16 + n] = static_cast<T>(b.wr[kk] * v);
       }
   const int npairs = (b.n_theta + 1) / 2;
   Pleg.resize(static_cast<size_t>(npairs) * LP);
@@ -175,14 +178,15 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
   wt.resize(b.n_theta);
   for (int j = 0; j < b.n_theta; ++j) wt[j] = static_cast<T>(b.wt[j]);
   const int nt = b.n_theta;
-  Pm.assign(static_cast<size_t>(L) * L * nt, T(0));
-  PwT.assign(static_cast<size_t>(L) * L * nt, T(0));
+  const int J64 = int(round_up(nt, 64)), J4 = int(round_up(nt, 4)), L16 = int(round_up(L, 16));
+  Pm.assign(static_cast<size_t>(L) * (L + 4) * J64, T(0));   // [m][l][j]
+  PwT.assign(static_cast<size_t>(L) * J4 * L16, T(0));       // [m][j][l - m]
   for (int m = 0; m < L; ++m)
     for (int l = m; l < L; ++l)
       for (int j = 0; j < nt; ++j) {
         const double v = b.legendre[size_t(j) * LP + l * (l + 1) / 2 + m] * (m > 0 ? std::sqrt(2.0) : 1.0);
-        Pm[(size_t(m) * L + l) * nt + j] = static_cast<T>(v);
-        PwT[(size_t(m) * nt + j) * L + l] = static_cast<T>(b.wt[j] * v);
+        Pm[(size_t(m) * (L + 4) + l) * J64 + j] = static_cast<T>(v);
+        PwT[(size_t(m) * J4 + j) * L16 + (l - m)] = static_cast<T>(b.wt[j] * v);
       }
   trig.resize(static_cast<size_t>(S) * b.n_phi);
   for (int s = 0; s < S; ++s)
@@ -217,10 +221,10 @@ ces_status ensure_device(Basis& b) {
     void** dst;
   };
   std::vector<Piece> pieces = {
-      {R64.data(), R64.size() * 8, (void**)&b.t64.Rinv}, {F64.data(), F64.size() * 8, (void**)&b.t64.Rfwd},
+      {R64.data(), R64.size() * 8, (void**)&b.t64.RiT}, {F64.data(), F64.size() * 8, (void**)&b.t64.RfT},
       {P64.data(), P64.size() * 8, (void**)&b.t64.Pleg}, {l64.data(), l64.size() * 8, (void**)&b.t64.lamh},
       {w64.data(), w64.size() * 8, (void**)&b.t64.wt},   {t64.data(), t64.size() * 8, (void**)&b.t64.trig},
-      {R32.data(), R32.size() * 4, (void**)&b.t32.Rinv}, {F32.data(), F32.size() * 4, (void**)&b.t32.Rfwd},
+      {R32.data(), R32.size() * 4, (void**)&b.t32.RiT}, {F32.data(), F32.size() * 4, (void**)&b.t32.RfT},
       {P32.data(), P32.size() * 4, (void**)&b.t32.Pleg}, {l32.data(), l32.size() * 4, (void**)&b.t32.lamh},
       {w32.data(), w32.size() * 4, (void**)&b.t32.wt},   {t32.data(), t32.size() * 4, (void**)&b.t32.trig},
       {M64.data(), M64.size() * 8, (void**)&b.t64.Pm},   {W64.data(), W64.size() * 8, (void**)&b.t64.PwT},
@@ -263,6 +267,8 @@ size_t solver_bytes_for(Ham& h, int k) {
       double* fake = reinterpret_cast<double*>(uintptr_t(4096));
       rocblas_int* ifake = reinterpret_cast<rocblas_int*>(uintptr_t(4096));
       (void)rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, fake, k, ifake);
+      (void)rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, fake, k,
+                             ifake);
       (void)rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, fake, k,
                              fake, fake, ifake);
     }
@@ -283,7 +289,7 @@ Layout layout_for(Ham& h, int k, int prec) {
   auto take = [&](size_t bytes) {
     off = align256(off);
     const size_t at = off;
-    off += bytes;
+    off += bytes + 4096;   // slack past every region
     return at;
   };
   L.G = take(gbytes);
@@ -328,6 +334,7 @@ template <>
 const double* ab_of<double>(const Ham& h) { return h.ab64; }
 template <>
 const float* ab_of<float>(const Ham& h) { return h.ab32; }
+
 
 inline rocblas_status gemm_t(rocblas_handle hb, rocblas_operation ta, rocblas_operation tb, int m,
                              int n, int kk, const double* alpha, const double* A, int lda,
@@ -500,10 +507,16 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     CES_HIP(hipStreamSynchronize(s));
     *ok = (hi == 0);
     if (!*ok) return CES_OK;
+    // X <- (X D) R^{-1}: invert the k x k factor, then one GEMM through B2
+    launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
+    CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1, k,
+                              info));
     launch_scale_cols(X, ldx, d, k, dinv, s);
-    CES_BLAS(rocblas_dtrsm(h.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                           rocblas_diagonal_non_unit, static_cast<int>(d), k, &one, S1, k, X,
-                           static_cast<int>(ldx)));
+    double* T2 = Ptr<double>::at(work, ly.B2);
+    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                           static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
+                           T2, static_cast<int>(d)));
+    launch_copy2d(T2, d, X, ldx, d, k, s);
     return CES_OK;
   };
   bool ok = false;
@@ -630,8 +643,11 @@ ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
   if (n_phi < 2 * lmax + 1) return fail(CES_ERR_INVALID_ARG, "n_phi must be >= 2*lmax+1");
   if (radial_rule != CES_RADIAL_GAUSS_JACOBI_R2 && radial_rule != CES_RADIAL_GAUSS_LEGENDRE)
     return fail(CES_ERR_INVALID_ARG, "unknown radial rule");
-  if (lmax > 200 || n_rad > 4000 || n_r > 8000 || n_theta > 4000 || n_phi > 2048)
-    return fail(CES_ERR_INVALID_ARG, "basis sizes beyond supported limits");
+  // kernel tile limits: L - m <= 96 and 2L-1 <= 192 (angular), N <= 192 and
+  // n_r <= 256 (radial), n_phi <= 2048 (density synthesis)
+  if (lmax > 95 || n_rad > 192 || n_r > 256 || n_theta > 4096 || n_phi > 2048)
+    return fail(CES_ERR_INVALID_ARG, "basis sizes beyond supported limits "
+                                     "(lmax <= 95, n_rad <= 192, n_r <= 256, n_phi <= 2048)");
   ces_basis_s* bb = new (std::nothrow) ces_basis_s();
   if (!bb) return fail(CES_ERR_ALLOC, "out of host memory");
   Basis& b = bb->b;

@@ -2,10 +2,12 @@
 // kernel launchers.  Device layouts (all row-major, innermost index last):
 //   X blocks   [i][alpha]            column-major d x k, ld >= d
 //   G, A       [r][lm][i]            per radial node and (l,m), i padded to kp
-//   Rinv       [l][r][n]             R_ln(r_k)
-//   Rfwd       [l][n][r]             w_k R_ln(r_k)
+//   RiT        [l][N4][R16]          R_ln(r_k) at [l][n][r]
+//   RfT        [l][R4][N16]          w_k R_ln(r_k) at [l][r][n]
 //   Pleg       [jp][l(l+1)/2 + m]    c_lm P_l^m(t_jp) * (sqrt2 for m > 0),
 //                                    jp over the nodes with t >= 0
+//   Pm, PwT, RiT, RfT                zero-padded MFMA operand tables (shapes
+//                                    in kernels_angular.hip / kernels_radial.hip)
 //   ab         [r][j][2][S]          halved phi-Fourier cosine / sine sums of
 //                                    V_eff at each (r, theta_j), S = 2L - 1
 //   V          [r][j][p]
@@ -29,14 +31,14 @@ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 template <typename T>
 struct DevTables {
-  T* Rinv = nullptr;
-  T* Rfwd = nullptr;
+  T* RiT = nullptr;
+  T* RfT = nullptr;
   T* Pleg = nullptr;
   T* lamh = nullptr;   // [l][n] Lambda_ln / 2
   T* wt = nullptr;     // [n_theta]
   T* trig = nullptr;   // [S][n_phi]: slot s < L cos(s phi_p), else sin((s-L+1) phi_p)
-  T* Pm = nullptr;     // [m][l][j]  c_lm P_l^m(t_j) (* sqrt2, m > 0); 0 for l < m
-  T* PwT = nullptr;    // [m][j][l]  w_j * Pm[m][l][j]
+  T* Pm = nullptr;     // [m][L+4][J64]  c_lm P_l^m(t_j) (* sqrt2, m > 0); 0 for l < m
+  T* PwT = nullptr;    // [m][J4][L16]   w_j * Pm[m][m + ll][j] at [m][j][ll]
 };
 
 struct Basis {
@@ -85,14 +87,11 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                            T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
                            const T* kbC, int k, int kp, hipStream_t s);
 
-template <typename T>
-void launch_angular(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* A,
-                    int kp, hipStream_t s);
-
 // Angular stage on MFMA: G -> gbuf (n_r x n_theta x S x kp) -> A.
 template <typename T>
-void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* gbuf,
-                         T* A, int kp, hipStream_t s);
+void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G,
+                         T* gbuf, T* A, int kp, hipStream_t s);
+
 
 // C (k x k, column-major) = A^T B for d x k blocks, split over rows with
 // partial sums in `part` (gram_chunks(rows, k) * k * k doubles).
@@ -129,6 +128,7 @@ void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double
                        hipStream_t s);
 void launch_symmetrize(double* S, int k, hipStream_t s);
 void launch_add_diag(double* S, int k, double shift, hipStream_t s);
+void launch_zero_lower(double* S, int k, hipStream_t s);
 void launch_residuals(const double* HX, int64_t ldh, const double* X, int64_t ldx,
                       const double* theta, double* res, int64_t rows, int k, hipStream_t s);
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,

@@ -1,17 +1,9 @@
-// HIP kernels (gfx950) for H*X in the spherical-Bessel x spherical-harmonic
-// basis: the separable transform pair of Section 2.2.2 around the pointwise
-// V_eff product of Section 2.2.4, plus the kinetic term, the projector term
-// and the Chebyshev recurrence fused into the last stage.
+// HIP kernels (gfx950): V_eff phi-Fourier sums, grid synthesis / analysis
+// for to_grid / from_grid / density, and small FP64 helpers of Cholesky-QR,
+// Rayleigh-Ritz and Lanczos.  The H*X stages are in kernels_radial.hip and
+// kernels_angular.hip.
 //
-// Stages of one H*X (layouts in ces_internal.h):
-//   radial_inverse  G[r][lm][i] = sum_n R_ln(r) X[lm*N+n][i]          eq. G_lmr
-//   angular         A[r][lm][i] = sum_j w_j Pbar_lm(t_j) Vphi_rj(Pbar G)   eq. Ar_lm
-//                   with the phi synthesis / V_eff / phi analysis done as
-//                   one exact contraction with V's phi-Fourier sums (below)
-//   radial_forward  out = alpha (sum_r w_r R_ln(r) A + Lambda/2 Y + P C
-//                   - c Y) + beta Yold                              eq. Arlm_to_coeff
-//
-// phi stage.  With f(phi) = sum_m g^c_m cos(m phi) + g^s_m sin(m phi), the
+// phi stage of H*X.  With f(phi) = sum_m g^c_m cos(m phi) + g^s_m sin(m phi), the
 // analysis of V f over the uniform phi grid is, exactly,
 //   gh^c_m' = sum_m (a_{|m-m'|} + a_{m+m'}) g^c_m + (b_{m+m'} + b_{m-m'}) g^s_m
 //   gh^s_m' = sum_m (b_{m'+m} + b_{m'-m}) g^c_m + (a_{|m-m'|} - a_{m+m'}) g^s_m
@@ -31,273 +23,6 @@ __device__ __forceinline__ int isqrt_lm(int lm) {
   while (l * l > lm) --l;
   while ((l + 1) * (l + 1) <= lm) ++l;
   return l;
-}
-
-// ------------------------------------------------------------ radial GEMMs
-
-constexpr int RT_M = 64, RT_N = 64, RT_K = 16;
-
-// G[r][lm][i] = sum_n Rinv[l][r][n] X[lm*N + n + i*ldx]; zero for k <= i < kp.
-template <typename T>
-__global__ __launch_bounds__(256) void k_radial_inverse(const T* __restrict__ Rinv,
-                                                        const T* __restrict__ X, int64_t ldx,
-                                                        T* __restrict__ G, int L, int N, int n_r,
-                                                        int k, int kp) {
-  const int lm = blockIdx.z;
-  const int l = isqrt_lm(lm);
-  const int LL = L * L;
-  const int r0 = blockIdx.x * RT_M, i0 = blockIdx.y * RT_N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  __shared__ T As[RT_K][RT_M + 1];
-  __shared__ T Bs[RT_K][RT_N + 1];
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
-  const T* Rl = Rinv + static_cast<int64_t>(l) * n_r * N;
-  const T* Xl = X + static_cast<int64_t>(lm) * N;
-  for (int n0 = 0; n0 < N; n0 += RT_K) {
-    for (int e = tid; e < RT_K * RT_M; e += 256) {
-      const int kk = e % RT_K, rr = e / RT_K;
-      const int r = r0 + rr, n = n0 + kk;
-      As[kk][rr] = (r < n_r && n < N) ? Rl[static_cast<int64_t>(r) * N + n] : T(0);
-    }
-    for (int e = tid; e < RT_K * RT_N; e += 256) {
-      const int kk = e % RT_K, ii = e / RT_K;
-      const int i = i0 + ii, n = n0 + kk;
-      Bs[kk][ii] = (i < k && n < N) ? Xl[static_cast<int64_t>(i) * ldx + n] : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < RT_K; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int r = r0 + ty + 16 * a;
-    if (r >= n_r) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = i0 + tx + 16 * c;
-      if (i < kp) G[(static_cast<int64_t>(r) * LL + lm) * kp + i] = acc[a][c];
-    }
-  }
-}
-
-// out[lm*N+n][i] = alpha * (Z + lamh*Yin - c*Yin) + beta*Yold,
-// Z = sum_r Rfwd[l][n][r] A[r][lm][i] + sum_q P[lm*N+n][q] C[q][i].
-template <typename T>
-__global__ __launch_bounds__(256) void k_radial_forward(
-    const T* __restrict__ Rfwd, const T* __restrict__ A, const T* __restrict__ lamh,
-    const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
-    T* __restrict__ out, int64_t ldout, T alpha, T cshift, T beta, int kinetic,
-    const T* __restrict__ P, int n_proj, const T* __restrict__ C, int64_t d, int L, int N,
-    int n_r, int k, int kp) {
-  const int lm = blockIdx.z;
-  const int l = isqrt_lm(lm);
-  const int LL = L * L;
-  const int n0b = blockIdx.x * RT_M, i0 = blockIdx.y * RT_N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  __shared__ T As[RT_K][RT_M + 1];
-  __shared__ T Bs[RT_K][RT_N + 1];
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
-  const T* Rl = Rfwd + static_cast<int64_t>(l) * N * n_r;
-  // radial quadrature, K = n_r
-  for (int q0 = 0; q0 < n_r; q0 += RT_K) {
-    for (int e = tid; e < RT_K * RT_M; e += 256) {
-      const int kk = e % RT_K, nn = e / RT_K;
-      const int n = n0b + nn, r = q0 + kk;
-      As[kk][nn] = (n < N && r < n_r) ? Rl[static_cast<int64_t>(n) * n_r + r] : T(0);
-    }
-    for (int e = tid; e < RT_K * RT_N; e += 256) {
-      const int ii = e % RT_N, kk = e / RT_N;
-      const int i = i0 + ii, r = q0 + kk;
-      Bs[kk][ii] = (i < kp && r < n_r) ? A[(static_cast<int64_t>(r) * LL + lm) * kp + i] : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < RT_K; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-    }
-    __syncthreads();
-  }
-  // projector term, K = n_proj
-  for (int q0 = 0; q0 < n_proj; q0 += RT_K) {
-    for (int e = tid; e < RT_K * RT_M; e += 256) {
-      const int nn = e % RT_M, kk = e / RT_M;
-      const int n = n0b + nn, q = q0 + kk;
-      As[kk][nn] = (n < N && q < n_proj)
-                       ? P[static_cast<int64_t>(q) * d + static_cast<int64_t>(lm) * N + n]
-                       : T(0);
-    }
-    for (int e = tid; e < RT_K * RT_N; e += 256) {
-      const int ii = e % RT_N, kk = e / RT_N;
-      const int i = i0 + ii, q = q0 + kk;
-      Bs[kk][ii] = (i < kp && q < n_proj) ? C[static_cast<int64_t>(q) * kp + i] : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < RT_K; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int i = i0 + ty + 16 * c;
-    if (i >= k) continue;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int n = n0b + tx + 16 * a;
-      if (n >= N) continue;
-      const int64_t row = static_cast<int64_t>(lm) * N + n;
-      T z = acc[a][c];
-      if (kinetic) {
-        const T y = Yin[static_cast<int64_t>(i) * ldin + row];
-        z += (lamh[static_cast<int64_t>(l) * N + n] - cshift) * y;
-      }
-      T v = alpha * z;
-      if (beta != T(0)) v += beta * Yold[static_cast<int64_t>(i) * ldold + row];
-      out[static_cast<int64_t>(i) * ldout + row] = v;
-    }
-  }
-}
-
-// ------------------------------------------------------------ angular stage
-
-// Coefficient of input slot s in output slot so of the phi stage (see the
-// file header); slots s < L are cos(m phi) with m = s, slots s >= L are
-// sin(m phi) with m = s - L + 1.  ha, hb hold a_q, b_q for q in [0, S).
-template <typename T>
-__device__ __forceinline__ T phi_coupling(const T* ha, const T* hb, int L, int so, int s) {
-  const bool so_sin = so >= L, s_sin = s >= L;
-  const int mo = so_sin ? so - L + 1 : so;
-  const int m = s_sin ? s - L + 1 : s;
-  const int dm = m - mo;
-  const int adm = dm < 0 ? -dm : dm;
-  const T bdif = dm >= 0 ? hb[adm] : -hb[adm];  // b_{m-m'}
-  if (!so_sin && !s_sin) return ha[adm] + ha[m + mo];
-  if (!so_sin && s_sin) return hb[m + mo] + bdif;
-  if (so_sin && !s_sin) return hb[m + mo] - bdif;
-  return ha[adm] - ha[m + mo];
-}
-
-// One workgroup per (radial node r, batch of KB columns).  G and the A
-// accumulators for the batch sit in LDS; the loop runs over pairs of theta
-// nodes t, -t (P_l^m(-t) = (-1)^{l+m} P_l^m(t)), for each pair:
-//   1. g(+-t) = E +- O, E/O the sums over even/odd l-m of Pbar G,
-//   2. gh = T_{r,t} g for both nodes (phi stage with V),
-//   3. A += w_t Pbar (gh(t) +- gh(-t)) with the sign of (-1)^{l-m}.
-template <typename T>
-__global__ __launch_bounds__(256) void k_angular(const T* __restrict__ G, T* __restrict__ A,
-                                                 const T* __restrict__ Pleg,
-                                                 const T* __restrict__ ab,
-                                                 const T* __restrict__ wt, int L, int n_r,
-                                                 int n_theta, int kp, int KB) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  const int r = blockIdx.x;
-  const int i0 = blockIdx.y * KB;
-  const int LL = L * L, S = 2 * L - 1;
-  const int LP = L * (L + 1) / 2;
-  T* Gs = smem;
-  T* As = Gs + LL * KB;
-  T* gp = As + LL * KB;
-  T* gm = gp + S * KB;
-  T* hp = gm + S * KB;
-  T* hm = hp + S * KB;
-  T* abp = hm + S * KB;
-  T* abm = abp + 2 * S;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < LL * KB; e += blockDim.x) {
-    const int lm = e / KB, ii = e % KB;
-    Gs[e] = G[(static_cast<int64_t>(r) * LL + lm) * kp + i0 + ii];
-    As[e] = T(0);
-  }
-  __syncthreads();
-  const int npairs = (n_theta + 1) / 2;
-  for (int jp = 0; jp < npairs; ++jp) {
-    const int j = jp, jn = n_theta - 1 - jp;
-    const T wfac = wt[j] * (j == jn ? T(0.5) : T(1));
-    for (int q = tid; q < 2 * S; q += blockDim.x) {
-      abp[q] = ab[(static_cast<int64_t>(r) * n_theta + j) * 2 * S + q];
-      abm[q] = ab[(static_cast<int64_t>(r) * n_theta + jn) * 2 * S + q];
-    }
-    const T* Pj = Pleg + static_cast<int64_t>(jp) * LP;
-    for (int e = tid; e < S * KB; e += blockDim.x) {
-      const int s = e / KB, ii = e % KB;
-      const bool sn = s >= L;
-      const int m = sn ? s - L + 1 : s;
-      T E = T(0), O = T(0);
-      for (int l = m; l < L; ++l) {
-        const T p = Pj[l * (l + 1) / 2 + m];
-        const T g = Gs[(l * l + l + (sn ? -m : m)) * KB + ii];
-        if ((l - m) & 1)
-          O += p * g;
-        else
-          E += p * g;
-      }
-      gp[e] = E + O;
-      gm[e] = E - O;
-    }
-    __syncthreads();
-    for (int e = tid; e < 2 * S * KB; e += blockDim.x) {
-      const int which = e / (S * KB), rem = e % (S * KB);
-      const int so = rem / KB, ii = rem % KB;
-      const T* abx = which ? abm : abp;
-      const T* gx = which ? gm : gp;
-      T acc = T(0);
-      for (int s = 0; s < S; ++s) acc += phi_coupling(abx, abx + S, L, so, s) * gx[s * KB + ii];
-      (which ? hm : hp)[rem] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < LL * KB; e += blockDim.x) {
-      const int lm = e / KB, ii = e % KB;
-      const int l = isqrt_lm(lm);
-      const int ms = lm - l * l - l;
-      const int m = ms < 0 ? -ms : ms;
-      const int s = ms >= 0 ? m : L - 1 + m;
-      const T p = Pj[l * (l + 1) / 2 + m];
-      const T a = hp[s * KB + ii], b = hm[s * KB + ii];
-      As[e] += wfac * p * (((l - m) & 1) ? (a - b) : (a + b));
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < LL * KB; e += blockDim.x) {
-    const int lm = e / KB, ii = e % KB;
-    A[(static_cast<int64_t>(r) * LL + lm) * kp + i0 + ii] = As[e];
-  }
 }
 
 // ab[r][j][0][q] = (pi/N_phi) sum_p V cos(q phi_p), ab[..][1][q] the sine sums;
@@ -491,6 +216,15 @@ __global__ void k_symmetrize(double* S, int k) {
   }
 }
 
+// Zero the strictly lower triangle of a column-major k x k matrix.
+__global__ void k_zero_lower(double* S, int k) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+       e < int64_t(k) * k; e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = e % k, j = e / k;
+    if (i > j) S[e] = 0.0;
+  }
+}
+
 __global__ void k_add_diag(double* S, int k, double shift) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
     S[int64_t(i) * k + i] += shift;
@@ -561,53 +295,6 @@ inline int grid1d(int64_t n) {
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T>
-void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
-                           T* G, int k, int kp, hipStream_t s) {
-  dim3 grid((b.n_r + RT_M - 1) / RT_M, (kp + RT_N - 1) / RT_N, b.L * b.L);
-  k_radial_inverse<T><<<grid, 256, 0, s>>>(tb.Rinv, X, ldx, G, b.L, b.N, b.n_r, k, kp);
-}
-
-template <typename T>
-void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
-                           int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
-                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
-                           const T* kbC, int k, int kp, hipStream_t s) {
-  dim3 grid((b.N + RT_M - 1) / RT_M, (k + RT_N - 1) / RT_N, b.L * b.L);
-  k_radial_forward<T><<<grid, 256, 0, s>>>(tb.Rfwd, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                           ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
-                                           kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k, kp);
-}
-
-int angular_batch(int L, size_t elem) {
-  // Largest power-of-two column batch whose LDS footprint stays within 80 KB
-  // (two workgroups per CU), capped at 16 (the column padding).
-  const size_t LL = size_t(L) * L, S = 2 * size_t(L) - 1;
-  for (int kb = 16; kb > 1; kb >>= 1)
-    if ((2 * LL + 4 * S) * kb * elem + 4 * S * elem <= 80 * 1024) return kb;
-  return 1;
-}
-
-size_t angular_lds(int L, int kb, size_t elem) {
-  const size_t LL = size_t(L) * L, S = 2 * size_t(L) - 1;
-  return ((2 * LL + 4 * S) * kb + 4 * S) * elem;
-}
-
-template <typename T>
-void launch_angular(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* A,
-                    int kp, hipStream_t s) {
-  const int kb = angular_batch(b.L, sizeof(T));
-  const size_t lds = angular_lds(b.L, kb, sizeof(T));
-  static size_t lds_set = 0;
-  if (lds > lds_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_angular<T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    lds_set = lds;
-  }
-  dim3 grid(b.n_r, kp / kb);
-  k_angular<T><<<grid, 256, lds, s>>>(G, A, tb.Pleg, ab, tb.wt, b.L, b.n_r, b.n_theta, kp, kb);
-}
-
 void launch_veff_fourier(const Basis& b, const double* V, double* ab64, float* ab32,
                          hipStream_t s) {
   const int S = 2 * b.L - 1;
@@ -663,6 +350,9 @@ void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double
 void launch_symmetrize(double* S, int k, hipStream_t s) {
   k_symmetrize<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k);
 }
+void launch_zero_lower(double* S, int k, hipStream_t s) {
+  k_zero_lower<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k);
+}
 void launch_add_diag(double* S, int k, double shift, hipStream_t s) {
   k_add_diag<<<grid1d(k), 256, 0, s>>>(S, k, shift);
 }
@@ -683,13 +373,6 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hip
 }
 
 #define CES_INST(T)                                                                           \
-  template void launch_radial_inverse<T>(const Basis&, const DevTables<T>&, const T*, int64_t, \
-                                         T*, int, int, hipStream_t);                          \
-  template void launch_radial_forward<T>(const Basis&, const DevTables<T>&, const T*, const T*, \
-                                         int64_t, const T*, int64_t, T*, int64_t, T, T, T, bool, \
-                                         const T*, int, const T*, int, int, hipStream_t);      \
-  template void launch_angular<T>(const Basis&, const DevTables<T>&, const T*, const T*, T*,  \
-                                  int, hipStream_t);                                          \
   template void launch_angular_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
                                         int, hipStream_t);                                    \
   template void launch_angular_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \

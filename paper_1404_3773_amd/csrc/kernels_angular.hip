@@ -19,41 +19,10 @@
 #include <hip/hip_runtime.h>
 
 #include "ces_internal.h"
+#include "mfma.h"
 
 namespace ces {
 namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct MF;
-template <>
-struct MF<float> {
-  typedef f4 acc;
-  __device__ static acc mma(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-template <>
-struct MF<double> {
-  typedef d4 acc;
-  __device__ static acc mma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-
-template <typename A>
-__device__ __forceinline__ A zero_acc() {
-  A z;
-  z[0] = 0;
-  z[1] = 0;
-  z[2] = 0;
-  z[3] = 0;
-  return z;
-}
 
 __device__ __forceinline__ void slot_to_m(int s, int L, int& m, int& sgn) {
   // slot s < L: cos(m phi), m = s, coefficient (l, +m); else sin, (l, -m)
@@ -66,69 +35,88 @@ __device__ __forceinline__ void slot_to_m(int s, int L, int& m, int& sgn) {
   }
 }
 
+// Padded table shapes (zeros outside the valid range, so K-loops need no
+// predicates on the table operand):
+//   Pm   [m][L + 4][J64]   J64 = n_theta rounded up to 64
+//   PwT  [m][J4][L16]      J4 = n_theta rounded up to 4, L16 = L up to 16;
+//                          entry [m][j][l - m] = w_j Pm[m][l][j]
+//   S4 / S16             S rounded up to 4 / 16 (phi-stage tiles)
+struct AngDims {
+  int L, S, LL, n_theta, kp, J64, J4, L16, S4, S16;
+};
+
+__host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+inline AngDims ang_dims(const Basis& b, int kp) {
+  AngDims a;
+  a.L = b.L;
+  a.S = 2 * b.L - 1;
+  a.LL = b.L * b.L;
+  a.n_theta = b.n_theta;
+  a.kp = kp;
+  a.J64 = rup(b.n_theta, 64);
+  a.J4 = rup(b.n_theta, 4);
+  a.L16 = rup(b.L, 16);
+  a.S4 = rup(a.S, 4);
+  a.S16 = rup(a.S, 16);
+  return a;
+}
+
 // ------------------------------------------------------- legendre_synth
 
-constexpr int LS_NT = 4;  // N-tiles (16 columns each) per wave
+constexpr int LS_NT = 4;  // 16-column tiles per workgroup (all waves share them)
 
+// Workgroup: one m-slot, 64 theta nodes (one 16-row tile per wave), 64
+// columns i of one radial node r.  g[r][j][s][i] = sum_l Pm[m][l][j] G[r][lm][i].
 template <typename T>
 __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm,
                                                         const T* __restrict__ G,
-                                                        T* __restrict__ g, int L, int n_theta,
-                                                        int kp, int64_t NC) {
+                                                        T* __restrict__ g, AngDims D,
+                                                        int n_ic) {
   typedef typename MF<T>::acc acc_t;
   const int s = blockIdx.z;
   int m, sgn;
-  slot_to_m(s, L, m, sgn);
-  const int S = 2 * L - 1, LL = L * L;
+  slot_to_m(s, D.L, m, sgn);
+  const int r = blockIdx.x / n_ic;
+  const int i0 = (blockIdx.x - r * n_ic) * (16 * LS_NT);
+  const int nt_valid = min(LS_NT, (D.kp - i0) / 16);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.y * 64 + wave * 16;
-  const int64_t cbase = static_cast<int64_t>(blockIdx.x) * (16 * LS_NT);
-  const int K = L - m;
-  const int jrow = j0 + (lane & 15);
-  const int kk = lane >> 4;
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int jt = blockIdx.y * 64 + wave * 16;
+  const T* Pa = Pm + (static_cast<int64_t>(m) * (D.L + 4)) * D.J64 + jt + l16;
+  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
   acc_t acc[LS_NT];
 #pragma unroll
   for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = zero_acc<acc_t>();
-  int64_t boff[LS_NT];
-  bool bok[LS_NT];
-#pragma unroll
-  for (int nt = 0; nt < LS_NT; ++nt) {
-    const int64_t c = cbase + nt * 16 + (lane & 15);
-    bok[nt] = c < NC;
-    const int64_t r = c / kp, i = c - r * kp;
-    boff[nt] = r * LL * static_cast<int64_t>(kp) + i;
-  }
-  const T* Pmm = Pm + static_cast<int64_t>(m) * L * n_theta;
+  const int K = D.L - m;
+#pragma unroll 4
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int l = m + k0 + kk;
-    const bool lok = l < L;
-    const T a = (lok && jrow < n_theta) ? Pmm[static_cast<int64_t>(l) * n_theta + jrow] : T(0);
-    const int64_t lmoff = static_cast<int64_t>(l * l + l + sgn * m) * kp;
+    const T a = Pa[l * D.J64];                    // zero rows for l >= L
+    const int lc = min(l, D.L - 1);
+    const int off = (lc * lc + lc + sgn * m) * D.kp;
 #pragma unroll
-    for (int nt = 0; nt < LS_NT; ++nt) {
-      const T b = (lok && bok[nt]) ? G[boff[nt] + lmoff] : T(0);
-      acc[nt] = MF<T>::mma(a, b, acc[nt]);
-    }
+    for (int nt = 0; nt < LS_NT; ++nt)
+      if (nt < nt_valid) acc[nt] = MF<T>::mma(a, Gr[off + nt * 16], acc[nt]);
   }
+  T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
 #pragma unroll
   for (int nt = 0; nt < LS_NT; ++nt) {
-    const int64_t c = cbase + nt * 16 + (lane & 15);
-    if (c >= NC) continue;
-    const int64_t r = c / kp, i = c - r * kp;
+    if (nt >= nt_valid) break;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int j = j0 + MF<T>::row(lane, v);
-      if (j < n_theta) g[((r * n_theta + j) * S + s) * kp + i] = acc[nt][v];
+      const int j = jt + MF<T>::row(lane, v);
+      if (j < D.n_theta) gr[static_cast<int64_t>(j) * D.S * D.kp + nt * 16] = acc[nt][v];
     }
   }
 }
 
 // ------------------------------------------------------------ phi_stage
 
-// Coupling of input slot s into output slot so (see kernels.hip header):
-// cos-cos a_|m-m'| + a_{m+m'}, cos(out)-sin(in) b_{m+m'} + b_{m-m'},
-// sin(out)-cos(in) b_{m+m'} - b_{m-m'}, sin-sin a_|m-m'| - a_{m+m'}, with
-// ha = a/2, hb = b/2 (already halved in the table) and b_{-q} = -b_q.
+// Coupling of input slot s into output slot so of the phi stage: with
+// ha = a/2, hb = b/2 and b_{-q} = -b_q,
+//   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
+//   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
 template <typename T>
 __device__ __forceinline__ T coupling(const T* ha, const T* hb, int L, int so, int s) {
   const bool so_sin = so >= L, s_sin = s >= L;
@@ -137,69 +125,107 @@ __device__ __forceinline__ T coupling(const T* ha, const T* hb, int L, int so, i
   const int dm = m - mo;
   const int adm = dm < 0 ? -dm : dm;
   const T bd = dm >= 0 ? hb[adm] : -hb[adm];
-  const T hsum = so_sin == s_sin ? ha[m + mo] : hb[m + mo];
-  const T hdif = so_sin == s_sin ? ha[adm] : bd;
-  // cos-cos: hdif + hsum; sin-sin: hdif - hsum; cos-sin: hsum + bd;
-  // sin-cos: hsum - bd
-  if (so_sin == s_sin) return so_sin ? hdif - hsum : hdif + hsum;
-  return so_sin ? hsum - bd : hsum + bd;
+  if (so_sin == s_sin) return so_sin ? ha[adm] - ha[m + mo] : ha[adm] + ha[m + mo];
+  return so_sin ? hb[m + mo] - bd : hb[m + mo] + bd;
 }
 
-constexpr int PS_NT = 2;   // N-tiles per wave
-constexpr int PS_MT = 3;   // M-tiles held per wave (S <= 16 * 4 * PS_MT = 192)
+constexpr int PS_NT = 2;   // 16-column tiles per workgroup
+constexpr int PS_MT = 3;   // M-tiles per wave (S16 <= 192)
 
+// Workgroup: one (r, theta_j), 32 columns; gh = T_rj g in place.  The A
+// fragments of T_rj are assembled from four LDS lookup tables of the
+// halved Fourier sums (branch-free form of `coupling`):
+//   D[q + L-1]          = ha_|q|           (q = m - m', same-type pairs)
+//   D[q + L-1 + S]      = sign(q) hb_|q|   (mixed pairs)
+//   E[sum]              = ha_sum,  E[sum + S] = hb_sum      (sum = m + m')
+//   T = sd * D[...] + se * E[...], sd = -1 only for sin <- cos,
+//   se = -1 only for sin <- sin.
 template <typename T>
 __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
-                                                   int L, int n_theta, int kp) {
+                                                   AngDims D) {
   typedef typename MF<T>::acc acc_t;
-  __shared__ T sab[2 * 192];
-  const int S = 2 * L - 1;
-  const int64_t rj = blockIdx.x;   // r * n_theta + j
+  constexpr int GW = 16 * PS_NT + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int S = D.S, L = D.L;
+  const int TW = 2 * S + 64;                   // table widths (padded)
+  T* Dt = reinterpret_cast<T*>(smem_raw);      // [TW]
+  T* Et = Dt + TW;                             // [TW]
+  T* gs = Et + TW;                             // [S4][GW]
+  const int64_t rj = blockIdx.x;
   const int i0 = blockIdx.y * (16 * PS_NT);
-  for (int q = threadIdx.x; q < 2 * S; q += blockDim.x) sab[q] = ab[rj * 2 * S + q];
+  const int nt_valid = min(PS_NT, (D.kp - i0) / 16);
+  T* gr = g + rj * S * static_cast<int64_t>(D.kp) + i0;
+  const T* abr = ab + rj * 2 * S;
+  for (int e = threadIdx.x; e < TW; e += blockDim.x) {
+    T dv = T(0), ev = T(0);
+    if (e < S) {                         // same-type difference, sum tables
+      const int q = e - (L - 1);
+      dv = (q > -L && q < L) ? abr[q < 0 ? -q : q] : T(0);
+      ev = abr[e];
+    } else if (e < 2 * S) {              // mixed difference (odd in q), hb sums
+      const int q = e - S - (L - 1);
+      dv = (q > -L && q < L) ? (q < 0 ? -abr[S - q] : abr[S + q]) : T(0);
+      ev = abr[S + e - S];
+    }
+    Dt[e] = dv;
+    Et[e] = ev;
+  }
+  {
+    const int ii = threadIdx.x & 31, s0 = threadIdx.x >> 5;
+    for (int s = s0; s < D.S4; s += 8)
+      gs[s * GW + ii] = (s < S && i0 + ii < D.kp) ? gr[s * D.kp + ii] : T(0);
+  }
   __syncthreads();
-  const T* ha = sab;
-  const T* hb = sab + S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nmt = (S + 15) / 16;
-  T* gr = g + rj * S * static_cast<int64_t>(kp);
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int nmt = D.S16 / 16;
+  // lane-constant output-slot data per M-tile
+  int mo[PS_MT];
+  bool osin[PS_MT];
+#pragma unroll
+  for (int u = 0; u < PS_MT; ++u) {
+    const int so = min((wave + 4 * u) * 16 + l16, S - 1);   // padded rows: any finite value
+    osin[u] = so >= L;
+    mo[u] = osin[u] ? so - L + 1 : so;
+  }
   acc_t acc[PS_MT][PS_NT];
 #pragma unroll
   for (int u = 0; u < PS_MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-  const int kk = lane >> 4;
-  for (int k0 = 0; k0 < S; k0 += 4) {
-    const int s = k0 + kk;
+#pragma unroll 2
+  for (int k0 = 0; k0 < D.S4; k0 += 4) {
+    const int s = min(k0 + kk, S - 1);         // padded g rows are zero
+    const bool ssin = s >= L;
+    const int m = ssin ? s - L + 1 : s;
     T b[PS_NT];
 #pragma unroll
-    for (int nt = 0; nt < PS_NT; ++nt) {
-      const int i = i0 + nt * 16 + (lane & 15);
-      b[nt] = (s < S && i < kp) ? gr[static_cast<int64_t>(s) * kp + i] : T(0);
-    }
+    for (int nt = 0; nt < PS_NT; ++nt) b[nt] = gs[(k0 + kk) * GW + nt * 16 + l16];
 #pragma unroll
     for (int u = 0; u < PS_MT; ++u) {
       const int mt = wave + 4 * u;
       if (mt >= nmt) break;
-      const int so = mt * 16 + (lane & 15);
-      const T a = (so < S && s < S) ? coupling(ha, hb, L, so, s) : T(0);
+      const bool same = ssin == osin[u];
+      const int di = m - mo[u] + (L - 1) + (same ? 0 : S);
+      const int ei = m + mo[u] + (same ? 0 : S);
+      const T dv = Dt[di], ev = Et[ei];
+      const T a = (same || !osin[u] ? dv : -dv) + (same && osin[u] ? -ev : ev);
 #pragma unroll
       for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
     }
   }
-  __syncthreads();  // every wave has read its g inputs; write gh in place
+  // inputs came from the LDS copy: write gh in place
 #pragma unroll
   for (int u = 0; u < PS_MT; ++u) {
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
 #pragma unroll
     for (int nt = 0; nt < PS_NT; ++nt) {
-      const int i = i0 + nt * 16 + (lane & 15);
-      if (i >= kp) continue;
+      if (nt >= nt_valid) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int so = mt * 16 + MF<T>::row(lane, v);
-        if (so < S) gr[static_cast<int64_t>(so) * kp + i] = acc[u][nt][v];
+        if (so < S) gr[so * D.kp + nt * 16 + l16] = acc[u][nt][v];
       }
     }
   }
@@ -207,67 +233,62 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
 
 // ---------------------------------------------------- legendre_analysis
 
-constexpr int LA_NT = 2;   // N-tiles per wave
-constexpr int LA_MT = 6;   // M-tiles per wave: L - m <= 96
+constexpr int LA_NT = 2;   // 16-column tiles per wave (128 columns per workgroup)
+constexpr int LA_MT = 6;   // M-tiles: L - m <= 96
 
+// Workgroup: one m-slot, up to 128 columns of one radial node (32 per wave).
+// A[r][lm][i] = sum_j w_j Pm[m][l][j] gh[r][j][s][i].
 template <typename T>
 __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__ PwT,
                                                            const T* __restrict__ g,
-                                                           T* __restrict__ A, int L,
-                                                           int n_theta, int kp, int64_t NC) {
+                                                           T* __restrict__ A, AngDims D,
+                                                           int n_ic) {
   typedef typename MF<T>::acc acc_t;
   const int s = blockIdx.y;
   int m, sgn;
-  slot_to_m(s, L, m, sgn);
-  const int S = 2 * L - 1, LL = L * L;
+  slot_to_m(s, D.L, m, sgn);
+  const int r = blockIdx.x / n_ic;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t cbase = static_cast<int64_t>(blockIdx.x) * (64 * LA_NT) + wave * (16 * LA_NT);
-  const int M = L - m;
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int i0 = (blockIdx.x - r * n_ic) * (64 * LA_NT) + wave * (16 * LA_NT);
+  const int nt_valid = min(LA_NT, (D.kp - i0) / 16);
+  if (nt_valid <= 0) return;
+  const int M = D.L - m;
   const int nmt = (M + 15) / 16;
-  const int kk = lane >> 4;
+  const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + l16;
+  const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
+  const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
   acc_t acc[LA_MT][LA_NT];
 #pragma unroll
   for (int u = 0; u < LA_MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-  int64_t boff[LA_NT];
-  bool bok[LA_NT];
-#pragma unroll
-  for (int nt = 0; nt < LA_NT; ++nt) {
-    const int64_t c = cbase + nt * 16 + (lane & 15);
-    bok[nt] = c < NC;
-    const int64_t r = c / kp, i = c - r * kp;
-    boff[nt] = (r * n_theta * S + s) * static_cast<int64_t>(kp) + i;
-  }
-  const T* Pw = PwT + static_cast<int64_t>(m) * n_theta * L;
-  const int64_t jstride = static_cast<int64_t>(S) * kp;
-  for (int k0 = 0; k0 < n_theta; k0 += 4) {
+#pragma unroll 4
+  for (int k0 = 0; k0 < D.n_theta; k0 += 4) {
     const int j = k0 + kk;
-    const bool jok = j < n_theta;
+    const int jc = min(j, D.n_theta - 1);          // padded A rows are zero
     T b[LA_NT];
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) b[nt] = (jok && bok[nt]) ? g[boff[nt] + j * jstride] : T(0);
+    for (int nt = 0; nt < LA_NT; ++nt) b[nt] = (nt < nt_valid) ? gb[jc * jstride + nt * 16] : T(0);
 #pragma unroll
     for (int u = 0; u < LA_MT; ++u) {
       if (u >= nmt) break;
-      const int l = m + u * 16 + (lane & 15);
-      const T a = (jok && l < L) ? Pw[static_cast<int64_t>(j) * L + l] : T(0);
+      const T a = Pa[j * D.L16 + u * 16];
 #pragma unroll
       for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
     }
   }
+  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
 #pragma unroll
   for (int nt = 0; nt < LA_NT; ++nt) {
-    const int64_t c = cbase + nt * 16 + (lane & 15);
-    if (c >= NC) continue;
-    const int64_t r = c / kp, i = c - r * kp;
+    if (nt >= nt_valid) break;
 #pragma unroll
     for (int u = 0; u < LA_MT; ++u) {
       if (u >= nmt) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int l = m + u * 16 + MF<T>::row(lane, v);
-        if (l < L) A[(r * LL + l * l + l + sgn * m) * kp + i] = acc[u][nt][v];
+        if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + nt * 16] = acc[u][nt][v];
       }
     }
   }
@@ -329,36 +350,39 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
   }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, double* __restrict__ C, int k,
-                              int nchunk) {
+// C[e] = sum_c part[c][e]: one wave per element, lanes stride the chunks.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+                                                     double* __restrict__ C, int k, int nchunk) {
   const int64_t kk = static_cast<int64_t>(k) * k;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < kk;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += part[c * kk + e];
-    C[e] = s;
-  }
+  const int lane = threadIdx.x & 63;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (e >= kk) return;
+  double s = 0.0;
+  for (int c = lane; c < nchunk; c += 64) s += part[c * kk + e];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) C[e] = s;
 }
 
 }  // namespace
 
 template <typename T>
-void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G, T* gbuf,
-                         T* A, int kp, hipStream_t s) {
-  const int L = b.L, S = 2 * L - 1;
-  const int64_t NC = static_cast<int64_t>(b.n_r) * kp;
+void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G,
+                         T* gbuf, T* A, int kp, hipStream_t s) {
+  const AngDims D = ang_dims(b, kp);
   {
-    dim3 grid(static_cast<unsigned>((NC + 16 * LS_NT - 1) / (16 * LS_NT)),
-              (b.n_theta + 63) / 64, S);
-    k_legendre_synth<T><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, L, b.n_theta, kp, NC);
+    const int n_ic = (kp + 16 * LS_NT - 1) / (16 * LS_NT);
+    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
+    k_legendre_synth<T><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   }
   {
     dim3 grid(b.n_r * b.n_theta, (kp + 16 * PS_NT - 1) / (16 * PS_NT));
-    k_phi_stage<T><<<grid, 256, 0, s>>>(gbuf, ab, L, b.n_theta, kp);
+    const size_t lds = (2 * size_t(2 * D.S + 64) + size_t(D.S4) * (16 * PS_NT + 1)) * sizeof(T);
+    k_phi_stage<T><<<grid, 256, lds, s>>>(gbuf, ab, D);
   }
   {
-    dim3 grid(static_cast<unsigned>((NC + 64 * LA_NT - 1) / (64 * LA_NT)), S);
-    k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, L, b.n_theta, kp, NC);
+    const int n_ic = (kp + 64 * LA_NT - 1) / (64 * LA_NT);
+    dim3 grid(b.n_r * n_ic, D.S);
+    k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
   }
 }
 
@@ -379,14 +403,13 @@ void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, dou
   dim3 grid((k + GR_T - 1) / GR_T, (k + GR_T - 1) / GR_T, nch);
   k_gram_partial<<<grid, 256, 0, s>>>(A, lda, B, ldb, part, rows, k, chunk);
   const int64_t kk = static_cast<int64_t>(k) * k;
-  int gb = static_cast<int>((kk + 255) / 256);
-  if (gb > 4096) gb = 4096;
-  k_gram_reduce<<<gb, 256, 0, s>>>(part, C, k, nch);
+  k_gram_reduce<<<static_cast<unsigned>((kk + 3) / 4), 256, 0, s>>>(part, C, k, nch);
 }
 
 template void launch_angular_mfma<float>(const Basis&, const DevTables<float>&, const float*,
                                          const float*, float*, float*, int, hipStream_t);
 template void launch_angular_mfma<double>(const Basis&, const DevTables<double>&, const double*,
                                           const double*, double*, double*, int, hipStream_t);
+
 
 }  // namespace ces

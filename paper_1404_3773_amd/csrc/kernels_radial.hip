@@ -1,0 +1,225 @@
+// Radial stages of H*X on MFMA (gfx950).
+//
+// radial_inverse (eq. G_lmr):  G[r][lm][i] = sum_n R_ln(r) X[lm*N + n][i]
+//   per (l, m): M = n_r, K = N, N = k.  The X tile (N x 32 columns) is
+//   staged through LDS so that the global loads run down the contiguous
+//   coefficient index n.  Index math is hoisted out of the K-loops: table
+//   operands are zero-padded and streaming-operand addresses clamped.
+// radial_forward (eq. Arlm_to_coeff with eq. matvec_final's kinetic term):
+//   Z[n][i] = sum_r w_r R_ln(r) A[r][lm][i] + sum_q P[lm*N+n][q] C[q][i]
+//   out = alpha (Z + (Lambda_ln/2 - c) Yin) + beta Yold
+//   per (l, m): M = N, K = n_r (+ n_proj), N = k; the last factor makes the
+//   kernel one step of the scaled Chebyshev recurrence.
+#include <hip/hip_runtime.h>
+
+#include "ces_internal.h"
+#include "mfma.h"
+
+namespace ces {
+namespace {
+
+__device__ __forceinline__ int isqrt_lm(int lm) {
+  int l = static_cast<int>(sqrtf(static_cast<float>(lm)));
+  while (l * l > lm) --l;
+  while ((l + 1) * (l + 1) <= lm) ++l;
+  return l;
+}
+
+constexpr int RI_NT = 2;   // 16-column tiles per workgroup (32 columns)
+constexpr int RI_MT = 4;   // M-tiles per wave: n_r <= 16 * 4 * 4 = 256
+constexpr int RF_MT = 3;   // M-tiles per wave: N <= 192
+
+// Padded tables (zeros outside the valid range):
+//   RiT [l][N4][R16]  R_ln(r_k) at [l][n][r];  N4 = N up to 4, R16 = n_r up to 16
+//   RfT [l][R4][N16]  w_k R_ln(r_k) at [l][r][n]; R4 = n_r up to 4, N16 = N up to 16
+__host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+// Workgroup: one (l, m), 32 columns; M = n_r split over the 4 waves.  The X
+// tile (all N rows x 32 columns) is staged in LDS; R comes from the table.
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
+                                                             const T* __restrict__ X,
+                                                             int64_t ldx, T* __restrict__ G,
+                                                             int L, int N, int n_r, int k,
+                                                             int kp) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int CW = 16 * RI_NT, XW = CW + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Xs = reinterpret_cast<T*>(smem_raw);  // [N4][XW]  X[n][i]
+  const int N4 = rup(N, 4), R16 = rup(n_r, 16);
+  const int lm = blockIdx.y;
+  const int l = isqrt_lm(lm);
+  const int i0 = blockIdx.x * CW;
+  {
+    const T* Xl = X + static_cast<int64_t>(lm) * N;
+    const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
+    const bool iok = i0 + ii < k;
+    const T* xc = Xl + static_cast<int64_t>(i0 + ii) * ldx;
+    for (int n = n0; n < N4; n += 8) Xs[n * XW + ii] = (iok && n < N) ? xc[n] : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int nmt = R16 / 16;
+  const T* Ra = RiT + static_cast<int64_t>(l) * N4 * R16 + l16;
+  acc_t acc[RI_MT][RI_NT];
+#pragma unroll
+  for (int u = 0; u < RI_MT; ++u)
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+#pragma unroll 4
+  for (int k0 = 0; k0 < N4; k0 += 4) {
+    const int n = k0 + kk;
+    T b[RI_NT];
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
+#pragma unroll
+    for (int u = 0; u < RI_MT; ++u) {
+      const int mt = wave + 4 * u;
+      if (mt >= nmt) break;
+      const T a = Ra[n * R16 + mt * 16];
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+    }
+  }
+  const int64_t rstride = static_cast<int64_t>(L) * L * kp;
+  T* Gb = G + static_cast<int64_t>(lm) * kp + i0 + l16;
+#pragma unroll
+  for (int u = 0; u < RI_MT; ++u) {
+    const int mt = wave + 4 * u;
+    if (mt >= nmt) break;
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) {
+      if (i0 + nt * 16 >= kp) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = mt * 16 + MF<T>::row(lane, v);
+        if (r < n_r) Gb[r * rstride + nt * 16] = acc[u][nt][v];
+      }
+    }
+  }
+}
+
+// Workgroup: one (l, m), 32 columns; M = N split over the 4 waves; K = n_r,
+// then n_proj for the projector term.
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_forward_mfma(
+    const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
+    const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
+    T* __restrict__ out, int64_t ldout, T alpha, T cshift, T beta, int kinetic,
+    const T* __restrict__ P, int n_proj, const T* __restrict__ C, int64_t d, int L, int N,
+    int n_r, int k, int kp) {
+  typedef typename MF<T>::acc acc_t;
+  const int R4 = rup(n_r, 4), N16 = rup(N, 16);
+  const int lm = blockIdx.y;
+  const int l = isqrt_lm(lm);
+  const int i0 = blockIdx.x * (16 * RI_NT);
+  const int nt_valid = min(RI_NT, (kp - i0) / 16);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int nmt = N16 / 16;
+  acc_t acc[RF_MT][RI_NT];
+#pragma unroll
+  for (int u = 0; u < RF_MT; ++u)
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+  const T* Ra = RfT + static_cast<int64_t>(l) * R4 * N16 + l16;
+  const T* Ab = A + static_cast<int64_t>(lm) * kp + i0 + l16;
+  const int64_t rstride = static_cast<int64_t>(L) * L * kp;
+#pragma unroll 4
+  for (int k0 = 0; k0 < R4; k0 += 4) {
+    const int r = k0 + kk;
+    const int64_t roff = min(r, n_r - 1) * rstride;   // padded table rows are zero
+    T b[RI_NT];
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = (nt < nt_valid) ? Ab[roff + nt * 16] : T(0);
+#pragma unroll
+    for (int u = 0; u < RF_MT; ++u) {
+      const int mt = wave + 4 * u;
+      if (mt >= nmt) break;
+      const T a = Ra[r * N16 + mt * 16];
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+    }
+  }
+  if (n_proj > 0) {
+    const T* Pl = P + static_cast<int64_t>(lm) * N;
+    const T* Cb = C + i0 + l16;
+    for (int q0 = 0; q0 < n_proj; q0 += 4) {
+      const int q = q0 + kk;
+      const int qc = min(q, n_proj - 1);
+      T b[RI_NT];
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt)
+        b[nt] = (nt < nt_valid) ? Cb[static_cast<int64_t>(qc) * kp + nt * 16] : T(0);
+#pragma unroll
+      for (int u = 0; u < RF_MT; ++u) {
+        const int mt = wave + 4 * u;
+        if (mt >= nmt) break;
+        const int n = mt * 16 + l16;
+        const T pv = Pl[static_cast<int64_t>(qc) * d + min(n, N - 1)];   // in-bounds address
+        const T a = (q < n_proj && n < N) ? pv : T(0);
+#pragma unroll
+        for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RF_MT; ++u) {
+    const int mt = wave + 4 * u;
+    if (mt >= nmt) break;
+#pragma unroll
+    for (int nt = 0; nt < RI_NT; ++nt) {
+      const int i = i0 + nt * 16 + l16;
+      if (i >= k) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = mt * 16 + MF<T>::row(lane, v);
+        if (n >= N) continue;
+        const int64_t row = static_cast<int64_t>(lm) * N + n;
+        T z = acc[u][nt][v];
+        if (kinetic) {
+          const T y = Yin[static_cast<int64_t>(i) * ldin + row];
+          z += (lamh[static_cast<int64_t>(l) * N + n] - cshift) * y;
+        }
+        T val = alpha * z;
+        if (beta != T(0)) val += beta * Yold[static_cast<int64_t>(i) * ldold + row];
+        out[static_cast<int64_t>(i) * ldout + row] = val;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
+                           T* G, int k, int kp, hipStream_t s) {
+  dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
+  const size_t lds = size_t(rup(b.N, 4)) * (16 * RI_NT + 1) * sizeof(T);
+  k_radial_inverse_mfma<T><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp);
+}
+
+template <typename T>
+void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
+                           int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
+                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
+                           const T* kbC, int k, int kp, hipStream_t s) {
+  dim3 grid((k + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
+  k_radial_forward_mfma<T><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
+                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
+                                                kp);
+}
+
+#define CES_INST(T)                                                                           \
+  template void launch_radial_inverse<T>(const Basis&, const DevTables<T>&, const T*, int64_t, \
+                                         T*, int, int, hipStream_t);                          \
+  template void launch_radial_forward<T>(const Basis&, const DevTables<T>&, const T*, const T*, \
+                                         int64_t, const T*, int64_t, T*, int64_t, T, T, T, bool, \
+                                         const T*, int, const T*, int, int, hipStream_t);
+CES_INST(float)
+CES_INST(double)
+#undef CES_INST
+
+}  // namespace ces

@@ -1,0 +1,42 @@
+// MFMA 16x16x4 wrappers for gfx950 (FP32 and FP64), one wave per tile.
+// Operand layout (wave64): lane q supplies A[q % 16][q / 16] and
+// B[q / 16][q % 16]; the FP32 result of lane q, register v is
+// D[4 (q / 16) + v][q % 16], the FP64 result D[q / 16 + 4 v][q % 16].
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ces {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MF;
+template <>
+struct MF<float> {
+  typedef f4 acc;
+  __device__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <>
+struct MF<double> {
+  typedef d4 acc;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <typename A>
+__device__ __forceinline__ A zero_acc() {
+  A z;
+  z[0] = 0;
+  z[1] = 0;
+  z[2] = 0;
+  z[3] = 0;
+  return z;
+}
+
+}  // namespace ces

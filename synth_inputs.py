@@ -59,9 +59,12 @@ C1 = Workload("ho_L9_N12", L=9, N=12, R=10.0, n_r=24, n_theta=18, n_phi=36,
               x0_seed=0, geom_seed=0, potential="harmonic", omega=0.5,
               fixed_iter=30)
 # 13-atom icosahedral cluster of Gaussian wells: R=14, L_max=30, 60 radial/l.
+# n_check = the 26 bound (negative-energy) states; the next 12 states form a
+# dense band of box states between 0.016 and 0.045 Ha that the block edge at
+# k = 32 would cut, so they serve as the guard states.
 C2 = Workload("ico13_L31_N60", L=31, N=60, R=14.0, n_r=90, n_theta=62,
-              n_phi=124, radial_rule=RADIAL_GAUSS_JACOBI_R2, k=32, n_check=28,
-              degree=16, x0_seed=0, geom_seed=1, potential="wells")
+              n_phi=124, radial_rule=RADIAL_GAUSS_JACOBI_R2, k=32, n_check=26,
+              degree=16, x0_seed=0, geom_seed=1, potential="wells", max_iter=120)
 # 147-atom Mackay icosahedron: R=24, L_max=60, 120 radial/l.
 C3 = Workload("mackay147_L61_N120", L=61, N=120, R=24.0, n_r=180,
               n_theta=122, n_phi=244, radial_rule=RADIAL_GAUSS_JACOBI_R2,

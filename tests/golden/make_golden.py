@@ -19,19 +19,21 @@ from oracle import eigensolver as oe  # noqa: E402
 from oracle import hamiltonian as oh  # noqa: E402
 
 
-def converge(w, res_tol=1e-7, dtheta_tol=1e-11, max_iter=400):
+def converge(w, k, degree, res_tol=1e-8, dtheta_tol=1e-12, max_iter=400):
+    """Oracle CheFSI with its own block size and degree (any convergent run
+    gives the same lowest eigenvalues of H)."""
     bs = ob.basis_for(w)
     V = si.potential_on_grid(w, bs.r, bs.theta, bs.phi)
     app = lambda Y: oh.apply_H_real(bs, V, Y)  # noqa: E731
     b = oe.lanczos_upper_bound(app, si.lanczos_start(bs.d))
-    X0 = si.x0_block(w)
+    X0 = si.x0_block(w, k=k)
     t0 = time.time()
 
     def log(it, theta, res):
         print(f"it {it:3d}  t={time.time() - t0:7.1f}s  max_res[:n_check]="
               f"{np.max(res[:w.n_check]):.3e}  theta0={theta[0]:.12f}", flush=True)
 
-    theta, X, res, it = oe.chefsi(app, X0, w.degree, b, w.n_check, max_iter=max_iter,
+    theta, X, res, it = oe.chefsi(app, X0, degree, b, w.n_check, max_iter=max_iter,
                                   res_tol=res_tol, dtheta_tol=dtheta_tol, log=log)
     return b, theta, res, it
 
@@ -41,14 +43,15 @@ def main(which):
         w = si.C2
     else:
         raise SystemExit(f"unknown workload {which}")
-    b, theta, res, it = converge(w)
+    k, degree = 40, 20
+    b, theta, res, it = converge(w, k, degree)
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                        f"{w.name}_eigenvalues.txt")
     with open(out, "w") as f:
         f.write(f"# Lowest eigenvalues (Ha) of the quadrature Hamiltonian for workload "
                 f"{w.name}\n# (synth_inputs), from the FP64 oracle's Chebyshev-filtered "
-                f"subspace iteration\n# run to max residual <= 1e-7 (k={w.k}, degree="
-                f"{w.degree}, {it} iterations,\n# Lanczos bound b={b:.10f}).  Written by "
+                f"subspace iteration\n# run to max residual <= 1e-8 (block {k}, degree "
+                f"{degree}, {it} iterations,\n# Lanczos bound b={b:.10f}).  Written by "
                 f"tests/golden/make_golden.py.\n# columns: index eigenvalue residual\n")
         for i in range(w.n_check):
             f.write(f"{i} {theta[i]:.15f} {res[i]:.3e}\n")
