@@ -52,9 +52,16 @@ def algorithmic_flops(w, k):
             "kinetic": kinetic, "total": radial + legendre + fft + pointwise + kinetic}
 
 
-def angular_flops(w, k):
+def stage_flops(w, k):
+    """Algorithmic flops of one launch of each H*X kernel (same accounting as
+    algorithmic_flops, split by stage)."""
     f = algorithmic_flops(w, k)
-    return f["legendre"] + f["phi"] + f["pointwise"]
+    return {"radial_inverse": f["radial"] / 2,
+            "legendre_synth": f["legendre"] / 2,
+            "phi_stage": f["phi"] + f["pointwise"],
+            "legendre_analysis": f["legendre"] / 2,
+            "radial_forward": f["radial"] / 2 + f["kinetic"],
+            "kb_gemm": 0.0}
 
 
 def radial_bytes(w, k, elem):
@@ -194,27 +201,19 @@ def main():
             print(f"[bench] time-to-eigenpairs {name}: {sec:.3f} s, {it} it, err={err}",
                   file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel (mixed-precision filter launches)
+    # ---- roofline of the dominant kernel: the FP32 launch class with the
+    # largest total time in the timed steps (HIP events around each launch)
     stage_avg = {s: (ms / c if c else 0.0, c) for s, (ms, c) in prof.items()}
-    dom = max(("radial_inverse", "angular", "radial_forward"), key=lambda s: prof[s][0])
+    fp32 = [s for s in prof if s.endswith("_fp32")]
+    dom = max(fp32, key=lambda s: prof[s][0])
     avg_ms, launches = stage_avg[dom]
-    # launches mix FP32 (filter) and FP64 (RR) applications; per step: degree
-    # FP32 + 1 FP64.  Roofline quoted for the FP32 class using the per-launch
-    # average over all launches of the stage (FP64 share is 1/(degree+1)).
-    if dom == "angular":
-        achieved = angular_flops(w, k) / (avg_ms * 1e-3)
-        roof = {"bound": "alu", "achieved": round(achieved / 1e12, 4),
-                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32, 5), "traffic": None}
-    else:
-        rf = algorithmic_flops(w, k)["radial"] / 2
-        achieved = rf / (avg_ms * 1e-3)
-        roof = {"bound": "mfma", "achieved": round(achieved / 1e12, 4),
-                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32, 5), "traffic": None}
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = round(avg_ms, 5)
-    roof["launches"] = launches
+    alg = stage_flops(w, k)[dom[:-5]]
+    achieved = alg / (avg_ms * 1e-3)
+    roof = {"bound": "mfma", "achieved": round(achieved / 1e12, 4),
+            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
+            "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+            "alg_flop_per_launch": alg}
 
     line = {
         "metric": "Chebyshev-filter H*X GFLOP/s & time-to-eigenpairs@1e-6Ha: mixed vs FP64",

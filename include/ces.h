@@ -184,15 +184,16 @@ ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64
 /* -------------------------------------------------------------- profiling */
 
 /* Stage timing with HIP events recorded around each launch of the H*X
- * stages on the caller's stream: 0 radial inverse (eq. G_lmr), 1 angular
- * stage (Legendre sums, phi stage with V_eff, Legendre quadrature), 2 radial
- * quadrature with the kinetic / projector / Chebyshev epilogue, 3 projector
- * GEMM.  ces_profile_enable(1, n) starts recording into a pool of n event
- * pairs (later launches beyond the pool are not recorded) and clears the
- * totals; ces_profile_enable(0, 0) stops and frees the pool.  Process-wide,
- * not thread-safe; meant for benchmarking. */
+ * kernels on the caller's stream.  Stage ids: 0 radial inverse (eq. G_lmr),
+ * 1 Legendre synthesis, 2 phi stage with V_eff, 3 Legendre quadrature
+ * (eq. Ar_lm), 4 radial quadrature with the kinetic / projector / Chebyshev
+ * epilogue (eq. Arlm_to_coeff), 5 projector GEMM; ids 6..11 are the same
+ * stages in FP64 (0..5 are FP32).  ces_profile_enable(1, n) starts
+ * recording into a pool of n event pairs (launches beyond the pool are not
+ * recorded) and clears the totals; ces_profile_enable(0, 0) stops and frees
+ * the pool.  Process-wide, not thread-safe; meant for benchmarking. */
 ces_status ces_profile_enable(int on, int max_records);
-/* Synchronise the recorded events and return, per stage s < n_stages (<= 4),
+/* Synchronise the recorded events and return, per stage s < n_stages (<= 12),
  * the summed milliseconds h_ms[s] and launch count h_count[s]. */
 ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count);
 

@@ -104,7 +104,9 @@ def _ld(X):
     return X.stride(0)
 
 
-STAGES = ("radial_inverse", "angular", "radial_forward", "kb_gemm")
+_STAGE_NAMES = ("radial_inverse", "legendre_synth", "phi_stage", "legendre_analysis",
+                "radial_forward", "kb_gemm")
+STAGES = tuple(f"{n}_fp32" for n in _STAGE_NAMES) + tuple(f"{n}_fp64" for n in _STAGE_NAMES)
 
 
 def profile_enable(on: bool, max_records: int = 65536):
@@ -114,11 +116,12 @@ def profile_enable(on: bool, max_records: int = 65536):
 
 def profile_read():
     """{stage: (total_ms, launches)} since profile_enable."""
-    ms = np.zeros(4)
-    cnt = np.zeros(4, dtype=np.int64)
-    _check(load().ces_profile_read(4, ms.ctypes.data_as(ctypes.c_void_p),
+    n = len(STAGES)
+    ms = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int64)
+    _check(load().ces_profile_read(n, ms.ctypes.data_as(ctypes.c_void_p),
                                    cnt.ctypes.data_as(ctypes.c_void_p)), "ces_profile_read")
-    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(4)}
+    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
 
 class Basis:

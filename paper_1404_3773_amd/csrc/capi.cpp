@@ -55,13 +55,18 @@ ces_status fail(ces_status s, const std::string& msg) {
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Stage timing (ces_profile_enable / ces_profile_read).
+// Stage timing (ces_profile_enable / ces_profile_read): stage ids 0..5 for
+// FP32 launches, 6..11 for FP64 launches.
+constexpr int kStages = 12;
+enum { ST_RADIAL_INV = 0, ST_LEG_SYNTH, ST_PHI, ST_LEG_ANALYSIS, ST_RADIAL_FWD, ST_KB_GEMM };
+template <typename T>
+constexpr int stage_id(int st) { return st + (sizeof(T) == 8 ? 6 : 0); }
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> ev;     // 2 per record
   std::vector<int> stage;         // stage of each used record
-  double ms[4] = {0, 0, 0, 0};
-  int64_t count[4] = {0, 0, 0, 0};
+  double ms[kStages] = {};
+  int64_t count[kStages] = {};
 };
 Profiler g_prof;
 
@@ -368,23 +373,32 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
     // C[q][i] (row-major n_proj x kp) is the column-major kp x n_proj matrix Y^T P
-    StageTimer t(3, s);
+    StageTimer t(stage_id<T>(ST_KB_GEMM), s);
     CES_BLAS(gemm_t(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, h.n_proj,
                     static_cast<int>(b.d), &one, Yin, static_cast<int>(ldin), Pd,
                     static_cast<int>(b.d), &zero, C, kp));
     launch_scale_rows<T>(C, h.n_proj, kp, hd, s);
     P = Pd;
   }
+  T* gbuf = Ptr<T>::at(work, ly.gbuf);
   {
-    StageTimer t(0, s);
+    StageTimer t(stage_id<T>(ST_RADIAL_INV), s);
     launch_radial_inverse<T>(b, tb, Yin, ldin, G, k, kp, s);
   }
   {
-    StageTimer t(1, s);
-    launch_angular_mfma<T>(b, tb, ab_of<T>(h), G, Ptr<T>::at(work, ly.gbuf), A, kp, s);
+    StageTimer t(stage_id<T>(ST_LEG_SYNTH), s);
+    launch_legendre_synth<T>(b, tb, G, gbuf, kp, s);
   }
   {
-    StageTimer t(2, s);
+    StageTimer t(stage_id<T>(ST_PHI), s);
+    launch_phi_stage<T>(b, ab_of<T>(h), gbuf, kp, s);
+  }
+  {
+    StageTimer t(stage_id<T>(ST_LEG_ANALYSIS), s);
+    launch_legendre_analysis<T>(b, tb, gbuf, A, kp, s);
+  }
+  {
+    StageTimer t(stage_id<T>(ST_RADIAL_FWD), s);
     launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true,
                              P, h.n_proj, C, k, kp, s);
   }
@@ -617,7 +631,7 @@ ces_status ces_profile_enable(int on, int max_records) {
 }
 
 ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count) {
-  if (n_stages < 0 || n_stages > 4 || (n_stages > 0 && (!h_ms || !h_count)))
+  if (n_stages < 0 || n_stages > kStages || (n_stages > 0 && (!h_ms || !h_count)))
     return fail(CES_ERR_INVALID_ARG, "bad profile_read arguments");
   for (size_t r = 0; r < g_prof.stage.size(); ++r) {
     CES_HIP(hipEventSynchronize(g_prof.ev[2 * r + 1]));

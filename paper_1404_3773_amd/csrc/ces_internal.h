@@ -87,10 +87,16 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                            T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
                            const T* kbC, int k, int kp, hipStream_t s);
 
-// Angular stage on MFMA: G -> gbuf (n_r x n_theta x S x kp) -> A.
+// Angular stage on MFMA: G -> gbuf (n_r x n_theta x S x kp) -> gh (in place)
+// -> A, as three launches.
 template <typename T>
-void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G,
-                         T* gbuf, T* A, int kp, hipStream_t s);
+void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* gbuf, int kp,
+                           hipStream_t s);
+template <typename T>
+void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s);
+template <typename T>
+void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* gbuf, T* A,
+                              int kp, hipStream_t s);
 
 
 // C (k x k, column-major) = A^T B for d x k blocks, split over rows with

@@ -366,24 +366,29 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 }  // namespace
 
 template <typename T>
-void launch_angular_mfma(const Basis& b, const DevTables<T>& tb, const T* ab, const T* G,
-                         T* gbuf, T* A, int kp, hipStream_t s) {
+void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* gbuf, int kp,
+                           hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
-  {
-    const int n_ic = (kp + 16 * LS_NT - 1) / (16 * LS_NT);
-    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    k_legendre_synth<T><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-  }
-  {
-    dim3 grid(b.n_r * b.n_theta, (kp + 16 * PS_NT - 1) / (16 * PS_NT));
-    const size_t lds = (2 * size_t(2 * D.S + 64) + size_t(D.S4) * (16 * PS_NT + 1)) * sizeof(T);
-    k_phi_stage<T><<<grid, 256, lds, s>>>(gbuf, ab, D);
-  }
-  {
-    const int n_ic = (kp + 64 * LA_NT - 1) / (64 * LA_NT);
-    dim3 grid(b.n_r * n_ic, D.S);
-    k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
-  }
+  const int n_ic = (kp + 16 * LS_NT - 1) / (16 * LS_NT);
+  dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
+  k_legendre_synth<T><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+}
+
+template <typename T>
+void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s) {
+  const AngDims D = ang_dims(b, kp);
+  dim3 grid(b.n_r * b.n_theta, (kp + 16 * PS_NT - 1) / (16 * PS_NT));
+  const size_t lds = (2 * size_t(2 * D.S + 64) + size_t(D.S4) * (16 * PS_NT + 1)) * sizeof(T);
+  k_phi_stage<T><<<grid, 256, lds, s>>>(gbuf, ab, D);
+}
+
+template <typename T>
+void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* gbuf, T* A,
+                              int kp, hipStream_t s) {
+  const AngDims D = ang_dims(b, kp);
+  const int n_ic = (kp + 64 * LA_NT - 1) / (64 * LA_NT);
+  dim3 grid(b.n_r * n_ic, D.S);
+  k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
 }
 
 int gram_chunks(int64_t rows, int k) {
@@ -406,10 +411,15 @@ void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, dou
   k_gram_reduce<<<static_cast<unsigned>((kk + 3) / 4), 256, 0, s>>>(part, C, k, nch);
 }
 
-template void launch_angular_mfma<float>(const Basis&, const DevTables<float>&, const float*,
-                                         const float*, float*, float*, int, hipStream_t);
-template void launch_angular_mfma<double>(const Basis&, const DevTables<double>&, const double*,
-                                          const double*, double*, double*, int, hipStream_t);
+#define CES_INST(T)                                                                          \
+  template void launch_legendre_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
+                                         hipStream_t);                                       \
+  template void launch_phi_stage<T>(const Basis&, const T*, T*, int, hipStream_t);             \
+  template void launch_legendre_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
+                                            int, hipStream_t);
+CES_INST(float)
+CES_INST(double)
+#undef CES_INST
 
 
 }  // namespace ces
