@@ -188,12 +188,25 @@ def spherical_to_cartesian(r, theta, phi):
 
 def gaussian_wells(points: np.ndarray, atoms: np.ndarray,
                    depth: float = WELL_DEPTH, sigma: float = WELL_SIGMA) -> np.ndarray:
-    """V(x) = sum_j -depth * exp(-|x - x_j|^2 / (2 sigma^2)) at the given points."""
-    v = np.zeros(points.shape[:-1])
-    for a in atoms:
-        d2 = np.sum((points - a) ** 2, axis=-1)
-        v -= depth * np.exp(-d2 / (2.0 * sigma * sigma))
-    return v
+    """V(x) = sum_j -depth * exp(-|x - x_j|^2 / (2 sigma^2)) at the given points.
+    Each well is evaluated where it exceeds depth * 1e-40 (|x - x_j| < 13.6
+    sigma); beyond that its contribution is set to zero."""
+    import torch   # multithreaded CPU elementwise work; float64 throughout
+    shape = points.shape[:-1]
+    p = torch.from_numpy(np.ascontiguousarray(points.reshape(-1, 3), dtype=np.float64))
+    a = torch.from_numpy(np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3)))
+    v = torch.zeros(p.shape[0], dtype=torch.float64)
+    if a.shape[0] == 0:
+        return v.numpy().reshape(shape)
+    cut2 = 2.0 * sigma * sigma * 92.1   # exp(-92.1) = 1e-40
+    chunk = max(1, int(2.0e8 // a.shape[0]))
+    for s in range(0, p.shape[0], chunk):
+        pc = p[s:s + chunk]
+        d2 = ((pc[:, None, :] - a[None, :, :]) ** 2).sum(-1)
+        e = torch.exp(-d2 / (2.0 * sigma * sigma))
+        e = torch.where(d2 < cut2, e, torch.zeros_like(e))
+        v[s:s + chunk] = -depth * e.sum(1)
+    return v.numpy().reshape(shape)
 
 
 def harmonic(points: np.ndarray, omega: float) -> np.ndarray:
