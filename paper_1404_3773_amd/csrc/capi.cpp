@@ -738,7 +738,7 @@ ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const 
   const size_t nab = size_t(b.n_r) * b.n_theta * 2 * S;
   const size_t sz_v = align256(size_t(b.n_grid) * 8), sz_ab64 = align256(nab * 8),
                sz_ab32 = align256(nab * 4), sz_p64 = align256(size_t(b.d) * n_proj * 8),
-               sz_p32 = align256(size_t(b.d) * n_proj * 4), sz_h = align256(size_t(n_proj) * 12 + 16);
+               sz_p32 = align256(size_t(b.d) * n_proj * 4), sz_h = align256(size_t(n_proj) * 8) + align256(size_t(n_proj) * 4);
   void* blk = nullptr;
   if (hipMalloc(&blk, sz_v + sz_ab64 + sz_ab32 + sz_p64 + sz_p32 + sz_h) != hipSuccess) {
     delete hh;
