@@ -181,6 +181,82 @@ ces_status ces_to_grid(ces_ham h, int k, const double* d_X, int64_t ldx, double*
 ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64_t ldx,
                          void* d_work, size_t work_bytes, void* stream);
 
+/* ------------------------------------------------------------ SCF extras */
+/* The self-consistent cluster model: V_eff = V_ext + V_H[rho - rho_ion] +
+ * V_x[rho] (Section 2.1 with LDA exchange only), rho_ion a caller-given
+ * positive background (e.g. Gaussian ion charges) that makes the cluster
+ * neutral.  Grid arrays are n_grid FP64 values [r][theta][phi].  Calls that
+ * take (d_work, work_bytes) need at least ces_workspace_size(h, 1, FP64)
+ * bytes unless stated otherwise. */
+
+/* Hartree potential of the density sum_lmn tau_lmn F_lmn (Section 2.3.1,
+ * eqs. Laplace_expansion, hartree_calc1, zeta_definition):
+ *   V_H(x) = sum_lmn tau_lmn (4 pi / (2l+1)) zeta_ln(r) S_lm(x/|x|),
+ * with the radial integral zeta_ln in closed form: the free-space potential
+ * (decaying as Q/r outside the ball), not a Dirichlet solve.  d_tau[d]
+ * coefficients in the real layout; d_vh[n_grid] output. */
+ces_status ces_hartree(ces_ham h, const double* d_tau, double* d_vh, void* d_work,
+                       size_t work_bytes, void* stream);
+
+/* d_v = V_ext + V_H[rho - rho_ion] + V_x[rho], V_x = -(3 rho_+ / pi)^(1/3),
+ * rho_+ = max(rho, 0).  V_H uses the forward transform of rho - rho_ion in
+ * the orbital basis (the dualing choice, Section 2.2.5) and ces_hartree.
+ * d_tau[d] (may be NULL) receives those coefficients.  d_v must not alias an
+ * input (CES_ERR_INVALID_ARG). */
+ces_status ces_ks_potential(ces_ham h, const double* d_rho, const double* d_rho_ion,
+                            const double* d_vext, double* d_v, double* d_tau, void* d_work,
+                            size_t work_bytes, void* stream);
+
+/* Anderson mixing of potentials (Section 3.4.1).  d_V, d_F: n x m history
+ * (column-major, leading dimension ld >= n, 1 <= m <= 64) of input
+ * potentials V_i and residuals F_i = V_out(V_i) - V_i; column `oldest` is the
+ * oldest pair and ages increase cyclically from it.  Writes
+ *   d_out = sum_i c_i (V_i + beta F_i),
+ * c minimising ||sum_i c_i F_i||_2 subject to sum_i c_i = 1 (the same V and F
+ * averages as the difference form of the method; one pair gives V + beta F).
+ * If that system is numerically singular the oldest pairs are left out
+ * (c_i = 0) until it is not.  h_coef[m] (may be NULL) receives c.
+ * Workspace: ces_anderson_workspace_size(n, m).  Each output element is
+ * written after its history row is read, so d_out may alias a V column.
+ * Synchronous. */
+ces_status ces_anderson_workspace_size(int64_t n, int m, size_t* bytes);
+ces_status ces_anderson_mix(int64_t n, int m, const double* d_V, const double* d_F, int64_t ld,
+                            int oldest, double beta, double* d_out, double* h_coef,
+                            void* d_work, size_t work_bytes, void* stream);
+
+/* Superposition of atomic densities (Section 3.2): d_rho(x_g) = sum_a
+ * rho_at(|x_g - a|), with the spherical atomic density
+ *   rho_at(r) = S_00 sum_n tau00[n] R_0n(r)  (r < R; 0 for r >= R),
+ * tau00[N] the l = 0 coefficients (alpha = n) of one atom's density in this
+ * basis (from ces_ks_potential's d_tau or ces_density of a one-atom SCF).
+ * h_atoms[3 n_atoms] host xyz (bohr).  Synchronous. */
+ces_status ces_sad_density(ces_ham h, int n_atoms, const double* h_atoms,
+                           const double* h_tau00, double* d_rho, void* d_work,
+                           size_t work_bytes, void* stream);
+
+/* Self-consistent field loop on the handle's basis (Sections 3.2, 3.4.1);
+ * the handle's V_eff is overwritten.  The n_occ lowest orbitals are doubly
+ * occupied (f_i = 1 in ces_density); the other k - n_occ are guard states.
+ *   V_in = ks_potential(d_rho0); then per step:
+ *   V_eff = V_in; b = ces_lanczos_bound(d_v0, 20 steps);
+ *   step 1: Rayleigh-Ritz of d_X, then first_iters x (filter + RR);
+ *   later steps: one filter (degree, prec; a = theta_k, a0 = theta_1) + RR
+ *   (Rayleigh-Ritz always with FP64 H*X);
+ *   rho = density of d_X; V_out = ks_potential(rho);
+ *   stop when max_{i < n_occ} |theta_i - theta_i(previous step)| < tol;
+ *   else V_in = ces_anderson_mix over the last `hist` pairs (V_in, V_out - V_in).
+ * Outputs: d_X (Ritz vectors), d_eval[k], d_rho[n_grid] (last density),
+ * *h_steps (steps taken, <= max_steps), h_dtheta[max_steps] (may be NULL:
+ * per-step max change, +inf at step 1).  The caller checks convergence from
+ * h_dtheta.  Workspace: ces_scf_workspace_size (includes 2 hist grid arrays
+ * of history).  Synchronous. */
+ces_status ces_scf_workspace_size(ces_ham h, int k, int prec, int hist, size_t* bytes);
+ces_status ces_scf(ces_ham h, int k, double* d_X, int64_t ldx, int n_occ, const double* d_vext,
+                   const double* d_rho_ion, const double* d_rho0, const double* d_v0, int degree,
+                   double beta, int hist, double tol, int max_steps, int first_iters, int prec,
+                   double* d_eval, double* d_rho, int* h_steps, double* h_dtheta, void* d_work,
+                   size_t work_bytes, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* Stage timing with HIP events recorded around each launch of the H*X

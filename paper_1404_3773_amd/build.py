@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libces.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["kernels.hip", "kernels_angular.hip", "kernels_radial.hip", "capi.cpp",
+SOURCES = ["kernels.hip", "kernels_angular.hip", "kernels_radial.hip", "kernels_scf.hip",
+           "capi.cpp", "scf.cpp",
            "setup_tables.cpp"]
 
 # Device code: gfx950 only; packed-FP32 instructions disabled.

@@ -26,6 +26,8 @@ EXPORTS = [
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
     "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
+    "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
+    "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_profile_enable", "ces_profile_read", "ces_status_string", "ces_last_error",
 ]
 
@@ -67,6 +69,14 @@ def load() -> ctypes.CDLL:
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
         "ces_to_grid": [P, I, P, I64, P, P, SZ, P],
         "ces_from_grid": [P, I, P, P, I64, P, SZ, P],
+        "ces_hartree": [P, P, P, P, SZ, P],
+        "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
+        "ces_anderson_workspace_size": [I64, I, ctypes.POINTER(SZ)],
+        "ces_anderson_mix": [I64, I, P, P, I64, I, D, P, P, P, SZ, P],
+        "ces_sad_density": [P, I, P, P, P, P, SZ, P],
+        "ces_scf_workspace_size": [P, I, I, I, ctypes.POINTER(SZ)],
+        "ces_scf": [P, I, P, I64, I, P, P, P, P, I, D, I, D, I, I, I, P, P,
+                    ctypes.POINTER(I), P, P, SZ, P],
         "ces_profile_enable": [I, I],
         "ces_profile_read": [I, P, P],
     }
@@ -122,6 +132,22 @@ def profile_read():
     _check(load().ces_profile_read(n, ms.ctypes.data_as(ctypes.c_void_p),
                                    cnt.ctypes.data_as(ctypes.c_void_p)), "ces_profile_read")
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def anderson_mix(V, F, oldest, beta, out, h_coef=None, stream=None):
+    """V, F: (m, ld) float64 history tensors (row i = pair i); out: n values."""
+    m, ld = V.shape
+    n = out.numel()
+    sz = ctypes.c_size_t()
+    lib = load()
+    _check(lib.ces_anderson_workspace_size(n, m, ctypes.byref(sz)), "ces_anderson_workspace_size")
+    import torch
+    work = torch.empty(sz.value, dtype=torch.uint8, device=V.device)
+    coef = np.zeros(m)
+    _check(lib.ces_anderson_mix(n, m, _ptr(V), _ptr(F), ld, int(oldest), float(beta), _ptr(out),
+                                coef.ctypes.data_as(ctypes.c_void_p), _ptr(work), sz.value,
+                                _stream(stream)), "ces_anderson_mix")
+    return coef
 
 
 class Basis:
@@ -252,6 +278,46 @@ class Ham:
     def from_grid(self, f, X, work, stream=None):
         _check(load().ces_from_grid(self._h, X.shape[0], _ptr(f), _ptr(X), _ld(X), _ptr(work),
                                     work.numel(), _stream(stream)), "ces_from_grid")
+
+    # ------------------------------------------------------------ SCF extras
+    # Grid arrays are flat torch float64 tensors of n_grid values.
+
+    def hartree(self, tau, vh, work, stream=None):
+        _check(load().ces_hartree(self._h, _ptr(tau), _ptr(vh), _ptr(work), work.numel(),
+                                  _stream(stream)), "ces_hartree")
+
+    def ks_potential(self, rho, rho_ion, vext, v, work, tau=None, stream=None):
+        _check(load().ces_ks_potential(self._h, _ptr(rho), _ptr(rho_ion), _ptr(vext), _ptr(v),
+                                       _ptr(tau), _ptr(work), work.numel(), _stream(stream)),
+               "ces_ks_potential")
+
+    def sad_density(self, atoms, tau00, rho, work, stream=None):
+        a = np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3))
+        t = np.ascontiguousarray(np.asarray(tau00, dtype=np.float64))
+        assert t.shape == (self.basis.N,)
+        _check(load().ces_sad_density(self._h, a.shape[0], a.ctypes.data_as(ctypes.c_void_p),
+                                      t.ctypes.data_as(ctypes.c_void_p), _ptr(rho), _ptr(work),
+                                      work.numel(), _stream(stream)), "ces_sad_density")
+
+    def scf_workspace(self, k, prec=CES_PREC_FP64, hist=20):
+        import torch
+        n = ctypes.c_size_t()
+        _check(load().ces_scf_workspace_size(self._h, int(k), int(prec), int(hist),
+                                             ctypes.byref(n)), "ces_scf_workspace_size")
+        return torch.empty(n.value, dtype=torch.uint8, device="cuda")
+
+    def scf(self, X, n_occ, vext, rho_ion, rho0, v0, evals, rho, work, degree=12, beta=0.2,
+            hist=20, tol=1e-6, max_steps=60, first_iters=12, prec=CES_PREC_FP64, stream=None):
+        """Returns (steps, per-step max |delta theta_occ|)."""
+        steps = ctypes.c_int()
+        dth = np.zeros(int(max_steps))
+        _check(load().ces_scf(self._h, X.shape[0], _ptr(X), _ld(X), int(n_occ), _ptr(vext),
+                              _ptr(rho_ion), _ptr(rho0), _ptr(v0), int(degree), float(beta),
+                              int(hist), float(tol), int(max_steps), int(first_iters), int(prec),
+                              _ptr(evals), _ptr(rho), ctypes.byref(steps),
+                              dth.ctypes.data_as(ctypes.c_void_p), _ptr(work), work.numel(),
+                              _stream(stream)), "ces_scf")
+        return steps.value, dth[:steps.value].copy()
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -16,15 +16,8 @@
 #include "ces_internal.h"
 #include "setup_tables.h"
 
-struct ces_basis_s {
-  ces::Basis b;
-};
-struct ces_ham_s {
-  ces::Ham h;
-};
 
 namespace ces {
-namespace {
 
 thread_local std::string g_err;
 
@@ -33,12 +26,6 @@ ces_status fail(ces_status s, const std::string& msg) {
   return s;
 }
 
-#define CES_HIP(call)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (call);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(CES_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 #define CES_BLAS(call)                                                             \
   do {                                                                             \
@@ -47,13 +34,6 @@ ces_status fail(ces_status s, const std::string& msg) {
       return fail(CES_ERR_DEVICE, std::string(#call) + ": " + rocblas_status_to_string(e_)); \
   } while (0)
 
-#define CES_TRY(expr)                 \
-  do {                                \
-    ces_status s_ = (expr);           \
-    if (s_ != CES_OK) return s_;      \
-  } while (0)
-
-inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Stage timing (ces_profile_enable / ces_profile_read): stage ids 0..5 for
 // FP32 launches, 6..11 for FP64 launches.
@@ -220,6 +200,30 @@ ces_status ensure_device(Basis& b) {
     cs[u] = std::cos(2.0 * M_PI * u / b.n_phi);
     cs[b.n_phi + u] = std::sin(2.0 * M_PI * u / b.n_phi);
   }
+  // Hartree radial table (Section 2.3.1): the Laplace-expansion radial
+  // integral zeta_ln(r) of R_ln in closed form, with k = b_ln / R,
+  //   (4 pi / (2l+1)) zeta_ln(r) = (4 pi / k^2) R_ln(r)
+  //                              + (4 pi / (2l+1)) sqrt(2/R^3) R (r/R)^l / k,
+  // the Dirichlet Poisson solution plus the harmonic term that continues it
+  // as the free-space potential outside the ball.
+  const int N4 = int(round_up(b.N, 4)), R16 = int(round_up(b.n_r, 16));
+  std::vector<double> hart(static_cast<size_t>(b.L) * N4 * R16, 0.0);
+  const double c0 = std::sqrt(2.0 / (b.R * b.R * b.R));
+  for (int l = 0; l < b.L; ++l)
+    for (int n = 0; n < b.N; ++n) {
+      const double k = b.zeros[size_t(l) * b.N + n] / b.R;
+      for (int kk = 0; kk < b.n_r; ++kk) {
+        const double rad = b.radial[(size_t(l) * b.n_r + kk) * b.N + n];
+        hart[(size_t(l) * N4 + n) * R16 + kk] =
+            4.0 * M_PI / (k * k) * rad +
+            4.0 * M_PI / (2 * l + 1) * c0 * b.R * std::pow(b.r[kk] / b.R, l) / k;
+      }
+    }
+  std::vector<double> cth(b.n_theta), sth(b.n_theta);
+  for (int j = 0; j < b.n_theta; ++j) {
+    cth[j] = b.t[j];
+    sth[j] = std::sin(b.theta[j]);
+  }
   struct Piece {
     const void* src;
     size_t bytes;
@@ -234,7 +238,11 @@ ces_status ensure_device(Basis& b) {
       {w32.data(), w32.size() * 4, (void**)&b.t32.wt},   {t32.data(), t32.size() * 4, (void**)&b.t32.trig},
       {M64.data(), M64.size() * 8, (void**)&b.t64.Pm},   {W64.data(), W64.size() * 8, (void**)&b.t64.PwT},
       {M32.data(), M32.size() * 4, (void**)&b.t32.Pm},   {W32.data(), W32.size() * 4, (void**)&b.t32.PwT},
-      {cs.data(), cs.size() * 8, (void**)&b.dev_cs}};
+      {cs.data(), cs.size() * 8, (void**)&b.dev_cs},
+      {hart.data(), hart.size() * 8, (void**)&b.dev_hart},
+      {b.r.data(), b.r.size() * 8, (void**)&b.dev_rnode},
+      {cth.data(), cth.size() * 8, (void**)&b.dev_cth},
+      {sth.data(), sth.size() * 8, (void**)&b.dev_sth}};
   size_t total = 0;
   for (auto& p : pieces) total += align256(p.bytes);
   void* blk = nullptr;
@@ -255,12 +263,6 @@ ces_status ensure_device(Basis& b) {
 
 // ------------------------------------------------------------- workspace
 
-struct Layout {
-  size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0,
-         vec = 0, part = 0, info = 0, solver = 0, total = 0;
-  size_t solver_bytes = 0;
-  int64_t kp = 0;
-};
 
 size_t solver_bytes_for(Ham& h, int k) {
   if (h.solver_ws_k == k) return h.solver_ws;
@@ -319,10 +321,6 @@ Layout layout_for(Ham& h, int k, int prec) {
   return L;
 }
 
-template <typename T>
-struct Ptr {
-  static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
-};
 
 // -------------------------------------------------------------- one H step
 
@@ -595,7 +593,6 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   return CES_OK;
 }
 
-}  // namespace
 }  // namespace ces
 
 using namespace ces;

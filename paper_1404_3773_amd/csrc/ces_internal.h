@@ -50,6 +50,10 @@ struct Basis {
   std::vector<double> legendre;  // [j][l(l+1)/2 + m]
   int device = -1;
   double* dev_cs = nullptr;      // [2][n_phi] cos, sin(2 pi u / n_phi)
+  double* dev_rnode = nullptr;   // [n_r] radial nodes
+  double* dev_cth = nullptr;     // [n_theta] cos(theta_j)
+  double* dev_sth = nullptr;     // [n_theta] sin(theta_j)
+  double* dev_hart = nullptr;    // [l][N4][R16] (4 pi / (2l+1)) zeta_ln(r_k), RiT layout
   DevTables<double> t64;
   DevTables<float> t32;
   void* dev_block = nullptr;     // single allocation holding all device tables
@@ -69,6 +73,41 @@ struct Ham {
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;
+};
+
+// ------------------------------------------- shared by the C interface files
+
+ces_status fail(ces_status s, const std::string& msg);   // sets the thread's last error
+
+#define CES_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::ces::fail(CES_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CES_TRY(expr)                 \
+  do {                                \
+    ces_status s_ = (expr);           \
+    if (s_ != CES_OK) return s_;      \
+  } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte offsets of the regions of a caller workspace for k columns.
+struct Layout {
+  size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0,
+         vec = 0, part = 0, info = 0, solver = 0, total = 0;
+  size_t solver_bytes = 0;
+  int64_t kp = 0;
+};
+Layout layout_for(Ham& h, int k, int prec);
+ces_status check_work(Ham& h, int k, int prec, void* work, size_t bytes, Layout& ly);
+ces_status check_block(const Ham& h, int k, const void* X, int64_t ldx, const char* what);
+
+template <typename T>
+struct Ptr {
+  static T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
 };
 
 // ---------------------------------------------------------------- launchers
@@ -128,6 +167,18 @@ template <typename T>
 void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, const double* occ,
                           double* rho, int k, int kp, hipStream_t s);
 
+// Self-consistent field extras (kernels_scf.hip).
+void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
+// v = vext + v - (3 rho / pi)^(1/3), v holding V_H on entry.
+void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
+                      hipStream_t s);
+// out = sum_i c_i (V_i + beta F_i) over m columns of ld-strided history.
+void launch_anderson_combine(const double* V, const double* F, int64_t ld, const double* c,
+                             int m, double beta, double* out, int64_t n, hipStream_t s);
+// rho on the grid = sum over atoms of sum_n cn[n] j0(n' pi |x - a| / R), n' = n + 1.
+void launch_sad_density(const Basis& b, const double* atoms, int n_atoms, const double* cn,
+                        double* rho, hipStream_t s);
+
 // Small FP64 helpers for Cholesky-QR / Rayleigh-Ritz / Lanczos.
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s);
 void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double* dinv,
@@ -142,4 +193,15 @@ void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int
 void launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 
+}  // namespace ces
+
+struct ces_basis_s {
+  ces::Basis b;
+};
+struct ces_ham_s {
+  ces::Ham h;
+};
+
+namespace ces {
+ces_status check_ham(ces_ham hh);   // non-null and on the current device
 }  // namespace ces

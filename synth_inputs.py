@@ -76,7 +76,14 @@ C4 = Workload("fcc309kb_L81_N150", L=81, N=150, R=30.0, n_r=225,
               k=1000, n_check=900, degree=20, x0_seed=0, geom_seed=3,
               potential="wells+kb")
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C4)}
+# Self-consistent clusters of 8-40 Gaussian-well atoms: R=16, L_max=24, 40
+# radial/l, grid 60x50x100, degree 12.  k and n_check here are the largest
+# block (40 occupied + 8 guards); each cluster uses its own (scf_occupation).
+C5 = Workload("scf_L25_N40", L=25, N=40, R=16.0, n_r=60, n_theta=50, n_phi=100,
+              radial_rule=RADIAL_GAUSS_JACOBI_R2, k=48, n_check=40, degree=12,
+              x0_seed=0, geom_seed=0, potential="scf")
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C4, C5)}
 
 # Gaussian-well model pseudopotential: V_j(r) = -2 exp(-r^2 / (2 * 1.2^2)) Ha.
 WELL_DEPTH = 2.0
@@ -86,6 +93,18 @@ JITTER_SIGMA = 0.1
 # channel energies h_0 = +1.5 Ha (l=0), h_1 = -0.8 Ha (l=1).
 KB_WIDTH = 1.0
 KB_ENERGY = {0: 1.5, 1: -0.8}
+
+
+# SCF cluster model: each atom is a Gaussian well plus a Gaussian ion charge
+# of +2 (width 1.2 bohr) carrying two valence electrons, so clusters are
+# neutral; atoms uniform in a ball of radius 8 bohr, pairwise >= 2.5 bohr.
+ION_CHARGE = 2.0
+ION_SIGMA = 1.2
+SCF_BALL = 8.0
+SCF_MIN_SEP = 2.5
+SCF_ATOMS = (8, 40)
+TRAIN_SEED0 = 0          # training cluster i uses seed i
+HELDOUT_SEED0 = 10000    # held-out cluster i uses seed 10000 + i
 
 
 def small(L, N, R=10.0, n_r=None, n_theta=None, n_phi=None, k=4,
@@ -271,3 +290,34 @@ def random_block(d: int, k: int, seed: int) -> np.ndarray:
 def lanczos_start(d: int, seed: int = 12345) -> np.ndarray:
     """Seeded start vector for the upper-bound Lanczos run."""
     return np.random.default_rng(seed).standard_normal(d)
+
+
+# ------------------------------------------------------------- SCF clusters
+
+def scf_cluster(seed: int) -> np.ndarray:
+    """n ~ U{8..40} atoms uniform in the radius-8 ball, rejection-sampled to a
+    minimum pair separation of 2.5 bohr.  Returns (n, 3)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(SCF_ATOMS[0], SCF_ATOMS[1] + 1))
+    pts: list[np.ndarray] = []
+    while len(pts) < n:
+        p = rng.uniform(-SCF_BALL, SCF_BALL, 3)
+        if np.dot(p, p) > SCF_BALL * SCF_BALL:
+            continue
+        if pts and np.min(np.sum((np.asarray(pts) - p) ** 2, axis=1)) < SCF_MIN_SEP ** 2:
+            continue
+        pts.append(p)
+    return np.asarray(pts)
+
+
+def scf_occupation(n_atoms: int) -> tuple[int, int]:
+    """(doubly occupied orbitals, guard states) for a neutral cluster."""
+    return n_atoms, max(4, math.ceil(0.2 * n_atoms))
+
+
+def ion_density(points: np.ndarray, atoms: np.ndarray, charge: float = ION_CHARGE,
+                sigma: float = ION_SIGMA) -> np.ndarray:
+    """Positive background: sum_j charge (2 pi sigma^2)^{-3/2}
+    exp(-|x - x_j|^2 / (2 sigma^2)), evaluated like gaussian_wells."""
+    depth = -charge * (2.0 * math.pi * sigma * sigma) ** -1.5
+    return gaussian_wells(points, atoms, depth=depth, sigma=sigma)

@@ -1,0 +1,210 @@
+"""Pins of the SCF part of the oracle against what mathematics and physics fix.
+
+- Slater exchange is the functional derivative of E_x = -3/4 (3/pi)^{1/3} int rho^{4/3}.
+- Anderson mixing: one pair is linear mixing; on an affine residual map in
+  n dimensions, n + 1 affinely independent pairs give the exact fixed point
+  (the least-squares residual average is zero), whatever beta is.
+- Hartree of an off-centre Gaussian charge is Q erf(s / (sqrt2 sigma)) / s.
+- The single-atom SCF of the cluster model (a spherical system) agrees with
+  an independent radial solver: Chebyshev collocation for -u''/2 + V u = e u
+  and for the radial Poisson equation, with its own self-consistency loop.
+- SAD of one atom at the origin reproduces that atom's density.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+from threadpoolctl import threadpool_limits
+
+import synth_inputs as si
+from oracle import basis as ob
+from oracle import density as od
+from oracle import hamiltonian as oh
+from oracle import scf as osf
+
+
+def test_slater_exchange_is_derivative_of_lda_energy():
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.01, 2.0, 50)
+    h = 1e-6
+
+    def ex(r):
+        return -0.75 * (3.0 / math.pi) ** (1.0 / 3.0) * r ** (4.0 / 3.0)
+
+    fd = (ex(rho + h) - ex(rho - h)) / (2 * h)
+    assert np.max(np.abs(od.slater_exchange(rho) - fd)) < 1e-8
+    assert np.all(od.slater_exchange(np.array([-1.0, 0.0])) == 0.0)
+
+
+def test_anderson_single_pair_is_linear_mixing():
+    rng = np.random.default_rng(4)
+    V, F = rng.standard_normal(30), rng.standard_normal(30)
+    out = osf.anderson_step([V], [F], 0.3)
+    assert np.max(np.abs(out - (V + 0.3 * F))) < 1e-15
+
+
+@pytest.mark.parametrize("beta", [0.2, 0.7])
+def test_anderson_solves_affine_fixed_point_exactly(beta):
+    # F(V) = b - A V, fixed point V* = A^{-1} b; n + 1 generic pairs span it.
+    n = 6
+    rng = np.random.default_rng(5)
+    A = np.eye(n) + 0.3 * rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    Vs = [rng.standard_normal(n) for _ in range(n + 1)]
+    Fs = [b - A @ v for v in Vs]
+    out = osf.anderson_step(Vs, Fs, beta)
+    assert np.max(np.abs(out - np.linalg.solve(A, b))) < 1e-10
+
+
+def test_hartree_of_offcentre_gaussian_is_erf():
+    sigma, Q = 1.0, 2.0
+    a = np.array([0.6, -0.4, 0.5])
+    bs = ob.make_basis(16, 36, 12.0, 54, 32, 64, ob.RADIAL_GAUSS_JACOBI_R2)
+    pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
+    s2 = np.sum((pts - a) ** 2, axis=-1)
+    rho = Q * (2 * math.pi * sigma ** 2) ** -1.5 * np.exp(-s2 / (2 * sigma ** 2))
+    tau = od.density_coefficients(bs, rho)
+    VH = od.hartree_grid(bs, tau)
+    s = np.sqrt(s2)
+    ref = Q * special.erf(s / (math.sqrt(2) * sigma)) / s
+    inner = bs.r < 8.0
+    assert np.max(np.abs(VH[inner] - ref[inner])) < 1e-7
+
+
+# ------------------------------------------------------- radial reference
+
+def _cheb(M):
+    """Chebyshev points x_j = cos(j pi / M) and differentiation matrix."""
+    x = np.cos(np.pi * np.arange(M + 1) / M)
+    c = np.ones(M + 1)
+    c[0] = c[-1] = 2.0
+    c *= (-1.0) ** np.arange(M + 1)
+    X = np.tile(x, (M + 1, 1)).T
+    dX = X - X.T
+    D = np.outer(c, 1.0 / c) / (dX + np.eye(M + 1))
+    D -= np.diag(D.sum(axis=1))
+    return x, D
+
+
+def _clenshaw_curtis(M):
+    """Weights of Clenshaw-Curtis quadrature at the points above."""
+    theta = np.pi * np.arange(M + 1) / M
+    w = np.zeros(M + 1)
+    v = np.ones(M - 1)
+    if M % 2 == 0:
+        w[0] = w[M] = 1.0 / (M * M - 1)
+        for kk in range(1, M // 2):
+            v -= 2 * np.cos(2 * kk * theta[1:-1]) / (4 * kk * kk - 1)
+        v -= np.cos(M * theta[1:-1]) / (M * M - 1)
+    else:
+        w[0] = w[M] = 1.0 / (M * M)
+        for kk in range(1, (M - 1) // 2 + 1):
+            v -= 2 * np.cos(2 * kk * theta[1:-1]) / (4 * kk * kk - 1)
+    w[1:-1] = 2 * v / M
+    return w
+
+
+def radial_atom_scf(R, M=140, tol=1e-12):
+    """Spherical atom of the cluster model by collocation on [0, R]:
+    -u''/2 + (V_ext + V_H[rho - rho_ion] + V_x[rho] + l(l+1)/(2r^2)) u = e u,
+    u(0) = u(R) = 0, rho = 2 u_s^2 / (4 pi r^2); (r V_H)'' = -4 pi r q with
+    r V_H = 0 at r = 0 and = int 4 pi r^2 q at r = R.  Returns (e_s, e_p)."""
+    x, D = _cheb(M)
+    r = R * (1 - x) / 2            # r ascending from 0 to R
+    D = -2.0 / R * D
+    D2 = D @ D
+    w = _clenshaw_curtis(M) * R / 2
+    I = slice(1, M)                # interior points, r > 0
+    ri = r[I]
+    sg = si.ION_SIGMA
+    vext = -si.WELL_DEPTH * np.exp(-ri ** 2 / (2 * si.WELL_SIGMA ** 2))
+    rion = si.ION_CHARGE * (2 * math.pi * sg * sg) ** -1.5 * np.exp(-r ** 2 / (2 * sg * sg))
+
+    def lowest(V, l):
+        H = -0.5 * D2[I, I] + np.diag(V + l * (l + 1) / (2 * ri ** 2))
+        e, U = np.linalg.eig(H)
+        j = np.argmin(e.real)
+        u = np.zeros(M + 1)
+        u[I] = U[:, j].real
+        u /= math.sqrt(np.sum(w * u * u))
+        return e[j].real, u
+
+    def potential(u):
+        rho = np.zeros(M + 1)
+        rho[I] = 2 * u[I] ** 2 / (4 * math.pi * ri ** 2)
+        q = rho - rion
+        Qt = np.sum(w * 4 * math.pi * r ** 2 * q)
+        A = D2.copy()
+        rhs = -4 * math.pi * r * q
+        A[0], A[-1] = 0, 0
+        A[0, 0] = A[-1, -1] = 1
+        rhs[0] = 0.0
+        rhs[-1] = Qt
+        phi = np.linalg.solve(A, rhs)
+        vx = -np.cbrt(3 * rho / math.pi)
+        return vext + phi[I] / ri + vx[I]
+
+    V = vext.copy()
+    with threadpool_limits(1):     # small dense problems: threads only add overhead
+        for _ in range(1000):
+            e, u = lowest(V, 0)
+            Vn = potential(u)
+            if np.max(np.abs(Vn - V)) < tol:
+                V = Vn
+                break
+            V = V + 0.5 * (Vn - V)
+        else:
+            raise AssertionError("radial SCF did not converge")
+        e_s, _ = lowest(V, 0)
+        e_p, _ = lowest(V, 1)
+    return e_s, e_p
+
+
+def test_radial_reference_is_converged_in_its_own_resolution():
+    a = radial_atom_scf(16.0, M=110)
+    b = radial_atom_scf(16.0, M=140)
+    assert abs(a[0] - b[0]) < 1e-10 and abs(a[1] - b[1]) < 1e-10
+
+
+def _oracle_atom(L=3, N=48, R=16.0):
+    bs = ob.make_basis(L, N, R, (3 * N) // 2, 2 * L + 2, 4 * L + 4, ob.RADIAL_GAUSS_JACOBI_R2)
+    pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
+    a1 = np.zeros((1, 3))
+    scf = osf.ClusterSCF(bs, a1, si.gaussian_wells(pts, a1), si.ion_density(pts, a1), 1, 4)
+    rion = si.ion_density(pts, a1)
+    theta, steps, rho, X = scf.run(rion, si.random_block(bs.d, 5, 1), tol=1e-11,
+                                   max_steps=80, first_iters=12)
+    return bs, theta, rho
+
+
+def test_single_atom_scf_matches_radial_solver():
+    bs, theta, rho = _oracle_atom()
+    e_s, e_p = radial_atom_scf(16.0)
+    assert abs(theta[0] - e_s) < 1e-8, (theta[0], e_s)
+    assert np.max(np.abs(theta[1:4] - e_p)) < 1e-8, (theta[1:4], e_p)
+    assert abs(od.integrate_grid(bs, rho) - 2.0) < 1e-6
+
+
+def test_sad_of_one_atom_at_origin_is_that_atom():
+    # the atom's density is spherical: its expansion has l = 0 terms only, and
+    # SAD with one atom at the origin is that expansion evaluated on the grid
+    bs, theta, rho = _oracle_atom(N=24)
+    tau = od.density_coefficients(bs, rho)
+    assert np.max(np.abs(tau[bs.N:])) < 1e-12 * np.max(np.abs(tau))
+    rho_sad = osf.sad_density(bs, tau[:bs.N], np.zeros((1, 3)))
+    expansion = oh.to_grid_real(bs, tau[:, None])[..., 0]
+    assert np.max(np.abs(rho_sad - expansion)) < 1e-12 * np.max(rho)
+    # what the N-term expansion misses of 2 psi^2 (the dualing basis truncates it)
+    assert np.max(np.abs(rho_sad - rho)) < 1e-2 * np.max(rho)
+    assert abs(od.integrate_grid(bs, rho_sad) - 2.0) < 1e-2
+
+
+def test_scf_cluster_generator():
+    for seed in (0, 1, 10000):
+        a = si.scf_cluster(seed)
+        assert si.SCF_ATOMS[0] <= len(a) <= si.SCF_ATOMS[1]
+        assert np.all(np.linalg.norm(a, axis=1) <= si.SCF_BALL)
+        d = np.linalg.norm(a[:, None] - a[None], axis=-1) + 1e9 * np.eye(len(a))
+        assert d.min() >= si.SCF_MIN_SEP
+    assert si.scf_occupation(8) == (8, 4) and si.scf_occupation(40) == (40, 8)
