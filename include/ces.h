@@ -257,6 +257,87 @@ ces_status ces_scf(ces_ham h, int k, double* d_X, int64_t ldx, int n_occ, const 
                    double* d_eval, double* d_rho, int* h_steps, double* h_dtheta, void* d_work,
                    size_t work_bytes, void* stream);
 
+/* ------------------------------------------------------ learned start */
+/* Not part of the paper's method: a learned correction to the SAD start
+ * density, so that the SCF (ces_scf) needs fewer steps; the converged
+ * eigenvalues do not depend on the start.  The start density is
+ *   rho_0(x) = rho_SAD(x) + sum_j sum_q c_jq Phi_q(x - a_j; u_j),
+ * c_j = network(descriptors of atom j), with the CES_MLP_CHANNELS functions
+ *   q < 5:  (2 pi s^2)^(-3/2) exp(-r^2 / (2 s^2)),        s = 0.6 0.9 1.3 1.9 2.8
+ *   q >= 5: (2 pi s^2)^(-3/2) (d.u_j / s) exp(-r^2/(2s^2)), s = 0.9 1.4 2.2
+ * (d = x - a_j, r = |d|, u_j the atom's unit environment direction), so
+ * rho_0 rotates with the cluster and does not depend on the atom order. */
+#define CES_MLP_FEATURES 24
+#define CES_MLP_CHANNELS 8
+
+/* Per-atom descriptors (host only, no device work).  h_atoms[3n] xyz
+ * (bohr); h_desc[n * 24] (row per atom): 16 radial symmetry functions
+ * sum_i exp(-2 (r_ij - mu)^2) fc(r_ij), mu = 2.0, 2.5, ..., 9.5; 4 angular
+ * ones 2^(1-z) sum_{i<k} (1 + l cos theta_ijk)^z exp(-0.02 (r_ij^2 + r_ik^2))
+ * fc fc for (z, l) = (1, 1), (1, -1), (4, 1), (4, -1); |a_j| / 8; n / 40;
+ * sum_i exp(-r_ij^2 / 18) / 10; |u_j|.  fc(r) = (cos(pi r / 10) + 1) / 2
+ * below 10 bohr, else 0.  u_j = sum_i exp(-r_ij^2 / 18) (a_i - a_j) / r_ij;
+ * h_dirs[3n] = u_j / |u_j| (zero when |u_j| <= 1e-6). */
+ces_status ces_atom_descriptors(int n_atoms, const double* h_atoms, float* h_desc,
+                                double* h_dirs);
+
+/* Gram matrix of the correction functions and a target on the grid:
+ * column c < 8 n of F holds sqrt(W_g) Phi_c(x_g) (c = 8 j + q), the last
+ * column sqrt(W_g) target(x_g) (zero if d_target is NULL); d_gram
+ * ((8n+1)^2, FP64) = F^T F.  Its leading block is M, its last column p,
+ * its corner t, so ||sum c Phi - target||_W^2 = c.M c - 2 p.c + t.
+ * Workspace: ces_density_fit_workspace_size.  Synchronous. */
+ces_status ces_density_fit_workspace_size(ces_ham h, int n_atoms, size_t* bytes);
+ces_status ces_density_fit_gram(ces_ham h, int n_atoms, const double* h_atoms,
+                                const double* h_dirs, const double* d_target, double* d_gram,
+                                void* d_work, size_t work_bytes, void* stream);
+
+/* d_rho[g] += sum_{j,q} d_coef[8 j + q] Phi_q(x_g - a_j; u_j) (d_coef FP32).
+ * d_work: at least 48 n_atoms bytes.  Synchronous. */
+ces_status ces_density_correction(ces_ham h, int n_atoms, const double* h_atoms,
+                                  const double* h_dirs, const float* d_coef, double* d_rho,
+                                  void* d_work, size_t work_bytes, void* stream);
+
+/* Per-atom network: n_in -> depth hidden layers of `width` (SiLU) -> n_out
+ * (linear), FP32 on the device, inputs standardised by a stored mean and
+ * std.  Weights start N(0, 1/fan_in) from a splitmix64 stream seeded by
+ * `seed`, biases 0, mean 0, std 1.  Parameter order (get/set): for each
+ * layer W (n_in_l x n_out_l, row-major) then b.  The handle owns its device
+ * memory (parameters, gradients, Adam moments). */
+typedef struct ces_mlp_s* ces_mlp;
+ces_status ces_mlp_create(int n_in, int width, int depth, int n_out, uint64_t seed, ces_mlp* out);
+ces_status ces_mlp_destroy(ces_mlp m);
+ces_status ces_mlp_num_params(ces_mlp m, int64_t* n);
+/* Host copies; any pointer may be NULL (not copied).  Synchronous. */
+ces_status ces_mlp_get_params(ces_mlp m, float* h_params, float* h_mean, float* h_std);
+ces_status ces_mlp_set_params(ces_mlp m, const float* h_params, const float* h_mean,
+                              const float* h_std);
+ces_status ces_mlp_get_grads(ces_mlp m, float* h_grads);
+/* Workspace for `rows` input rows: the activations that backward reuses. */
+ces_status ces_mlp_workspace_size(ces_mlp m, int rows, size_t* bytes);
+/* d_out[rows x n_out] = network(d_in[rows x n_in]) (row-major). */
+ces_status ces_mlp_forward(ces_mlp m, int rows, const float* d_in, float* d_out, void* d_work,
+                           size_t work_bytes, void* stream);
+/* Gradients of sum(d_gout * out) for the last forward on the same
+ * workspace, written (not accumulated) into the handle. */
+ces_status ces_mlp_backward(ces_mlp m, int rows, const float* d_gout, void* d_work,
+                            size_t work_bytes, void* stream);
+/* Adam (Kingma and Ba) with bias correction for step >= 1. */
+ces_status ces_mlp_adam_step(ces_mlp m, float lr, float beta1, float beta2, float eps, int step,
+                             void* stream);
+
+/* Batched quadratic loss of n_clusters clusters.  Cluster c owns network
+ * output rows [d_row_off[c], d_row_off[c+1]) (n_c atoms, at most max_atoms
+ * <= 2048), M_c (8 n_c x 8 n_c, symmetric, FP32) at d_M + d_m_off[c],
+ * p_c (8 n_c) at d_p + 8 d_row_off[c] and t_c = d_t[c].  With c the
+ * cluster's outputs flattened row-major:
+ *   d_loss[c] = c.M c - 2 p.c + t,  d_gout (rows) = scale (2 M c - 2 p).
+ * A cluster with more than max_atoms atoms gets loss NaN and no gradient. */
+ces_status ces_cluster_quad_loss(int n_clusters, int max_atoms, const int64_t* d_row_off,
+                                 const int64_t* d_m_off, const float* d_M, const float* d_p,
+                                 const float* d_t, const float* d_out, float* d_gout,
+                                 float* d_loss, float scale, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* Stage timing with HIP events recorded around each launch of the H*X

@@ -28,6 +28,10 @@ EXPORTS = [
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
+    "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
+    "ces_density_correction", "ces_mlp_create", "ces_mlp_destroy", "ces_mlp_num_params",
+    "ces_mlp_get_params", "ces_mlp_set_params", "ces_mlp_get_grads", "ces_mlp_workspace_size",
+    "ces_mlp_forward", "ces_mlp_backward", "ces_mlp_adam_step", "ces_cluster_quad_loss",
     "ces_profile_enable", "ces_profile_read", "ces_status_string", "ces_last_error",
 ]
 
@@ -77,6 +81,22 @@ def load() -> ctypes.CDLL:
         "ces_scf_workspace_size": [P, I, I, I, ctypes.POINTER(SZ)],
         "ces_scf": [P, I, P, I64, I, P, P, P, P, I, D, I, D, I, I, I, P, P,
                     ctypes.POINTER(I), P, P, SZ, P],
+        "ces_atom_descriptors": [I, P, P, P],
+        "ces_density_fit_workspace_size": [P, I, ctypes.POINTER(SZ)],
+        "ces_density_fit_gram": [P, I, P, P, P, P, P, SZ, P],
+        "ces_density_correction": [P, I, P, P, P, P, P, SZ, P],
+        "ces_mlp_create": [I, I, I, I, ctypes.c_uint64, ctypes.POINTER(P)],
+        "ces_mlp_destroy": [P],
+        "ces_mlp_num_params": [P, ctypes.POINTER(I64)],
+        "ces_mlp_get_params": [P, P, P, P],
+        "ces_mlp_set_params": [P, P, P, P],
+        "ces_mlp_get_grads": [P, P],
+        "ces_mlp_workspace_size": [P, I, ctypes.POINTER(SZ)],
+        "ces_mlp_forward": [P, I, P, P, P, SZ, P],
+        "ces_mlp_backward": [P, I, P, P, SZ, P],
+        "ces_mlp_adam_step": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              I, P],
+        "ces_cluster_quad_loss": [I, I, P, P, P, P, P, P, P, P, ctypes.c_float, P],
         "ces_profile_enable": [I, I],
         "ces_profile_read": [I, P, P],
     }
@@ -148,6 +168,108 @@ def anderson_mix(V, F, oldest, beta, out, h_coef=None, stream=None):
                                 coef.ctypes.data_as(ctypes.c_void_p), _ptr(work), sz.value,
                                 _stream(stream)), "ces_anderson_mix")
     return coef
+
+
+MLP_FEATURES = 24
+MLP_CHANNELS = 8
+
+
+def _host3(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, 3))
+
+
+def atom_descriptors(atoms):
+    """(descriptors (n, 24) float32, unit environment directions (n, 3))."""
+    a = _host3(atoms)
+    desc = np.zeros((a.shape[0], MLP_FEATURES), dtype=np.float32)
+    dirs = np.zeros((a.shape[0], 3))
+    _check(load().ces_atom_descriptors(a.shape[0], a.ctypes.data_as(ctypes.c_void_p),
+                                       desc.ctypes.data_as(ctypes.c_void_p),
+                                       dirs.ctypes.data_as(ctypes.c_void_p)),
+           "ces_atom_descriptors")
+    return desc, dirs
+
+
+def cluster_quad_loss(row_off, m_off, M, p, t, out, gout, loss, max_atoms, scale=1.0,
+                      stream=None):
+    _check(load().ces_cluster_quad_loss(int(loss.numel()), int(max_atoms), _ptr(row_off),
+                                        _ptr(m_off), _ptr(M), _ptr(p), _ptr(t), _ptr(out),
+                                        _ptr(gout), _ptr(loss), float(scale), _stream(stream)),
+           "ces_cluster_quad_loss")
+
+
+class MLP:
+    """Handle of ces_mlp (per-atom network, FP32 on the device)."""
+
+    def __init__(self, n_in=MLP_FEATURES, width=256, depth=3, n_out=MLP_CHANNELS, seed=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.ces_mlp_create(int(n_in), int(width), int(depth), int(n_out), int(seed),
+                                  ctypes.byref(h)), "ces_mlp_create")
+        self._h = h
+        self.n_in, self.n_out = n_in, n_out
+        self.sizes = [n_in] + [width] * depth + [n_out]
+        n = ctypes.c_int64()
+        _check(lib.ces_mlp_num_params(h, ctypes.byref(n)), "ces_mlp_num_params")
+        self.n_params = n.value
+
+    def get(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        mean = np.zeros(self.n_in, dtype=np.float32)
+        std = np.zeros(self.n_in, dtype=np.float32)
+        _check(load().ces_mlp_get_params(self._h, *[x.ctypes.data_as(ctypes.c_void_p)
+                                                    for x in (p, mean, std)]),
+               "ces_mlp_get_params")
+        return p, mean, std
+
+    def set(self, params=None, mean=None, std=None):
+        args = []
+        keep = []
+        for x in (params, mean, std):
+            if x is None:
+                args.append(None)
+            else:
+                a = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+                keep.append(a)
+                args.append(a.ctypes.data_as(ctypes.c_void_p))
+        _check(load().ces_mlp_set_params(self._h, *args), "ces_mlp_set_params")
+
+    def grads(self):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().ces_mlp_get_grads(self._h, g.ctypes.data_as(ctypes.c_void_p)),
+               "ces_mlp_get_grads")
+        return g
+
+    def workspace(self, rows):
+        import torch
+        sz = ctypes.c_size_t()
+        _check(load().ces_mlp_workspace_size(self._h, int(rows), ctypes.byref(sz)),
+               "ces_mlp_workspace_size")
+        return torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+
+    def forward(self, X, out, work, stream=None):
+        _check(load().ces_mlp_forward(self._h, X.shape[0], _ptr(X), _ptr(out), _ptr(work),
+                                      work.numel(), _stream(stream)), "ces_mlp_forward")
+
+    def backward(self, gout, work, stream=None):
+        _check(load().ces_mlp_backward(self._h, gout.shape[0], _ptr(gout), _ptr(work),
+                                       work.numel(), _stream(stream)), "ces_mlp_backward")
+
+    def adam_step(self, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(load().ces_mlp_adam_step(self._h, float(lr), float(beta1), float(beta2),
+                                        float(eps), int(step), _stream(stream)),
+               "ces_mlp_adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ces_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Basis:
@@ -318,6 +440,36 @@ class Ham:
                               dth.ctypes.data_as(ctypes.c_void_p), _ptr(work), work.numel(),
                               _stream(stream)), "ces_scf")
         return steps.value, dth[:steps.value].copy()
+
+    # ---------------------------------------------------------- learned start
+
+    def density_fit_gram(self, atoms, dirs, target, stream=None):
+        """(8n+1)^2 FP64 Gram of sqrt(W) [Phi | target] (torch, column-major)."""
+        import torch
+        a = _host3(atoms)
+        u = _host3(dirs)
+        n = a.shape[0]
+        sz = ctypes.c_size_t()
+        _check(load().ces_density_fit_workspace_size(self._h, n, ctypes.byref(sz)),
+               "ces_density_fit_workspace_size")
+        work = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+        nc = MLP_CHANNELS * n + 1
+        gram = torch.empty((nc, nc), dtype=torch.float64, device="cuda")
+        _check(load().ces_density_fit_gram(self._h, n, a.ctypes.data_as(ctypes.c_void_p),
+                                           u.ctypes.data_as(ctypes.c_void_p), _ptr(target),
+                                           _ptr(gram), _ptr(work), sz.value, _stream(stream)),
+               "ces_density_fit_gram")
+        return gram
+
+    def density_correction(self, atoms, dirs, coef, rho, stream=None):
+        import torch
+        a = _host3(atoms)
+        u = _host3(dirs)
+        work = torch.empty(48 * a.shape[0], dtype=torch.uint8, device="cuda")
+        _check(load().ces_density_correction(self._h, a.shape[0], a.ctypes.data_as(ctypes.c_void_p),
+                                             u.ctypes.data_as(ctypes.c_void_p), _ptr(coef),
+                                             _ptr(rho), _ptr(work), work.numel(),
+                                             _stream(stream)), "ces_density_correction")
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

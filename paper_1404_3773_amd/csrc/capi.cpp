@@ -241,6 +241,7 @@ ces_status ensure_device(Basis& b) {
       {cs.data(), cs.size() * 8, (void**)&b.dev_cs},
       {hart.data(), hart.size() * 8, (void**)&b.dev_hart},
       {b.r.data(), b.r.size() * 8, (void**)&b.dev_rnode},
+      {b.wr.data(), b.wr.size() * 8, (void**)&b.dev_wr},
       {cth.data(), cth.size() * 8, (void**)&b.dev_cth},
       {sth.data(), sth.size() * 8, (void**)&b.dev_sth}};
   size_t total = 0;

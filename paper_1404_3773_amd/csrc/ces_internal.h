@@ -51,6 +51,7 @@ struct Basis {
   int device = -1;
   double* dev_cs = nullptr;      // [2][n_phi] cos, sin(2 pi u / n_phi)
   double* dev_rnode = nullptr;   // [n_r] radial nodes
+  double* dev_wr = nullptr;      // [n_r] radial weights (r^2 included)
   double* dev_cth = nullptr;     // [n_theta] cos(theta_j)
   double* dev_sth = nullptr;     // [n_theta] sin(theta_j)
   double* dev_hart = nullptr;    // [l][N4][R16] (4 pi / (2l+1)) zeta_ln(r_k), RiT layout
@@ -178,6 +179,27 @@ void launch_anderson_combine(const double* V, const double* F, int64_t ld, const
 // rho on the grid = sum over atoms of sum_n cn[n] j0(n' pi |x - a| / R), n' = n + 1.
 void launch_sad_density(const Basis& b, const double* atoms, int n_atoms, const double* cn,
                         double* rho, hipStream_t s);
+
+// Learned start density (kernels_mlp.hip).  Row-major FP32 GEMM:
+// C = alpha op(A) op(B) + beta C, op(A) = A^T if ta (A stored K x M).
+void launch_gemm_f32(bool ta, bool tb, const float* A, int lda, const float* B, int ldb, float* C,
+                     int ldc, int M, int N, int K, float alpha, float beta, hipStream_t s);
+void launch_standardize(const float* X, const float* mean, const float* sd, float* H,
+                        int64_t rows, int cols, hipStream_t s);
+void launch_bias_act(float* Z, const float* b, float* H, int64_t rows, int cols, bool act,
+                     hipStream_t s);
+void launch_act_grad(float* G, const float* Z, int64_t n, hipStream_t s);
+void launch_colsum(const float* G, float* db, int64_t rows, int cols, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s);
+// F: n_grid x (8 n_atoms + 1) column-major, sqrt(W) Phi and sqrt(W) target.
+void launch_fit_columns(const Basis& b, const double* atoms, const double* dirs, int n_atoms,
+                        const double* target, double* F, hipStream_t s);
+void launch_density_correction(const Basis& b, const double* atoms, const double* dirs,
+                               int n_atoms, const float* coef, double* rho, hipStream_t s);
+void launch_cluster_quad_loss(int n_clusters, const int64_t* row_off, const int64_t* m_off,
+                              const float* M, const float* p, const float* t, const float* out,
+                              float* gout, float* loss, float scale, int max_nq, hipStream_t s);
 
 // Small FP64 helpers for Cholesky-QR / Rayleigh-Ritz / Lanczos.
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s);

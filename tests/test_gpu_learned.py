@@ -1,0 +1,187 @@
+"""GPU parity of the learned-start kernels with the FP64 oracle (oracle/mlp.py).
+
+FP32 network work (GEMM, forward, gradients, Adam, loss) is compared with
+FP64 references to a relative 1e-4 (FP32 rounding through a few 256-wide
+layers); the FP64 grid work (correction functions, their Gram matrix) to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import basis as ob
+from oracle import mlp as om
+
+torch = pytest.importorskip("torch")
+from paper_1404_3773_amd import ces  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [om.N_FEATURES, 256, 256, 256, om.N_CHANNELS]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in params])
+
+
+@pytest.mark.parametrize("M,N,K", [(77, 130, 45), (1000, 256, 256), (5, 8, 300)])
+def test_network_forward_and_gradients_via_gemm_shapes(M, N, K):
+    # single-layer network (depth 0): out = standardise(X) W + b exercises the
+    # NN product; backward exercises the TN product (and NT with depth > 0)
+    _say(f"case linear layer rows={M} in={K} out={N}")
+    rng = np.random.default_rng(M + N + K)
+    net = ces.MLP(n_in=K, width=1, depth=0, n_out=N, seed=1)
+    W = rng.standard_normal((K, N)) / np.sqrt(K)
+    b = rng.standard_normal(N)
+    net.set(np.concatenate([W.reshape(-1), b]), np.zeros(K), np.ones(K))
+    X = rng.standard_normal((M, K)).astype(np.float32)
+    out = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    work = net.workspace(M)
+    net.forward(_f32(X), out, work)
+    ref = X.astype(np.float64) @ W.astype(np.float32).astype(np.float64) + b.astype(np.float32)
+    e = rel(out.cpu().numpy(), ref)
+    G = rng.standard_normal((M, N)).astype(np.float32)
+    net.backward(_f32(G), work)
+    g = net.grads()
+    dW = X.astype(np.float64).T @ G
+    e2 = rel(g[:K * N].reshape(K, N), dW)
+    e3 = rel(g[K * N:], G.astype(np.float64).sum(0))
+    _say(f"  out {e:.1e}  dW {e2:.1e}  db {e3:.1e}")
+    assert e < 1e-5 and e2 < 1e-5 and e3 < 1e-5
+
+
+def test_mlp_forward_backward_match_oracle():
+    _say("case mlp 24-256x3-8 rows=517")
+    rng = np.random.default_rng(3)
+    params = om.init_params(SIZES, 4)
+    params = [(W.astype(np.float32).astype(np.float64), b + 0.1 * rng.standard_normal(b.shape))
+              for W, b in params]
+    X = (rng.standard_normal((517, om.N_FEATURES)) * 2 + 1).astype(np.float32)
+    mean = X.mean(0).astype(np.float32)
+    std = (X.std(0) + 0.3).astype(np.float32)
+    net = ces.MLP(seed=5)
+    net.set(_flat(params), mean, std)
+    out = torch.empty((517, om.N_CHANNELS), dtype=torch.float32, device="cuda")
+    work = net.workspace(517)
+    net.forward(_f32(X), out, work)
+    ref, cache = om.forward(params, X.astype(np.float64), mean.astype(np.float64),
+                            std.astype(np.float64))
+    e = rel(out.cpu().numpy(), ref)
+    G = rng.standard_normal((517, om.N_CHANNELS))
+    net.backward(_f32(G), work)
+    g = net.grads()
+    gref = _flat(om.backward(params, cache, G))
+    off = 0
+    worst = 0.0
+    for W, b in params:
+        for arr in (W, b):
+            n = arr.size
+            worst = max(worst, rel(g[off:off + n], gref[off:off + n]))
+            off += n
+    _say(f"  forward {e:.1e}  worst layer gradient {worst:.1e}")
+    assert e < 1e-4 and worst < 1e-4
+
+
+def test_adam_step_matches_oracle():
+    _say("case adam")
+    rng = np.random.default_rng(6)
+    net = ces.MLP(n_in=5, width=7, depth=1, n_out=3, seed=7)
+    p0, mean, std = net.get()
+    X = rng.standard_normal((9, 5)).astype(np.float32)
+    work = net.workspace(9)
+    out = torch.empty((9, 3), dtype=torch.float32, device="cuda")
+    params = []
+    off = 0
+    for a, c in zip(net.sizes[:-1], net.sizes[1:]):
+        params.append((p0[off:off + a * c].reshape(a, c).astype(np.float64),
+                       p0[off + a * c:off + a * c + c].astype(np.float64)))
+        off += a * c + c
+    m = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+    v = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+    for step in (1, 2, 3):
+        net.forward(_f32(X), out, work)
+        net.backward(_f32(rng.standard_normal((9, 3))), work)
+        g = net.grads().astype(np.float64)
+        grads, o = [], 0
+        for W, b in params:
+            grads.append((g[o:o + W.size].reshape(W.shape), g[o + W.size:o + W.size + b.size]))
+            o += W.size + b.size
+        net.adam_step(step, 1e-2)
+        om.adam_update(params, grads, m, v, step, 1e-2)
+    p, _, _ = net.get()
+    e = np.max(np.abs(p - _flat(params)))
+    _say(f"  max parameter difference after 3 steps {e:.1e}")
+    assert e < 1e-5
+
+
+def test_density_fit_gram_and_correction_match_oracle():
+    _say("case density fit small")
+    w = si.small(6, 12, R=12.0, n_r=18, n_theta=12, n_phi=24, name="fit_small")
+    B = ces.Basis.for_workload(w)
+    H = ces.Ham(B, torch.zeros(B.n_grid, dtype=torch.float64, device="cuda"))
+    bs = ob.basis_for(w)
+    pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
+    atoms = si.scf_cluster(21)[:3] * 0.5
+    desc, dirs = ces.atom_descriptors(atoms)
+    target = np.random.default_rng(8).standard_normal(pts.shape[:-1])
+    gram = H.density_fit_gram(atoms, dirs, torch.from_numpy(target.reshape(-1)).cuda())
+    M, p, t = om.quadratic_form(om.correction_functions(pts, atoms, dirs), bs.weights(), target)
+    G = gram.cpu().numpy()
+    nq = M.shape[0]
+    e = max(rel(G[:nq, :nq], M), rel(G[:nq, nq], p), abs(G[nq, nq] - t) / t)
+    _say(f"  gram rel err {e:.1e}")
+    assert e < 1e-10
+    coef = np.random.default_rng(9).standard_normal((3, om.N_CHANNELS)).astype(np.float32)
+    rho = torch.zeros(B.n_grid, dtype=torch.float64, device="cuda")
+    H.density_correction(atoms, dirs, _f32(coef), rho)
+    ref = np.einsum("jq,jq...->...", coef.astype(np.float64),
+                    om.correction_functions(pts, atoms, dirs))
+    e2 = rel(rho.cpu().numpy().reshape(ref.shape), ref)
+    _say(f"  correction rel err {e2:.1e}")
+    assert e2 < 1e-12
+
+
+def test_cluster_quad_loss_matches_oracle():
+    _say("case cluster loss")
+    rng = np.random.default_rng(10)
+    sizes = [3, 1, 7]
+    rows = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    Ms, ps, ts, moff = [], [], [], [0]
+    for n in sizes:
+        A = rng.standard_normal((8 * n, 8 * n))
+        Ms.append(A @ A.T)
+        ps.append(rng.standard_normal(8 * n))
+        ts.append(float(rng.uniform(1, 2)))
+        moff.append(moff[-1] + (8 * n) ** 2)
+    out = rng.standard_normal((rows[-1], 8)).astype(np.float32)
+    gout = torch.empty((rows[-1], 8), dtype=torch.float32, device="cuda")
+    loss = torch.empty(3, dtype=torch.float32, device="cuda")
+    ces.cluster_quad_loss(torch.from_numpy(rows).cuda(),
+                          torch.from_numpy(np.array(moff[:-1], dtype=np.int64)).cuda(),
+                          _f32(np.concatenate([M.reshape(-1) for M in Ms])),
+                          _f32(np.concatenate(ps)), _f32(np.array(ts)), _f32(out), gout, loss,
+                          max_atoms=7, scale=0.5)
+    L = loss.cpu().numpy()
+    g = gout.cpu().numpy()
+    for c, n in enumerate(sizes):
+        Lr, Gr = om.cluster_loss(Ms[c], ps[c], ts[c], out[rows[c]:rows[c + 1]].astype(np.float64))
+        assert abs(L[c] - Lr) < 1e-4 * max(1.0, abs(Lr))
+        assert rel(g[rows[c]:rows[c + 1]], 0.5 * Gr) < 1e-4
+    # a cluster above max_atoms is refused on the device (loss NaN)
+    ces.cluster_quad_loss(torch.from_numpy(rows).cuda(),
+                          torch.from_numpy(np.array(moff[:-1], dtype=np.int64)).cuda(),
+                          _f32(np.concatenate([M.reshape(-1) for M in Ms])),
+                          _f32(np.concatenate(ps)), _f32(np.array(ts)), _f32(out), gout, loss,
+                          max_atoms=3, scale=0.5)
+    assert np.isnan(loss.cpu().numpy()[2]) and np.isfinite(loss.cpu().numpy()[0])

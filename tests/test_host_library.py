@@ -73,3 +73,16 @@ def test_large_basis_tables_are_finite():
     assert np.all(np.diff(z, axis=1) > 0)
     bs_z = ob.bessel_zeros(81, 150)
     assert np.max(np.abs(z - bs_z) / bs_z) < 1e-14
+
+
+def test_atom_descriptors_match_oracle():
+    # host-only call of the library: descriptors and environment directions
+    from oracle import mlp as om
+    import synth_inputs as si
+    for seed in (0, 5):
+        atoms = si.scf_cluster(seed)
+        desc, dirs = ces.atom_descriptors(atoms)
+        ref = om.descriptors(atoms)
+        _, rdirs = om.environment(atoms)
+        assert np.max(np.abs(desc - ref) / np.maximum(1.0, np.abs(ref))) < 1e-6
+        assert np.max(np.abs(dirs - rdirs)) < 1e-12
