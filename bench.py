@@ -32,9 +32,11 @@ sys.path.insert(0, ROOT)
 
 import synth_inputs as si  # noqa: E402
 
-PEAK_FP32 = 157.3e12   # MI355X dense FP32 (vector = matrix), FLOP/s
+PEAK_FP32 = 157.3e12   # MI355X FP32: vector (256 CUs x 2.4 GHz) = dense matrix, FLOP/s
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12      # B/s
+PMC_COPY_BYTES = 1 << 30      # calibration copy of --pmc-run (read and written once)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "phi_stage_fp32_ico13_L31_N60_pmc.json")
 
 
 def algorithmic_flops(w, k):
@@ -68,6 +70,47 @@ def radial_bytes(w, k, elem):
     """Algorithmic HBM bytes of one radial-inverse launch: read X (d k),
     write G (n_r L^2 k); tables are L2-resident."""
     return elem * (w.d * k + w.n_r * w.L * w.L * k)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None if absent or taken on other kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    with open(PMC_SUMMARY) as f:
+        pmc = json.load(f)
+    if pmc.get("kernel") != kernel:
+        return None
+    from paper_1404_3773_amd import pmc_summary
+    if pmc_summary.source_digest(pmc["sources"]) != pmc["source_sha256"]:
+        return None
+    return pmc["traffic_bytes"]
+
+
+def pmc_run():
+    """Short run for the counter passes: two mixed-precision filters on the
+    13-atom workload (32 H*X) and a plain elementwise copy of PMC_COPY_BYTES."""
+    import torch
+    from paper_1404_3773_amd import ces
+    w = si.C2
+    B = ces.Basis.for_workload(w)
+    r, wr, th, wt, ph = B.grid()
+    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
+    work = H.workspace(w.k, ces.CES_PREC_MIXED)
+    X = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
+    ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
+    b = H.lanczos_bound(torch.from_numpy(si.lanczos_start(B.d)).cuda(), work)
+    H.rayleigh_ritz(X, ev, rs, work)
+    theta = ev.cpu().numpy()
+    for _ in range(2):
+        H.cheb_filter(X, w.degree, theta[-1], b, theta[0], ces.CES_PREC_MIXED, work)
+    src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"[bench] pmc run done: 32 H*X, 3 copies of {PMC_COPY_BYTES} bytes", flush=True)
 
 
 def golden_eigenvalues(w):
@@ -113,11 +156,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for rocprofv3 counter passes (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+
+    if args.pmc_run:
+        pmc_run()
+        return
 
     import torch
     from paper_1404_3773_amd import ces
@@ -202,18 +251,34 @@ def main():
                   file=sys.stderr, flush=True)
 
     # ---- roofline of the dominant kernel: the FP32 launch class with the
-    # largest total time in the timed steps (HIP events around each launch)
+    # largest total time in the timed steps (HIP events around each launch).
+    # The phi stage (synthesis, V, analysis) is credited at nominal real-FFT
+    # flops and priced against the FP32 ALU peak; the transform GEMM stages
+    # (radial, Legendre) against the FP32 MFMA peak (the same 157.3 TFLOP/s).
     stage_avg = {s: (ms / c if c else 0.0, c) for s, (ms, c) in prof.items()}
     fp32 = [s for s in prof if s.endswith("_fp32")]
     dom = max(fp32, key=lambda s: prof[s][0])
     avg_ms, launches = stage_avg[dom]
-    alg = stage_flops(w, k)[dom[:-5]]
+    sf = stage_flops(w, k)
+    alg = sf[dom[:-5]]
     achieved = alg / (avg_ms * 1e-3)
-    roof = {"bound": "mfma", "achieved": round(achieved / 1e12, 4),
+    kernel_name = {"phi_stage_fp32": "k_phi_stage<float>"}.get(dom)
+    traffic = measured_traffic(kernel_name) if kernel_name else None
+    roof = {"bound": "alu" if dom.startswith("phi") else "mfma",
+            "achieved": round(achieved / 1e12, 4),
             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
+            "frac": round(achieved / PEAK_FP32, 5),
+            "traffic": None if traffic is None else round(traffic),
             "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": launches,
             "alg_flop_per_launch": alg}
+    if traffic is not None:
+        roof["hbm_GBps_measured"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        roof["hbm_frac_measured"] = round(traffic / (avg_ms * 1e-3) / PEAK_HBM, 4)
+    gemm_frac = {}
+    for st in ("radial_inverse", "legendre_synth", "legendre_analysis", "radial_forward"):
+        ms_, c_ = stage_avg.get(st + "_fp32", (0.0, 0))
+        if c_:
+            gemm_frac[st] = round(sf[st] / (ms_ * 1e-3) / PEAK_FP32, 4)
 
     line = {
         "metric": "Chebyshev-filter H*X GFLOP/s & time-to-eigenpairs@1e-6Ha: mixed vs FP64",
@@ -228,6 +293,7 @@ def main():
                           "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4)},
         "time_to_eigenpairs": tte,
         "stage_ms_avg": {s: round(v[0], 5) for s, v in stage_avg.items()},
+        "transform_gemm_frac_fp32_mfma": gemm_frac,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
