@@ -64,11 +64,9 @@ inline AngDims ang_dims(const Basis& b, int kp) {
 
 // ------------------------------------------------------- legendre_synth
 
-constexpr int LS_NT = 4;  // 16-column tiles per workgroup (all waves share them)
-
-// Workgroup: one m-slot, 64 theta nodes (one 16-row tile per wave), 64
+// Workgroup: one m-slot, 64 theta nodes (one 16-row tile per wave), 16 NT
 // columns i of one radial node r.  g[r][j][s][i] = sum_l Pm[m][l][j] G[r][lm][i].
-template <typename T>
+template <typename T, int LS_NT>
 __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm,
                                                         const T* __restrict__ G,
                                                         T* __restrict__ g, AngDims D,
@@ -89,15 +87,39 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 #pragma unroll
   for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = zero_acc<acc_t>();
   const int K = D.L - m;
+  // column of each N-tile clamped into the block (tiles past nt_valid are not stored)
+  int col[LS_NT];
+#pragma unroll
+  for (int nt = 0; nt < LS_NT; ++nt) col[nt] = min(nt * 16, D.kp - i0 - 16);
+  // steps whose four l rows are all below L: row offset (l^2 + l + sgn m) kp
+  // advanced by second differences (l grows by 4 per step)
+  const int nfull = K >> 2;
+  {
+    const int l = m + kk;
+    int64_t off = static_cast<int64_t>(l * l + l + sgn * m) * D.kp;
+    int64_t dof = static_cast<int64_t>(8 * l + 20) * D.kp;
+    const int64_t ddof = 32 * static_cast<int64_t>(D.kp);
+    const T* pa = Pa + static_cast<int64_t>(l) * D.J64;
 #pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int l = m + k0 + kk;
+    for (int t = 0; t < nfull; ++t) {
+      const T a = *pa;
+      T b[LS_NT];
+#pragma unroll
+      for (int nt = 0; nt < LS_NT; ++nt) b[nt] = Gr[off + col[nt]];
+#pragma unroll
+      for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(a, b[nt], acc[nt]);
+      pa += 4 * D.J64;
+      off += dof;
+      dof += ddof;
+    }
+  }
+  if (K & 3) {
+    const int l = m + 4 * nfull + kk;
     const T a = Pa[l * D.J64];                    // zero rows for l >= L
     const int lc = min(l, D.L - 1);
     const int off = (lc * lc + lc + sgn * m) * D.kp;
 #pragma unroll
-    for (int nt = 0; nt < LS_NT; ++nt)
-      if (nt < nt_valid) acc[nt] = MF<T>::mma(a, Gr[off + nt * 16], acc[nt]);
+    for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(a, Gr[off + col[nt]], acc[nt]);
   }
   T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
 #pragma unroll
@@ -117,115 +139,120 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 // ha = a/2, hb = b/2 and b_{-q} = -b_q,
 //   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
 //   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
-template <typename T>
-__device__ __forceinline__ T coupling(const T* ha, const T* hb, int L, int so, int s) {
-  const bool so_sin = so >= L, s_sin = s >= L;
-  const int mo = so_sin ? so - L + 1 : so;
-  const int m = s_sin ? s - L + 1 : s;
-  const int dm = m - mo;
-  const int adm = dm < 0 ? -dm : dm;
-  const T bd = dm >= 0 ? hb[adm] : -hb[adm];
-  if (so_sin == s_sin) return so_sin ? ha[adm] - ha[m + mo] : ha[adm] + ha[m + mo];
-  return so_sin ? hb[m + mo] - bd : hb[m + mo] + bd;
-}
-
 constexpr int PS_NT = 2;   // 16-column tiles per workgroup
-constexpr int PS_MT = 3;   // M-tiles per wave (S16 <= 192)
 
-// Workgroup: one (r, theta_j), 32 columns; gh = T_rj g in place.  The A
-// fragments of T_rj are assembled from four LDS lookup tables of the
-// halved Fourier sums (branch-free form of `coupling`):
-//   D[q + L-1]          = ha_|q|           (q = m - m', same-type pairs)
-//   D[q + L-1 + S]      = sign(q) hb_|q|   (mixed pairs)
-//   E[sum]              = ha_sum,  E[sum + S] = hb_sum      (sum = m + m')
-//   T = sd * D[...] + se * E[...], sd = -1 only for sin <- cos,
-//   se = -1 only for sin <- sin.
-template <typename T>
+// phi stage: gh = C g per (r, theta_j) row, C the (2L-1)^2 coupling of the
+// product-to-sum identity above.  K (input slots) and M (output slots) are
+// laid out as a cos part (m = 0..L-1) and a sin part (m = 1..L-1), each
+// padded to LP = 16 ceil(L/16) rows, so that every 16 x 4 MFMA operand tile
+// lies in one of four blocks with uniform signs:
+//   (out cos, in cos)  a_|q| + a_p      (out cos, in sin)  b_q + b_p
+//   (out sin, in cos) -b_q  + b_p       (out sin, in sin)  a_|q| - a_p
+// with q = m - m', p = m + m'.  Each block entry is T[k - r + LP] + H[k + r]
+// for block-local input / output indices k, r, from six LDS tables of 2 LP
+// values built per row, so an A operand costs two LDS reads and one add.
+template <typename T, int LP>
 __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
                                                    AngDims D) {
   typedef typename MF<T>::acc acc_t;
   constexpr int GW = 16 * PS_NT + 1;
+  constexpr int K2 = 2 * LP, NMT = K2 / 16, MT = (NMT + 3) / 4;   // M-tiles per wave
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int S = D.S, L = D.L;
-  const int TW = 2 * S + 64;                   // table widths (padded)
-  T* Dt = reinterpret_cast<T*>(smem_raw);      // [TW]
-  T* Et = Dt + TW;                             // [TW]
-  T* gs = Et + TW;                             // [S4][GW]
+  T* tab = reinterpret_cast<T*>(smem_raw);     // 6 tables of K2 values
+  T* gs = tab + 6 * K2;                         // [K2][GW]
   const int64_t rj = blockIdx.x;
   const int i0 = blockIdx.y * (16 * PS_NT);
   const int nt_valid = min(PS_NT, (D.kp - i0) / 16);
   T* gr = g + rj * S * static_cast<int64_t>(D.kp) + i0;
   const T* abr = ab + rj * 2 * S;
-  for (int e = threadIdx.x; e < TW; e += blockDim.x) {
-    T dv = T(0), ev = T(0);
-    if (e < S) {                         // same-type difference, sum tables
-      const int q = e - (L - 1);
-      dv = (q > -L && q < L) ? abr[q < 0 ? -q : q] : T(0);
-      ev = abr[e];
-    } else if (e < 2 * S) {              // mixed difference (odd in q), hb sums
-      const int q = e - S - (L - 1);
-      dv = (q > -L && q < L) ? (q < 0 ? -abr[S - q] : abr[S + q]) : T(0);
-      ev = abr[S + e - S];
-    }
-    Dt[e] = dv;
-    Et[e] = ev;
+  for (int e = threadIdx.x; e < K2; e += blockDim.x) {
+    // a_x, b_x for x >= 0 (zero past the stored 0..S-1); b is odd in x
+    const int q = e - LP;
+    const int aq = q < 0 ? -q : q;
+    const int q1 = q + 1, q2 = q - 1;
+    const int a1 = q1 < 0 ? -q1 : q1, a2 = q2 < 0 ? -q2 : q2;
+    const T bq1 = a1 < S ? abr[S + a1] : T(0);
+    const T bq2 = a2 < S ? abr[S + a2] : T(0);
+    tab[e] = aq < S ? abr[aq] : T(0);                          // T cc, ss:  a_|q|
+    tab[K2 + e] = q1 >= 0 ? bq1 : -bq1;                        // T cs:  b_{q+1}
+    tab[2 * K2 + e] = q2 >= 0 ? -bq2 : bq2;                    // T sc: -b_{q-1}
+    tab[3 * K2 + e] = e < S ? abr[e] : T(0);                   // H cc:  a_h
+    tab[4 * K2 + e] = e + 1 < S ? abr[S + e + 1] : T(0);       // H cs, sc: b_{h+1}
+    tab[5 * K2 + e] = e + 2 < S ? -abr[e + 2] : T(0);          // H ss: -a_{h+2}
   }
   {
-    const int ii = threadIdx.x & 31, s0 = threadIdx.x >> 5;
-    for (int s = s0; s < D.S4; s += 8)
-      gs[s * GW + ii] = (s < S && i0 + ii < D.kp) ? gr[s * D.kp + ii] : T(0);
+    // g rows: slot s < L -> K row s; slot L + j (sin m = j + 1) -> row LP + j
+    const int ii = threadIdx.x & 31, k0 = threadIdx.x >> 5;
+    for (int k = k0; k < K2; k += 8) {
+      const bool sn = k >= LP;
+      const int kl = sn ? k - LP : k;
+      const bool ok = sn ? kl < L - 1 : kl < L;
+      const int s = sn ? L + kl : kl;
+      gs[k * GW + ii] = (ok && i0 + ii < D.kp) ? gr[static_cast<int64_t>(s) * D.kp + ii] : T(0);
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
-  const int nmt = D.S16 / 16;
-  // lane-constant output-slot data per M-tile
-  int mo[PS_MT];
-  bool osin[PS_MT];
+  int toff[MT], hoff[MT];
+  bool ocs[MT];
 #pragma unroll
-  for (int u = 0; u < PS_MT; ++u) {
-    const int so = min((wave + 4 * u) * 16 + l16, S - 1);   // padded rows: any finite value
-    osin[u] = so >= L;
-    mo[u] = osin[u] ? so - L + 1 : so;
+  for (int u = 0; u < MT; ++u) {
+    // tiles past NMT (when NMT is not a multiple of 4) repeat the last tile;
+    // their results are not written, so the MFMA loop needs no branch
+    const int mt = min(wave + 4 * u, NMT - 1);
+    ocs[u] = mt * 16 >= LP;
+    const int rl = mt * 16 - (ocs[u] ? LP : 0) + l16;
+    toff[u] = LP - rl + kk;
+    hoff[u] = rl + kk;
   }
-  acc_t acc[PS_MT][PS_NT];
+  acc_t acc[MT][PS_NT];
 #pragma unroll
-  for (int u = 0; u < PS_MT; ++u)
+  for (int u = 0; u < MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-#pragma unroll 2
-  for (int k0 = 0; k0 < D.S4; k0 += 4) {
-    const int s = min(k0 + kk, S - 1);         // padded g rows are zero
-    const bool ssin = s >= L;
-    const int m = ssin ? s - L + 1 : s;
-    T b[PS_NT];
 #pragma unroll
-    for (int nt = 0; nt < PS_NT; ++nt) b[nt] = gs[(k0 + kk) * GW + nt * 16 + l16];
+  for (int ic = 0; ic < 2; ++ic) {
+    const T* Tb[MT];
+    const T* Hb[MT];
 #pragma unroll
-    for (int u = 0; u < PS_MT; ++u) {
-      const int mt = wave + 4 * u;
-      if (mt >= nmt) break;
-      const bool same = ssin == osin[u];
-      const int di = m - mo[u] + (L - 1) + (same ? 0 : S);
-      const int ei = m + mo[u] + (same ? 0 : S);
-      const T dv = Dt[di], ev = Et[ei];
-      const T a = (same || !osin[u] ? dv : -dv) + (same && osin[u] ? -ev : ev);
+    for (int u = 0; u < MT; ++u) {
+      const int tsel = ocs[u] == (ic == 1) ? 0 : (ic == 1 ? 1 : 2);
+      const int hsel = ic == 0 ? (ocs[u] ? 4 : 3) : (ocs[u] ? 5 : 4);
+      Tb[u] = tab + tsel * K2 + toff[u];
+      Hb[u] = tab + hsel * K2 + hoff[u];
+    }
+    const T* grow = gs + (ic * LP + kk) * GW + l16;
 #pragma unroll
-      for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+    for (int k0 = 0; k0 < LP; k0 += 4) {
+      T b[PS_NT];
+#pragma unroll
+      for (int nt = 0; nt < PS_NT; ++nt) b[nt] = grow[k0 * GW + nt * 16];
+#pragma unroll
+      for (int u = 0; u < MT; ++u) {
+        const T a = Tb[u][k0] + Hb[u][k0];
+#pragma unroll
+        for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      }
     }
   }
   // inputs came from the LDS copy: write gh in place
 #pragma unroll
-  for (int u = 0; u < PS_MT; ++u) {
+  for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
-    if (mt >= nmt) break;
+    if (mt >= NMT) break;
 #pragma unroll
     for (int nt = 0; nt < PS_NT; ++nt) {
       if (nt >= nt_valid) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int so = mt * 16 + MF<T>::row(lane, v);
-        if (so < S) gr[so * D.kp + nt * 16 + l16] = acc[u][nt][v];
+        const int row = mt * 16 + MF<T>::row(lane, v);
+        const bool sn = row >= LP;
+        const int rl = sn ? row - LP : row;
+        if (sn ? rl < L - 1 : rl < L)
+          gr[static_cast<int64_t>(sn ? L + rl : rl) * D.kp + nt * 16 + l16] = acc[u][nt][v];
       }
     }
   }
@@ -233,10 +260,10 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
 
 // ---------------------------------------------------- legendre_analysis
 
-constexpr int LA_NT = 2;   // 16-column tiles per wave (128 columns per workgroup)
-constexpr int LA_MT = 6;   // M-tiles: L - m <= 96
+constexpr int LA_NT = 2;   // 16-column tiles per wave (32 columns per workgroup)
+constexpr int LA_SW = 4;   // m-slots per workgroup, one per wave
 
-// Workgroup: one m-slot, up to 128 columns of one radial node (32 per wave).
+// Workgroup: 32 columns of one radial node and four m-slots (one per wave).
 // A[r][lm][i] = sum_j w_j Pm[m][l][j] gh[r][j][s][i].
 template <typename T>
 __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__ PwT,
@@ -244,51 +271,65 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
                                                            T* __restrict__ A, AngDims D,
                                                            int n_ic) {
   typedef typename MF<T>::acc acc_t;
-  const int s = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = blockIdx.y * LA_SW + wave;
+  if (s >= D.S) return;
   int m, sgn;
   slot_to_m(s, D.L, m, sgn);
   const int r = blockIdx.x / n_ic;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kk = lane >> 4;
-  const int i0 = (blockIdx.x - r * n_ic) * (64 * LA_NT) + wave * (16 * LA_NT);
+  const int i0 = (blockIdx.x - r * n_ic) * (16 * LA_NT);
   const int nt_valid = min(LA_NT, (D.kp - i0) / 16);
-  if (nt_valid <= 0) return;
   const int M = D.L - m;
   const int nmt = (M + 15) / 16;
-  const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + l16;
   const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
-  const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
-  acc_t acc[LA_MT][LA_NT];
+  const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp;
+  // column of each N-tile, clamped into the block (tiles past nt_valid are
+  // computed on valid data and not stored)
+  int col[LA_NT];
 #pragma unroll
-  for (int u = 0; u < LA_MT; ++u)
+  for (int nt = 0; nt < LA_NT; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
+  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
+  for (int u = 0; u < nmt; ++u) {          // uniform loop over 16-row tiles of l
+    const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + u * 16 + l16;
+    acc_t acc[LA_NT];
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+    for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = zero_acc<acc_t>();
+    // steps whose four theta rows are all valid, by pointer increments
+    const int nfull = D.n_theta >> 2;
+    const T* pa = Pa + kk * D.L16;
+    const T* pb[LA_NT];
+#pragma unroll
+    for (int nt = 0; nt < LA_NT; ++nt) pb[nt] = gb + kk * jstride + col[nt];
 #pragma unroll 4
-  for (int k0 = 0; k0 < D.n_theta; k0 += 4) {
-    const int j = k0 + kk;
-    const int jc = min(j, D.n_theta - 1);          // padded A rows are zero
-    T b[LA_NT];
+    for (int t = 0; t < nfull; ++t) {
+      const T a = *pa;
+      T b[LA_NT];
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) b[nt] = (nt < nt_valid) ? gb[jc * jstride + nt * 16] : T(0);
+      for (int nt = 0; nt < LA_NT; ++nt) b[nt] = *pb[nt];
 #pragma unroll
-    for (int u = 0; u < LA_MT; ++u) {
-      if (u >= nmt) break;
-      const T a = Pa[j * D.L16 + u * 16];
+      for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = MF<T>::mma(a, b[nt], acc[nt]);
+      pa += 4 * D.L16;
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      for (int nt = 0; nt < LA_NT; ++nt) pb[nt] += 4 * jstride;
     }
-  }
-  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
+    if (D.n_theta & 3) {
+      // tail: weights of rows past n_theta are zero; read row n_theta - 1
+      const int j = 4 * nfull + kk;
+      const int jc = min(j, D.n_theta - 1);
+      const T a = Pa[j * D.L16];
 #pragma unroll
-  for (int nt = 0; nt < LA_NT; ++nt) {
-    if (nt >= nt_valid) break;
+      for (int nt = 0; nt < LA_NT; ++nt)
+        acc[nt] = MF<T>::mma(a, gb[jc * jstride + col[nt]], acc[nt]);
+    }
 #pragma unroll
-    for (int u = 0; u < LA_MT; ++u) {
-      if (u >= nmt) break;
+    for (int nt = 0; nt < LA_NT; ++nt) {
+      if (nt >= nt_valid) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int l = m + u * 16 + MF<T>::row(lane, v);
-        if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + nt * 16] = acc[u][nt][v];
+        if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + i0 + nt * 16] = acc[nt][v];
       }
     }
   }
@@ -369,25 +410,39 @@ template <typename T>
 void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* gbuf, int kp,
                            hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
-  const int n_ic = (kp + 16 * LS_NT - 1) / (16 * LS_NT);
-  dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-  k_legendre_synth<T><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+  // two column tiles when the block is narrow (no idle MFMA columns), else four
+  if (kp <= 32) {
+    const int n_ic = (kp + 31) / 32;
+    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
+    k_legendre_synth<T, 2><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+  } else {
+    const int n_ic = (kp + 63) / 64;
+    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
+    k_legendre_synth<T, 4><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+  }
 }
 
 template <typename T>
 void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
   dim3 grid(b.n_r * b.n_theta, (kp + 16 * PS_NT - 1) / (16 * PS_NT));
-  const size_t lds = (2 * size_t(2 * D.S + 64) + size_t(D.S4) * (16 * PS_NT + 1)) * sizeof(T);
-  k_phi_stage<T><<<grid, 256, lds, s>>>(gbuf, ab, D);
+  const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
+  switch (D.L16) {   // L <= 96 (checked at basis creation)
+    case 16: k_phi_stage<T, 16><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    case 32: k_phi_stage<T, 32><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    case 48: k_phi_stage<T, 48><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    case 64: k_phi_stage<T, 64><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    case 80: k_phi_stage<T, 80><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    default: k_phi_stage<T, 96><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+  }
 }
 
 template <typename T>
 void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* gbuf, T* A,
                               int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
-  const int n_ic = (kp + 64 * LA_NT - 1) / (64 * LA_NT);
-  dim3 grid(b.n_r * n_ic, D.S);
+  const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
+  dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
 }
 
