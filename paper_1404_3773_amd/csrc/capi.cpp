@@ -509,6 +509,7 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   // Section 3.1.1.  *ok reports whether the factorisation succeeded (X is
   // left untouched otherwise).
   double* part = Ptr<double>::at(work, ly.part);
+  const int64_t part_cap = int64_t(gram_chunks(d, k)) * k * k;   // doubles in the region
   auto pass = [&](double shift, bool* ok) -> ces_status {
     launch_gram(X, ldx, X, ldx, S1, part, d, k, s);
     launch_symmetrize(S1, k, s);
@@ -562,8 +563,11 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   // Hs = Q^T H Q, eigen-decomposition (ascending)
   launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s);
   launch_symmetrize(S1, k, s);
-  CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k, evals,
-                            Ework, info));
+  if (k <= kJacobiMax)   // small blocks: one-workgroup Jacobi (no host round trips)
+    launch_jacobi_eig(S1, k, evals, info, s);
+  else
+    CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k, evals,
+                              Ework, info));
   // X <- Q S ; HX <- HQ S  (through B1 when HX is given, else B1 holds HQ)
   if (HX) {
     CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
@@ -574,7 +578,7 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
                            static_cast<int>(d), k, k, &one, HX, static_cast<int>(ldhx), S1, k,
                            &zero, B1, static_cast<int>(d)));
     launch_copy2d(B1, d, HX, ldhx, d, k, s);
-    launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, s);
+    launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, part, part_cap, s);
   } else {
     // B1 holds HQ; rotate X through B2, then HQ S into B2 for the residuals
     double* T2 = Ptr<double>::at(work, ly.B2);
@@ -585,12 +589,12 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
                            static_cast<int>(d), k, k, &one, B1, static_cast<int>(d), S1, k, &zero,
                            T2, static_cast<int>(d)));
-    launch_residuals(T2, d, X, ldx, evals, res, d, k, s);
+    launch_residuals(T2, d, X, ldx, evals, res, d, k, part, part_cap, s);
   }
   CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   CES_HIP(hipStreamSynchronize(s));
-  if (hinfo != 0) return fail(CES_ERR_EIGENSOLVER, "syevd did not converge");
+  if (hinfo != 0) return fail(CES_ERR_EIGENSOLVER, "projected eigenproblem did not converge");
   return CES_OK;
 }
 
@@ -894,7 +898,7 @@ ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* 
   double* w = v + 2 * d;
   double* sc = Ptr<double>::at(d_work, ly.vec);
   CES_HIP(hipMemsetAsync(vp, 0, size_t(d) * 8, s));
-  launch_dot(d_v0, d_v0, d, sc, s);
+  launch_dot(d_v0, d_v0, d, sc, sc + 64, s);
   double nrm2 = 0;
   CES_HIP(hipMemcpyAsync(&nrm2, sc, 8, hipMemcpyDeviceToHost, s));
   CES_HIP(hipStreamSynchronize(s));
@@ -904,13 +908,13 @@ ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* 
   double beta = 0.0;
   for (int j = 0; j < steps; ++j) {
     CES_TRY(h_step<double>(h, ly, d_work, 1, v, d, nullptr, 0, w, d, 1.0, 0.0, 0.0, s));
-    launch_dot(v, w, d, sc, s);
+    launch_dot(v, w, d, sc, sc + 64, s);
     double alpha = 0;
     CES_HIP(hipMemcpyAsync(&alpha, sc, 8, hipMemcpyDeviceToHost, s));
     CES_HIP(hipStreamSynchronize(s));
     launch_axpby(-alpha, v, 1.0, w, d, s);
     if (j > 0) launch_axpby(-beta, vp, 1.0, w, d, s);
-    launch_dot(w, w, d, sc, s);
+    launch_dot(w, w, d, sc, sc + 64, s);
     double b2 = 0;
     CES_HIP(hipMemcpyAsync(&b2, sc, 8, hipMemcpyDeviceToHost, s));
     CES_HIP(hipStreamSynchronize(s));

@@ -201,6 +201,12 @@ void launch_cluster_quad_loss(int n_clusters, const int64_t* row_off, const int6
                               const float* M, const float* p, const float* t, const float* out,
                               float* gout, float* loss, float scale, int max_nq, hipStream_t s);
 
+// Eigenpairs of a symmetric k x k matrix (column-major, full) for k <=
+// kJacobiMax in one workgroup: eigenvectors overwrite S, eigenvalues
+// ascending in evals; *info = 0 on convergence.
+constexpr int kJacobiMax = 60;
+void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s);
+
 // Small FP64 helpers for Cholesky-QR / Rayleigh-Ritz / Lanczos.
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s);
 void launch_scale_cols(double* X, int64_t ldx, int64_t rows, int k, const double* dinv,
@@ -209,10 +215,14 @@ void launch_symmetrize(double* S, int k, hipStream_t s);
 void launch_add_diag(double* S, int k, double shift, hipStream_t s);
 void launch_zero_lower(double* S, int k, hipStream_t s);
 void launch_residuals(const double* HX, int64_t ldh, const double* X, int64_t ldx,
-                      const double* theta, double* res, int64_t rows, int k, hipStream_t s);
+                      const double* theta, double* res, int64_t rows, int k, double* part,
+                      int64_t part_cap, hipStream_t s);
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                    int cols, hipStream_t s);
-void launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
+// *out = x . y; part: kDotBlocks doubles of scratch.
+constexpr int kDotBlocks = 64;
+void launch_dot(const double* x, const double* y, int64_t n, double* out, double* part,
+                hipStream_t s);
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 
 }  // namespace ces

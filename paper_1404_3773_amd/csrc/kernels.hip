@@ -241,20 +241,31 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-__global__ __launch_bounds__(256) void k_residuals(const double* HX, int64_t ldh,
-                                                   const double* X, int64_t ldx,
-                                                   const double* theta, double* res,
-                                                   int64_t rows) {
+// Two-pass reductions over long vectors: per-block partial sums, then one
+// thread per result.  res_c = || HX_c - theta_c X_c ||_2 and dot = x . y.
+__global__ __launch_bounds__(256) void k_residual_partial(const double* HX, int64_t ldh,
+                                                          const double* X, int64_t ldx,
+                                                          const double* theta, double* part,
+                                                          int64_t rows) {
   __shared__ double red[4];
-  const int c = blockIdx.x;
+  const int c = blockIdx.y, nb = gridDim.x;
   const double th = theta[c];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < rows; e += blockDim.x) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows;
+       e += static_cast<int64_t>(nb) * blockDim.x) {
     const double v = HX[c * ldh + e] - th * X[c * ldx + e];
     acc += v * v;
   }
   const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) res[c] = sqrt(t);
+  if (threadIdx.x == 0) part[static_cast<int64_t>(c) * nb + blockIdx.x] = t;
+}
+
+__global__ void k_finish_sums(const double* part, int nb, int ncol, double* out, int take_sqrt) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[static_cast<int64_t>(c) * nb + b];
+    out[c] = take_sqrt ? sqrt(t) : t;
+  }
 }
 
 __global__ void k_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd,
@@ -265,13 +276,15 @@ __global__ void k_copy2d(const double* src, int64_t lds, double* dst, int64_t ld
     dst[c * ldd + e] = src[c * lds + e];
 }
 
-__global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, int64_t n,
-                                             double* out) {
+__global__ __launch_bounds__(256) void k_dot_partial(const double* x, const double* y, int64_t n,
+                                                     double* part) {
   __shared__ double red[4];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) acc += x[e] * y[e];
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    acc += x[e] * y[e];
   const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) *out = t;
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
@@ -284,6 +297,115 @@ template <typename T>
 __global__ void k_scale_rows(T* C, int rows, int ld, const T* h) {
   const int q = blockIdx.x;
   for (int i = threadIdx.x; i < ld; i += blockDim.x) C[static_cast<int64_t>(q) * ld + i] *= h[q];
+}
+
+// Symmetric eigenproblem of a small k x k matrix (k <= kJacobiMax) in one
+// workgroup: parallel cyclic Jacobi.  Each round rotates n/2 disjoint pairs
+// (p, q) chosen by the round-robin (circle) schedule, n = k rounded up to
+// even, so that n - 1 rounds make a sweep over all pairs; each rotation is
+// the 2 x 2 symmetric Schur rotation zeroing A_pq (t = sign(th) / (|th| +
+// sqrt(th^2 + 1)), th = (A_qq - A_pp) / (2 A_pq), c = 1/sqrt(1 + t^2),
+// s = t c), applied as A <- J^T A J and V <- V J.  Sweeps stop when the
+// off-diagonal Frobenius norm is below 1e-14 of the whole; then eigenvalues
+// are sorted ascending (ties by index) with their columns of V.
+// S: k x k column-major in (full symmetric), eigenvectors out; info = 0 on
+// convergence within 40 sweeps, else 1.
+__device__ __forceinline__ int rr_player(int pos, int r, int n) {
+  return pos == 0 ? 0 : (pos - 1 + r) % (n - 1) + 1;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_eig(double* __restrict__ S, int k,
+                                                    double* __restrict__ evals, int* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = k + (k & 1);
+  const int ld = n + 1;
+  double* A = reinterpret_cast<double*>(smem_raw);   // [n][ld]
+  double* V = A + n * ld;                             // [n][ld]
+  double* cs = V + n * ld;                            // [n/2][2]
+  int* pq = reinterpret_cast<int*>(cs + n);           // [n/2][2]
+  __shared__ double red[4];
+  __shared__ int done;
+  const int tid = threadIdx.x, nt = blockDim.x, half = n / 2;
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e / n, j = e - (e / n) * n;
+    A[i * ld + j] = (i < k && j < k) ? S[static_cast<int64_t>(j) * k + i] : 0.0;
+    V[i * ld + j] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double f = 0.0;
+  for (int e = tid; e < n * n; e += nt) {
+    const double a = A[(e / n) * ld + e % n];
+    f += a * a;
+  }
+  const double fro2 = block_sum(f, red);
+  int converged = 0;
+  for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+    for (int r = 0; r < n - 1; ++r) {
+      for (int pi = tid; pi < half; pi += nt) {
+        int p = rr_player(pi, r, n), q = rr_player(n - 1 - pi, r, n);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, sn = 0.0;
+        const double apq = A[p * ld + q];
+        if (q < k && apq != 0.0) {
+          const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sn = t * c;
+        }
+        cs[2 * pi] = c;
+        cs[2 * pi + 1] = sn;
+        pq[2 * pi] = p;
+        pq[2 * pi + 1] = q;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * n; e += nt) {          // rows p, q of J^T A
+        const int pi = e / n, j = e - pi * n;
+        const int p = pq[2 * pi], q = pq[2 * pi + 1];
+        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
+        const double a = A[p * ld + j], b = A[q * ld + j];
+        A[p * ld + j] = c * a - sn * b;
+        A[q * ld + j] = sn * a + c * b;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * n; e += nt) {          // columns p, q of (.) J and V J
+        const int pi = e / n, i = e - pi * n;
+        const int p = pq[2 * pi], q = pq[2 * pi + 1];
+        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
+        const double a = A[i * ld + p], b = A[i * ld + q];
+        A[i * ld + p] = c * a - sn * b;
+        A[i * ld + q] = sn * a + c * b;
+        const double va = V[i * ld + p], vb = V[i * ld + q];
+        V[i * ld + p] = c * va - sn * vb;
+        V[i * ld + q] = sn * va + c * vb;
+      }
+      __syncthreads();
+    }
+    double o = 0.0;
+    for (int e = tid; e < n * n; e += nt) {
+      const int i = e / n, j = e - (e / n) * n;
+      if (i != j) o += A[i * ld + j] * A[i * ld + j];
+    }
+    const double off = block_sum(o, red);
+    if (tid == 0) done = off <= 1e-28 * fro2 ? 1 : 0;
+    __syncthreads();
+    converged = done;
+    __syncthreads();
+  }
+  for (int i = tid; i < k; i += nt) {
+    const double lam = A[i * ld + i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double mu = A[j * ld + j];
+      rank += (mu < lam || (mu == lam && j < i)) ? 1 : 0;
+    }
+    evals[rank] = lam;
+    for (int rr = 0; rr < k; ++rr) S[static_cast<int64_t>(rank) * k + rr] = V[rr * ld + i];
+  }
+  if (tid == 0) *info = converged ? 0 : 1;
 }
 
 inline int grid1d(int64_t n) {
@@ -357,16 +479,31 @@ void launch_add_diag(double* S, int k, double shift, hipStream_t s) {
   k_add_diag<<<grid1d(k), 256, 0, s>>>(S, k, shift);
 }
 void launch_residuals(const double* HX, int64_t ldh, const double* X, int64_t ldx,
-                      const double* theta, double* res, int64_t rows, int k, hipStream_t s) {
-  k_residuals<<<k, 256, 0, s>>>(HX, ldh, X, ldx, theta, res, rows);
+                      const double* theta, double* res, int64_t rows, int k, double* part,
+                      int64_t part_cap, hipStream_t s) {
+  int64_t nb = (rows + 2047) / 2048;                 // >= 2048 rows per block
+  nb = nb < 1 ? 1 : (nb > 64 ? 64 : nb);
+  if (nb * k > part_cap) nb = part_cap / k > 0 ? part_cap / k : 1;
+  k_residual_partial<<<dim3(static_cast<unsigned>(nb), k), 256, 0, s>>>(HX, ldh, X, ldx, theta,
+                                                                         part, rows);
+  k_finish_sums<<<(k + 255) / 256, 256, 0, s>>>(part, static_cast<int>(nb), k, res, 1);
 }
 void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                    int cols, hipStream_t s) {
   dim3 grid(grid1d(rows), cols);
   k_copy2d<<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows);
 }
-void launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
-  k_dot<<<1, 256, 0, s>>>(x, y, n, out);
+void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s) {
+  const int n = k + (k & 1);
+  const size_t lds = (2 * size_t(n) * (n + 1) + n) * sizeof(double) + size_t(n) * sizeof(int);
+  k_jacobi_eig<<<1, 256, lds, s>>>(S, k, evals, info);
+}
+void launch_dot(const double* x, const double* y, int64_t n, double* out, double* part,
+                hipStream_t s) {
+  int64_t nb = (n + 2047) / 2048;
+  nb = nb < 1 ? 1 : (nb > kDotBlocks ? kDotBlocks : nb);
+  k_dot_partial<<<static_cast<unsigned>(nb), 256, 0, s>>>(x, y, n, part);
+  k_finish_sums<<<1, 64, 0, s>>>(part, static_cast<int>(nb), 1, out, 0);
 }
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
   k_axpby<<<grid1d(n), 256, 0, s>>>(a, x, b, y, n);
