@@ -72,14 +72,15 @@ def radial_bytes(w, k, elem):
     return elem * (w.d * k + w.n_r * w.L * w.L * k)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None if absent or taken on other kernel sources."""
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of the kernel whose name starts with
+    `kernel_prefix` (template arguments follow), from the committed
+    FETCH_SIZE / WRITE_SIZE summary; None if absent or taken on other sources."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     with open(PMC_SUMMARY) as f:
         pmc = json.load(f)
-    if pmc.get("kernel") != kernel:
+    if not str(pmc.get("kernel", "")).startswith(kernel_prefix):
         return None
     from paper_1404_3773_amd import pmc_summary
     if pmc_summary.source_digest(pmc["sources"]) != pmc["source_sha256"]:
@@ -262,7 +263,7 @@ def main():
     sf = stage_flops(w, k)
     alg = sf[dom[:-5]]
     achieved = alg / (avg_ms * 1e-3)
-    kernel_name = {"phi_stage_fp32": "k_phi_stage<float>"}.get(dom)
+    kernel_name = {"phi_stage_fp32": "k_phi_stage<float"}.get(dom)
     traffic = measured_traffic(kernel_name) if kernel_name else None
     roof = {"bound": "alu" if dom.startswith("phi") else "mfma",
             "achieved": round(achieved / 1e12, 4),

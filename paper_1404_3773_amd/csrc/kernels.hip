@@ -314,7 +314,7 @@ __device__ __forceinline__ int rr_player(int pos, int r, int n) {
   return pos == 0 ? 0 : (pos - 1 + r) % (n - 1) + 1;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_eig(double* __restrict__ S, int k,
+__global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ S, int k,
                                                     double* __restrict__ evals, int* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = k + (k & 1);
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_jacobi_eig(double* __restrict__ S, int 
   double* V = A + n * ld;                             // [n][ld]
   double* cs = V + n * ld;                            // [n/2][2]
   int* pq = reinterpret_cast<int*>(cs + n);           // [n/2][2]
-  __shared__ double red[4];
+  __shared__ double red[16];
   __shared__ int done;
   const int tid = threadIdx.x, nt = blockDim.x, half = n / 2;
   for (int e = tid; e < n * n; e += nt) {
@@ -496,7 +496,7 @@ void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int
 void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s) {
   const int n = k + (k & 1);
   const size_t lds = (2 * size_t(n) * (n + 1) + n) * sizeof(double) + size_t(n) * sizeof(int);
-  k_jacobi_eig<<<1, 256, lds, s>>>(S, k, evals, info);
+  k_jacobi_eig<<<1, 1024, lds, s>>>(S, k, evals, info);
 }
 void launch_dot(const double* x, const double* y, int64_t n, double* out, double* part,
                 hipStream_t s) {
