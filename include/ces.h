@@ -138,9 +138,13 @@ ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degre
  * (Section 3.2), all FP64: Q = X D R^{-1}; theta, S = eig(Q^T H Q) ascending;
  * X <- Q S; HX <- (H Q) S; r_i = ||H x_i - theta_i x_i||.  d_HX (d x k, ld =
  * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles.  hx_prec selects
- * the precision of the H*Q product.  Synchronises `stream`; returns
- * CES_ERR_NOT_POSITIVE_DEFINITE if the scaled Gram matrix is not positive
- * definite after a shifted retry (X is then left scaled but not rotated). */
+ * the precision of the H*Q product.  If the scaled Gram matrix is not
+ * positive definite, one shifted Cholesky-QR pass followed by two plain passes
+ * (shifted CholeskyQR3) orthonormalises X; CES_ERR_NOT_POSITIVE_DEFINITE if
+ * the shifted pass fails too (X is then left scaled but not rotated).  The
+ * k x k eigenproblem is solved by a one-workgroup Jacobi method for k <= 60,
+ * by rocSOLVER syevd above; CES_ERR_EIGENSOLVER if it does not converge.
+ * Synchronises `stream`. */
 ces_status ces_rayleigh_ritz(ces_ham h, int k, double* d_X, int64_t ldx, double* d_HX,
                              double* d_eval, double* d_resnorm, int hx_prec,
                              void* d_work, size_t work_bytes, void* stream);
