@@ -18,6 +18,8 @@
 // register v is D[4(q/16)+v][q%16], the FP64 result D[q/16+4v][q%16].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ces_internal.h"
 #include "mfma.h"
 
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 // ha = a/2, hb = b/2 and b_{-q} = -b_q,
 //   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
 //   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
-constexpr int PS_NT = 2;   // 16-column tiles per workgroup
+constexpr int PS_NT = 2;             // 16-column tiles per workgroup
+constexpr int kPhiWorkgroups = 1024; // resident rows in flight (4 per CU)
 
 // phi stage: gh = C g per (r, theta_j) row, C the (2L-1)^2 coupling of the
 // product-to-sum identity above.  K (input slots) and M (output slots) are
@@ -153,48 +156,47 @@ constexpr int PS_NT = 2;   // 16-column tiles per workgroup
 // values built per row, so an A operand costs two LDS reads and one add.
 template <typename T, int LP>
 __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
-                                                   AngDims D) {
+                                                   AngDims D, int64_t n_rows) {
   typedef typename MF<T>::acc acc_t;
   constexpr int GW = 16 * PS_NT + 1;
   constexpr int K2 = 2 * LP, NMT = K2 / 16, MT = (NMT + 3) / 4;   // M-tiles per wave
+  constexpr int GPT = K2 / 8;                   // g values per thread per row
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int S = D.S, L = D.L;
   T* tab = reinterpret_cast<T*>(smem_raw);     // 6 tables of K2 values
-  T* gs = tab + 6 * K2;                         // [K2][GW]
-  const int64_t rj = blockIdx.x;
+  T* abs_ = tab + 6 * K2;                       // raw Fourier sums of the row, 2S <= 2 K2
+  T* gs = abs_ + 2 * K2;                        // [K2][GW]
   const int i0 = blockIdx.y * (16 * PS_NT);
   const int nt_valid = min(PS_NT, (D.kp - i0) / 16);
-  T* gr = g + rj * S * static_cast<int64_t>(D.kp) + i0;
-  const T* abr = ab + rj * 2 * S;
-  for (int e = threadIdx.x; e < K2; e += blockDim.x) {
-    // a_x, b_x for x >= 0 (zero past the stored 0..S-1); b is odd in x
-    const int q = e - LP;
-    const int aq = q < 0 ? -q : q;
-    const int q1 = q + 1, q2 = q - 1;
-    const int a1 = q1 < 0 ? -q1 : q1, a2 = q2 < 0 ? -q2 : q2;
-    const T bq1 = a1 < S ? abr[S + a1] : T(0);
-    const T bq2 = a2 < S ? abr[S + a2] : T(0);
-    tab[e] = aq < S ? abr[aq] : T(0);                          // T cc, ss:  a_|q|
-    tab[K2 + e] = q1 >= 0 ? bq1 : -bq1;                        // T cs:  b_{q+1}
-    tab[2 * K2 + e] = q2 >= 0 ? -bq2 : bq2;                    // T sc: -b_{q-1}
-    tab[3 * K2 + e] = e < S ? abr[e] : T(0);                   // H cc:  a_h
-    tab[4 * K2 + e] = e + 1 < S ? abr[S + e + 1] : T(0);       // H cs, sc: b_{h+1}
-    tab[5 * K2 + e] = e + 2 < S ? -abr[e + 2] : T(0);          // H ss: -a_{h+2}
+  const int tid = threadIdx.x;
+  const int ii = tid & 31, kr = tid >> 5;
+  // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j)
+  int soff[GPT];
+  bool sok[GPT];
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    const int k = kr + 8 * u;
+    const bool sn = k >= LP;
+    const int kl = sn ? k - LP : k;
+    sok[u] = (sn ? kl < L - 1 : kl < L) && i0 + ii < D.kp;
+    soff[u] = (sn ? L + kl : kl) * D.kp + i0 + ii;
   }
-  {
-    // g rows: slot s < L -> K row s; slot L + j (sin m = j + 1) -> row LP + j
-    const int ii = threadIdx.x & 31, k0 = threadIdx.x >> 5;
-    for (int k = k0; k < K2; k += 8) {
-      const bool sn = k >= LP;
-      const int kl = sn ? k - LP : k;
-      const bool ok = sn ? kl < L - 1 : kl < L;
-      const int s = sn ? L + kl : kl;
-      gs[k * GW + ii] = (ok && i0 + ii < D.kp) ? gr[static_cast<int64_t>(s) * D.kp + ii] : T(0);
+  const int64_t rstride = static_cast<int64_t>(S) * D.kp;
+  // registers holding the next row (software pipeline across rows)
+  T gp[GPT], ap[2];
+  auto fetch = [&](int64_t row) {
+    const T* gr = g + row * rstride;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) gp[u] = sok[u] ? gr[soff[u]] : T(0);
+    const T* abr = ab + row * 2 * S;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int e = tid + 256 * v;
+      ap[v] = e < 2 * S ? abr[e] : T(0);
     }
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  };
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
   int toff[MT], hoff[MT];
   bool ocs[MT];
@@ -208,53 +210,84 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
     toff[u] = LP - rl + kk;
     hoff[u] = rl + kk;
   }
-  acc_t acc[MT][PS_NT];
+  int64_t row = blockIdx.x;
+  if (row < n_rows) fetch(row);
+  for (; row < n_rows; row += gridDim.x) {
 #pragma unroll
-  for (int u = 0; u < MT; ++u)
+    for (int u = 0; u < GPT; ++u) gs[(kr + 8 * u) * GW + ii] = gp[u];
 #pragma unroll
-    for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-#pragma unroll
-  for (int ic = 0; ic < 2; ++ic) {
-    const T* Tb[MT];
-    const T* Hb[MT];
-#pragma unroll
-    for (int u = 0; u < MT; ++u) {
-      const int tsel = ocs[u] == (ic == 1) ? 0 : (ic == 1 ? 1 : 2);
-      const int hsel = ic == 0 ? (ocs[u] ? 4 : 3) : (ocs[u] ? 5 : 4);
-      Tb[u] = tab + tsel * K2 + toff[u];
-      Hb[u] = tab + hsel * K2 + hoff[u];
+    for (int v = 0; v < 2; ++v) {
+      const int e = tid + 256 * v;
+      if (e < 2 * S) abs_[e] = ap[v];
     }
-    const T* grow = gs + (ic * LP + kk) * GW + l16;
+    __syncthreads();
+    for (int e = tid; e < K2; e += blockDim.x) {
+      // a_x, b_x for x >= 0 (zero past the stored 0..S-1); b is odd in x
+      const int q = e - LP;
+      const int aq = q < 0 ? -q : q;
+      const int q1 = q + 1, q2 = q - 1;
+      const int a1 = q1 < 0 ? -q1 : q1, a2 = q2 < 0 ? -q2 : q2;
+      const T bq1 = a1 < S ? abs_[S + a1] : T(0);
+      const T bq2 = a2 < S ? abs_[S + a2] : T(0);
+      tab[e] = aq < S ? abs_[aq] : T(0);                         // T cc, ss:  a_|q|
+      tab[K2 + e] = q1 >= 0 ? bq1 : -bq1;                        // T cs:  b_{q+1}
+      tab[2 * K2 + e] = q2 >= 0 ? -bq2 : bq2;                    // T sc: -b_{q-1}
+      tab[3 * K2 + e] = e < S ? abs_[e] : T(0);                  // H cc:  a_h
+      tab[4 * K2 + e] = e + 1 < S ? abs_[S + e + 1] : T(0);      // H cs, sc: b_{h+1}
+      tab[5 * K2 + e] = e + 2 < S ? -abs_[e + 2] : T(0);         // H ss: -a_{h+2}
+    }
+    if (row + gridDim.x < n_rows) fetch(row + gridDim.x);     // next row, in flight
+    __syncthreads();
+    acc_t acc[MT][PS_NT];
 #pragma unroll
-    for (int k0 = 0; k0 < LP; k0 += 4) {
-      T b[PS_NT];
+    for (int u = 0; u < MT; ++u)
 #pragma unroll
-      for (int nt = 0; nt < PS_NT; ++nt) b[nt] = grow[k0 * GW + nt * 16];
+      for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+#pragma unroll
+    for (int ic = 0; ic < 2; ++ic) {
+      const T* Tb[MT];
+      const T* Hb[MT];
 #pragma unroll
       for (int u = 0; u < MT; ++u) {
-        const T a = Tb[u][k0] + Hb[u][k0];
+        const int tsel = ocs[u] == (ic == 1) ? 0 : (ic == 1 ? 1 : 2);
+        const int hsel = ic == 0 ? (ocs[u] ? 4 : 3) : (ocs[u] ? 5 : 4);
+        Tb[u] = tab + tsel * K2 + toff[u];
+        Hb[u] = tab + hsel * K2 + hoff[u];
+      }
+      const T* grow = gs + (ic * LP + kk) * GW + l16;
 #pragma unroll
-        for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      for (int k0 = 0; k0 < LP; k0 += 4) {
+        T b[PS_NT];
+#pragma unroll
+        for (int nt = 0; nt < PS_NT; ++nt) b[nt] = grow[k0 * GW + nt * 16];
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+          const T a = Tb[u][k0] + Hb[u][k0];
+#pragma unroll
+          for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+        }
       }
     }
-  }
-  // inputs came from the LDS copy: write gh in place
+    // inputs came from the LDS copy: write gh in place
+    T* gr = g + row * rstride + i0;
 #pragma unroll
-  for (int u = 0; u < MT; ++u) {
-    const int mt = wave + 4 * u;
-    if (mt >= NMT) break;
+    for (int u = 0; u < MT; ++u) {
+      const int mt = wave + 4 * u;
+      if (mt >= NMT) break;
 #pragma unroll
-    for (int nt = 0; nt < PS_NT; ++nt) {
-      if (nt >= nt_valid) break;
+      for (int nt = 0; nt < PS_NT; ++nt) {
+        if (nt >= nt_valid) break;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = mt * 16 + MF<T>::row(lane, v);
-        const bool sn = row >= LP;
-        const int rl = sn ? row - LP : row;
-        if (sn ? rl < L - 1 : rl < L)
-          gr[static_cast<int64_t>(sn ? L + rl : rl) * D.kp + nt * 16 + l16] = acc[u][nt][v];
+        for (int v = 0; v < 4; ++v) {
+          const int rrow = mt * 16 + MF<T>::row(lane, v);
+          const bool sn = rrow >= LP;
+          const int rl = sn ? rrow - LP : rrow;
+          if (sn ? rl < L - 1 : rl < L)
+            gr[static_cast<int64_t>(sn ? L + rl : rl) * D.kp + nt * 16 + l16] = acc[u][nt][v];
+        }
       }
     }
+    __syncthreads();   // LDS is refilled for the next row
   }
 }
 
@@ -425,15 +458,20 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
 template <typename T>
 void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
-  dim3 grid(b.n_r * b.n_theta, (kp + 16 * PS_NT - 1) / (16 * PS_NT));
-  const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
+  // persistent workgroups: each walks (r, theta_j) rows with a stride of the
+  // grid, prefetching the next row while the current one runs on MFMA
+  const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
+  const int ncg = (kp + 16 * PS_NT - 1) / (16 * PS_NT);
+  const int64_t want = std::max<int64_t>(1, kPhiWorkgroups / ncg);
+  dim3 grid(static_cast<unsigned>(std::min(n_rows, want)), ncg);
+  const size_t lds = (8 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
   switch (D.L16) {   // L <= 96 (checked at basis creation)
-    case 16: k_phi_stage<T, 16><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
-    case 32: k_phi_stage<T, 32><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
-    case 48: k_phi_stage<T, 48><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
-    case 64: k_phi_stage<T, 64><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
-    case 80: k_phi_stage<T, 80><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
-    default: k_phi_stage<T, 96><<<grid, 256, lds, s>>>(gbuf, ab, D); break;
+    case 16: k_phi_stage<T, 16><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    case 32: k_phi_stage<T, 32><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    case 48: k_phi_stage<T, 48><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    case 64: k_phi_stage<T, 64><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    case 80: k_phi_stage<T, 80><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    default: k_phi_stage<T, 96><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
   }
 }
 
