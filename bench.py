@@ -102,8 +102,7 @@ def pmc_run():
     ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
     rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
     b = H.lanczos_bound(torch.from_numpy(si.lanczos_start(B.d)).cuda(), work)
-    H.rayleigh_ritz(X, ev, rs, work)
-    theta = ev.cpu().numpy()
+    theta = H.rayleigh_ritz(X, ev, rs, work)
     for _ in range(2):
         H.cheb_filter(X, w.degree, theta[-1], b, theta[0], ces.CES_PREC_MIXED, work)
     src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -191,14 +190,12 @@ def main():
 
     # ---- timed CheFSI steps (mixed filter + FP64 RR)
     X = X0.clone()
-    H.rayleigh_ritz(X, ev, rs, work)
-    theta = ev.cpu().numpy()
+    theta = H.rayleigh_ritz(X, ev, rs, work)
 
     def step():
         nonlocal theta
         H.cheb_filter(X, w.degree, theta[-1], b, theta[0], MIXED, work)
-        H.rayleigh_ritz(X, ev, rs, work)          # synchronises
-        theta = ev.cpu().numpy()
+        theta = H.rayleigh_ritz(X, ev, rs, work)  # synchronises; eigenvalues on the host
 
     for _ in range(args.warmup):
         step()

@@ -137,7 +137,8 @@ ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degre
 /* Cholesky-QR with column scaling (Section 3.1.1, 3.2), then Rayleigh-Ritz
  * (Section 3.2), all FP64: Q = X D R^{-1}; theta, S = eig(Q^T H Q) ascending;
  * X <- Q S; HX <- (H Q) S; r_i = ||H x_i - theta_i x_i||.  d_HX (d x k, ld =
- * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles.  hx_prec selects
+ * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles; h_eval[k] (host,
+ * may be NULL) receives a copy of the eigenvalues.  hx_prec selects
  * the precision of the H*Q product.  If the scaled Gram matrix is not
  * positive definite, one shifted Cholesky-QR pass followed by two plain passes
  * (shifted CholeskyQR3) orthonormalises X; CES_ERR_NOT_POSITIVE_DEFINITE if
@@ -146,7 +147,7 @@ ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degre
  * by rocSOLVER syevd above; CES_ERR_EIGENSOLVER if it does not converge.
  * Synchronises `stream`. */
 ces_status ces_rayleigh_ritz(ces_ham h, int k, double* d_X, int64_t ldx, double* d_HX,
-                             double* d_eval, double* d_resnorm, int hx_prec,
+                             double* d_eval, double* d_resnorm, double* h_eval, int hx_prec,
                              void* d_work, size_t work_bytes, void* stream);
 
 /* Upper bound of the spectrum of H: `steps` Lanczos steps from the start

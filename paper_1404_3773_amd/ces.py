@@ -67,7 +67,7 @@ def load() -> ctypes.CDLL:
         "ces_workspace_size": [P, I, I, ctypes.POINTER(SZ)],
         "ces_apply_H": [P, I, P, I64, P, I64, I, P, SZ, P],
         "ces_cheb_filter": [P, I, P, I64, I, D, D, D, I, P, SZ, P],
-        "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, I, P, SZ, P],
+        "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, P, I, P, SZ, P],
         "ces_lanczos_bound": [P, P, I, ctypes.POINTER(D), P, SZ, P],
         "ces_chefsi": [P, I, P, I64, I, D, I, I, I, D, D, I, P, P, ctypes.POINTER(I), P, SZ, P],
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
@@ -367,9 +367,14 @@ class Ham:
                                       work.numel(), _stream(stream)), "ces_cheb_filter")
 
     def rayleigh_ritz(self, X, evals, res, work, HX=None, hx_prec=CES_PREC_FP64, stream=None):
+        """Returns the eigenvalues as a host array (copied in the call's own
+        synchronisation); evals / res receive them on the device."""
+        h = np.zeros(X.shape[0])
         _check(load().ces_rayleigh_ritz(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(HX),
-                                        _ptr(evals), _ptr(res), int(hx_prec), _ptr(work),
-                                        work.numel(), _stream(stream)), "ces_rayleigh_ritz")
+                                        _ptr(evals), _ptr(res), h.ctypes.data_as(ctypes.c_void_p),
+                                        int(hx_prec), _ptr(work), work.numel(), _stream(stream)),
+               "ces_rayleigh_ritz")
+        return h
 
     def lanczos_bound(self, v0, work, steps=20, stream=None) -> float:
         out = ctypes.c_double()

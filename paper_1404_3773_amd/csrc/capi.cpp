@@ -490,8 +490,11 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& bb) 
   return hi;
 }
 
+// h_eval / h_res (host, may be null) receive the eigenvalues / residual norms
+// in the same synchronisation that checks the factorisation.
 ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx, double* HX,
-                   int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s) {
+                   int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s,
+                   double* h_eval = nullptr, double* h_res = nullptr) {
   const Basis& b = *h.basis;
   const int64_t d = b.d;
   double* S1 = Ptr<double>::at(work, ly.S1);
@@ -499,102 +502,122 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   double* dinv = vec;
   double* evals = vec + k;
   double* Ework = vec + 2 * k;
+  // info[0]: factorisation, info[1]: triangular inverse, info[2]: eigensolver
   rocblas_int* info = Ptr<rocblas_int>::at(work, ly.info);
   double* B1 = Ptr<double>::at(work, ly.B1);
+  double* T2 = Ptr<double>::at(work, ly.B2);
   CES_BLAS(rocblas_set_stream(h.blas, s));
   CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
   const double one = 1.0, zero = 0.0;
-  // One Cholesky-QR pass in place: S = X^T X, D = diag(S)^{-1/2}, R^T R = D S D
-  // (+ shift I), X <- X D R^{-1}.  Column scaling before factorising follows
-  // Section 3.1.1.  *ok reports whether the factorisation succeeded (X is
-  // left untouched otherwise).
   double* part = Ptr<double>::at(work, ly.part);
   const int64_t part_cap = int64_t(gram_chunks(d, k)) * k * k;   // doubles in the region
-  auto pass = [&](double shift, bool* ok) -> ces_status {
+  const bool small = k <= kJacobiMax;
+  CES_HIP(hipMemsetAsync(info, 0, 4 * sizeof(rocblas_int), s));
+  // One Cholesky-QR pass: S = X^T X, D = diag(S)^{-1/2}, R^T R = D S D (+ shift I),
+  // X <- X D R^{-1} (column scaling before factorising follows Section 3.1.1).
+  // X is written only if the factorisation succeeded (checked on the device),
+  // so a failed pass leaves X as it was.
+  auto pass = [&](double shift) -> ces_status {
     launch_gram(X, ldx, X, ldx, S1, part, d, k, s);
     launch_symmetrize(S1, k, s);
     launch_scale_gram(S1, k, dinv, s);
     if (shift > 0) launch_add_diag(S1, k, shift, s);
-    CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
-    rocblas_int hi = 0;
-    CES_HIP(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
-    CES_HIP(hipStreamSynchronize(s));
-    *ok = (hi == 0);
-    if (!*ok) return CES_OK;
-    // X <- (X D) R^{-1}: invert the k x k factor, then one GEMM through B2
-    launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
-    CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1, k,
-                              info));
-    launch_scale_cols(X, ldx, d, k, dinv, s);
-    double* T2 = Ptr<double>::at(work, ly.B2);
+    if (small) {
+      launch_chol_inv(S1, k, dinv, info, s);            // S1 <- D R^{-1}
+    } else {
+      CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+      launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
+      CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1,
+                                k, info + 1));
+      launch_scale_rows_k(S1, k, dinv, s);              // S1 <- D R^{-1}
+    }
     CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
                            static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
                            T2, static_cast<int>(d)));
-    launch_copy2d(T2, d, X, ldx, d, k, s);
+    launch_copy2d_if(T2, d, X, ldx, d, k, info, s);
     return CES_OK;
   };
-  bool ok = false;
-  CES_TRY(pass(0.0, &ok));
-  if (!ok) {
-    // Shifted Cholesky-QR (shift ~ 11 (d k + k(k+1)) u ||D S D||), then two
-    // plain passes restore orthonormality (shifted CholeskyQR3).
+  auto read_info = [&](rocblas_int* h3) -> ces_status {
+    CES_HIP(hipMemcpyAsync(h3, info, 3 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    CES_HIP(hipStreamSynchronize(s));
+    return CES_OK;
+  };
+  // Rayleigh-Ritz on the (orthonormal) block; X and HX are written only if
+  // the Cholesky-QR before it succeeded.
+  auto rayleigh = [&]() -> ces_status {
+    double* HQ = HX ? HX : B1;
+    const int64_t ldhq = HX ? ldhx : d;
+    if (hx_prec == CES_PREC_FP64) {
+      CES_TRY(h_step<double>(h, ly, work, k, X, ldx, nullptr, 0, HQ, ldhq, 1.0, 0.0, 0.0, s));
+    } else {
+      float* F0 = Ptr<float>::at(work, ly.F0);
+      float* F1 = Ptr<float>::at(work, ly.F1);
+      launch_convert<double, float>(X, ldx, F0, d, d, k, s);
+      CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
+      launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
+    }
+    // Hs = Q^T H Q, eigen-decomposition (ascending)
+    launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s);
+    launch_symmetrize(S1, k, s);
+    if (small)   // one-workgroup Jacobi
+      launch_jacobi_eig(S1, k, evals, info + 2, s);
+    else
+      CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k,
+                                evals, Ework, info + 2));
+    // X <- Q S ; HX <- HQ S  (through B1 when HX is given, else B1 holds HQ)
+    if (HX) {
+      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                             static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k,
+                             &zero, B1, static_cast<int>(d)));
+      launch_copy2d_if(B1, d, X, ldx, d, k, info, s);
+      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                             static_cast<int>(d), k, k, &one, HX, static_cast<int>(ldhx), S1, k,
+                             &zero, B1, static_cast<int>(d)));
+      launch_copy2d_if(B1, d, HX, ldhx, d, k, info, s);
+      launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, part, part_cap, s);
+    } else {
+      // B1 holds HQ; rotate X through B2, then HQ S into B2 for the residuals
+      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                             static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k,
+                             &zero, T2, static_cast<int>(d)));
+      launch_copy2d_if(T2, d, X, ldx, d, k, info, s);
+      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
+                             static_cast<int>(d), k, k, &one, B1, static_cast<int>(d), S1, k,
+                             &zero, T2, static_cast<int>(d)));
+      launch_residuals(T2, d, X, ldx, evals, res, d, k, part, part_cap, s);
+    }
+    CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CES_OK;
+  };
+  auto finish = [&](rocblas_int* h3) -> ces_status {
+    if (h_eval) CES_HIP(hipMemcpyAsync(h_eval, evals, size_t(k) * 8, hipMemcpyDeviceToHost, s));
+    if (h_res) CES_HIP(hipMemcpyAsync(h_res, res, size_t(k) * 8, hipMemcpyDeviceToHost, s));
+    return read_info(h3);
+  };
+  CES_TRY(pass(0.0));
+  CES_TRY(rayleigh());
+  rocblas_int h3[3] = {0, 0, 0};
+  CES_TRY(finish(h3));
+  if (h3[0] != 0 || h3[1] != 0) {
+    // The plain pass failed and X is unchanged: shifted Cholesky-QR (shift ~
+    // 11 (d k + k(k+1)) u ||D S D||), then two plain passes restore
+    // orthonormality (shifted CholeskyQR3); then Rayleigh-Ritz again.
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * (double(d) * k + double(k) * (k + 1)) * u * k;
-    CES_TRY(pass(shift, &ok));
-    if (!ok) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "shifted Cholesky-QR failed");
+    CES_HIP(hipMemsetAsync(info, 0, 4 * sizeof(rocblas_int), s));
+    CES_TRY(pass(shift));
+    CES_TRY(read_info(h3));
+    if (h3[0] != 0 || h3[1] != 0) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "shifted Cholesky-QR failed");
     for (int rep = 0; rep < 2; ++rep) {
-      CES_TRY(pass(0.0, &ok));
-      if (!ok) return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky-QR after the shifted pass failed");
+      CES_TRY(pass(0.0));
+      CES_TRY(read_info(h3));
+      if (h3[0] != 0 || h3[1] != 0)
+        return fail(CES_ERR_NOT_POSITIVE_DEFINITE, "Cholesky-QR after the shifted pass failed");
     }
+    CES_TRY(rayleigh());
+    CES_TRY(finish(h3));
   }
-  rocblas_int hinfo = 0;
-  // HQ
-  double* HQ = HX ? HX : B1;
-  const int64_t ldhq = HX ? ldhx : d;
-  if (hx_prec == CES_PREC_FP64) {
-    CES_TRY(h_step<double>(h, ly, work, k, X, ldx, nullptr, 0, HQ, ldhq, 1.0, 0.0, 0.0, s));
-  } else {
-    float* F0 = Ptr<float>::at(work, ly.F0);
-    float* F1 = Ptr<float>::at(work, ly.F1);
-    launch_convert<double, float>(X, ldx, F0, d, d, k, s);
-    CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
-    launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
-  }
-  // Hs = Q^T H Q, eigen-decomposition (ascending)
-  launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s);
-  launch_symmetrize(S1, k, s);
-  if (k <= kJacobiMax)   // small blocks: one-workgroup Jacobi (no host round trips)
-    launch_jacobi_eig(S1, k, evals, info, s);
-  else
-    CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k, evals,
-                              Ework, info));
-  // X <- Q S ; HX <- HQ S  (through B1 when HX is given, else B1 holds HQ)
-  if (HX) {
-    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                           static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
-                           B1, static_cast<int>(d)));
-    launch_copy2d(B1, d, X, ldx, d, k, s);
-    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                           static_cast<int>(d), k, k, &one, HX, static_cast<int>(ldhx), S1, k,
-                           &zero, B1, static_cast<int>(d)));
-    launch_copy2d(B1, d, HX, ldhx, d, k, s);
-    launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, part, part_cap, s);
-  } else {
-    // B1 holds HQ; rotate X through B2, then HQ S into B2 for the residuals
-    double* T2 = Ptr<double>::at(work, ly.B2);
-    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                           static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
-                           T2, static_cast<int>(d)));
-    launch_copy2d(T2, d, X, ldx, d, k, s);
-    CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                           static_cast<int>(d), k, k, &one, B1, static_cast<int>(d), S1, k, &zero,
-                           T2, static_cast<int>(d)));
-    launch_residuals(T2, d, X, ldx, evals, res, d, k, part, part_cap, s);
-  }
-  CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  CES_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  CES_HIP(hipStreamSynchronize(s));
-  if (hinfo != 0) return fail(CES_ERR_EIGENSOLVER, "projected eigenproblem did not converge");
+  if (h3[2] != 0) return fail(CES_ERR_EIGENSOLVER, "projected eigenproblem did not converge");
   return CES_OK;
 }
 
@@ -870,8 +893,8 @@ ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degr
 }
 
 ces_status ces_rayleigh_ritz(ces_ham hh, int k, double* d_X, int64_t ldx, double* d_HX,
-                             double* d_eval, double* d_resnorm, int hx_prec, void* d_work,
-                             size_t work_bytes, void* stream) {
+                             double* d_eval, double* d_resnorm, double* h_eval, int hx_prec,
+                             void* d_work, size_t work_bytes, void* stream) {
   CES_TRY(check_ham(hh));
   Ham& h = hh->h;
   CES_TRY(check_block(h, k, d_X, ldx, "X"));
@@ -880,7 +903,7 @@ ces_status ces_rayleigh_ritz(ces_ham hh, int k, double* d_X, int64_t ldx, double
   Layout ly;
   CES_TRY(check_work(h, k, hx_prec, d_work, work_bytes, ly));
   return rr_impl(h, ly, d_work, k, d_X, ldx, d_HX, ldx, d_eval, d_resnorm, hx_prec,
-                 static_cast<hipStream_t>(stream));
+                 static_cast<hipStream_t>(stream), h_eval);
 }
 
 ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* h_bound,
@@ -949,8 +972,8 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t d = h.basis->d;
   std::vector<double> theta(k), theta_old(k), res(k);
-  CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s));
-  CES_HIP(hipMemcpy(theta.data(), d_eval, size_t(k) * 8, hipMemcpyDeviceToHost));
+  CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s,
+                  theta.data(), res.data()));
   int it = 0;
   while (true) {
     ++it;
@@ -973,9 +996,8 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
       launch_convert<float, double>(out, ldr, d_X, ldx, d, k, s);
     }
     theta_old = theta;
-    CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s));
-    CES_HIP(hipMemcpy(theta.data(), d_eval, size_t(k) * 8, hipMemcpyDeviceToHost));
-    CES_HIP(hipMemcpy(res.data(), d_resnorm, size_t(k) * 8, hipMemcpyDeviceToHost));
+    CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s,
+                    theta.data(), res.data()));
     if (fixed_iter > 0) {
       if (it >= fixed_iter) break;
       continue;

@@ -206,6 +206,14 @@ void launch_cluster_quad_loss(int n_clusters, const int64_t* row_off, const int6
 // ascending in evals; *info = 0 on convergence.
 constexpr int kJacobiMax = 60;
 void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s);
+// S (SPD, k <= kJacobiMax, column-major) <- D R^{-1}, S = R^T R, D = diag(dinv);
+// *info = 0 or the 1-based index of the first non-positive pivot.
+void launch_chol_inv(double* S, int k, const double* dinv, int* info, hipStream_t s);
+// S(i, j) *= dinv[i], k x k column-major.
+void launch_scale_rows_k(double* S, int k, const double* dinv, hipStream_t s);
+// dst <- src unless flags[0] or flags[1] is nonzero (checked on the device).
+void launch_copy2d_if(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                      int cols, const int* flags, hipStream_t s);
 
 // Small FP64 helpers for Cholesky-QR / Rayleigh-Ritz / Lanczos.
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s);

@@ -408,6 +408,75 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ S, int
   if (tid == 0) *info = converged ? 0 : 1;
 }
 
+// Cholesky factor and scaled inverse of a small SPD matrix (k <= kJacobiMax)
+// in one workgroup: S = R^T R (R upper), then W = D R^{-1} with D = diag(dinv)
+// written over S (column-major, zero below the diagonal), so that
+// X D R^{-1} = X W.  *info = 0, or j + 1 if the j-th pivot is not positive.
+__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, int k,
+                                                   const double* __restrict__ dinv, int* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ld = k + 1;
+  double* A = reinterpret_cast<double*>(smem_raw);   // [k][ld], A[i*ld + j] = S(i, j)
+  double* W = A + k * ld;                             // [k][ld], W[c*ld + i] = R^{-1}(i, c)
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < k * k; e += nt) {
+    const int j = e / k, i = e - j * k;               // column-major source
+    A[i * ld + j] = S[e];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double dj = A[j * ld + j];
+      if (!(dj > 0.0) && bad == 0) bad = j + 1;
+      A[j * ld + j] = dj > 0.0 ? sqrt(dj) : 1.0;
+    }
+    __syncthreads();
+    const double rjj = A[j * ld + j];
+    for (int i = j + 1 + tid; i < k; i += nt) A[j * ld + i] /= rjj;       // row j of R
+    __syncthreads();
+    const int m = k - j - 1;                                               // trailing update
+    for (int e = tid; e < m * m; e += nt) {
+      const int a = j + 1 + e / m, c = j + 1 + e % m;
+      if (c >= a) A[a * ld + c] -= A[j * ld + a] * A[j * ld + c];
+    }
+    __syncthreads();
+  }
+  // W = R^{-1} by back substitution in LDS, one column per thread
+  for (int c = tid; c < k; c += nt) {
+    double* Wc = W + c * ld;
+    Wc[c] = 1.0 / A[c * ld + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += A[i * ld + l] * Wc[l];
+      Wc[i] = -acc / A[i * ld + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += nt) {          // S = D W, zero below the diagonal
+    const int c = e / k, i = e - c * k;
+    S[e] = i <= c ? dinv[i] * W[c * ld + i] : 0.0;
+  }
+  if (tid == 0) *info = bad;
+}
+
+// S(i, j) *= dinv[i] for a k x k column-major matrix
+__global__ void k_scale_rows_k(double* S, int k, const double* dinv) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < k * k; e += gridDim.x * blockDim.x)
+    S[e] *= dinv[e % k];
+}
+
+// dst = src where flags[0] == 0 and flags[1] == 0 (device-side guard)
+__global__ void k_copy2d_if(const double* src, int64_t lds, double* dst, int64_t ldd,
+                            int64_t rows, const int* flags) {
+  if (flags[0] != 0 || flags[1] != 0) return;
+  const int c = blockIdx.y;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[c * ldd + e] = src[c * lds + e];
+}
+
 inline int grid1d(int64_t n) {
   int64_t g = (n + 255) / 256;
   return static_cast<int>(g > 4096 ? 4096 : (g < 1 ? 1 : g));
@@ -497,6 +566,17 @@ void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s
   const int n = k + (k & 1);
   const size_t lds = (2 * size_t(n) * (n + 1) + n) * sizeof(double) + size_t(n) * sizeof(int);
   k_jacobi_eig<<<1, 1024, lds, s>>>(S, k, evals, info);
+}
+void launch_scale_rows_k(double* S, int k, const double* dinv, hipStream_t s) {
+  k_scale_rows_k<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k, dinv);
+}
+void launch_chol_inv(double* S, int k, const double* dinv, int* info, hipStream_t s) {
+  k_chol_inv<<<1, 1024, 2 * size_t(k) * (k + 1) * sizeof(double), s>>>(S, k, dinv, info);
+}
+void launch_copy2d_if(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                      int cols, const int* flags, hipStream_t s) {
+  dim3 grid(grid1d(rows), cols);
+  k_copy2d_if<<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows, flags);
 }
 void launch_dot(const double* x, const double* y, int64_t n, double* out, double* part,
                 hipStream_t s) {
