@@ -329,32 +329,36 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
     acc_t acc[LA_NT];
 #pragma unroll
     for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = zero_acc<acc_t>();
-    // steps whose four theta rows are all valid, by pointer increments
-    const int nfull = D.n_theta >> 2;
-    const T* pa = Pa + kk * D.L16;
-    const T* pb[LA_NT];
+    // theta in chunks of 16 rows (four MFMA k-steps); the next chunk's
+    // operands are loaded into registers while the current chunk runs.
+    // Rows past n_theta get zero weights (and read row n_theta - 1).
+    const int nch = (D.n_theta + 15) >> 4;
+    T ca[4], cb[4][LA_NT], na[4], nb[4][LA_NT];
+    auto load = [&](int chunk, T* a, T (*b)[LA_NT]) {
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) pb[nt] = gb + kk * jstride + col[nt];
-#pragma unroll 4
-    for (int t = 0; t < nfull; ++t) {
-      const T a = *pa;
-      T b[LA_NT];
+      for (int t = 0; t < 4; ++t) {
+        const int j = chunk * 16 + t * 4 + kk;
+        const bool ok = j < D.n_theta;
+        const int jc = ok ? j : D.n_theta - 1;
+        const T av = Pa[jc * D.L16];
+        a[t] = ok ? av : T(0);
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) b[nt] = *pb[nt];
+        for (int nt = 0; nt < LA_NT; ++nt) b[t][nt] = gb[jc * jstride + col[nt]];
+      }
+    };
+    load(0, ca, cb);
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load(c + 1, na, nb);
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = MF<T>::mma(a, b[nt], acc[nt]);
-      pa += 4 * D.L16;
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) pb[nt] += 4 * jstride;
-    }
-    if (D.n_theta & 3) {
-      // tail: weights of rows past n_theta are zero; read row n_theta - 1
-      const int j = 4 * nfull + kk;
-      const int jc = min(j, D.n_theta - 1);
-      const T a = Pa[j * D.L16];
+        for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = MF<T>::mma(ca[t], cb[t][nt], acc[nt]);
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt)
-        acc[nt] = MF<T>::mma(a, gb[jc * jstride + col[nt]], acc[nt]);
+      for (int t = 0; t < 4; ++t) {
+        ca[t] = na[t];
+#pragma unroll
+        for (int nt = 0; nt < LA_NT; ++nt) cb[t][nt] = nb[t][nt];
+      }
     }
 #pragma unroll
     for (int nt = 0; nt < LA_NT; ++nt) {
