@@ -26,17 +26,18 @@ __device__ __forceinline__ int isqrt_lm(int lm) {
 }
 
 constexpr int RI_NT = 2;   // 16-column tiles per workgroup (32 columns)
-constexpr int RI_MT = 4;   // M-tiles per wave: n_r <= 16 * 4 * 4 = 256
-constexpr int RF_MT = 3;   // M-tiles per wave: N <= 192
 
 // Padded tables (zeros outside the valid range):
 //   RiT [l][N4][R16]  R_ln(r_k) at [l][n][r];  N4 = N up to 4, R16 = n_r up to 16
 //   RfT [l][R4][N16]  w_k R_ln(r_k) at [l][r][n]; R4 = n_r up to 4, N16 = N up to 16
 __host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 
-// Workgroup: one (l, m), 32 columns; M = n_r split over the 4 waves.  The X
-// tile (all N rows x 32 columns) is staged in LDS; R comes from the table.
-template <typename T>
+// Workgroup: one (l, m), 32 columns; M = n_r split over the 4 waves (MT
+// 16-row tiles each; tiles past the last repeat it and are not stored).  The
+// X tile (N rows x 32 columns, zero-padded to a multiple of 16 rows) is staged
+// in LDS; the table operand is read in chunks of four k-steps, the next chunk
+// in flight while the current one runs.
+template <typename T, int MT>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
                                                              int64_t ldx, T* __restrict__ G,
@@ -45,8 +46,8 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
   typedef typename MF<T>::acc acc_t;
   constexpr int CW = 16 * RI_NT, XW = CW + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Xs = reinterpret_cast<T*>(smem_raw);  // [N4][XW]  X[n][i]
-  const int N4 = rup(N, 4), R16 = rup(n_r, 16);
+  T* Xs = reinterpret_cast<T*>(smem_raw);  // [N16][XW]  X[n][i]
+  const int N4 = rup(N, 4), N16 = rup(N, 16), R16 = rup(n_r, 16);
   const int lm = blockIdx.y;
   const int l = isqrt_lm(lm);
   const int i0 = blockIdx.x * CW;
@@ -55,37 +56,60 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
     const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
     const bool iok = i0 + ii < k;
     const T* xc = Xl + static_cast<int64_t>(i0 + ii) * ldx;
-    for (int n = n0; n < N4; n += 8) Xs[n * XW + ii] = (iok && n < N) ? xc[n] : T(0);
+    for (int n = n0; n < N16; n += 8) Xs[n * XW + ii] = (iok && n < N) ? xc[n] : T(0);
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
   const int nmt = R16 / 16;
-  const T* Ra = RiT + static_cast<int64_t>(l) * N4 * R16 + l16;
-  acc_t acc[RI_MT][RI_NT];
+  const T* Rl = RiT + static_cast<int64_t>(l) * N4 * R16 + l16;
+  int mrow[MT];
 #pragma unroll
-  for (int u = 0; u < RI_MT; ++u)
+  for (int u = 0; u < MT; ++u) mrow[u] = min(wave + 4 * u, nmt - 1) * 16;
+  acc_t acc[MT][RI_NT];
+#pragma unroll
+  for (int u = 0; u < MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-#pragma unroll 4
-  for (int k0 = 0; k0 < N4; k0 += 4) {
-    const int n = k0 + kk;
-    T b[RI_NT];
+  const int nch = N16 / 16;
+  T ca[4][MT], na[4][MT];
+  auto load = [&](int chunk, T (*a)[MT]) {
 #pragma unroll
-    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
+    for (int t = 0; t < 4; ++t) {
+      const int n = chunk * 16 + t * 4 + kk;
+      const bool ok = n < N4;                       // table rows N..N4-1 are zero
+      const int nc = ok ? n : N4 - 1;
 #pragma unroll
-    for (int u = 0; u < RI_MT; ++u) {
-      const int mt = wave + 4 * u;
-      if (mt >= nmt) break;
-      const T a = Ra[n * R16 + mt * 16];
-#pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      for (int u = 0; u < MT; ++u) {
+        const T v = Rl[static_cast<int64_t>(nc) * R16 + mrow[u]];
+        a[t][u] = ok ? v : T(0);
+      }
     }
+  };
+  load(0, ca);
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) load(c + 1, na);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int n = c * 16 + t * 4 + kk;
+      T b[RI_NT];
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
+#pragma unroll
+      for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(ca[t][u], b[nt], acc[u][nt]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
   }
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
   T* Gb = G + static_cast<int64_t>(lm) * kp + i0 + l16;
 #pragma unroll
-  for (int u = 0; u < RI_MT; ++u) {
+  for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
 #pragma unroll
@@ -100,9 +124,11 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
   }
 }
 
-// Workgroup: one (l, m), 32 columns; M = N split over the 4 waves; K = n_r,
-// then n_proj for the projector term.
-template <typename T>
+// Workgroup: one (l, m), 32 columns; M = N split over the 4 waves (MT tiles
+// each, repeated past the last and not stored); K = n_r in chunks of four
+// k-steps with the next chunk's operands in flight, then n_proj for the
+// projector term.
+template <typename T, int MT>
 __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
     const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
@@ -114,32 +140,59 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   const int lm = blockIdx.y;
   const int l = isqrt_lm(lm);
   const int i0 = blockIdx.x * (16 * RI_NT);
-  const int nt_valid = min(RI_NT, (kp - i0) / 16);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
   const int nmt = N16 / 16;
-  acc_t acc[RF_MT][RI_NT];
+  int mrow[MT];
 #pragma unroll
-  for (int u = 0; u < RF_MT; ++u)
+  for (int u = 0; u < MT; ++u) mrow[u] = min(wave + 4 * u, nmt - 1) * 16;
+  // column of each N-tile clamped into the block (tiles past kp are not stored)
+  int col[RI_NT];
+#pragma unroll
+  for (int nt = 0; nt < RI_NT; ++nt) col[nt] = min(nt * 16, kp - i0 - 16);
+  acc_t acc[MT][RI_NT];
+#pragma unroll
+  for (int u = 0; u < MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-  const T* Ra = RfT + static_cast<int64_t>(l) * R4 * N16 + l16;
+  const T* Rl = RfT + static_cast<int64_t>(l) * R4 * N16 + l16;
   const T* Ab = A + static_cast<int64_t>(lm) * kp + i0 + l16;
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
-#pragma unroll 4
-  for (int k0 = 0; k0 < R4; k0 += 4) {
-    const int r = k0 + kk;
-    const int64_t roff = min(r, n_r - 1) * rstride;   // padded table rows are zero
-    T b[RI_NT];
+  const int nch = (R4 + 15) / 16;
+  T ca[4][MT], cb[4][RI_NT], na[4][MT], nb[4][RI_NT];
+  auto load = [&](int chunk, T (*a)[MT], T (*b)[RI_NT]) {
 #pragma unroll
-    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = (nt < nt_valid) ? Ab[roff + nt * 16] : T(0);
+    for (int t = 0; t < 4; ++t) {
+      const int r = chunk * 16 + t * 4 + kk;
+      const bool ok = r < R4;                       // table rows n_r..R4-1 are zero
+      const int rt = ok ? r : R4 - 1;
+      const int64_t roff = static_cast<int64_t>(min(r, n_r - 1)) * rstride;
 #pragma unroll
-    for (int u = 0; u < RF_MT; ++u) {
-      const int mt = wave + 4 * u;
-      if (mt >= nmt) break;
-      const T a = Ra[r * N16 + mt * 16];
+      for (int u = 0; u < MT; ++u) {
+        const T v = Rl[static_cast<int64_t>(rt) * N16 + mrow[u]];
+        a[t][u] = ok ? v : T(0);
+      }
 #pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+      for (int nt = 0; nt < RI_NT; ++nt) b[t][nt] = Ab[roff + col[nt]];
+    }
+  };
+  load(0, ca, cb);
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) load(c + 1, na, nb);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int nt = 0; nt < RI_NT; ++nt)
+          acc[u][nt] = MF<T>::mma(ca[t][u], cb[t][nt], acc[u][nt]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) cb[t][nt] = nb[t][nt];
     }
   }
   if (n_proj > 0) {
@@ -150,13 +203,10 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
       const int qc = min(q, n_proj - 1);
       T b[RI_NT];
 #pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt)
-        b[nt] = (nt < nt_valid) ? Cb[static_cast<int64_t>(qc) * kp + nt * 16] : T(0);
+      for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Cb[static_cast<int64_t>(qc) * kp + col[nt]];
 #pragma unroll
-      for (int u = 0; u < RF_MT; ++u) {
-        const int mt = wave + 4 * u;
-        if (mt >= nmt) break;
-        const int n = mt * 16 + l16;
+      for (int u = 0; u < MT; ++u) {
+        const int n = mrow[u] + l16;
         const T pv = Pl[static_cast<int64_t>(qc) * d + min(n, N - 1)];   // in-bounds address
         const T a = (q < n_proj && n < N) ? pv : T(0);
 #pragma unroll
@@ -165,7 +215,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     }
   }
 #pragma unroll
-  for (int u = 0; u < RF_MT; ++u) {
+  for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
 #pragma unroll
@@ -196,8 +246,14 @@ template <typename T>
 void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
                            T* G, int k, int kp, hipStream_t s) {
   dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
-  const size_t lds = size_t(rup(b.N, 4)) * (16 * RI_NT + 1) * sizeof(T);
-  k_radial_inverse_mfma<T><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp);
+  const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 1) * sizeof(T);
+  const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
+  switch (mt) {
+    case 1: k_radial_inverse_mfma<T, 1><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 2: k_radial_inverse_mfma<T, 2><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 3: k_radial_inverse_mfma<T, 3><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    default: k_radial_inverse_mfma<T, 4><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+  }
 }
 
 template <typename T>
@@ -206,10 +262,21 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                            T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
                            const T* kbC, int k, int kp, hipStream_t s) {
   dim3 grid((k + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
-  k_radial_forward_mfma<T><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+  const int mt = (rup(b.N, 16) / 16 + 3) / 4;   // N <= 192: at most 3 tiles per wave
+  switch (mt) {
+    case 1: k_radial_forward_mfma<T, 1><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
                                                 ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
                                                 kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
-                                                kp);
+                                                kp); break;
+    case 2: k_radial_forward_mfma<T, 2><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
+                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
+                                                kp); break;
+    default: k_radial_forward_mfma<T, 3><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
+                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
+                                                kp); break;
+  }
 }
 
 #define CES_INST(T)                                                                           \
