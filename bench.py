@@ -113,6 +113,48 @@ def pmc_run():
     print(f"[bench] pmc run done: 32 H*X, 3 copies of {PMC_COPY_BYTES} bytes", flush=True)
 
 
+def large_workload_rates(ces, torch, reps=5):
+    """H*X on the 147-atom workload (L_max = 60, N = 120, 180 x 122 x 244 grid,
+    k = 400) in mixed and FP64: algorithmic TFLOP/s per H*X and per stage, and
+    each stage's fraction of the FP32 / FP64 peak."""
+    w = si.C3
+    B = ces.Basis.for_workload(w)
+    r, wr, th, wt, ph = B.grid()
+    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
+    F = algorithmic_flops(w, w.k)["total"]
+    sf = stage_flops(w, w.k)
+    out = {"workload": w.name, "d": w.d, "orbitals": w.k, "alg_flop_per_HX": F}
+    for name, prec, peak in (("mixed", ces.CES_PREC_MIXED, PEAK_FP32),
+                             ("fp64", ces.CES_PREC_FP64, PEAK_FP64)):
+        work = H.workspace(w.k, prec)
+        X = torch.from_numpy(np.ascontiguousarray(si.random_block(B.d, w.k, 3).T)).cuda()
+        Y = torch.empty_like(X)
+        H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        ces.profile_enable(True, 4096)
+        t = time.perf_counter()
+        for _ in range(reps):
+            H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        prof = ces.profile_read()
+        ces.profile_enable(False)
+        suffix = "_fp32" if name == "mixed" else "_fp64"
+        stages = {}
+        for st, (ms, c) in prof.items():
+            if c and st.endswith(suffix) and sf[st[:-5]] > 0:
+                rate = sf[st[:-5]] / (ms / c * 1e-3)
+                stages[st[:-5]] = {"ms": round(ms / c, 4), "tflops": round(rate / 1e12, 2),
+                                   "frac_peak": round(rate / peak, 4)}
+        out[name] = {"ms_per_HX": round(sec * 1e3, 4), "tflops": round(F / sec / 1e12, 3),
+                     "stages": stages}
+        del work, X, Y
+        torch.cuda.empty_cache()
+    print(f"[bench] 147-atom H*X: mixed {out['mixed']['ms_per_HX']} ms, "
+          f"fp64 {out['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def golden_eigenvalues(w):
     path = os.path.join(ROOT, "tests", "golden", f"{w.name}_eigenvalues.txt")
     if not os.path.exists(path):
@@ -156,6 +198,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 147-atom H*X rates")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes (no JSON line)")
     args = ap.parse_args()
@@ -294,6 +338,10 @@ def main():
         "transform_gemm_frac_fp32_mfma": gemm_frac,
         "roofline": roof,
     }
+    if not args.no_large:
+        del work
+        torch.cuda.empty_cache()
+        line["large_workload"] = large_workload_rates(ces, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
