@@ -86,3 +86,24 @@ def test_atom_descriptors_match_oracle():
         _, rdirs = om.environment(atoms)
         assert np.max(np.abs(desc - ref) / np.maximum(1.0, np.abs(ref))) < 1e-6
         assert np.max(np.abs(dirs - rdirs)) < 1e-12
+
+
+def test_scf_and_learned_calls_validate_on_the_host():
+    # argument checks that run before any device work
+    lib = ces.load()
+    n = ctypes.c_size_t()
+    assert lib.ces_anderson_workspace_size(0, 1, ctypes.byref(n)) == 1
+    assert lib.ces_anderson_workspace_size(10, 65, ctypes.byref(n)) == 1
+    assert lib.ces_anderson_workspace_size(10, 3, ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.ces_anderson_mix(10, 0, None, None, 10, 0, 0.2, None, None, None, 0, None) == 1
+    assert lib.ces_anderson_mix(10, 2, None, None, 5, 0, 0.2, None, None, None, 0, None) == 1
+    assert lib.ces_hartree(None, None, None, None, 0, None) == 1
+    assert lib.ces_ks_potential(None, None, None, None, None, None, None, 0, None) == 1
+    assert lib.ces_scf_workspace_size(None, 4, 0, 20, ctypes.byref(n)) == 1
+    h = ctypes.c_void_p()
+    assert lib.ces_mlp_create(0, 256, 3, 8, 0, ctypes.byref(h)) == 1
+    assert lib.ces_mlp_create(24, 256, 65, 8, 0, ctypes.byref(h)) == 1
+    assert lib.ces_cluster_quad_loss(0, 1, None, None, None, None, None, None, None, None,
+                                     1.0, None) == 1
+    assert lib.ces_atom_descriptors(-1, None, None, None) == 1
+    assert lib.ces_atom_descriptors(0, None, None, None) == 0
