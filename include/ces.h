@@ -139,13 +139,14 @@ ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degre
  * X <- Q S; HX <- (H Q) S; r_i = ||H x_i - theta_i x_i||.  d_HX (d x k, ld =
  * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles; h_eval[k] (host,
  * may be NULL) receives a copy of the eigenvalues.  hx_prec selects
- * the precision of the H*Q product.  If the scaled Gram matrix is not
- * positive definite, one shifted Cholesky-QR pass followed by two plain passes
- * (shifted CholeskyQR3) orthonormalises X; CES_ERR_NOT_POSITIVE_DEFINITE if
- * the shifted pass fails too (X is then left scaled but not rotated).  The
- * k x k eigenproblem is solved by a one-workgroup Jacobi method for k <= 60,
- * by rocSOLVER syevd above; CES_ERR_EIGENSOLVER if it does not converge.
- * Synchronises `stream`. */
+ * the precision of the H*Q product.  If factorising the scaled Gram matrix
+ * meets a pivot not above 2 k eps (a numerically dependent column; for k > 60
+ * a non-positive pivot), X is left as it was and one shifted Cholesky-QR pass
+ * followed by two plain passes (shifted CholeskyQR3) orthonormalises it;
+ * CES_ERR_NOT_POSITIVE_DEFINITE if one of these passes fails too (X then holds
+ * the output of the last pass that succeeded).  The k x k eigenproblem is
+ * solved by a one-workgroup Jacobi method for k <= 60, by rocSOLVER syevd
+ * above; CES_ERR_EIGENSOLVER if it does not converge.  Synchronises `stream`. */
 ces_status ces_rayleigh_ritz(ces_ham h, int k, double* d_X, int64_t ldx, double* d_HX,
                              double* d_eval, double* d_resnorm, double* h_eval, int hx_prec,
                              void* d_work, size_t work_bytes, void* stream);

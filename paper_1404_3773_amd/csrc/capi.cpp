@@ -311,8 +311,9 @@ Layout layout_for(Ham& h, int k, int prec) {
     L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
   }
   L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * sizeof(double));
-  L.S1 = take(size_t(k) * k * sizeof(double));
-  L.S2 = take(size_t(k) * k * sizeof(double));
+  const size_t kk = std::max<size_t>(size_t(k) * k, size_t(small_ld(k)) * small_ld(k));
+  L.S1 = take(kk * sizeof(double));
+  L.S2 = take(kk * sizeof(double));
   L.vec = take(size_t(8) * std::max(k, 64) * sizeof(double));
   L.part = take(size_t(gram_chunks(b.d, k)) * k * k * sizeof(double));
   L.info = take(256);
@@ -518,19 +519,19 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   // X is written only if the factorisation succeeded (checked on the device),
   // so a failed pass leaves X as it was.
   auto pass = [&](double shift) -> ces_status {
-    launch_gram(X, ldx, X, ldx, S1, part, d, k, s);
-    launch_symmetrize(S1, k, s);
+    launch_gram(X, ldx, X, ldx, S1, part, d, k, s, true);
+    if (small) {
+      launch_chol_inv(S1, k, shift, dinv, info, s);     // S1 <- D R^{-1}
+      launch_block_apply(X, ldx, S1, k, d, info, s);     // X <- X D R^{-1}
+      return CES_OK;
+    }
     launch_scale_gram(S1, k, dinv, s);
     if (shift > 0) launch_add_diag(S1, k, shift, s);
-    if (small) {
-      launch_chol_inv(S1, k, dinv, info, s);            // S1 <- D R^{-1}
-    } else {
-      CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
-      launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
-      CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1,
-                                k, info + 1));
-      launch_scale_rows_k(S1, k, dinv, s);              // S1 <- D R^{-1}
-    }
+    CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+    launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
+    CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1, k,
+                              info + 1));
+    launch_scale_rows_k(S1, k, dinv, s);                // S1 <- D R^{-1}
     CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
                            static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k, &zero,
                            T2, static_cast<int>(d)));
@@ -557,34 +558,23 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
       launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
     }
     // Hs = Q^T H Q, eigen-decomposition (ascending)
-    launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s);
-    launch_symmetrize(S1, k, s);
-    if (small)   // one-workgroup Jacobi
+    launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s, true);
+    if (small) {   // one-workgroup Jacobi, then X <- Q S, HQ <- HQ S in place
       launch_jacobi_eig(S1, k, evals, info + 2, s);
-    else
+      launch_block_rotate(X, ldx, HQ, ldhq, S1, k, d, info, evals, res, part, part_cap, s);
+    } else {
       CES_BLAS(rocsolver_dsyevd(h.blas, rocblas_evect_original, rocblas_fill_upper, k, S1, k,
                                 evals, Ework, info + 2));
-    // X <- Q S ; HX <- HQ S  (through B1 when HX is given, else B1 holds HQ)
-    if (HX) {
-      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                             static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k,
-                             &zero, B1, static_cast<int>(d)));
-      launch_copy2d_if(B1, d, X, ldx, d, k, info, s);
-      CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                             static_cast<int>(d), k, k, &one, HX, static_cast<int>(ldhx), S1, k,
-                             &zero, B1, static_cast<int>(d)));
-      launch_copy2d_if(B1, d, HX, ldhx, d, k, info, s);
-      launch_residuals(HX, ldhx, X, ldx, evals, res, d, k, part, part_cap, s);
-    } else {
-      // B1 holds HQ; rotate X through B2, then HQ S into B2 for the residuals
+      // X <- Q S ; HQ <- HQ S through T2
       CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
                              static_cast<int>(d), k, k, &one, X, static_cast<int>(ldx), S1, k,
                              &zero, T2, static_cast<int>(d)));
       launch_copy2d_if(T2, d, X, ldx, d, k, info, s);
       CES_BLAS(rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none,
-                             static_cast<int>(d), k, k, &one, B1, static_cast<int>(d), S1, k,
+                             static_cast<int>(d), k, k, &one, HQ, static_cast<int>(ldhq), S1, k,
                              &zero, T2, static_cast<int>(d)));
-      launch_residuals(T2, d, X, ldx, evals, res, d, k, part, part_cap, s);
+      launch_copy2d_if(T2, d, HQ, ldhq, d, k, info, s);
+      launch_residuals(HQ, ldhq, X, ldx, evals, res, d, k, part, part_cap, s);
     }
     CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
     return CES_OK;

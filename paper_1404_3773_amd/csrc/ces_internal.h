@@ -139,11 +139,12 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
                               int kp, hipStream_t s);
 
 
-// C (k x k, column-major) = A^T B for d x k blocks, split over rows with
-// partial sums in `part` (gram_chunks(rows, k) * k * k doubles).
+// C (k x k, column-major, ld k) = A^T B for d x k blocks, or its symmetric
+// part (A^T B + B^T A) / 2 with sym, split over rows with partial sums in
+// `part` (gram_chunks(rows, k) * k * k doubles).
 int gram_chunks(int64_t rows, int k);
 void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                 double* part, int64_t rows, int k, hipStream_t s);
+                 double* part, int64_t rows, int k, hipStream_t s, bool sym = false);
 
 void launch_veff_fourier(const Basis& b, const double* V, double* ab64, float* ab32,
                          hipStream_t s);
@@ -201,14 +202,29 @@ void launch_cluster_quad_loss(int n_clusters, const int64_t* row_off, const int6
                               const float* M, const float* p, const float* t, const float* out,
                               float* gout, float* loss, float scale, int max_nq, hipStream_t s);
 
-// Eigenpairs of a symmetric k x k matrix (column-major, full) for k <=
-// kJacobiMax in one workgroup: eigenvectors overwrite S, eigenvalues
-// ascending in evals; *info = 0 on convergence.
+// Small blocks (k <= kJacobiMax): the k x k matrices that rotate a block are
+// written with leading dimension small_ld(k) = k rounded up to 16, zero
+// outside k x k (buffers hold small_ld(k)^2 doubles).
 constexpr int kJacobiMax = 60;
+int small_ld(int k);
+// Eigenpairs of a symmetric k x k matrix S (column-major, ld k) in one
+// workgroup: eigenvectors overwrite S (ld small_ld(k)), eigenvalues ascending
+// in evals; *info = 0 on convergence.
 void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s);
-// S (SPD, k <= kJacobiMax, column-major) <- D R^{-1}, S = R^T R, D = diag(dinv);
-// *info = 0 or the 1-based index of the first non-positive pivot.
-void launch_chol_inv(double* S, int k, const double* dinv, int* info, hipStream_t s);
+// From the Gram matrix S (ld k): D = diag(S)^{-1/2} into dinv, D S D + shift I
+// = R^T R, S <- D R^{-1} (ld small_ld(k), zero-padded); *info = 0 or the
+// 1-based index of the first pivot not above 2 k eps.
+void launch_chol_inv(double* S, int k, double shift, double* dinv, int* info, hipStream_t s);
+// X <- X W in place (W ld small_ld(k), zero-padded); rows are written only
+// where flags[0] and flags[1] are zero.
+void launch_block_apply(double* X, int64_t ldx, const double* W, int k, int64_t rows,
+                        const int* flags, hipStream_t s);
+// X <- X W and Y <- Y W in place (W dense, ld small_ld(k), zero-padded) and
+// res_j = || (Y W)_j - theta_j (X W)_j ||; X and Y are written only where
+// flags[0] and flags[1] are zero.
+void launch_block_rotate(double* X, int64_t ldx, double* Y, int64_t ldy, const double* W, int k,
+                         int64_t rows, const int* flags, const double* theta, double* res,
+                         double* part, int64_t part_cap, hipStream_t s);
 // S(i, j) *= dinv[i], k x k column-major.
 void launch_scale_rows_k(double* S, int k, const double* dinv, hipStream_t s);
 // dst <- src unless flags[0] or flags[1] is nonzero (checked on the device).

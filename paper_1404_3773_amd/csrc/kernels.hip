@@ -299,168 +299,6 @@ __global__ void k_scale_rows(T* C, int rows, int ld, const T* h) {
   for (int i = threadIdx.x; i < ld; i += blockDim.x) C[static_cast<int64_t>(q) * ld + i] *= h[q];
 }
 
-// Symmetric eigenproblem of a small k x k matrix (k <= kJacobiMax) in one
-// workgroup: parallel cyclic Jacobi.  Each round rotates n/2 disjoint pairs
-// (p, q) chosen by the round-robin (circle) schedule, n = k rounded up to
-// even, so that n - 1 rounds make a sweep over all pairs; each rotation is
-// the 2 x 2 symmetric Schur rotation zeroing A_pq (t = sign(th) / (|th| +
-// sqrt(th^2 + 1)), th = (A_qq - A_pp) / (2 A_pq), c = 1/sqrt(1 + t^2),
-// s = t c), applied as A <- J^T A J and V <- V J.  Sweeps stop when the
-// off-diagonal Frobenius norm is below 1e-14 of the whole; then eigenvalues
-// are sorted ascending (ties by index) with their columns of V.
-// S: k x k column-major in (full symmetric), eigenvectors out; info = 0 on
-// convergence within 40 sweeps, else 1.
-__device__ __forceinline__ int rr_player(int pos, int r, int n) {
-  return pos == 0 ? 0 : (pos - 1 + r) % (n - 1) + 1;
-}
-
-__global__ __launch_bounds__(1024) void k_jacobi_eig(double* __restrict__ S, int k,
-                                                    double* __restrict__ evals, int* info) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = k + (k & 1);
-  const int ld = n + 1;
-  double* A = reinterpret_cast<double*>(smem_raw);   // [n][ld]
-  double* V = A + n * ld;                             // [n][ld]
-  double* cs = V + n * ld;                            // [n/2][2]
-  int* pq = reinterpret_cast<int*>(cs + n);           // [n/2][2]
-  __shared__ double red[16];
-  __shared__ int done;
-  const int tid = threadIdx.x, nt = blockDim.x, half = n / 2;
-  for (int e = tid; e < n * n; e += nt) {
-    const int i = e / n, j = e - (e / n) * n;
-    A[i * ld + j] = (i < k && j < k) ? S[static_cast<int64_t>(j) * k + i] : 0.0;
-    V[i * ld + j] = i == j ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double f = 0.0;
-  for (int e = tid; e < n * n; e += nt) {
-    const double a = A[(e / n) * ld + e % n];
-    f += a * a;
-  }
-  const double fro2 = block_sum(f, red);
-  int converged = 0;
-  for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
-    for (int r = 0; r < n - 1; ++r) {
-      for (int pi = tid; pi < half; pi += nt) {
-        int p = rr_player(pi, r, n), q = rr_player(n - 1 - pi, r, n);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, sn = 0.0;
-        const double apq = A[p * ld + q];
-        if (q < k && apq != 0.0) {
-          const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          sn = t * c;
-        }
-        cs[2 * pi] = c;
-        cs[2 * pi + 1] = sn;
-        pq[2 * pi] = p;
-        pq[2 * pi + 1] = q;
-      }
-      __syncthreads();
-      for (int e = tid; e < half * n; e += nt) {          // rows p, q of J^T A
-        const int pi = e / n, j = e - pi * n;
-        const int p = pq[2 * pi], q = pq[2 * pi + 1];
-        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
-        const double a = A[p * ld + j], b = A[q * ld + j];
-        A[p * ld + j] = c * a - sn * b;
-        A[q * ld + j] = sn * a + c * b;
-      }
-      __syncthreads();
-      for (int e = tid; e < half * n; e += nt) {          // columns p, q of (.) J and V J
-        const int pi = e / n, i = e - pi * n;
-        const int p = pq[2 * pi], q = pq[2 * pi + 1];
-        const double c = cs[2 * pi], sn = cs[2 * pi + 1];
-        const double a = A[i * ld + p], b = A[i * ld + q];
-        A[i * ld + p] = c * a - sn * b;
-        A[i * ld + q] = sn * a + c * b;
-        const double va = V[i * ld + p], vb = V[i * ld + q];
-        V[i * ld + p] = c * va - sn * vb;
-        V[i * ld + q] = sn * va + c * vb;
-      }
-      __syncthreads();
-    }
-    double o = 0.0;
-    for (int e = tid; e < n * n; e += nt) {
-      const int i = e / n, j = e - (e / n) * n;
-      if (i != j) o += A[i * ld + j] * A[i * ld + j];
-    }
-    const double off = block_sum(o, red);
-    if (tid == 0) done = off <= 1e-28 * fro2 ? 1 : 0;
-    __syncthreads();
-    converged = done;
-    __syncthreads();
-  }
-  for (int i = tid; i < k; i += nt) {
-    const double lam = A[i * ld + i];
-    int rank = 0;
-    for (int j = 0; j < k; ++j) {
-      const double mu = A[j * ld + j];
-      rank += (mu < lam || (mu == lam && j < i)) ? 1 : 0;
-    }
-    evals[rank] = lam;
-    for (int rr = 0; rr < k; ++rr) S[static_cast<int64_t>(rank) * k + rr] = V[rr * ld + i];
-  }
-  if (tid == 0) *info = converged ? 0 : 1;
-}
-
-// Cholesky factor and scaled inverse of a small SPD matrix (k <= kJacobiMax)
-// in one workgroup: S = R^T R (R upper), then W = D R^{-1} with D = diag(dinv)
-// written over S (column-major, zero below the diagonal), so that
-// X D R^{-1} = X W.  *info = 0, or j + 1 if the j-th pivot is not positive.
-__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, int k,
-                                                   const double* __restrict__ dinv, int* info) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ld = k + 1;
-  double* A = reinterpret_cast<double*>(smem_raw);   // [k][ld], A[i*ld + j] = S(i, j)
-  double* W = A + k * ld;                             // [k][ld], W[c*ld + i] = R^{-1}(i, c)
-  __shared__ int bad;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < k * k; e += nt) {
-    const int j = e / k, i = e - j * k;               // column-major source
-    A[i * ld + j] = S[e];
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double dj = A[j * ld + j];
-      if (!(dj > 0.0) && bad == 0) bad = j + 1;
-      A[j * ld + j] = dj > 0.0 ? sqrt(dj) : 1.0;
-    }
-    __syncthreads();
-    const double rjj = A[j * ld + j];
-    for (int i = j + 1 + tid; i < k; i += nt) A[j * ld + i] /= rjj;       // row j of R
-    __syncthreads();
-    const int m = k - j - 1;                                               // trailing update
-    for (int e = tid; e < m * m; e += nt) {
-      const int a = j + 1 + e / m, c = j + 1 + e % m;
-      if (c >= a) A[a * ld + c] -= A[j * ld + a] * A[j * ld + c];
-    }
-    __syncthreads();
-  }
-  // W = R^{-1} by back substitution in LDS, one column per thread
-  for (int c = tid; c < k; c += nt) {
-    double* Wc = W + c * ld;
-    Wc[c] = 1.0 / A[c * ld + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += A[i * ld + l] * Wc[l];
-      Wc[i] = -acc / A[i * ld + i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < k * k; e += nt) {          // S = D W, zero below the diagonal
-    const int c = e / k, i = e - c * k;
-    S[e] = i <= c ? dinv[i] * W[c * ld + i] : 0.0;
-  }
-  if (tid == 0) *info = bad;
-}
-
 // S(i, j) *= dinv[i] for a k x k column-major matrix
 __global__ void k_scale_rows_k(double* S, int k, const double* dinv) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < k * k; e += gridDim.x * blockDim.x)
@@ -562,16 +400,8 @@ void launch_copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int
   dim3 grid(grid1d(rows), cols);
   k_copy2d<<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows);
 }
-void launch_jacobi_eig(double* S, int k, double* evals, int* info, hipStream_t s) {
-  const int n = k + (k & 1);
-  const size_t lds = (2 * size_t(n) * (n + 1) + n) * sizeof(double) + size_t(n) * sizeof(int);
-  k_jacobi_eig<<<1, 1024, lds, s>>>(S, k, evals, info);
-}
 void launch_scale_rows_k(double* S, int k, const double* dinv, hipStream_t s) {
   k_scale_rows_k<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k, dinv);
-}
-void launch_chol_inv(double* S, int k, const double* dinv, int* info, hipStream_t s) {
-  k_chol_inv<<<1, 1024, 2 * size_t(k) * (k + 1) * sizeof(double), s>>>(S, k, dinv, info);
 }
 void launch_copy2d_if(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                       int cols, const int* flags, hipStream_t s) {

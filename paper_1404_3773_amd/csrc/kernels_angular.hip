@@ -1,5 +1,4 @@
-// Angular stage of H*X on MFMA (gfx950), and the FP64 Gram product of
-// Cholesky-QR / Rayleigh-Ritz.
+// Angular stage of H*X on MFMA (gfx950).
 //
 // Per radial node r and orbital i the angular stage maps G(l,m) to A(l,m)
 // (eqs. G_lmr -> Ar_lm of Section 2.2.2 with V_eff between them).  It runs as
@@ -372,75 +371,6 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
   }
 }
 
-// ------------------------------------------------------------ FP64 Gram
-
-constexpr int GR_T = 64, GR_K = 16;
-
-// part[chunk][j][i] = sum over rows of this chunk of A[row][i] B[row][j]
-// (column-major A, B with leading dimensions lda, ldb); tiles of 64 x 64.
-__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Am, int64_t lda,
-                                                      const double* __restrict__ Bm, int64_t ldb,
-                                                      double* __restrict__ part, int64_t rows,
-                                                      int k, int64_t chunk) {
-  __shared__ double As[GR_K][GR_T + 1];
-  __shared__ double Bs[GR_K][GR_T + 1];
-  const int i0 = blockIdx.x * GR_T, j0 = blockIdx.y * GR_T;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.z) * chunk;
-  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int64_t q0 = r0; q0 < r1; q0 += GR_K) {
-    for (int e = tid; e < GR_K * GR_T; e += 256) {
-      const int kk = e % GR_K, cc = e / GR_K;
-      const int64_t row = q0 + kk;
-      As[kk][cc] = (row < r1 && i0 + cc < k) ? Am[static_cast<int64_t>(i0 + cc) * lda + row] : 0.0;
-      Bs[kk][cc] = (row < r1 && j0 + cc < k) ? Bm[static_cast<int64_t>(j0 + cc) * ldb + row] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GR_K; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-    }
-    __syncthreads();
-  }
-  double* P = part + static_cast<int64_t>(blockIdx.z) * k * k;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + tx + 16 * a;
-    if (i >= k) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + ty + 16 * c;
-      if (j < k) P[static_cast<int64_t>(j) * k + i] = acc[a][c];
-    }
-  }
-}
-
-// C[e] = sum_c part[c][e]: one wave per element, lanes stride the chunks.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
-                                                     double* __restrict__ C, int k, int nchunk) {
-  const int64_t kk = static_cast<int64_t>(k) * k;
-  const int lane = threadIdx.x & 63;
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (e >= kk) return;
-  double s = 0.0;
-  for (int c = lane; c < nchunk; c += 64) s += part[c * kk + e];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) C[e] = s;
-}
-
 }  // namespace
 
 template <typename T>
@@ -486,26 +416,6 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
-}
-
-int gram_chunks(int64_t rows, int k) {
-  const int tiles = ((k + GR_T - 1) / GR_T) * ((k + GR_T - 1) / GR_T);
-  int64_t want = (1024 + tiles - 1) / tiles;   // ~1024 workgroups in flight
-  const int64_t maxc = (rows + 255) / 256;     // at least 256 rows per chunk
-  if (want > maxc) want = maxc;
-  if (want < 1) want = 1;
-  if (want > 256) want = 256;
-  return static_cast<int>(want);
-}
-
-void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                 double* part, int64_t rows, int k, hipStream_t s) {
-  const int nch = gram_chunks(rows, k);
-  const int64_t chunk = (rows + nch - 1) / nch;
-  dim3 grid((k + GR_T - 1) / GR_T, (k + GR_T - 1) / GR_T, nch);
-  k_gram_partial<<<grid, 256, 0, s>>>(A, lda, B, ldb, part, rows, k, chunk);
-  const int64_t kk = static_cast<int64_t>(k) * k;
-  k_gram_reduce<<<static_cast<unsigned>((kk + 3) / 4), 256, 0, s>>>(part, C, k, nch);
 }
 
 #define CES_INST(T)                                                                          \

@@ -199,6 +199,39 @@ def test_rayleigh_ritz_matches_oracle():
     assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * np.max(np.abs(theta_ref))
 
 
+@pytest.mark.parametrize("k", [17, 33, 60, 64])
+def test_rayleigh_ritz_block_sizes_match_oracle(k):
+    # k = 17, 33, 60 run the one-workgroup Cholesky / Jacobi solvers with the
+    # fused block rotation (16-, 48- and 64-wide rotation kernels, with and
+    # without fused residuals); k = 64 runs the rocSOLVER path
+    w = SMALL
+    _say(f"case rayleigh_ritz k={k}")
+    s = setup(w)
+    X = si.random_block(s.B.d, k, 30 + k) * np.linspace(0.5, 3.0, k)
+    theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
+    scale = np.max(np.abs(theta_ref))
+    work = s.H.workspace(k, FP64)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    for with_hx in (True, False):
+        Xt = dev(X, ld=s.B.d + 3)
+        HXt = torch.empty_like(Xt) if with_hx else None
+        h_ev = s.H.rayleigh_ritz(Xt, ev, rs, work, HX=HXt)
+        Xg = host(Xt, s.B.d)
+        assert np.max(np.abs(h_ev - theta_ref)) < 1e-11 * scale
+        assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * scale
+        assert np.max(np.abs(Xg.T @ Xg - np.eye(k))) < 1e-12
+        # same span as the oracle's Ritz vectors, and X^T H X diagonal with
+        # the Ritz values (fixes each vector up to sign without comparing
+        # vectors of close eigenvalues one by one)
+        assert np.max(np.abs(Xg @ Xg.T - Xr @ Xr.T)) < 1e-10
+        assert np.max(np.abs(Xg.T @ s.oracle_apply(Xg) - np.diag(theta_ref))) < 1e-11 * scale
+        assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-9 * scale
+        if with_hx:
+            HXg = host(HXt, s.B.d)
+            assert np.max(np.abs(HXg - s.oracle_apply(Xg))) < 1e-10 * scale
+
+
 def test_rayleigh_ritz_rank_deficient_block_reports_error():
     w = SMALL
     s = setup(w)
