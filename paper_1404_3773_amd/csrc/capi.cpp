@@ -414,8 +414,15 @@ ces_status check_ham(ces_ham hh) {
   return CES_OK;
 }
 
+// Largest block: (radial node, theta node, 32-column group) work items and
+// the angular kernels' grid sizes stay below 2^31.
+bool k_fits(const Basis& b, int k) {
+  return int64_t(b.n_r) * b.n_theta * ((round_up(k, kColPad) + 31) / 32) < (int64_t(1) << 31);
+}
+
 ces_status check_block(const Ham& h, int k, const void* X, int64_t ldx, const char* what) {
   if (k < 1) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": k must be >= 1");
+  if (!k_fits(*h.basis, k)) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": k too large");
   if (!X) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": null block");
   if (ldx < h.basis->d) return fail(CES_ERR_INVALID_ARG, std::string(what) + ": ld < d");
   return CES_OK;
@@ -823,6 +830,7 @@ ces_status ces_ham_destroy(ces_ham hh) {
 ces_status ces_workspace_size(ces_ham hh, int k, int prec, size_t* bytes) {
   if (!hh || !bytes) return fail(CES_ERR_INVALID_ARG, "null argument");
   if (k < 1) return fail(CES_ERR_INVALID_ARG, "k must be >= 1");
+  if (!k_fits(*hh->h.basis, k)) return fail(CES_ERR_INVALID_ARG, "k too large");
   if (prec != CES_PREC_FP64 && prec != CES_PREC_MIXED)
     return fail(CES_ERR_INVALID_ARG, "unknown precision");
   *bytes = layout_for(hh->h, k, prec).total;
