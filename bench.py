@@ -11,7 +11,8 @@ residuals, with the filter bounds taken from the previous Rayleigh-Ritz.
 (degree + 1) * F / step_time, with F the separable method's algorithmic
 flops per H*X (phi stage counted at nominal real-FFT cost).
 
-Also reported: filter-only H*X GFLOP/s in mixed and FP64, time to eigenpairs
+Also reported: filter-only H*X GFLOP/s in mixed and FP64, the per-stage rates of
+H*X on the 147-atom and 309-atom (projector) shapes, time to eigenpairs
 (all n_check eigenvalues within 1e-6 Ha of the stored oracle values) for both,
 the roofline of the dominant kernel measured with HIP events (over a second
 run of the timed steps, so that the event records stay out of the step
@@ -40,31 +41,35 @@ PMC_COPY_BYTES = 1 << 30      # calibration copy of --pmc-run (read and written 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "phi_stage_fp32_ico13_L31_N60_pmc.json")
 
 
-def algorithmic_flops(w, k):
+def algorithmic_flops(w, k, n_proj=0):
     """Algorithmic flops of one H*X for k orbitals (separable method):
     radial sums both ways, Legendre sums both ways with even/odd folding,
     phi synthesis + analysis at nominal real-FFT cost 2.5 N log2 N each,
-    pointwise V, kinetic term."""
+    pointwise V, kinetic term, and the two projector products (2 d n_proj k
+    each)."""
     L2 = w.L * w.L
     radial = 2 * (2 * w.n_r * w.N * L2) * k
     legendre = 2 * (w.n_r * w.n_theta * L2) * k
     fft = 2 * w.n_r * w.n_theta * k * 2.5 * w.n_phi * math.log2(w.n_phi)
     pointwise = w.n_grid * k
     kinetic = 2 * w.d * k
+    kb = 2 * (2 * w.d * n_proj * k)
     return {"radial": radial, "legendre": legendre, "phi": fft, "pointwise": pointwise,
-            "kinetic": kinetic, "total": radial + legendre + fft + pointwise + kinetic}
+            "kinetic": kinetic, "kb": kb,
+            "total": radial + legendre + fft + pointwise + kinetic + kb}
 
 
-def stage_flops(w, k):
+def stage_flops(w, k, n_proj=0):
     """Algorithmic flops of one launch of each H*X kernel (same accounting as
-    algorithmic_flops, split by stage)."""
-    f = algorithmic_flops(w, k)
+    algorithmic_flops, split by stage; the second projector product is fused
+    into the radial forward kernel)."""
+    f = algorithmic_flops(w, k, n_proj)
     return {"radial_inverse": f["radial"] / 2,
             "legendre_synth": f["legendre"] / 2,
             "phi_stage": f["phi"] + f["pointwise"],
             "legendre_analysis": f["legendre"] / 2,
-            "radial_forward": f["radial"] / 2 + f["kinetic"],
-            "kb_gemm": 0.0}
+            "radial_forward": f["radial"] / 2 + f["kinetic"] + f["kb"] / 2,
+            "kb_gemm": f["kb"] / 2}
 
 
 def radial_bytes(w, k, elem):
@@ -159,6 +164,62 @@ def large_workload_rates(ces, torch, reps=5):
     return out
 
 
+def kb_workload_rates(ces, torch, reps=3):
+    """H*X on the 309-atom nonlocal shape (L_max = 80, N = 150, 225 x 162 x 324
+    grid, k = 1000, 1236 Kleinman-Bylander projectors) in mixed and FP64, per
+    stage.  Timing only: V_eff and the projector coefficients are seeded
+    random values of the real shapes (the kernels' work does not depend on
+    them); parity at this shape is tested with the physical projectors of a
+    few atoms."""
+    w = si.C4
+    n_proj = 4 * len(si.atoms_for(w))
+    B = ces.Basis.for_workload(w)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    V = -0.5 + 0.1 * torch.rand(B.n_grid, dtype=torch.float64, device="cuda", generator=gen)
+    P = 1e-3 * torch.randn(n_proj, B.d, dtype=torch.float64, device="cuda", generator=gen)
+    H = ces.Ham(B, V, P, np.tile([1.5, -0.8, -0.8, -0.8], n_proj // 4))
+    del P
+    torch.cuda.empty_cache()
+    F = algorithmic_flops(w, w.k, n_proj)["total"]
+    sf = stage_flops(w, w.k, n_proj)
+    X = torch.randn(w.k, B.d, dtype=torch.float64, device="cuda", generator=gen)
+    Y = torch.empty_like(X)
+    out = {"workload": w.name, "d": w.d, "orbitals": w.k, "projectors": n_proj,
+           "values": "seeded random V_eff and projector coefficients (timing only)",
+           "alg_flop_per_HX": F}
+    for name, prec, peak in (("mixed", ces.CES_PREC_MIXED, PEAK_FP32),
+                             ("fp64", ces.CES_PREC_FP64, PEAK_FP64)):
+        work = H.workspace(w.k, prec)
+        H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        ces.profile_enable(True, 1024)      # stage durations over a second pass
+        for _ in range(reps):
+            H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        prof = ces.profile_read()
+        ces.profile_enable(False)
+        suffix = "_fp32" if name == "mixed" else "_fp64"
+        stages = {}
+        for st, (ms, c) in prof.items():
+            if c and st.endswith(suffix) and sf[st[:-5]] > 0:
+                rate = sf[st[:-5]] / (ms / c * 1e-3)
+                stages[st[:-5]] = {"ms": round(ms / c, 3), "tflops": round(rate / 1e12, 2),
+                                   "frac_peak": round(rate / peak, 4)}
+        out[name] = {"ms_per_HX": round(sec * 1e3, 2), "tflops": round(F / sec / 1e12, 3),
+                     "stages": stages}
+        del work
+        torch.cuda.empty_cache()
+    print(f"[bench] 309-atom KB H*X: mixed {out['mixed']['ms_per_HX']} ms, "
+          f"fp64 {out['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def golden_eigenvalues(w):
     path = os.path.join(ROOT, "tests", "golden", f"{w.name}_eigenvalues.txt")
     if not os.path.exists(path):
@@ -203,7 +264,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the 147-atom H*X rates")
+                    help="skip the 147-atom and 309-atom H*X rates")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes (no JSON line)")
     args = ap.parse_args()
@@ -355,6 +416,12 @@ def main():
         del work
         torch.cuda.empty_cache()
         line["large_workload"] = large_workload_rates(ces, torch)
+        torch.cuda.empty_cache()
+        try:
+            line["kb_workload"] = kb_workload_rates(ces, torch)
+        except Exception as e:   # reported, never fatal to the line
+            line["kb_workload"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -311,6 +311,7 @@ Layout layout_for(Ham& h, int k, int prec) {
     L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
   }
   L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * sizeof(double));
+  L.Cpart = take(kb_partial_bytes(h.n_proj, k, b.d));
   const size_t kk = std::max<size_t>(size_t(k) * k, size_t(small_ld(k)) * small_ld(k));
   L.S1 = take(kk * sizeof(double));
   L.S2 = take(kk * sizeof(double));
@@ -341,17 +342,6 @@ template <>
 const float* ab_of<float>(const Ham& h) { return h.ab32; }
 
 
-inline rocblas_status gemm_t(rocblas_handle hb, rocblas_operation ta, rocblas_operation tb, int m,
-                             int n, int kk, const double* alpha, const double* A, int lda,
-                             const double* B, int ldb, const double* beta, double* C, int ldc) {
-  return rocblas_dgemm(hb, ta, tb, m, n, kk, alpha, A, lda, B, ldb, beta, C, ldc);
-}
-inline rocblas_status gemm_t(rocblas_handle hb, rocblas_operation ta, rocblas_operation tb, int m,
-                             int n, int kk, const float* alpha, const float* A, int lda,
-                             const float* B, int ldb, const float* beta, float* C, int ldc) {
-  return rocblas_sgemm(hb, ta, tb, m, n, kk, alpha, A, lda, B, ldb, beta, C, ldc);
-}
-
 // out = alpha * (H Yin - c Yin) + beta * Yold  (kinetic and projector terms
 // included).  Uses the G, A and C regions of the workspace.
 template <typename T>
@@ -367,17 +357,10 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
   const T* P = nullptr;
   if (h.n_proj > 0) {
     // C = diag(h) P^T Yin  (n_proj x kp, row-major)
-    const T one = 1, zero = 0;
-    CES_BLAS(rocblas_set_stream(h.blas, s));
-    CES_BLAS(rocblas_set_workspace(h.blas, Ptr<char>::at(work, ly.solver), ly.solver_bytes));
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
-    // C[q][i] (row-major n_proj x kp) is the column-major kp x n_proj matrix Y^T P
     StageTimer t(stage_id<T>(ST_KB_GEMM), s);
-    CES_BLAS(gemm_t(h.blas, rocblas_operation_transpose, rocblas_operation_none, k, h.n_proj,
-                    static_cast<int>(b.d), &one, Yin, static_cast<int>(ldin), Pd,
-                    static_cast<int>(b.d), &zero, C, kp));
-    launch_scale_rows<T>(C, h.n_proj, kp, hd, s);
+    launch_kb_gemm<T>(Pd, b.d, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k, kp, s);
     P = Pd;
   }
   T* gbuf = Ptr<T>::at(work, ly.gbuf);

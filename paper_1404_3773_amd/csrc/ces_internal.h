@@ -97,8 +97,8 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Byte offsets of the regions of a caller workspace for k columns.
 struct Layout {
-  size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, S1 = 0, S2 = 0,
-         vec = 0, part = 0, info = 0, solver = 0, total = 0;
+  size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, Cpart = 0,
+         S1 = 0, S2 = 0, vec = 0, part = 0, info = 0, solver = 0, total = 0;
   size_t solver_bytes = 0;
   int64_t kp = 0;
 };
@@ -154,8 +154,13 @@ void launch_convert(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t
                     int cols, hipStream_t s);
 
 // C[q][i] *= h[q] for q < rows, i < ld.
+// C[q][i] = h_q sum_alpha P[q][alpha] Y[alpha][i] (projector product; P n_proj x d
+// row-major, Y column-major d x k, C row-major n_proj x kp with zeros for i >= k);
+// part: kb_partial_bytes(n_proj, k, d) bytes of scratch.
+size_t kb_partial_bytes(int n_proj, int k, int64_t d);
 template <typename T>
-void launch_scale_rows(T* C, int rows, int ld, const T* h, hipStream_t s);
+void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
+                    int n_proj, int k, int kp, hipStream_t s);
 
 // Transforms for grids of k functions (column i at offset i*n_grid).
 template <typename T>

@@ -293,11 +293,6 @@ __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t 
     y[e] = a * x[e] + b * y[e];
 }
 
-template <typename T>
-__global__ void k_scale_rows(T* C, int rows, int ld, const T* h) {
-  const int q = blockIdx.x;
-  for (int i = threadIdx.x; i < ld; i += blockDim.x) C[static_cast<int64_t>(q) * ld + i] *= h[q];
-}
 
 // S(i, j) *= dinv[i] for a k x k column-major matrix
 __global__ void k_scale_rows_k(double* S, int k, const double* dinv) {
@@ -363,10 +358,6 @@ void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, co
       G, occ, rho, tb.Pleg, tb.trig, b.L, b.n_theta, b.n_phi, k, kp);
 }
 
-template <typename T>
-void launch_scale_rows(T* C, int rows, int ld, const T* h, hipStream_t s) {
-  k_scale_rows<T><<<rows, 256, 0, s>>>(C, rows, ld, h);
-}
 
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s) {
   k_scale_gram<<<1, 256, 0, s>>>(S, k, dinv);
@@ -425,8 +416,7 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hip
   template void launch_angular_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
                                            int, int, hipStream_t);                            \
   template void launch_density_synth<T>(const Basis&, const DevTables<T>&, const T*,          \
-                                        const double*, double*, int, int, hipStream_t);        \
-  template void launch_scale_rows<T>(T*, int, int, const T*, hipStream_t);
+                                        const double*, double*, int, int, hipStream_t);
 CES_INST(float)
 CES_INST(double)
 #undef CES_INST

@@ -1,0 +1,208 @@
+// Kleinman-Bylander projector product of H*X (Section 2.3.2): the first of
+// the two projector GEMMs, C[q][i] = h_q sum_alpha P[q][alpha] Y[alpha][i]
+// (M = n_proj, N = k, K = d); the second, sum_q P[alpha][q] C[q][i], is
+// fused into the radial forward kernel.
+//
+// Both operands run contiguously along the contraction index alpha (P is
+// stored n_proj x d row-major, Y column-major): a workgroup stages a BM x BK
+// tile of P and a BN x BK tile of Y per step in LDS, loaded as whole row
+// segments (consecutive lanes on consecutive alpha), the next step's tiles
+// in registers while the current one runs on 16x16x4 MFMA (2 x 2 waves, TM x
+// TN fragments each).  K is split into chunks whose partial products go to a
+// buffer; a second kernel sums them in a fixed order and applies h.
+// Workgroups that share projector rows (same chunk and M tile) are placed on
+// one XCD (workgroup ids are dealt round-robin over the 8 XCDs) so that its
+// L2 serves their common loads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ces_internal.h"
+#include "mfma.h"
+
+namespace ces {
+namespace {
+
+template <typename T>
+struct KbShape;
+template <>
+struct KbShape<float> {   // wave tile 64 x 64, workgroup 128 x 128, 32 alpha per step
+  static constexpr int KB = 32, TM = 4, TN = 4;
+};
+template <>
+struct KbShape<double> {  // wave tile 64 x 32, workgroup 128 x 64, 32 alpha per step
+  static constexpr int KB = 32, TM = 4, TN = 2;
+};
+constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_t d,
+                                                 const T* __restrict__ Y, int64_t ldy,
+                                                 T* __restrict__ part, int n_proj, int k, int kp,
+                                                 int64_t kchunk, int nM, int nN, int n_groups) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
+  constexpr int BM = 32 * TM, BN = 32 * TN;      // 2 x 2 waves
+  constexpr int KW = KB + 1;                     // padded LDS row
+  constexpr int RA = 256 / KB;                   // tile rows loaded per pass
+  constexpr int LA = BM / RA, LB = BN / RA;      // passes for the P and Y tiles
+  __shared__ T As[BM * KW];
+  __shared__ T Bs[BN * KW];
+  // workgroup id -> (XCD x, position j on it) -> (group g = chunk and M tile, N tile)
+  const int id = blockIdx.x;
+  const int x = id & 7, j = id >> 3;
+  const int g = x + 8 * (j / nN), ntb = j - (j / nN) * nN;
+  if (g >= n_groups) return;
+  const int chunk = g / nM, mtb = g - chunk * nM;
+  const int64_t k0 = static_cast<int64_t>(chunk) * kchunk;
+  const int64_t k1 = k0 + kchunk < d ? k0 + kchunk : d;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int c16 = lane & 15, kk = lane >> 4;
+  // staging: thread -> (tile row r0 + RA p, alpha offset kc)
+  const int kc = tid % KB, r0 = tid / KB;
+  const T* pa[LA];
+  bool aok[LA];
+#pragma unroll
+  for (int p = 0; p < LA; ++p) {
+    const int row = mtb * BM + r0 + RA * p;
+    aok[p] = row < n_proj;
+    pa[p] = P + static_cast<int64_t>(aok[p] ? row : n_proj - 1) * d;
+  }
+  const T* pb[LB];
+  bool bok[LB];
+#pragma unroll
+  for (int p = 0; p < LB; ++p) {
+    const int col = ntb * BN + r0 + RA * p;
+    bok[p] = col < k;
+    pb[p] = Y + static_cast<int64_t>(bok[p] ? col : k - 1) * ldy;
+  }
+  T ra[LA], rb[LB];
+  auto fetch = [&](int64_t kb) {
+    const int64_t kx = kb + kc;
+    const bool ok = kx < k1;
+    const int64_t kcl = ok ? kx : k1 - 1;
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+      const T v = pa[p][kcl];
+      ra[p] = ok && aok[p] ? v : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      const T v = pb[p][kcl];
+      rb[p] = ok && bok[p] ? v : T(0);
+    }
+  };
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int u = 0; u < TM; ++u)
+#pragma unroll
+    for (int v = 0; v < TN; ++v) acc[u][v] = zero_acc<acc_t>();
+  const T* Aw = As + (wm * 16 * TM + c16) * KW + kk;
+  const T* Bw = Bs + (wn * 16 * TN + c16) * KW + kk;
+  if (k0 < k1) fetch(k0);
+  for (int64_t kb = k0; kb < k1; kb += KB) {
+#pragma unroll
+    for (int p = 0; p < LA; ++p) As[(r0 + RA * p) * KW + kc] = ra[p];
+#pragma unroll
+    for (int p = 0; p < LB; ++p) Bs[(r0 + RA * p) * KW + kc] = rb[p];
+    __syncthreads();
+    if (kb + KB < k1) fetch(kb + KB);          // next step's tiles, in flight
+#pragma unroll
+    for (int st = 0; st < KB / 4; ++st) {
+      T a[TM], b[TN];
+#pragma unroll
+      for (int u = 0; u < TM; ++u) a[u] = Aw[16 * u * KW + 4 * st];
+#pragma unroll
+      for (int v = 0; v < TN; ++v) b[v] = Bw[16 * v * KW + 4 * st];
+#pragma unroll
+      for (int u = 0; u < TM; ++u)
+#pragma unroll
+        for (int v = 0; v < TN; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  T* pc = part + static_cast<int64_t>(chunk) * n_proj * kp;
+#pragma unroll
+  for (int u = 0; u < TM; ++u)
+#pragma unroll
+    for (int v = 0; v < TN; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mtb * BM + wm * 16 * TM + 16 * u + MF<T>::row(lane, r);
+        const int col = ntb * BN + wn * 16 * TN + 16 * v + c16;
+        if (row < n_proj && col < k) pc[static_cast<int64_t>(row) * kp + col] = acc[u][v][r];
+      }
+}
+
+// C[q][i] = h_q sum_c part[c][q][i] for i < k (chunks in order), 0 for k <= i < kp.
+template <typename T>
+__global__ void k_kb_reduce(const T* __restrict__ part, int nchunk, const T* __restrict__ h,
+                            T* __restrict__ C, int n_proj, int k, int kp) {
+  const int64_t n = static_cast<int64_t>(n_proj) * kp;
+  const int64_t stride = n;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int q = static_cast<int>(e / kp), i = static_cast<int>(e - static_cast<int64_t>(q) * kp);
+    T s = T(0);
+    if (i < k)
+      for (int c = 0; c < nchunk; ++c) s += part[c * stride + e];
+    C[e] = h[q] * s;
+  }
+}
+
+template <typename T>
+struct KbGrid {
+  int nM, nN, nchunk, n_groups;
+  int64_t kchunk;
+};
+
+template <typename T>
+KbGrid<T> kb_grid(int n_proj, int k, int64_t d) {
+  constexpr int KB = KbShape<T>::KB;
+  KbGrid<T> gr;
+  gr.nM = (n_proj + 32 * KbShape<T>::TM - 1) / (32 * KbShape<T>::TM);
+  gr.nN = (k + 32 * KbShape<T>::TN - 1) / (32 * KbShape<T>::TN);
+  // groups (chunk, M tile) of nN workgroups each are dealt to the 8 XCDs; as
+  // many chunks as keep every XCD's groups resident at once (one round), with
+  // chunks of at least 16 steps
+  const int groups_per_xcd = std::max(1, kKbPerXcd / gr.nN);
+  int want = std::max(1, 8 * groups_per_xcd / gr.nM);
+  const int64_t maxc = std::max<int64_t>(1, (d + 16 * KB - 1) / (16 * KB));
+  want = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({int64_t(want), maxc, 64})));
+  gr.kchunk = round_up((d + want - 1) / want, KB);
+  gr.nchunk = static_cast<int>((d + gr.kchunk - 1) / gr.kchunk);
+  gr.n_groups = gr.nchunk * gr.nM;
+  return gr;
+}
+
+}  // namespace
+
+size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
+  if (n_proj <= 0) return 0;
+  const int kp = static_cast<int>(round_up(k, kColPad));
+  const size_t c32 = size_t(kb_grid<float>(n_proj, k, d).nchunk) * sizeof(float);
+  const size_t c64 = size_t(kb_grid<double>(n_proj, k, d).nchunk) * sizeof(double);
+  return std::max(c32, c64) * size_t(n_proj) * size_t(kp);
+}
+
+template <typename T>
+void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
+                    int n_proj, int k, int kp, hipStream_t s) {
+  const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
+  const int per_xcd = (gr.n_groups + 7) / 8;   // groups per XCD (the last ones idle)
+  const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
+  k_kb_gemm<T><<<nwg, 256, 0, s>>>(P, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM, gr.nN,
+                                   gr.n_groups);
+  const int64_t n = int64_t(n_proj) * kp;
+  const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
+  k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
+}
+
+template void launch_kb_gemm<float>(const float*, int64_t, const float*, int64_t, const float*,
+                                    float*, float*, int, int, int, hipStream_t);
+template void launch_kb_gemm<double>(const double*, int64_t, const double*, int64_t,
+                                     const double*, double*, double*, int, int, int, hipStream_t);
+
+}  // namespace ces

@@ -135,6 +135,37 @@ def test_apply_H_kb_projectors():
         assert rel_err(host(Yt, s.B.d), Z) < tol, prec
 
 
+def test_apply_H_many_projectors_several_tiles_and_chunks():
+    # 40 atoms -> 160 projectors, k = 140, d = 1200: the projector product runs
+    # on 2 x 2 (FP32) / 2 x 3 (FP64) output tiles with ragged edges and splits
+    # the contraction over d into 2 / 3 chunks
+    w = si.small(10, 12, R=12.0, k=140, name="kb_tiles")
+    _say(f"case apply_H KB tiles {w.name} k={w.k}")
+    B = ces.Basis.for_workload(w)
+    r, wr, th, wt, ph = B.grid()
+    bs = ob.basis_for(w)
+    V = si.potential_on_grid(w, r, th, ph)
+    Vo = si.potential_on_grid(w, bs.r, bs.theta, bs.phi)
+    rng = np.random.default_rng(41)
+    atoms = rng.uniform(-5.0, 5.0, size=(40, 3))
+    pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
+    pg, h = si.kb_projector_values(pts, atoms)
+    P = oh.kb_projectors(bs, pg.reshape(*Vo.shape, -1))
+    assert P.shape == (B.d, 160)
+    H = ces.Ham(B, torch.from_numpy(V.reshape(-1)).cuda(),
+                proj=torch.from_numpy(np.ascontiguousarray(P.T)).cuda(), energies=h)
+    X = si.random_block(B.d, w.k, 43)
+    Z = oh.apply_H_real(bs, Vo, X, proj=P, h=h)
+    for prec, tol in ((FP64, TOL64), (MIXED, TOL32)):
+        work = H.workspace(w.k, prec)
+        Xt, Yt = dev(X, ld=B.d + 1), torch.empty((w.k, B.d), dtype=torch.float64, device="cuda")
+        H.apply_H(Xt, Yt, prec, work)
+        torch.cuda.synchronize()
+        e = rel_err(host(Yt, B.d), Z)
+        _say(f"  prec={prec} rel err {e:.2e}")
+        assert e < tol, (prec, e)
+
+
 def test_apply_H_13_atom_cluster_full_size():
     """L_max = 30, N = 60, 90 x 62 x 124 grid, k = 32, in the launch shape the
     benchmark uses; columns sampled for the oracle."""
