@@ -60,16 +60,15 @@ def algorithmic_flops(w, k, n_proj=0):
 
 
 def stage_flops(w, k, n_proj=0):
-    """Algorithmic flops of one launch of each H*X kernel (same accounting as
-    algorithmic_flops, split by stage; the second projector product is fused
-    into the radial forward kernel)."""
+    """Algorithmic flops of one launch of each H*X stage (same accounting as
+    algorithmic_flops, split by stage; kb_gemm is both projector products)."""
     f = algorithmic_flops(w, k, n_proj)
     return {"radial_inverse": f["radial"] / 2,
             "legendre_synth": f["legendre"] / 2,
             "phi_stage": f["phi"] + f["pointwise"],
             "legendre_analysis": f["legendre"] / 2,
-            "radial_forward": f["radial"] / 2 + f["kinetic"] + f["kb"] / 2,
-            "kb_gemm": f["kb"] / 2}
+            "radial_forward": f["radial"] / 2 + f["kinetic"],
+            "kb_gemm": f["kb"]}
 
 
 def radial_bytes(w, k, elem):

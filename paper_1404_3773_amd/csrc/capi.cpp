@@ -312,6 +312,7 @@ Layout layout_for(Ham& h, int k, int prec) {
   }
   L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * sizeof(double));
   L.Cpart = take(kb_partial_bytes(h.n_proj, k, b.d));
+  L.Zkb = take(h.n_proj > 0 ? size_t(b.d) * L.kp * sizeof(double) : 0);
   const size_t kk = std::max<size_t>(size_t(k) * k, size_t(small_ld(k)) * small_ld(k));
   L.S1 = take(kk * sizeof(double));
   L.S2 = take(kk * sizeof(double));
@@ -354,14 +355,15 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
   T* A = Ptr<T>::at(work, ly.A);
   T* C = Ptr<T>::at(work, ly.C);
   const int kp = static_cast<int>(ly.kp);
-  const T* P = nullptr;
+  T* Zkb = nullptr;
   if (h.n_proj > 0) {
-    // C = diag(h) P^T Yin  (n_proj x kp, row-major)
+    // C = diag(h) P^T Yin (n_proj x kp, row-major), then Zkb = P C (d x k)
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
     StageTimer t(stage_id<T>(ST_KB_GEMM), s);
     launch_kb_gemm<T>(Pd, b.d, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k, kp, s);
-    P = Pd;
+    Zkb = Ptr<T>::at(work, ly.Zkb);
+    launch_kb_apply<T>(Pd, b.d, C, Zkb, h.n_proj, k, kp, s);
   }
   T* gbuf = Ptr<T>::at(work, ly.gbuf);
   {
@@ -383,7 +385,7 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
   {
     StageTimer t(stage_id<T>(ST_RADIAL_FWD), s);
     launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true,
-                             P, h.n_proj, C, k, kp, s);
+                             Zkb, k, kp, s);
   }
   CES_HIP(hipGetLastError());
   return CES_OK;
@@ -1025,7 +1027,7 @@ ces_status ces_from_grid(ces_ham hh, int k, const double* d_f, double* d_X, int6
   const int kp = static_cast<int>(ly.kp);
   launch_angular_analysis<double>(b, b.t64, d_f, A, k, kp, s);
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_X, ldx, 1.0, 0.0, 0.0,
-                                false, nullptr, 0, nullptr, k, kp, s);
+                                false, nullptr, k, kp, s);
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -1057,7 +1059,7 @@ ces_status ces_density(ces_ham hh, int k, const double* d_X, int64_t ldx, const 
     double* A = Ptr<double>::at(d_work, ly.A);
     launch_angular_analysis<double>(b, b.t64, d_rho_grid, A, 1, kp, s);
     launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_rho_coef, b.d, 1.0, 0.0,
-                                  0.0, false, nullptr, 0, nullptr, 1, kp, s);
+                                  0.0, false, nullptr, 1, kp, s);
   }
   CES_HIP(hipGetLastError());
   return CES_OK;

@@ -98,7 +98,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Byte offsets of the regions of a caller workspace for k columns.
 struct Layout {
   size_t G = 0, A = 0, gbuf = 0, B1 = 0, B2 = 0, V3 = 0, F0 = 0, F1 = 0, C = 0, Cpart = 0,
-         S1 = 0, S2 = 0, vec = 0, part = 0, info = 0, solver = 0, total = 0;
+         Zkb = 0, S1 = 0, S2 = 0, vec = 0, part = 0, info = 0, solver = 0, total = 0;
   size_t solver_bytes = 0;
   int64_t kp = 0;
 };
@@ -119,13 +119,13 @@ void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, i
                            T* G, int k, int kp, hipStream_t s);
 
 // out = alpha * (Z + lamh o Yin + KB - c * Yin) + beta * Yold, with
-// Z = Rfwd^T A (per lm).  Yold may be null when beta == 0.  kbP/kbC may be
-// null (no projector term); kbC is n_proj x kp (ld kp) already scaled by h.
+// Z = Rfwd^T A (per lm) (+ Zkb, the projector term: column-major d x k, ld d,
+// or null).  Yold may be null when beta == 0.
 template <typename T>
 void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
                            int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
-                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
-                           const T* kbC, int k, int kp, hipStream_t s);
+                           T alpha, T cshift, T beta, bool kinetic, const T* Zkb, int k, int kp,
+                           hipStream_t s);
 
 // Angular stage on MFMA: G -> gbuf (n_r x n_theta x S x kp) -> gh (in place)
 // -> A, as three launches.
@@ -161,6 +161,10 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d);
 template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
                     int n_proj, int k, int kp, hipStream_t s);
+// Z[alpha][i] = sum_q P[q][alpha] C[q][i] (Z column-major d x k, ld d).
+template <typename T>
+void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,
+                     hipStream_t s);
 
 // Transforms for grids of k functions (column i at offset i*n_grid).
 template <typename T>

@@ -1,8 +1,9 @@
-// Kleinman-Bylander projector product of H*X (Section 2.3.2): the first of
-// the two projector GEMMs, C[q][i] = h_q sum_alpha P[q][alpha] Y[alpha][i]
-// (M = n_proj, N = k, K = d); the second, sum_q P[alpha][q] C[q][i], is
-// fused into the radial forward kernel.
+// Kleinman-Bylander projector products of H*X (Section 2.3.2):
+//   kb_gemm   C[q][i] = h_q sum_alpha P[q][alpha] Y[alpha][i]   (M = n_proj, N = k, K = d)
+//   kb_apply  Z[alpha][i] = sum_q P[q][alpha] C[q][i]          (M = k, N = d, K = n_proj)
+// Z is added in the radial forward kernel's epilogue.
 //
+// kb_gemm:
 // Both operands run contiguously along the contraction index alpha (P is
 // stored n_proj x d row-major, Y column-major): a workgroup stages a BM x BK
 // tile of P and a BN x BK tile of Y per step in LDS, loaded as whole row
@@ -60,24 +61,10 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int c16 = lane & 15, kk = lane >> 4;
-  // staging: thread -> (tile row r0 + RA p, alpha offset kc)
+  // staging: thread -> (tile row r0 + RA p, alpha offset kc); row addresses
+  // are formed per load (keeps the register count at three waves per SIMD)
   const int kc = tid % KB, r0 = tid / KB;
-  const T* pa[LA];
-  bool aok[LA];
-#pragma unroll
-  for (int p = 0; p < LA; ++p) {
-    const int row = mtb * BM + r0 + RA * p;
-    aok[p] = row < n_proj;
-    pa[p] = P + static_cast<int64_t>(aok[p] ? row : n_proj - 1) * d;
-  }
-  const T* pb[LB];
-  bool bok[LB];
-#pragma unroll
-  for (int p = 0; p < LB; ++p) {
-    const int col = ntb * BN + r0 + RA * p;
-    bok[p] = col < k;
-    pb[p] = Y + static_cast<int64_t>(bok[p] ? col : k - 1) * ldy;
-  }
+  const int arow0 = mtb * BM + r0, bcol0 = ntb * BN + r0;
   T ra[LA], rb[LB];
   auto fetch = [&](int64_t kb) {
     const int64_t kx = kb + kc;
@@ -85,13 +72,15 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
     const int64_t kcl = ok ? kx : k1 - 1;
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
-      const T v = pa[p][kcl];
-      ra[p] = ok && aok[p] ? v : T(0);
+      const int row = arow0 + RA * p;
+      const T v = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * d + kcl];
+      ra[p] = ok && row < n_proj ? v : T(0);
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
-      const T v = pb[p][kcl];
-      rb[p] = ok && bok[p] ? v : T(0);
+      const int col = bcol0 + RA * p;
+      const T v = Y[static_cast<int64_t>(col < k ? col : k - 1) * ldy + kcl];
+      rb[p] = ok && col < k ? v : T(0);
     }
   };
   acc_t acc[TM][TN];
@@ -133,6 +122,98 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
         const int row = mtb * BM + wm * 16 * TM + 16 * u + MF<T>::row(lane, r);
         const int col = ntb * BN + wn * 16 * TN + 16 * v + c16;
         if (row < n_proj && col < k) pc[static_cast<int64_t>(row) * kp + col] = acc[u][v][r];
+      }
+}
+
+// kb_apply: Z^T = C^T P on 16x16x4 MFMA, workgroup tile BM columns i x BN rows
+// alpha, both operands staged per step of KB projectors in LDS (C rows run
+// along i, P rows along alpha), the next step's tiles in registers.  The
+// result lane holds 16 consecutive alpha of one column, so stores are
+// coalesced.  Workgroups that read the same P tile (same alpha tile) share
+// an XCD.
+template <typename T>
+__global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64_t d,
+                                                  const T* __restrict__ C, int n_proj, int k,
+                                                  int kp, T* __restrict__ Z, int nI, int nA) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
+  constexpr int BM = 32 * TN, BN = 32 * TM;      // i tile, alpha tile (2 x 2 waves)
+  constexpr int KW = KB + 1;
+  constexpr int RC = 256 / BM, RP = 256 / BN;    // q rows per staging pass
+  constexpr int LC = KB / RC, LP = KB / RP;
+  __shared__ T Cs[BM * KW];                       // [i][q]
+  __shared__ T Ps[BN * KW];                       // [alpha][q]
+  const int id = blockIdx.x;
+  const int x = id & 7, j = id >> 3;
+  const int ga = x + 8 * (j / nI), itb = j - (j / nI) * nI;
+  if (ga >= nA) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int c16 = lane & 15, kk = lane >> 4;
+  const int ci = tid % BM, cq = tid / BM;
+  const int pa_ = tid % BN, pq = tid / BN;
+  const int i_s = itb * BM + ci;
+  const bool iok = i_s < kp;
+  const int64_t a_s = static_cast<int64_t>(ga) * BN + pa_;
+  const bool aok = a_s < d;
+  const T* cbase = C + (iok ? i_s : 0);
+  const T* pbase = P + (aok ? a_s : 0);
+  T rc[LC], rp[LP];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int p = 0; p < LC; ++p) {
+      const int q = q0 + cq + RC * p;
+      const bool ok = q < n_proj && iok;
+      const T v = cbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp];
+      rc[p] = ok ? v : T(0);
+    }
+#pragma unroll
+    for (int p = 0; p < LP; ++p) {
+      const int q = q0 + pq + RP * p;
+      const bool ok = q < n_proj && aok;
+      const T v = pbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * d];
+      rp[p] = ok ? v : T(0);
+    }
+  };
+  acc_t acc[TN][TM];
+#pragma unroll
+  for (int u = 0; u < TN; ++u)
+#pragma unroll
+    for (int v = 0; v < TM; ++v) acc[u][v] = zero_acc<acc_t>();
+  const T* Aw = Cs + (wm * 16 * TN + c16) * KW + kk;
+  const T* Bw = Ps + (wn * 16 * TM + c16) * KW + kk;
+  fetch(0);
+  for (int q0 = 0; q0 < n_proj; q0 += KB) {
+#pragma unroll
+    for (int p = 0; p < LC; ++p) Cs[ci * KW + cq + RC * p] = rc[p];
+#pragma unroll
+    for (int p = 0; p < LP; ++p) Ps[pa_ * KW + pq + RP * p] = rp[p];
+    __syncthreads();
+    if (q0 + KB < n_proj) fetch(q0 + KB);
+#pragma unroll
+    for (int st = 0; st < KB / 4; ++st) {
+      T a[TN], b[TM];
+#pragma unroll
+      for (int u = 0; u < TN; ++u) a[u] = Aw[16 * u * KW + 4 * st];
+#pragma unroll
+      for (int v = 0; v < TM; ++v) b[v] = Bw[16 * v * KW + 4 * st];
+#pragma unroll
+      for (int u = 0; u < TN; ++u)
+#pragma unroll
+        for (int v = 0; v < TM; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < TN; ++u)
+#pragma unroll
+    for (int v = 0; v < TM; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = itb * BM + wm * 16 * TN + 16 * u + MF<T>::row(lane, r);
+        const int64_t a = static_cast<int64_t>(ga) * BN + wn * 16 * TM + 16 * v + c16;
+        if (i < k && a < d) Z[static_cast<int64_t>(i) * d + a] = acc[u][v][r];
       }
 }
 
@@ -200,6 +281,20 @@ void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, 
   k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
 }
 
+template <typename T>
+void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,
+                     hipStream_t s) {
+  constexpr int BM = 32 * KbShape<T>::TN, BN = 32 * KbShape<T>::TM;
+  const int nI = (k + BM - 1) / BM;
+  const int nA = static_cast<int>((d + BN - 1) / BN);
+  const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
+  k_kb_apply<T><<<nwg, 256, 0, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
+}
+
+template void launch_kb_apply<float>(const float*, int64_t, const float*, float*, int, int, int,
+                                     hipStream_t);
+template void launch_kb_apply<double>(const double*, int64_t, const double*, double*, int, int,
+                                      int, hipStream_t);
 template void launch_kb_gemm<float>(const float*, int64_t, const float*, int64_t, const float*,
                                     float*, float*, int, int, int, hipStream_t);
 template void launch_kb_gemm<double>(const double*, int64_t, const double*, int64_t,

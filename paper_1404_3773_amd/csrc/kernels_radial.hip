@@ -6,10 +6,10 @@
 //   coefficient index n.  Index math is hoisted out of the K-loops: table
 //   operands are zero-padded and streaming-operand addresses clamped.
 // radial_forward (eq. Arlm_to_coeff with eq. matvec_final's kinetic term):
-//   Z[n][i] = sum_r w_r R_ln(r) A[r][lm][i] + sum_q P[lm*N+n][q] C[q][i]
+//   Z[n][i] = sum_r w_r R_ln(r) A[r][lm][i] (+ Zkb[lm*N+n][i], the projector term)
 //   out = alpha (Z + (Lambda_ln/2 - c) Yin) + beta Yold
-//   per (l, m): M = N, K = n_r (+ n_proj), N = k; the last factor makes the
-//   kernel one step of the scaled Chebyshev recurrence.
+//   per (l, m): M = N, K = n_r, N = k; the last factor makes the kernel one
+//   step of the scaled Chebyshev recurrence.
 #include <hip/hip_runtime.h>
 
 #include "ces_internal.h"
@@ -126,15 +126,14 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
 
 // Workgroup: one (l, m), 32 columns; M = N split over the 4 waves (MT tiles
 // each, repeated past the last and not stored); K = n_r in chunks of four
-// k-steps with the next chunk's operands in flight, then n_proj for the
-// projector term.
+// k-steps with the next chunk's operands in flight.  The projector term
+// (column-major d x k, ld d) is added in the epilogue when Zkb is given.
 template <typename T, int MT>
 __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
     const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
     T* __restrict__ out, int64_t ldout, T alpha, T cshift, T beta, int kinetic,
-    const T* __restrict__ P, int n_proj, const T* __restrict__ C, int64_t d, int L, int N,
-    int n_r, int k, int kp) {
+    const T* __restrict__ Zkb, int64_t d, int L, int N, int n_r, int k, int kp) {
   typedef typename MF<T>::acc acc_t;
   const int R4 = rup(n_r, 4), N16 = rup(N, 16);
   const int lm = blockIdx.y;
@@ -195,25 +194,6 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
       for (int nt = 0; nt < RI_NT; ++nt) cb[t][nt] = nb[t][nt];
     }
   }
-  if (n_proj > 0) {
-    const T* Pl = P + static_cast<int64_t>(lm) * N;
-    const T* Cb = C + i0 + l16;
-    for (int q0 = 0; q0 < n_proj; q0 += 4) {
-      const int q = q0 + kk;
-      const int qc = min(q, n_proj - 1);
-      T b[RI_NT];
-#pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Cb[static_cast<int64_t>(qc) * kp + col[nt]];
-#pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const int n = mrow[u] + l16;
-        const T pv = Pl[static_cast<int64_t>(qc) * d + min(n, N - 1)];   // in-bounds address
-        const T a = (q < n_proj && n < N) ? pv : T(0);
-#pragma unroll
-        for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
-      }
-    }
-  }
 #pragma unroll
   for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
@@ -228,6 +208,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
         if (n >= N) continue;
         const int64_t row = static_cast<int64_t>(lm) * N + n;
         T z = acc[u][nt][v];
+        if (Zkb) z += Zkb[static_cast<int64_t>(i) * d + row];
         if (kinetic) {
           const T y = Yin[static_cast<int64_t>(i) * ldin + row];
           z += (lamh[static_cast<int64_t>(l) * N + n] - cshift) * y;
@@ -259,23 +240,20 @@ void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, i
 template <typename T>
 void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
                            int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
-                           T alpha, T cshift, T beta, bool kinetic, const T* kbP, int n_proj,
-                           const T* kbC, int k, int kp, hipStream_t s) {
+                           T alpha, T cshift, T beta, bool kinetic, const T* Zkb, int k, int kp,
+                           hipStream_t s) {
   dim3 grid((k + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
   const int mt = (rup(b.N, 16) / 16 + 3) / 4;   // N <= 192: at most 3 tiles per wave
   switch (mt) {
     case 1: k_radial_forward_mfma<T, 1><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
-                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
-                                                kp); break;
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
+                                                b.d, b.L, b.N, b.n_r, k, kp); break;
     case 2: k_radial_forward_mfma<T, 2><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
-                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
-                                                kp); break;
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
+                                                b.d, b.L, b.N, b.n_r, k, kp); break;
     default: k_radial_forward_mfma<T, 3><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, kbP,
-                                                kbP ? n_proj : 0, kbC, b.d, b.L, b.N, b.n_r, k,
-                                                kp); break;
+                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
+                                                b.d, b.L, b.N, b.n_r, k, kp); break;
   }
 }
 
@@ -284,7 +262,7 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                                          T*, int, int, hipStream_t);                          \
   template void launch_radial_forward<T>(const Basis&, const DevTables<T>&, const T*, const T*, \
                                          int64_t, const T*, int64_t, T*, int64_t, T, T, T, bool, \
-                                         const T*, int, const T*, int, int, hipStream_t);
+                                         const T*, int, int, hipStream_t);
 CES_INST(float)
 CES_INST(double)
 #undef CES_INST

@@ -158,7 +158,7 @@ ces_status ces_ks_potential(ces_ham hh, const double* d_rho, const double* d_rho
   launch_sub(d_rho, d_rho_ion, d_v, b.n_grid, s);                  // d_v <- rho - rho_ion
   launch_angular_analysis<double>(b, b.t64, d_v, A, 1, kp, s);     // dualing forward transform
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, tau, b.d, 1.0, 0.0, 0.0,
-                                false, nullptr, 0, nullptr, 1, kp, s);
+                                false, nullptr, 1, kp, s);
   hartree_to_grid(b, ly, d_work, tau, d_v, s);                      // d_v <- V_H
   launch_ks_finish(d_vext, d_rho, d_v, b.n_grid, s);                // + V_ext + V_x
   CES_HIP(hipGetLastError());
