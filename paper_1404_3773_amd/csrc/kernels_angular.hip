@@ -67,7 +67,9 @@ inline AngDims ang_dims(const Basis& b, int kp) {
 
 // Workgroup: one m-slot, 64 theta nodes (one 16-row tile per wave), 16 NT
 // columns i of one radial node r.  g[r][j][s][i] = sum_l Pm[m][l][j] G[r][lm][i].
-template <typename T, int LS_NT>
+// KS > 0 (L <= 4 KS): every operand of the K loop is loaded before the first
+// MFMA; KS = 0: the K loop streams its operands.
+template <typename T, int LS_NT, int KS>
 __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm,
                                                         const T* __restrict__ G,
                                                         T* __restrict__ g, AngDims D,
@@ -92,6 +94,28 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
   int col[LS_NT];
 #pragma unroll
   for (int nt = 0; nt < LS_NT; ++nt) col[nt] = min(nt * 16, D.kp - i0 - 16);
+  if constexpr (KS > 0) {
+    const int ks = (K + 3) >> 2;
+    T a[KS], b[KS][LS_NT];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      if (t >= ks) break;
+      // rows l >= L read row L - 1 and are masked where used
+      const int lc = min(m + 4 * t + kk, D.L - 1);
+      a[t] = Pa[lc * D.J64];
+      const int off = (lc * lc + lc + sgn * m) * D.kp;
+#pragma unroll
+      for (int nt = 0; nt < LS_NT; ++nt) b[t][nt] = Gr[off + col[nt]];
+    }
+    __builtin_amdgcn_sched_barrier(0);   // every load issued before the first MFMA
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      if (t >= ks) break;
+      const T av = m + 4 * t + kk < D.L ? a[t] : T(0);
+#pragma unroll
+      for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(av, b[t][nt], acc[nt]);
+    }
+  } else {
   // steps whose four l rows are all below L: row offset (l^2 + l + sgn m) kp
   // advanced by second differences (l grows by 4 per step)
   const int nfull = K >> 2;
@@ -121,6 +145,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
     const int off = (lc * lc + lc + sgn * m) * D.kp;
 #pragma unroll
     for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(a, Gr[off + col[nt]], acc[nt]);
+  }
   }
   T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
 #pragma unroll
@@ -297,7 +322,10 @@ constexpr int LA_SW = 4;   // m-slots per workgroup, one per wave
 
 // Workgroup: 32 columns of one radial node and four m-slots (one per wave).
 // A[r][lm][i] = sum_j w_j Pm[m][l][j] gh[r][j][s][i].
-template <typename T>
+// JK > 0 (n_theta <= 4 JK, L <= 32): every operand is loaded before the first
+// MFMA and both l-tiles of the slot share the loaded gh; JK = 0: theta streams
+// in 16-row chunks per l-tile.
+template <typename T, int JK>
 __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__ PwT,
                                                            const T* __restrict__ g,
                                                            T* __restrict__ A, AngDims D,
@@ -323,6 +351,51 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 #pragma unroll
   for (int nt = 0; nt < LA_NT; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
   T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
+  if constexpr (JK > 0) {
+    constexpr int MT = 2;                  // L <= 32
+    const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + l16;
+    T a[JK][MT], b[JK][LA_NT];
+    // all JK k-steps (no early exit, so the loops unroll): rows past n_theta
+    // read row n_theta - 1 and are masked where used
+#pragma unroll
+    for (int t = 0; t < JK; ++t) {
+      const int jc = min(4 * t + kk, D.n_theta - 1);
+#pragma unroll
+      for (int u = 0; u < MT; ++u) a[t][u] = Pa[jc * D.L16 + 16 * u];
+#pragma unroll
+      for (int nt = 0; nt < LA_NT; ++nt) b[t][nt] = gb[jc * jstride + col[nt]];
+    }
+    __builtin_amdgcn_sched_barrier(0);     // every load issued before the first MFMA
+    acc_t acc[MT][LA_NT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+      for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+#pragma unroll
+    for (int t = 0; t < JK; ++t) {
+      const bool ok = 4 * t + kk < D.n_theta;
+#pragma unroll
+      for (int u = 0; u < MT; ++u) {
+        const T av = ok ? a[t][u] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[t][nt], acc[u][nt]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+      if (u >= nmt) break;
+#pragma unroll
+      for (int nt = 0; nt < LA_NT; ++nt) {
+        if (nt >= nt_valid) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int l = m + u * 16 + MF<T>::row(lane, v);
+          if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + i0 + nt * 16] = acc[u][nt][v];
+        }
+      }
+    }
+    return;
+  }
   for (int u = 0; u < nmt; ++u) {          // uniform loop over 16-row tiles of l
     const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + u * 16 + l16;
     acc_t acc[LA_NT];
@@ -378,14 +451,21 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
                            hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
   // two column tiles when the block is narrow (no idle MFMA columns), else four
+  // (short K loops, L <= 32, load all their operands at once)
   if (kp <= 32) {
     const int n_ic = (kp + 31) / 32;
     dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    k_legendre_synth<T, 2><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    if (b.L <= 32)
+      k_legendre_synth<T, 2, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    else
+      k_legendre_synth<T, 2, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   } else {
     const int n_ic = (kp + 63) / 64;
     dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    k_legendre_synth<T, 4><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    if (b.L <= 32)
+      k_legendre_synth<T, 4, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    else
+      k_legendre_synth<T, 4, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   }
 }
 
@@ -415,7 +495,10 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   const AngDims D = ang_dims(b, kp);
   const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
-  k_legendre_analysis<T><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  if (b.L <= 32 && b.n_theta <= 64)
+    k_legendre_analysis<T, 16><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  else
+    k_legendre_analysis<T, 0><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
 }
 
 #define CES_INST(T)                                                                          \

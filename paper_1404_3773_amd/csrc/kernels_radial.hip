@@ -37,7 +37,7 @@ __host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 // X tile (N rows x 32 columns, zero-padded to a multiple of 16 rows) is staged
 // in LDS; the table operand is read in chunks of four k-steps, the next chunk
 // in flight while the current one runs.
-template <typename T, int MT>
+template <typename T, int MT, int CK>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
                                                              int64_t ldx, T* __restrict__ G,
@@ -51,14 +51,6 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
   const int lm = blockIdx.y;
   const int l = isqrt_lm(lm);
   const int i0 = blockIdx.x * CW;
-  {
-    const T* Xl = X + static_cast<int64_t>(lm) * N;
-    const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
-    const bool iok = i0 + ii < k;
-    const T* xc = Xl + static_cast<int64_t>(i0 + ii) * ldx;
-    for (int n = n0; n < N16; n += 8) Xs[n * XW + ii] = (iok && n < N) ? xc[n] : T(0);
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
@@ -67,44 +59,76 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
   int mrow[MT];
 #pragma unroll
   for (int u = 0; u < MT; ++u) mrow[u] = min(wave + 4 * u, nmt - 1) * 16;
+  // table operand in chunks of CK k-steps (4 CK rows n)
+  auto load = [&](int chunk, T (*a)[MT]) {
+#pragma unroll
+    for (int t = 0; t < CK; ++t) {
+      // rows past N4 read row N4 - 1 and are masked where used (a select
+      // here would wait for each load)
+      const int nc = min(chunk * 4 * CK + t * 4 + kk, N4 - 1);
+#pragma unroll
+      for (int u = 0; u < MT; ++u) a[t][u] = Rl[static_cast<int64_t>(nc) * R16 + mrow[u]];
+    }
+  };
+  T ca[CK][MT];
+  load(0, ca);   // the first chunk is in flight with the X tile below
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    // X tile: thread (column ii, rows n0 + 8 q), every load issued before the
+    // LDS writes; N16 <= 4 CK rows in one chunk, N <= 192 otherwise
+    constexpr int XQ = CK > 4 ? CK / 2 : 24;
+    const T* Xl = X + static_cast<int64_t>(lm) * N;
+    const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
+    const bool iok = i0 + ii < k;
+    const T* xc = Xl + static_cast<int64_t>(min(i0 + ii, k - 1)) * ldx;
+    T xv[XQ];
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) xv[q] = xc[min(n0 + 8 * q, N - 1)];
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int n = n0 + 8 * q;
+      if (n < N16) Xs[n * XW + ii] = (iok && n < N) ? xv[q] : T(0);
+    }
+  }
+  __syncthreads();
   acc_t acc[MT][RI_NT];
 #pragma unroll
   for (int u = 0; u < MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-  const int nch = N16 / 16;
-  T ca[4][MT], na[4][MT];
-  auto load = [&](int chunk, T (*a)[MT]) {
+  auto step = [&](int n, const T* a) {
+    T b[RI_NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = chunk * 16 + t * 4 + kk;
-      const bool ok = n < N4;                       // table rows N..N4-1 are zero
-      const int nc = ok ? n : N4 - 1;
+    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
+    const bool ok = n < N4;                       // table rows N..N4-1 are zero
 #pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const T v = Rl[static_cast<int64_t>(nc) * R16 + mrow[u]];
-        a[t][u] = ok ? v : T(0);
-      }
+    for (int u = 0; u < MT; ++u) {
+      const T av = ok ? a[u] : T(0);
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[nt], acc[u][nt]);
     }
   };
-  load(0, ca);
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) load(c + 1, na);
+  if constexpr (CK > 4) {                         // whole contraction in one chunk (N16 <= 4 CK)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = c * 16 + t * 4 + kk;
-      T b[RI_NT];
-#pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
-#pragma unroll
-      for (int u = 0; u < MT; ++u)
-#pragma unroll
-        for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(ca[t][u], b[nt], acc[u][nt]);
+    for (int t = 0; t < CK; ++t) {
+      if (4 * t >= N16) break;                    // Xs holds N16 rows
+      step(t * 4 + kk, ca[t]);
     }
+  } else {
+    const int nch = (N16 + 4 * CK - 1) / (4 * CK);
+    T na[CK][MT];
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load(c + 1, na);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < CK; ++t) {
+        if (c * 4 * CK + 4 * t >= N16) break;
+        step(c * 4 * CK + t * 4 + kk, ca[t]);
+      }
 #pragma unroll
-      for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
+      for (int t = 0; t < CK; ++t)
+#pragma unroll
+        for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
+    }
   }
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
   T* Gb = G + static_cast<int64_t>(lm) * kp + i0 + l16;
@@ -128,7 +152,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
 // each, repeated past the last and not stored); K = n_r in chunks of four
 // k-steps with the next chunk's operands in flight.  The projector term
 // (column-major d x k, ld d) is added in the epilogue when Zkb is given.
-template <typename T, int MT>
+template <typename T, int MT, int CK>
 __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
     const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
@@ -158,63 +182,99 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   const T* Rl = RfT + static_cast<int64_t>(l) * R4 * N16 + l16;
   const T* Ab = A + static_cast<int64_t>(lm) * kp + i0 + l16;
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
-  const int nch = (R4 + 15) / 16;
-  T ca[4][MT], cb[4][RI_NT], na[4][MT], nb[4][RI_NT];
-  auto load = [&](int chunk, T (*a)[MT], T (*b)[RI_NT]) {
+  // operands in chunks of CK k-steps (4 CK radial nodes)
+  auto load = [&](int chunk, T (*a)[MT], T (*b)[RI_NT]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = chunk * 16 + t * 4 + kk;
-      const bool ok = r < R4;                       // table rows n_r..R4-1 are zero
-      const int rt = ok ? r : R4 - 1;
+    for (int t = 0; t < CK; ++t) {
+      // rows past R4 read row R4 - 1 and are masked where used (a select
+      // here would wait for each load)
+      const int r = chunk * 4 * CK + t * 4 + kk;
+      const int rt = min(r, R4 - 1);
       const int64_t roff = static_cast<int64_t>(min(r, n_r - 1)) * rstride;
 #pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const T v = Rl[static_cast<int64_t>(rt) * N16 + mrow[u]];
-        a[t][u] = ok ? v : T(0);
-      }
+      for (int u = 0; u < MT; ++u) a[t][u] = Rl[static_cast<int64_t>(rt) * N16 + mrow[u]];
 #pragma unroll
       for (int nt = 0; nt < RI_NT; ++nt) b[t][nt] = Ab[roff + col[nt]];
     }
   };
+  // transposed product Z^T = A^T Rf: the streamed A block is the MFMA A
+  // operand and the table the B operand, so the result has lanes along n
+  // and the epilogue reads and writes runs of n in each column i
+  auto step = [&](int r, const T* a, const T* b) __attribute__((always_inline)) {
+    const bool ok = r < R4;                         // table rows n_r..R4-1 are zero
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+      const T av = ok ? a[u] : T(0);
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(b[nt], av, acc[u][nt]);
+    }
+  };
+  T ca[CK][MT], cb[CK][RI_NT];
   load(0, ca, cb);
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) load(c + 1, na, nb);
+  // epilogue operands (lanes along n, registers along i): in the one-chunk
+  // form they are loaded with the contraction's, so the epilogue waits for
+  // nothing new; indices clamped into the block, invalid entries not stored
+  constexpr int EP = CK > 4 ? 1 : 0;
+  T yin[MT][RI_NT][4 * EP + 1 - EP], yold[MT][RI_NT][4 * EP + 1 - EP];
+  auto epi_load = [&](const T* Y, int64_t ld, T (*y)[RI_NT][4 * EP + 1 - EP]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int u = 0; u < MT; ++u) {
+      const int64_t row = static_cast<int64_t>(lm) * N + min(mrow[u] + l16, N - 1);
 #pragma unroll
-      for (int u = 0; u < MT; ++u)
+      for (int nt = 0; nt < RI_NT; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < RI_NT; ++nt)
-          acc[u][nt] = MF<T>::mma(ca[t][u], cb[t][nt], acc[u][nt]);
+        for (int v = 0; v < 4 * EP; ++v)
+          y[u][nt][v] = Y[min(i0 + nt * 16 + MF<T>::row(lane, v), k - 1) * ld + row];
+    }
+  };
+  if constexpr (EP) {
+    if (kinetic) epi_load(Yin, ldin, yin);
+    if (beta != T(0)) epi_load(Yold, ldold, yold);
+  }
+  __builtin_amdgcn_sched_barrier(0);   // issue every load of the chunk before the first MFMA
+  if constexpr (CK > 4) {   // whole contraction in one chunk (R4 <= 4 CK; rows past R4 are zero)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < CK; ++t) step(4 * t + kk, ca[t], cb[t]);
+  } else {
+    const int nch = (R4 + 4 * CK - 1) / (4 * CK);
+    T na[CK][MT], nb[CK][RI_NT];
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load(c + 1, na, nb);
 #pragma unroll
-      for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
+      for (int t = 0; t < CK; ++t) {
+        if (c * 4 * CK + 4 * t >= R4) break;
+        step(c * 4 * CK + 4 * t + kk, ca[t], cb[t]);
+      }
 #pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) cb[t][nt] = nb[t][nt];
+      for (int t = 0; t < CK; ++t) {
+#pragma unroll
+        for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
+#pragma unroll
+        for (int nt = 0; nt < RI_NT; ++nt) cb[t][nt] = nb[t][nt];
+      }
     }
   }
 #pragma unroll
   for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
+    const int n = mt * 16 + l16;
+    if (n >= N) continue;
+    const int64_t row = static_cast<int64_t>(lm) * N + n;
+    const T kin = kinetic ? lamh[static_cast<int64_t>(l) * N + n] - cshift : T(0);
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) {
-      const int i = i0 + nt * 16 + l16;
-      if (i >= k) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int n = mt * 16 + MF<T>::row(lane, v);
-        if (n >= N) continue;
-        const int64_t row = static_cast<int64_t>(lm) * N + n;
+        // columns of a tile past kp were clamped onto valid data: skip them
+        const int i = i0 + nt * 16 + MF<T>::row(lane, v);
+        if (i >= k || i0 + nt * 16 >= kp) continue;
         T z = acc[u][nt][v];
         if (Zkb) z += Zkb[static_cast<int64_t>(i) * d + row];
-        if (kinetic) {
-          const T y = Yin[static_cast<int64_t>(i) * ldin + row];
-          z += (lamh[static_cast<int64_t>(l) * N + n] - cshift) * y;
-        }
+        if (kinetic) z += kin * (EP ? yin[u][nt][v * EP] : Yin[static_cast<int64_t>(i) * ldin + row]);
         T val = alpha * z;
-        if (beta != T(0)) val += beta * Yold[static_cast<int64_t>(i) * ldold + row];
+        if (beta != T(0))
+          val += beta * (EP ? yold[u][nt][v * EP] : Yold[static_cast<int64_t>(i) * ldold + row]);
         out[static_cast<int64_t>(i) * ldout + row] = val;
       }
     }
@@ -223,17 +283,48 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
 
 }  // namespace
 
-template <typename T>
-void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
-                           T* G, int k, int kp, hipStream_t s) {
+// Short contractions (N <= 64 for the inverse, n_r <= 96 for the forward)
+// load every operand fragment at once (CK > 4: one chunk of CK k-steps);
+// longer ones stream 16-row chunks (CK = 4) with the next chunk in flight.
+template <typename T, int CK>
+void radial_inverse_ck(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx, T* G,
+                       int k, int kp, hipStream_t s) {
   dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
   const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 1) * sizeof(T);
   const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
   switch (mt) {
-    case 1: k_radial_inverse_mfma<T, 1><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 2: k_radial_inverse_mfma<T, 2><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 3: k_radial_inverse_mfma<T, 3><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    default: k_radial_inverse_mfma<T, 4><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 1: k_radial_inverse_mfma<T, 1, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 2: k_radial_inverse_mfma<T, 2, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 3: k_radial_inverse_mfma<T, 3, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    default: k_radial_inverse_mfma<T, 4, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+  }
+}
+
+template <typename T>
+void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
+                           T* G, int k, int kp, hipStream_t s) {
+  if (rup(b.N, 16) <= 64) return radial_inverse_ck<T, 16>(b, tb, X, ldx, G, k, kp, s);
+  radial_inverse_ck<T, 4>(b, tb, X, ldx, G, k, kp, s);
+}
+
+template <typename T, int CK>
+void radial_forward_ck(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
+                       int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
+                       T alpha, T cshift, T beta, bool kinetic, const T* Zkb, int k, int kp,
+                       hipStream_t s) {
+  dim3 grid((k + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
+  const int mt = (rup(b.N, 16) / 16 + 3) / 4;   // N <= 192: at most 3 tiles per wave
+  const int kin = kinetic ? 1 : 0;
+  switch (mt) {
+    case 1: k_radial_forward_mfma<T, 1, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                    ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                    b.n_r, k, kp); break;
+    case 2: k_radial_forward_mfma<T, 2, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                    ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                    b.n_r, k, kp); break;
+    default: k_radial_forward_mfma<T, 3, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+                                                     ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                     b.n_r, k, kp); break;
   }
 }
 
@@ -242,19 +333,18 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                            int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
                            T alpha, T cshift, T beta, bool kinetic, const T* Zkb, int k, int kp,
                            hipStream_t s) {
-  dim3 grid((k + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
-  const int mt = (rup(b.N, 16) / 16 + 3) / 4;   // N <= 192: at most 3 tiles per wave
-  switch (mt) {
-    case 1: k_radial_forward_mfma<T, 1><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
-                                                b.d, b.L, b.N, b.n_r, k, kp); break;
-    case 2: k_radial_forward_mfma<T, 2><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
-                                                b.d, b.L, b.N, b.n_r, k, kp); break;
-    default: k_radial_forward_mfma<T, 3><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                ldout, alpha, cshift, beta, kinetic ? 1 : 0, Zkb,
-                                                b.d, b.L, b.N, b.n_r, k, kp); break;
-  }
+  const int ks = rup(b.n_r, 4) / 4;   // k-steps of the contraction over r
+  if (ks <= 8)
+    return radial_forward_ck<T, 8>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+                                   beta, kinetic, Zkb, k, kp, s);
+  if (ks <= 16)
+    return radial_forward_ck<T, 16>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+                                    beta, kinetic, Zkb, k, kp, s);
+  if (ks <= 24)
+    return radial_forward_ck<T, 24>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+                                    beta, kinetic, Zkb, k, kp, s);
+  radial_forward_ck<T, 4>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift, beta,
+                          kinetic, Zkb, k, kp, s);
 }
 
 #define CES_INST(T)                                                                           \
