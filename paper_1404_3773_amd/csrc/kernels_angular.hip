@@ -97,23 +97,30 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
   if constexpr (KS > 0) {
     const int ks = (K + 3) >> 2;
     T a[KS], b[KS][LS_NT];
+    // up to 8 k-steps the loops exit early; longer ones take uniform guards
+    // instead, which keeps them unrolled (an early exit there leaves a rolled
+    // loop indexing the operand arrays through scratch)
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
-      if (t >= ks) break;
-      // rows l >= L read row L - 1 and are masked where used
-      const int lc = min(m + 4 * t + kk, D.L - 1);
-      a[t] = Pa[lc * D.J64];
-      const int off = (lc * lc + lc + sgn * m) * D.kp;
+      if (KS <= 8 && t >= ks) break;
+      if (t < ks) {
+        // rows l >= L read row L - 1 and are masked where used
+        const int lc = min(m + 4 * t + kk, D.L - 1);
+        a[t] = Pa[lc * D.J64];
+        const int off = (lc * lc + lc + sgn * m) * D.kp;
 #pragma unroll
-      for (int nt = 0; nt < LS_NT; ++nt) b[t][nt] = Gr[off + col[nt]];
+        for (int nt = 0; nt < LS_NT; ++nt) b[t][nt] = Gr[off + col[nt]];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);   // every load issued before the first MFMA
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
-      if (t >= ks) break;
-      const T av = m + 4 * t + kk < D.L ? a[t] : T(0);
+      if (KS <= 8 && t >= ks) break;
+      if (t < ks) {
+        const T av = m + 4 * t + kk < D.L ? a[t] : T(0);
 #pragma unroll
-      for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(av, b[t][nt], acc[nt]);
+        for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(av, b[t][nt], acc[nt]);
+      }
     }
   } else {
   // steps whose four l rows are all below L: row offset (l^2 + l + sgn m) kp
@@ -321,11 +328,14 @@ constexpr int LA_NT = 2;   // 16-column tiles per wave (32 columns per workgroup
 constexpr int LA_SW = 4;   // m-slots per workgroup, one per wave
 
 // Workgroup: 32 columns of one radial node and four m-slots (one per wave).
-// A[r][lm][i] = sum_j w_j Pm[m][l][j] gh[r][j][s][i].
-// JK > 0 (n_theta <= 4 JK, L <= 32): every operand is loaded before the first
-// MFMA and both l-tiles of the slot share the loaded gh; JK = 0: theta streams
-// in 16-row chunks per l-tile.
-template <typename T, int JK>
+// A[r][lm][i] = sum_j w_j Pm[m][l][j] gh[r][j][s][i].  Each wave computes all
+// l-tiles of its slot (MT covers L) from one pass over gh, so gh is read once.
+// Theta is taken CH k-steps (4 CH rows) at a time: with ONE (n_theta <= 4 CH)
+// every operand is loaded before the first MFMA, otherwise chunks stream with
+// the next one in flight while the current one runs.  Rows past n_theta read
+// row n_theta - 1 and get a zero weight where used (a select on the load would
+// make it wait).
+template <typename T, int MT, int CH, bool ONE>
 __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__ PwT,
                                                            const T* __restrict__ g,
                                                            T* __restrict__ A, AngDims D,
@@ -341,8 +351,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
   const int l16 = lane & 15, kk = lane >> 4;
   const int i0 = (blockIdx.x - r * n_ic) * (16 * LA_NT);
   const int nt_valid = min(LA_NT, (D.kp - i0) / 16);
-  const int M = D.L - m;
-  const int nmt = (M + 15) / 16;
+  const int nmt = (D.L - m + 15) / 16;     // l-tiles of this slot (<= MT)
   const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
   const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp;
   // column of each N-tile, clamped into the block (tiles past nt_valid are
@@ -350,95 +359,69 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
   int col[LA_NT];
 #pragma unroll
   for (int nt = 0; nt < LA_NT; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
-  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
-  if constexpr (JK > 0) {
-    constexpr int MT = 2;                  // L <= 32
-    const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + l16;
-    T a[JK][MT], b[JK][LA_NT];
-    // all JK k-steps (no early exit, so the loops unroll): rows past n_theta
-    // read row n_theta - 1 and are masked where used
+  const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + l16;
+  acc_t acc[MT][LA_NT];
 #pragma unroll
-    for (int t = 0; t < JK; ++t) {
-      const int jc = min(4 * t + kk, D.n_theta - 1);
+  for (int u = 0; u < MT; ++u)
 #pragma unroll
-      for (int u = 0; u < MT; ++u) a[t][u] = Pa[jc * D.L16 + 16 * u];
+    for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+  auto load = [&](int c, T (*a)[MT], T (*b)[LA_NT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int jc = min(c * 4 * CH + 4 * t + kk, D.n_theta - 1);
+#pragma unroll
+      for (int u = 0; u < MT; ++u)
+        if (u < nmt) a[t][u] = Pa[jc * D.L16 + 16 * u];
 #pragma unroll
       for (int nt = 0; nt < LA_NT; ++nt) b[t][nt] = gb[jc * jstride + col[nt]];
     }
-    __builtin_amdgcn_sched_barrier(0);     // every load issued before the first MFMA
-    acc_t acc[MT][LA_NT];
-#pragma unroll
-    for (int u = 0; u < MT; ++u)
-#pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
-#pragma unroll
-    for (int t = 0; t < JK; ++t) {
-      const bool ok = 4 * t + kk < D.n_theta;
-#pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const T av = ok ? a[t][u] : T(0);
-#pragma unroll
-        for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[t][nt], acc[u][nt]);
-      }
-    }
+  };
+  auto step = [&](int j, const T* a, const T* b) __attribute__((always_inline)) {
+    const bool ok = j < D.n_theta;
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
-      if (u >= nmt) break;
+      if (u < nmt) {
+        const T av = ok ? a[u] : T(0);
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) {
-        if (nt >= nt_valid) break;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int l = m + u * 16 + MF<T>::row(lane, v);
-          if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + i0 + nt * 16] = acc[u][nt][v];
-        }
+        for (int nt = 0; nt < LA_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[nt], acc[u][nt]);
       }
     }
-    return;
-  }
-  for (int u = 0; u < nmt; ++u) {          // uniform loop over 16-row tiles of l
-    const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16 + u * 16 + l16;
-    acc_t acc[LA_NT];
+  };
+  T ca[CH][MT], cb[CH][LA_NT];
+  load(0, ca, cb);
+  __builtin_amdgcn_sched_barrier(0);     // the chunk's loads go out before its MFMAs
+  if constexpr (ONE) {
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = zero_acc<acc_t>();
-    // theta in chunks of 16 rows (four MFMA k-steps); the next chunk's
-    // operands are loaded into registers while the current chunk runs.
-    // Rows past n_theta get zero weights (and read row n_theta - 1).
-    const int nch = (D.n_theta + 15) >> 4;
-    T ca[4], cb[4][LA_NT], na[4], nb[4][LA_NT];
-    auto load = [&](int chunk, T* a, T (*b)[LA_NT]) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = chunk * 16 + t * 4 + kk;
-        const bool ok = j < D.n_theta;
-        const int jc = ok ? j : D.n_theta - 1;
-        const T av = Pa[jc * D.L16];
-        a[t] = ok ? av : T(0);
-#pragma unroll
-        for (int nt = 0; nt < LA_NT; ++nt) b[t][nt] = gb[jc * jstride + col[nt]];
-      }
-    };
-    load(0, ca, cb);
+    for (int t = 0; t < CH; ++t) step(4 * t + kk, ca[t], cb[t]);
+  } else {
+    const int nch = (D.n_theta + 4 * CH - 1) / (4 * CH);
+    T na[CH][MT], nb[CH][LA_NT];
     for (int c = 0; c < nch; ++c) {
       if (c + 1 < nch) load(c + 1, na, nb);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < CH; ++t) step(c * 4 * CH + 4 * t + kk, ca[t], cb[t]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int nt = 0; nt < LA_NT; ++nt) acc[nt] = MF<T>::mma(ca[t], cb[t][nt], acc[nt]);
+      for (int t = 0; t < CH; ++t) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        ca[t] = na[t];
+        for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
 #pragma unroll
         for (int nt = 0; nt < LA_NT; ++nt) cb[t][nt] = nb[t][nt];
       }
     }
+  }
+  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    if (u >= nmt) break;
 #pragma unroll
     for (int nt = 0; nt < LA_NT; ++nt) {
       if (nt >= nt_valid) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int l = m + u * 16 + MF<T>::row(lane, v);
-        if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + i0 + nt * 16] = acc[nt][v];
+        if (l < D.L) Ar[(l * l + l + sgn * m) * D.kp + i0 + nt * 16] = acc[u][nt][v];
       }
     }
   }
@@ -451,12 +434,16 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
                            hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
   // two column tiles when the block is narrow (no idle MFMA columns), else four
-  // (short K loops, L <= 32, load all their operands at once)
+  // (K loops of up to 8 k-steps, L <= 32, load all their operands at once;
+  // up to 16 (L <= 64) in FP32, where the registers allow it)
+  constexpr bool f32 = sizeof(T) == 4;
   if (kp <= 32) {
     const int n_ic = (kp + 31) / 32;
     dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
     if (b.L <= 32)
       k_legendre_synth<T, 2, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    else if (f32 && b.L <= 64)
+      k_legendre_synth<T, 2, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
     else
       k_legendre_synth<T, 2, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   } else {
@@ -464,6 +451,8 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
     dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
     if (b.L <= 32)
       k_legendre_synth<T, 4, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    else if (f32 && b.L <= 64)
+      k_legendre_synth<T, 4, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
     else
       k_legendre_synth<T, 4, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   }
@@ -495,10 +484,18 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   const AngDims D = ang_dims(b, kp);
   const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
-  if (b.L <= 32 && b.n_theta <= 64)
-    k_legendre_analysis<T, 16><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
-  else
-    k_legendre_analysis<T, 0><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  constexpr bool f32 = sizeof(T) == 4;
+  // l-tiles per slot cover L; theta chunks sized to the registers left
+  if (b.L <= 32) {
+    if (b.n_theta <= 64)
+      k_legendre_analysis<T, 2, 16, true><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+    else
+      k_legendre_analysis<T, 2, 8, false><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  } else if (b.L <= 64) {
+    k_legendre_analysis<T, 4, f32 ? 8 : 4, false><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  } else {   // L <= 96
+    k_legendre_analysis<T, 6, f32 ? 4 : 2, false><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic);
+  }
 }
 
 #define CES_INST(T)                                                                          \
