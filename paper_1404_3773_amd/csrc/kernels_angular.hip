@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 //   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
 //   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
 constexpr int PS_NT = 2;             // 16-column tiles per workgroup
-constexpr int kPhiWorkgroups = 1024; // resident rows in flight (4 per CU)
+constexpr int kPhiWorkgroups = 1792; // resident rows in flight (7 per CU)
 
 // phi stage: gh = C g per (r, theta_j) row, C the (2L-1)^2 coupling of the
 // product-to-sum identity above.  K (input slots) and M (output slots) are
@@ -184,7 +184,11 @@ constexpr int kPhiWorkgroups = 1024; // resident rows in flight (4 per CU)
 //   (out sin, in cos) -b_q  + b_p       (out sin, in sin)  a_|q| - a_p
 // with q = m - m', p = m + m'.  Each block entry is T[k - r + LP] + H[k + r]
 // for block-local input / output indices k, r, from six LDS tables of 2 LP
-// values built per row, so an A operand costs two LDS reads and one add.
+// values per row, so an A operand costs two LDS reads and one add.  Every
+// table entry is one of the row's Fourier sums times +1, -1 or 0, fixed by
+// its position alone: each thread works out the source and sign of its
+// entries once, and fetches their values with the row's g block, one row
+// ahead, so a row takes one LDS fill and two barriers.
 template <typename T, int LP>
 __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
                                                    AngDims D, int64_t n_rows) {
@@ -192,16 +196,17 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   constexpr int GW = 16 * PS_NT + 1;
   constexpr int K2 = 2 * LP, NMT = K2 / 16, MT = (NMT + 3) / 4;   // M-tiles per wave
   constexpr int GPT = K2 / 8;                   // g values per thread per row
+  constexpr int NE = (6 * K2 + 255) / 256;      // table entries per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int S = D.S, L = D.L;
   T* tab = reinterpret_cast<T*>(smem_raw);     // 6 tables of K2 values
-  T* abs_ = tab + 6 * K2;                       // raw Fourier sums of the row, 2S <= 2 K2
-  T* gs = abs_ + 2 * K2;                        // [K2][GW]
+  T* gs = tab + 6 * K2;                         // [K2][GW]
   const int i0 = blockIdx.y * (16 * PS_NT);
   const int nt_valid = min(PS_NT, (D.kp - i0) / 16);
   const int tid = threadIdx.x;
   const int ii = tid & 31, kr = tid >> 5;
-  // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j)
+  // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j);
+  // rows past the slots read offset 0 and are written as zero
   int soff[GPT];
   bool sok[GPT];
 #pragma unroll
@@ -210,21 +215,43 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
     const bool sn = k >= LP;
     const int kl = sn ? k - LP : k;
     sok[u] = (sn ? kl < L - 1 : kl < L) && i0 + ii < D.kp;
-    soff[u] = (sn ? L + kl : kl) * D.kp + i0 + ii;
+    soff[u] = sok[u] ? (sn ? L + kl : kl) * D.kp + i0 + ii : 0;
+  }
+  // this thread's table entries E = tid + 256 v (table E / K2, index E % K2):
+  // value = sign * ab[src] with the row's sums a_x at x, b_x at S + x (x < S);
+  // with q = index - LP:
+  //   T0 a_|q|   T1 b_{q+1}   T2 -b_{q-1}   (b odd: b_{-x} = -b_x)
+  //   H3 a_h     H4 b_{h+1}   H5 -a_{h+2}   (h = index; zero past S)
+  int esrc[NE];
+  T esgn[NE];
+#pragma unroll
+  for (int v = 0; v < NE; ++v) {
+    const int E = tid + 256 * v;
+    const int t = E / K2, e = E - t * K2, q = e - LP;
+    int x = 0, base = 0;
+    T sg = T(1);
+    switch (t) {
+      case 0: x = q < 0 ? -q : q; break;
+      case 1: x = q + 1 < 0 ? -(q + 1) : q + 1; base = S; sg = q + 1 >= 0 ? T(1) : T(-1); break;
+      case 2: x = q - 1 < 0 ? -(q - 1) : q - 1; base = S; sg = q - 1 >= 0 ? T(-1) : T(1); break;
+      case 3: x = e; break;
+      case 4: x = e + 1; base = S; break;
+      default: x = e + 2; sg = T(-1); break;
+    }
+    const bool ok = E < 6 * K2 && x < S;
+    esrc[v] = ok ? base + x : 0;
+    esgn[v] = ok ? sg : T(0);
   }
   const int64_t rstride = static_cast<int64_t>(S) * D.kp;
   // registers holding the next row (software pipeline across rows)
-  T gp[GPT], ap[2];
+  T gp[GPT], ap[NE];
   auto fetch = [&](int64_t row) {
     const T* gr = g + row * rstride;
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) gp[u] = sok[u] ? gr[soff[u]] : T(0);
+    for (int u = 0; u < GPT; ++u) gp[u] = gr[soff[u]];
     const T* abr = ab + row * 2 * S;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int e = tid + 256 * v;
-      ap[v] = e < 2 * S ? abr[e] : T(0);
-    }
+    for (int v = 0; v < NE; ++v) ap[v] = abr[esrc[v]];
   };
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -245,30 +272,14 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   if (row < n_rows) fetch(row);
   for (; row < n_rows; row += gridDim.x) {
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) gs[(kr + 8 * u) * GW + ii] = gp[u];
+    for (int u = 0; u < GPT; ++u) gs[(kr + 8 * u) * GW + ii] = sok[u] ? gp[u] : T(0);
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int e = tid + 256 * v;
-      if (e < 2 * S) abs_[e] = ap[v];
+    for (int v = 0; v < NE; ++v) {
+      const int E = tid + 256 * v;
+      if (E < 6 * K2) tab[E] = esgn[v] * ap[v];
     }
     __syncthreads();
-    for (int e = tid; e < K2; e += blockDim.x) {
-      // a_x, b_x for x >= 0 (zero past the stored 0..S-1); b is odd in x
-      const int q = e - LP;
-      const int aq = q < 0 ? -q : q;
-      const int q1 = q + 1, q2 = q - 1;
-      const int a1 = q1 < 0 ? -q1 : q1, a2 = q2 < 0 ? -q2 : q2;
-      const T bq1 = a1 < S ? abs_[S + a1] : T(0);
-      const T bq2 = a2 < S ? abs_[S + a2] : T(0);
-      tab[e] = aq < S ? abs_[aq] : T(0);                         // T cc, ss:  a_|q|
-      tab[K2 + e] = q1 >= 0 ? bq1 : -bq1;                        // T cs:  b_{q+1}
-      tab[2 * K2 + e] = q2 >= 0 ? -bq2 : bq2;                    // T sc: -b_{q-1}
-      tab[3 * K2 + e] = e < S ? abs_[e] : T(0);                  // H cc:  a_h
-      tab[4 * K2 + e] = e + 1 < S ? abs_[S + e + 1] : T(0);      // H cs, sc: b_{h+1}
-      tab[5 * K2 + e] = e + 2 < S ? -abs_[e + 2] : T(0);         // H ss: -a_{h+2}
-    }
     if (row + gridDim.x < n_rows) fetch(row + gridDim.x);     // next row, in flight
-    __syncthreads();
     acc_t acc[MT][PS_NT];
 #pragma unroll
     for (int u = 0; u < MT; ++u)
@@ -467,7 +478,7 @@ void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t 
   const int ncg = (kp + 16 * PS_NT - 1) / (16 * PS_NT);
   const int64_t want = std::max<int64_t>(1, kPhiWorkgroups / ncg);
   dim3 grid(static_cast<unsigned>(std::min(n_rows, want)), ncg);
-  const size_t lds = (8 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
+  const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
   switch (D.L16) {   // L <= 96 (checked at basis creation)
     case 16: k_phi_stage<T, 16><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
     case 32: k_phi_stage<T, 32><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
