@@ -65,22 +65,22 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   // are formed per load (keeps the register count at three waves per SIMD)
   const int kc = tid % KB, r0 = tid / KB;
   const int arow0 = mtb * BM + r0, bcol0 = ntb * BN + r0;
+  // loads read clamped addresses and are masked when stored to LDS (a
+  // select on a load makes the wave wait for it, which would serialise the
+  // next step's loads)
   T ra[LA], rb[LB];
   auto fetch = [&](int64_t kb) {
     const int64_t kx = kb + kc;
-    const bool ok = kx < k1;
-    const int64_t kcl = ok ? kx : k1 - 1;
+    const int64_t kcl = kx < k1 ? kx : k1 - 1;
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
       const int row = arow0 + RA * p;
-      const T v = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * d + kcl];
-      ra[p] = ok && row < n_proj ? v : T(0);
+      ra[p] = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * d + kcl];
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
       const int col = bcol0 + RA * p;
-      const T v = Y[static_cast<int64_t>(col < k ? col : k - 1) * ldy + kcl];
-      rb[p] = ok && col < k ? v : T(0);
+      rb[p] = Y[static_cast<int64_t>(col < k ? col : k - 1) * ldy + kcl];
     }
   };
   acc_t acc[TM][TN];
@@ -92,10 +92,13 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   const T* Bw = Bs + (wn * 16 * TN + c16) * KW + kk;
   if (k0 < k1) fetch(k0);
   for (int64_t kb = k0; kb < k1; kb += KB) {
+    const bool okk = kb + kc < k1;
 #pragma unroll
-    for (int p = 0; p < LA; ++p) As[(r0 + RA * p) * KW + kc] = ra[p];
+    for (int p = 0; p < LA; ++p)
+      As[(r0 + RA * p) * KW + kc] = okk && arow0 + RA * p < n_proj ? ra[p] : T(0);
 #pragma unroll
-    for (int p = 0; p < LB; ++p) Bs[(r0 + RA * p) * KW + kc] = rb[p];
+    for (int p = 0; p < LB; ++p)
+      Bs[(r0 + RA * p) * KW + kc] = okk && bcol0 + RA * p < k ? rb[p] : T(0);
     __syncthreads();
     if (kb + KB < k1) fetch(kb + KB);          // next step's tiles, in flight
 #pragma unroll
@@ -160,20 +163,17 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
   const T* cbase = C + (iok ? i_s : 0);
   const T* pbase = P + (aok ? a_s : 0);
   T rc[LC], rp[LP];
+  // clamped loads, masked when stored to LDS (see k_kb_gemm)
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int p = 0; p < LC; ++p) {
       const int q = q0 + cq + RC * p;
-      const bool ok = q < n_proj && iok;
-      const T v = cbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp];
-      rc[p] = ok ? v : T(0);
+      rc[p] = cbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp];
     }
 #pragma unroll
     for (int p = 0; p < LP; ++p) {
       const int q = q0 + pq + RP * p;
-      const bool ok = q < n_proj && aok;
-      const T v = pbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * d];
-      rp[p] = ok ? v : T(0);
+      rp[p] = pbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * d];
     }
   };
   acc_t acc[TN][TM];
@@ -186,9 +186,11 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
   fetch(0);
   for (int q0 = 0; q0 < n_proj; q0 += KB) {
 #pragma unroll
-    for (int p = 0; p < LC; ++p) Cs[ci * KW + cq + RC * p] = rc[p];
+    for (int p = 0; p < LC; ++p)
+      Cs[ci * KW + cq + RC * p] = iok && q0 + cq + RC * p < n_proj ? rc[p] : T(0);
 #pragma unroll
-    for (int p = 0; p < LP; ++p) Ps[pa_ * KW + pq + RP * p] = rp[p];
+    for (int p = 0; p < LP; ++p)
+      Ps[pa_ * KW + pq + RP * p] = aok && q0 + pq + RP * p < n_proj ? rp[p] : T(0);
     __syncthreads();
     if (q0 + KB < n_proj) fetch(q0 + KB);
 #pragma unroll
