@@ -83,29 +83,34 @@ __global__ __launch_bounds__(256) void k_gram_ts(const double* __restrict__ A, i
     for (int b = 0; b < KT; ++b) acc[a][b] = zero_acc<d4>();
   // batch: groups g = 0..GB-1 of this wave at rows base + 64 g .. + 16
   for (int64_t base = r0 + 16 * wave; base < r1; base += 64 * GB) {
+    // every load of the batch is issued first (clamped rows and columns),
+    // the masks are applied at the MFMA (a select on a load would wait for it)
     double av[KS][KT], bv[KS][KT];
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
       const int64_t row = base + 64 * (u >> 2) + 4 * (u & 3) + kk;
-      const bool ok = row < r1;
-      const int64_t rc = ok ? row : r1 - 1;
+      const int64_t rc = row < r1 ? row : r1 - 1;
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
-        const double x = pa[t][rc];
-        av[u][t] = ok && cok[t] ? x : 0.0;
-        if (!SAME) {
-          const double y = pb[t][rc];
-          bv[u][t] = ok && cok[t] ? y : 0.0;
-        }
+        av[u][t] = pa[t][rc];
+        if (!SAME) bv[u][t] = pb[t][rc];
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < KS; ++u)
+    for (int u = 0; u < KS; ++u) {
+      const bool ok = base + 64 * (u >> 2) + 4 * (u & 3) + kk < r1;
+      double am[KT], bm[KT];
+#pragma unroll
+      for (int a = 0; a < KT; ++a) {
+        am[a] = ok && cok[a] ? av[u][a] : 0.0;
+        bm[a] = SAME ? am[a] : (ok && cok[a] ? bv[u][a] : 0.0);
+      }
 #pragma unroll
       for (int a = 0; a < KT; ++a)
 #pragma unroll
-        for (int b = 0; b < KT; ++b)
-          acc[a][b] = MF<double>::mma(av[u][a], SAME ? av[u][b] : bv[u][b], acc[a][b]);
+        for (int b = 0; b < KT; ++b) acc[a][b] = MF<double>::mma(am[a], bm[b], acc[a][b]);
+    }
   }
   // waves 3, 2, 1 pass their running sums down; wave 0 writes the chunk sum
   for (int w = 3; w >= 0; --w) {
