@@ -11,7 +11,9 @@ residuals, with the filter bounds taken from the previous Rayleigh-Ritz.
 (degree + 1) * F / step_time, with F the separable method's algorithmic
 flops per H*X (phi stage counted at nominal real-FFT cost).
 
-Also reported: filter-only H*X GFLOP/s in mixed and FP64, the per-stage rates of
+Also reported: filter-only H*X GFLOP/s in mixed and FP64, the density call
+(rho on the grid and its coefficients for the same 32 orbitals, both
+precisions, against the HBM and MFMA peaks), the per-stage rates of
 H*X on the 147-atom and 309-atom (projector) shapes, time to eigenpairs
 (all n_check eigenvalues within 1e-6 Ha of the stored oracle values) for both,
 the roofline of the dominant kernel measured with HIP events (over a second
@@ -75,6 +77,45 @@ def radial_bytes(w, k, elem):
     """Algorithmic HBM bytes of one radial-inverse launch: read X (d k),
     write G (n_r L^2 k); tables are L2-resident."""
     return elem * (w.d * k + w.n_r * w.L * w.L * k)
+
+
+def density_rates(ces, torch, H, w, X, work_mixed, reps=10):
+    """ces_density on the benchmark workload: rho on the grid for all k
+    orbitals (occupations 1) and its coefficients tau, mixed and FP64.
+    Algorithmic flops: the inverse radial and Legendre sums and the phi
+    synthesis at real-FFT cost (half of an H*X's), plus the square, weight and
+    add per grid point and orbital; algorithmic bytes: read X (FP64), write
+    rho, read rho and write tau.  Also the mixed rho's error against FP64."""
+    k = X.shape[0]
+    f = algorithmic_flops(w, k)
+    flops = f["radial"] / 2 + f["legendre"] / 2 + f["phi"] / 2 + 3 * w.n_grid * k
+    nbytes = 8 * (w.d * k + 2 * w.n_grid + w.d)
+    occ = torch.ones(k, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "orbitals": k, "with_coefficients": True,
+           "alg_flop": flops, "alg_bytes": nbytes}
+    rho = {}
+    for name, prec in (("mixed", ces.CES_PREC_MIXED), ("fp64", ces.CES_PREC_FP64)):
+        work = work_mixed if prec == ces.CES_PREC_MIXED else H.workspace(k, prec)
+        r = torch.empty(w.n_grid, dtype=torch.float64, device="cuda")
+        tau = torch.empty(w.d, dtype=torch.float64, device="cuda")
+        H.density(X, occ, r, tau, prec, work)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            H.density(X, occ, r, tau, prec, work)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        rho[name] = r
+        peak = PEAK_FP32 if name == "mixed" else PEAK_FP64
+        out[name] = {"ms": round(sec * 1e3, 4), "tflops": round(flops / sec / 1e12, 3),
+                     "frac_mfma_peak": round(flops / sec / peak, 4),
+                     "alg_GBps": round(nbytes / sec / 1e9, 1),
+                     "frac_hbm_peak": round(nbytes / sec / PEAK_HBM, 4)}
+    out["mixed_rho_rel_err_vs_fp64"] = float(
+        (rho["mixed"] - rho["fp64"]).abs().max() / rho["fp64"].abs().max())
+    print(f"[bench] density (k={k}, with tau): mixed {out['mixed']['ms']} ms, "
+          f"fp64 {out['fp64']['ms']} ms", file=sys.stderr, flush=True)
+    return out
 
 
 def measured_traffic(kernel_prefix):
@@ -342,6 +383,9 @@ def main():
     gf_mixed, ms_f_mixed = filter_rate(MIXED)
     gf_fp64, ms_f_fp64 = filter_rate(FP64)
 
+    # ---- density (rho and tau) for the same block
+    dens = density_rates(ces, torch, H, w, X0, work)
+
     # ---- time to eigenpairs
     tte = {}
     ref = golden_eigenvalues(w)
@@ -407,6 +451,7 @@ def main():
         "filter_gflops": {"mixed": round(gf_mixed, 3), "fp64": round(gf_fp64, 3),
                           "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4)},
         "time_to_eigenpairs": tte,
+        "density": dens,
         "stage_ms_avg": {s: round(v[0], 5) for s, v in stage_avg.items()},
         "transform_gemm_frac_fp32_mfma": gemm_frac,
         "roofline": roof,

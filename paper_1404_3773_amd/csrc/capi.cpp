@@ -1044,22 +1044,30 @@ ces_status ces_density(ces_ham hh, int k, const double* d_X, int64_t ldx, const 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Basis& b = *h.basis;
   const int kp = static_cast<int>(ly.kp);
+  // psi through the H*X transforms up to the Legendre synthesis, then the phi
+  // synthesis with the squared, occupation-weighted sum over orbitals
   if (prec == CES_PREC_FP64) {
     double* G = Ptr<double>::at(d_work, ly.G);
+    double* gbuf = Ptr<double>::at(d_work, ly.gbuf);
     launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, kp, s);
-    launch_density_synth<double>(b, b.t64, G, d_occ, d_rho_grid, k, kp, s);
+    launch_legendre_synth<double>(b, b.t64, G, gbuf, kp, s);
+    launch_density_phi<double>(b, gbuf, d_occ, d_rho_grid, k, kp, s);
   } else {
     float* F0 = Ptr<float>::at(d_work, ly.F0);
     float* G = Ptr<float>::at(d_work, ly.G);
+    float* gbuf = Ptr<float>::at(d_work, ly.gbuf);
     launch_convert<double, float>(d_X, ldx, F0, b.d, b.d, k, s);
     launch_radial_inverse<float>(b, b.t32, F0, b.d, G, k, kp, s);
-    launch_density_synth<float>(b, b.t32, G, d_occ, d_rho_grid, k, kp, s);
+    launch_legendre_synth<float>(b, b.t32, G, gbuf, kp, s);
+    launch_density_phi<float>(b, gbuf, d_occ, d_rho_grid, k, kp, s);
   }
-  if (d_rho_coef) {
+  if (d_rho_coef) {   // tau: the forward transform of rho as one 16-column block
+    double* gh = Ptr<double>::at(d_work, ly.gbuf);
     double* A = Ptr<double>::at(d_work, ly.A);
-    launch_angular_analysis<double>(b, b.t64, d_rho_grid, A, 1, kp, s);
+    launch_phi_analysis_one(b, d_rho_grid, gh, s);
+    launch_legendre_analysis<double>(b, b.t64, gh, A, kColPad, s);
     launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_rho_coef, b.d, 1.0, 0.0,
-                                  0.0, false, nullptr, 1, kp, s);
+                                  0.0, false, nullptr, 1, kColPad, s);
   }
   CES_HIP(hipGetLastError());
   return CES_OK;

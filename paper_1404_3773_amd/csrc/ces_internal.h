@@ -173,10 +173,17 @@ void launch_angular_synth(const Basis& b, const DevTables<T>& tb, const T* G, T*
 template <typename T>
 void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f, T* A, int k,
                              int kp, hipStream_t s);
-// rho[g] = 2 sum_i occ_i psi_i(g)^2 from G (inverse-radial output).
+// rho[r][j][p] = 2 sum_i occ_i psi_i(r, j, p)^2 from the Legendre-synthesis
+// output gbuf (n_r x n_theta x S x kp), accumulated in FP64.
 template <typename T>
-void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, const double* occ,
-                          double* rho, int k, int kp, hipStream_t s);
+void launch_density_phi(const Basis& b, const T* gbuf, const double* occ, double* rho, int k,
+                        int kp, hipStream_t s);
+// gh[r][j][s][c] (16 columns, c > 0 zero) = phi analysis of one grid
+// function f[r][j][p], the input of launch_legendre_analysis with kp = 16.
+void launch_phi_analysis_one(const Basis& b, const double* f, double* gh, hipStream_t s);
+// f[r][j][p] = phi synthesis of column 0 of g (Legendre-synthesis output with
+// kp = 16): one grid function.
+void launch_phi_synthesis_one(const Basis& b, const double* g, double* f, hipStream_t s);
 
 // Self-consistent field extras (kernels_scf.hip).
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);

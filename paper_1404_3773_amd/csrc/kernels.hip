@@ -128,52 +128,6 @@ __global__ __launch_bounds__(256) void k_angular_analysis(const T* __restrict__ 
     A[(static_cast<int64_t>(r) * LL + e) * kp + i] = As[e];
 }
 
-// rho[r][j][p] = 2 sum_i occ_i psi_i^2, psi from G, one workgroup per (r, j).
-template <typename T>
-__global__ __launch_bounds__(256) void k_density_synth(const T* __restrict__ G,
-                                                       const double* __restrict__ occ,
-                                                       double* __restrict__ rho,
-                                                       const T* __restrict__ Pleg,
-                                                       const T* __restrict__ trig, int L,
-                                                       int n_theta, int n_phi, int k, int kp) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* gs = reinterpret_cast<T*>(smem_raw);
-  const int r = blockIdx.x, j = blockIdx.y;
-  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
-  constexpr int MAXP = 8;  // n_phi <= 8 * blockDim
-  double acc[MAXP];
-#pragma unroll
-  for (int u = 0; u < MAXP; ++u) acc[u] = 0.0;
-  for (int i = 0; i < k; ++i) {
-    for (int s = threadIdx.x; s < S; s += blockDim.x) {
-      const bool sn = s >= L;
-      const int m = sn ? s - L + 1 : s;
-      T a = T(0);
-      for (int l = m; l < L; ++l)
-        a += pleg_at(Pleg, n_theta, LP, j, l, m) *
-             G[(static_cast<int64_t>(r) * LL + l * l + l + (sn ? -m : m)) * kp + i];
-      gs[s] = a;
-    }
-    __syncthreads();
-    const double o = 2.0 * occ[i];
-#pragma unroll
-    for (int u = 0; u < MAXP; ++u) {
-      const int p = threadIdx.x + u * blockDim.x;
-      if (p < n_phi) {
-        T psi = T(0);
-        for (int s = 0; s < S; ++s) psi += gs[s] * trig[static_cast<int64_t>(s) * n_phi + p];
-        acc[u] += o * static_cast<double>(psi) * static_cast<double>(psi);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < MAXP; ++u) {
-    const int p = threadIdx.x + u * blockDim.x;
-    if (p < n_phi) rho[(static_cast<int64_t>(r) * n_theta + j) * n_phi + p] = acc[u];
-  }
-}
-
 // --------------------------------------------------------------- utilities
 
 template <typename Tin, typename Tout>
@@ -350,13 +304,6 @@ void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f,
                                                b.n_phi, b.n_grid, kp);
 }
 
-template <typename T>
-void launch_density_synth(const Basis& b, const DevTables<T>& tb, const T* G, const double* occ,
-                          double* rho, int k, int kp, hipStream_t s) {
-  dim3 grid(b.n_r, b.n_theta);
-  k_density_synth<T><<<grid, 256, (2 * b.L - 1) * sizeof(T), s>>>(
-      G, occ, rho, tb.Pleg, tb.trig, b.L, b.n_theta, b.n_phi, k, kp);
-}
 
 
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s) {
@@ -414,9 +361,7 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hip
   template void launch_angular_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
                                         int, hipStream_t);                                    \
   template void launch_angular_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
-                                           int, int, hipStream_t);                            \
-  template void launch_density_synth<T>(const Basis&, const DevTables<T>&, const T*,          \
-                                        const double*, double*, int, int, hipStream_t);
+                                           int, int, hipStream_t);
 CES_INST(float)
 CES_INST(double)
 #undef CES_INST

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ces_internal.h"
 #include "mfma.h"
@@ -438,6 +439,216 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
   }
 }
 
+// ------------------------------------------------------------- density
+
+// Density from the Legendre-synthesis output g[r][j][s][i] (Section 2.2.5):
+//   psi_i(r, j, p) = sum_s trig[s][p] g[r][j][s][i],
+//   rho[r][j][p]   = 2 sum_i occ_i psi_i(r, j, p)^2,
+// the phi synthesis of each (r, theta_j) row as a GEMM on MFMA (M = phi
+// points, K = the cos and sin halves of the slots laid out as in the phi
+// stage, N = orbitals in 32-column blocks) with each psi tile squared,
+// weighted and summed over its columns in FP64.  Persistent workgroups walk
+// the rows; the (row, column block) g tile goes through LDS with the next one
+// in registers.  The A operand cos / sin(2 pi m p / n_phi) is read from a
+// table of the n_phi angles, its index (m p) mod n_phi advanced by 4p per
+// k-step.  Each wave owns the M tiles wave + 4u and adds their column sums to
+// an LDS row of rho, written out when the row is done.
+constexpr int kDensityWorkgroups = 1024;
+
+template <typename T, int LP>
+__global__ __launch_bounds__(256) void k_density_phi(const T* __restrict__ g,
+                                                     const double* __restrict__ occ,
+                                                     double* __restrict__ rho,
+                                                     const double* __restrict__ cs, AngDims D,
+                                                     int n_phi, int k, int64_t n_rows) {
+  typedef typename MF<T>::acc acc_t;
+  constexpr int GW = 16 * PS_NT + 1;
+  constexpr int K2 = 2 * LP, KPH = LP / 4;
+  constexpr int GPT = K2 / 8;                   // g values per thread per tile
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int S = D.S, L = D.L;
+  double* racc = reinterpret_cast<double*>(smem_raw);            // [n_phi]
+  T* ct = reinterpret_cast<T*>(racc + n_phi);                    // [2][n_phi] cos | sin
+  T* gs = ct + 2 * n_phi;                                        // [K2][GW]
+  const int tid = threadIdx.x;
+  const int ii = tid & 31, kr = tid >> 5;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int ncb = (D.kp + 16 * PS_NT - 1) / (16 * PS_NT);
+  const int nMT = (n_phi + 15) / 16;
+  for (int e = tid; e < 2 * n_phi; e += 256) ct[e] = static_cast<T>(cs[e]);
+  // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j)
+  int sof[GPT];
+  bool sok[GPT];
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    const int kx = kr + 8 * u;
+    const bool sn = kx >= LP;
+    const int kl = sn ? kx - LP : kx;
+    sok[u] = sn ? kl < L - 1 : kl < L;
+    sof[u] = sok[u] ? (sn ? L + kl : kl) * D.kp : 0;
+  }
+  const int64_t rstride = static_cast<int64_t>(S) * D.kp;
+  const int64_t ntask = n_rows * ncb;
+  T gp[GPT];
+  auto fetch = [&](int64_t task) {
+    const int64_t row = task / ncb;
+    const int cb = static_cast<int>(task - row * ncb);
+    const int col = min(cb * 16 * PS_NT + ii, D.kp - 1);
+    const T* gr = g + row * rstride + col;
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) gp[u] = gr[sof[u]];
+  };
+  int64_t task = static_cast<int64_t>(blockIdx.x) * ncb;   // first column block of a row
+  if (task < ntask) fetch(task);
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    for (int e = tid; e < n_phi; e += 256) racc[e] = 0.0;
+    for (int cb = 0; cb < ncb; ++cb) {
+      const int i0 = cb * 16 * PS_NT;
+      const bool ok_col = i0 + ii < D.kp;
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) gs[(kr + 8 * u) * GW + ii] = sok[u] && ok_col ? gp[u] : T(0);
+      __syncthreads();   // gs (and, at cb = 0, the zeroed racc and the tables) visible
+      const int64_t next = cb + 1 < ncb ? row * ncb + cb + 1 : (row + gridDim.x) * ncb;
+      if (next < ntask) fetch(next);                  // next tile, in flight
+      // column weights 2 occ_i of this lane's columns (0 past k)
+      double wcol[PS_NT];
+#pragma unroll
+      for (int nt = 0; nt < PS_NT; ++nt) {
+        const int i = i0 + nt * 16 + l16;
+        wcol[nt] = i < k ? 2.0 * occ[i] : 0.0;
+      }
+      for (int mt = wave; mt < nMT; mt += 4) {
+        const int p = mt * 16 + l16;
+        const int pc = p < n_phi ? p : 0;             // padded rows: any finite value
+        const int d4 = (4 * pc) % n_phi;
+        acc_t acc[PS_NT];
+#pragma unroll
+        for (int nt = 0; nt < PS_NT; ++nt) acc[nt] = zero_acc<acc_t>();
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          // m = 4t + kk (cos half) or 4t + kk + 1 (sin half): u = (m p) mod n_phi
+          int u = ((kk + half) * pc) % n_phi;
+          const T* tb = ct + half * n_phi;
+          const T* grow = gs + (half * LP + kk) * GW + l16;
+#pragma unroll
+          for (int t = 0; t < KPH; ++t) {
+            const T a = tb[u];
+#pragma unroll
+            for (int nt = 0; nt < PS_NT; ++nt)
+              acc[nt] = MF<T>::mma(a, grow[4 * t * GW + nt * 16], acc[nt]);
+            u += d4;
+            u -= u >= n_phi ? n_phi : 0;
+          }
+        }
+        // sum over this lane's columns, then over the 16 lanes of a row
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double sum = 0.0;
+#pragma unroll
+          for (int nt = 0; nt < PS_NT; ++nt) {
+            const double x = static_cast<double>(acc[nt][v]);
+            sum = fma(wcol[nt] * x, x, sum);
+          }
+#pragma unroll
+          for (int off = 1; off < 16; off <<= 1) sum += __shfl_xor(sum, off, 64);
+          const int pr = mt * 16 + MF<T>::row(lane, v);
+          if (l16 == 0 && pr < n_phi) racc[pr] += sum;
+        }
+      }
+      __syncthreads();   // gs is refilled next; racc complete after the last block
+    }
+    double* out = rho + row * n_phi;
+    for (int e = tid; e < n_phi; e += 256) out[e] = racc[e];
+    __syncthreads();   // racc is zeroed for the next row
+  }
+}
+
+// One-column phi transforms (the SCF potential and the density coefficients).
+// A workgroup takes four (r, theta_j) rows, one per wave; the angle table
+// cos | sin(2 pi u / n_phi) sits in LDS, and with n_phi <= kOneRowLds also the
+// wave's input row, so the inner loops read LDS only.
+constexpr int kOneRowLds = 1024;
+
+// f[r][j][p] = sum_s g[r][j][s][0] trig[s][p] from the Legendre-synthesis
+// output with 16 columns; lane p walks the slots with index (m p) mod n_phi.
+__global__ __launch_bounds__(256) void k_phi_synthesis_one(const double* __restrict__ g,
+                                                           double* __restrict__ f,
+                                                           const double* __restrict__ cs,
+                                                           int L, int n_phi, int64_t n_rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* ct = reinterpret_cast<double*>(smem_raw);           // [2][n_phi]
+  double* gw = ct + 2 * n_phi;                                 // [4][S] slot values per wave
+  const int S = 2 * L - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < 2 * n_phi; e += 256) ct[e] = cs[e];
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  double* gv = gw + wave * S;
+  if (row < n_rows)
+    for (int e = lane; e < S; e += 64) gv[e] = g[(row * S + e) * 16];
+  __syncthreads();
+  if (row >= n_rows) return;
+  for (int p = lane; p < n_phi; p += 64) {
+    double acc = 0.0;
+    int u = 0;                                   // cos part, m = 0..L-1
+#pragma unroll 4
+    for (int m = 0; m < L; ++m) {
+      acc = fma(gv[m], ct[u], acc);
+      u += p;
+      u -= u >= n_phi ? n_phi : 0;
+    }
+    u = p;                                       // sin part, m = 1..L-1 at slot L - 1 + m
+#pragma unroll 4
+    for (int m = 1; m < L; ++m) {
+      acc = fma(gv[L - 1 + m], ct[n_phi + u], acc);
+      u += p;
+      u -= u >= n_phi ? n_phi : 0;
+    }
+    f[row * n_phi + p] = acc;
+  }
+}
+
+// gh[r][j][s][0] = (2 pi / n_phi) sum_p f[p] trig[s][p], in the Legendre
+// analysis' layout with 16 columns (columns 1..15 zero); lane s walks p with
+// index (m p) mod n_phi.
+__global__ __launch_bounds__(256) void k_phi_analysis_one(const double* __restrict__ f,
+                                                          double* __restrict__ gh,
+                                                          const double* __restrict__ cs,
+                                                          int L, int n_phi, int64_t n_rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* ct = reinterpret_cast<double*>(smem_raw);           // [2][n_phi]
+  double* fw = ct + 2 * n_phi;                                 // [4][n_phi] when staged
+  const int S = 2 * L - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool staged = n_phi <= kOneRowLds;
+  for (int e = threadIdx.x; e < 2 * n_phi; e += 256) ct[e] = cs[e];
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  const double* fr = f + row * n_phi;
+  if (staged && row < n_rows)
+    for (int e = lane; e < n_phi; e += 64) fw[wave * n_phi + e] = fr[e];
+  __syncthreads();
+  if (row >= n_rows) return;
+  const double* fv = staged ? fw + wave * n_phi : fr;
+  const double dphi = 2.0 * M_PI / n_phi;
+  for (int s = lane; s < S; s += 64) {
+    const int m = s < L ? s : s - L + 1;
+    const double* tb = ct + (s < L ? 0 : n_phi);
+    double acc = 0.0;
+    int u = 0;
+#pragma unroll 4
+    for (int p = 0; p < n_phi; ++p) {
+      acc = fma(fv[p], tb[u], acc);
+      u += m;
+      u -= u >= n_phi ? n_phi : 0;
+    }
+    double* o = gh + (row * S + s) * 16;
+    o[0] = dphi * acc;
+#pragma unroll
+    for (int c = 1; c < 16; ++c) o[c] = 0.0;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -447,26 +658,25 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
   // two column tiles when the block is narrow (no idle MFMA columns), else four
   // (K loops of up to 8 k-steps, L <= 32, load all their operands at once;
   // up to 16 (L <= 64) in FP32, where the registers allow it)
-  constexpr bool f32 = sizeof(T) == 4;
-  if (kp <= 32) {
-    const int n_ic = (kp + 31) / 32;
+  auto go = [&](auto nt_tag, int n_ic) {
+    constexpr int NT = decltype(nt_tag)::value;
     dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    if (b.L <= 32)
-      k_legendre_synth<T, 2, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-    else if (f32 && b.L <= 64)
-      k_legendre_synth<T, 2, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-    else
-      k_legendre_synth<T, 2, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-  } else {
-    const int n_ic = (kp + 63) / 64;
-    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    if (b.L <= 32)
-      k_legendre_synth<T, 4, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-    else if (f32 && b.L <= 64)
-      k_legendre_synth<T, 4, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-    else
-      k_legendre_synth<T, 4, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-  }
+    if (b.L <= 32) {
+      k_legendre_synth<T, NT, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+      return;
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (b.L <= 64) {
+        k_legendre_synth<T, NT, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+        return;
+      }
+    }
+    k_legendre_synth<T, NT, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+  };
+  if (kp <= 32)
+    go(std::integral_constant<int, 2>(), (kp + 31) / 32);
+  else
+    go(std::integral_constant<int, 4>(), (kp + 63) / 64);
 }
 
 template <typename T>
@@ -509,12 +719,56 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   }
 }
 
+template <typename T>
+void launch_density_phi(const Basis& b, const T* gbuf, const double* occ, double* rho, int k,
+                        int kp, hipStream_t s) {
+  const AngDims D = ang_dims(b, kp);
+  const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
+  dim3 grid(static_cast<unsigned>(std::min<int64_t>(n_rows, kDensityWorkgroups)));
+  const size_t lds = size_t(b.n_phi) * sizeof(double) + 2 * size_t(b.n_phi) * sizeof(T) +
+                     size_t(2 * D.L16) * (16 * PS_NT + 1) * sizeof(T);
+  auto go = [&](auto kern) {
+    static bool raised = false;   // large n_phi needs more than the default 64 KB
+    if (!raised && lds > 65536) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+      raised = true;
+    }
+    kern<<<grid, 256, lds, s>>>(gbuf, occ, rho, b.dev_cs, D, b.n_phi, k, n_rows);
+  };
+  switch (D.L16) {   // L <= 96 (checked at basis creation)
+    case 16: go(&k_density_phi<T, 16>); break;
+    case 32: go(&k_density_phi<T, 32>); break;
+    case 48: go(&k_density_phi<T, 48>); break;
+    case 64: go(&k_density_phi<T, 64>); break;
+    case 80: go(&k_density_phi<T, 80>); break;
+    default: go(&k_density_phi<T, 96>); break;
+  }
+}
+
+void launch_phi_synthesis_one(const Basis& b, const double* g, double* f, hipStream_t s) {
+  const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
+  const size_t lds = (2 * size_t(b.n_phi) + 4 * (2 * size_t(b.L) - 1)) * sizeof(double);
+  k_phi_synthesis_one<<<static_cast<unsigned>((n_rows + 3) / 4), 256, lds, s>>>(
+      g, f, b.dev_cs, b.L, b.n_phi, n_rows);
+}
+
+void launch_phi_analysis_one(const Basis& b, const double* f, double* gh, hipStream_t s) {
+  const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
+  const size_t lds = (2 * size_t(b.n_phi) + (b.n_phi <= kOneRowLds ? 4 * size_t(b.n_phi) : 0)) *
+                     sizeof(double);
+  k_phi_analysis_one<<<static_cast<unsigned>((n_rows + 3) / 4), 256, lds, s>>>(
+      f, gh, b.dev_cs, b.L, b.n_phi, n_rows);
+}
+
 #define CES_INST(T)                                                                          \
   template void launch_legendre_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
                                          hipStream_t);                                       \
   template void launch_phi_stage<T>(const Basis&, const T*, T*, int, hipStream_t);             \
   template void launch_legendre_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
-                                            int, hipStream_t);
+                                            int, hipStream_t);                                 \
+  template void launch_density_phi<T>(const Basis&, const T*, const double*, double*, int, int,  \
+                                      hipStream_t);
 CES_INST(float)
 CES_INST(double)
 #undef CES_INST

@@ -28,9 +28,10 @@ void hartree_to_grid(const Basis& b, const Layout& ly, void* work, const double*
   DevTables<double> th = b.t64;
   th.RiT = b.dev_hart;
   double* G = Ptr<double>::at(work, ly.G);
-  const int kp = static_cast<int>(ly.kp);
-  launch_radial_inverse<double>(b, th, tau, b.d, G, 1, kp, s);
-  launch_angular_synth<double>(b, b.t64, G, vh, 1, kp, s);
+  double* g = Ptr<double>::at(work, ly.gbuf);
+  launch_radial_inverse<double>(b, th, tau, b.d, G, 1, kColPad, s);
+  launch_legendre_synth<double>(b, b.t64, G, g, kColPad, s);
+  launch_phi_synthesis_one(b, g, vh, s);
 }
 
 // min || sum_t c_t F_t ||_2 subject to sum_t c_t = 1 over the columns in
@@ -154,11 +155,12 @@ ces_status ces_ks_potential(ces_ham hh, const double* d_rho, const double* d_rho
   const Basis& b = *h.basis;
   double* tau = d_tau ? d_tau : Ptr<double>::at(d_work, ly.V3);
   double* A = Ptr<double>::at(d_work, ly.A);
-  const int kp = static_cast<int>(ly.kp);
+  double* gh = Ptr<double>::at(d_work, ly.gbuf);
   launch_sub(d_rho, d_rho_ion, d_v, b.n_grid, s);                  // d_v <- rho - rho_ion
-  launch_angular_analysis<double>(b, b.t64, d_v, A, 1, kp, s);     // dualing forward transform
+  launch_phi_analysis_one(b, d_v, gh, s);                          // dualing forward transform
+  launch_legendre_analysis<double>(b, b.t64, gh, A, kColPad, s);
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, tau, b.d, 1.0, 0.0, 0.0,
-                                false, nullptr, 1, kp, s);
+                                false, nullptr, 1, kColPad, s);
   hartree_to_grid(b, ly, d_work, tau, d_v, s);                      // d_v <- V_H
   launch_ks_finish(d_vext, d_rho, d_v, b.n_grid, s);                // + V_ext + V_x
   CES_HIP(hipGetLastError());

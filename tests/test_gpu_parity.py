@@ -384,6 +384,31 @@ def test_density_and_transforms_match_oracle():
     assert rel_err(host(Xb, s.B.d), oh.from_grid_real(s.bs, fref)) < 1e-11
 
 
+DENSITY_WIDE = si.small(18, 10, R=10.0, k=40)   # n_phi 72: five 16-point tiles; kp 48: 32 + 16
+
+
+@pytest.mark.parametrize("w,k", [(DENSITY_WIDE, 40), (ODD_THETA, 3)],
+                         ids=["L18_k40", "odd_theta_odd_phi"])
+def test_density_column_blocks_and_phi_tiles_match_oracle(w, k):
+    """Density over several 32-column blocks (the last one half full), several
+    phi tiles per wave and an odd phi count, with uneven occupations, for both
+    precisions; the coefficients tau in both."""
+    _say(f"case density {w.name} k={k}")
+    s = setup(w)
+    X = si.random_block(s.B.d, k, 9)
+    occ = np.random.default_rng(9).uniform(0.0, 1.0, k)
+    rho_ref = od.density_grid(s.bs, X, occ)
+    tau_ref = od.density_coefficients(s.bs, rho_ref)
+    for prec, tol in ((FP64, 1e-11), (MIXED, 5e-5)):
+        work = s.H.workspace(k, prec)
+        rho = torch.empty(s.B.n_grid, dtype=torch.float64, device="cuda")
+        tau = torch.empty(s.B.d, dtype=torch.float64, device="cuda")
+        s.H.density(dev(X), torch.from_numpy(occ).cuda(), rho, tau, prec, work)
+        torch.cuda.synchronize()
+        assert rel_err(rho.cpu().numpy().reshape(rho_ref.shape), rho_ref) < tol, prec
+        assert rel_err(tau.cpu().numpy(), tau_ref) < tol, prec
+
+
 def test_invalid_arguments_rejected_before_launch():
     s = setup(SMALL)
     work = s.H.workspace(3, FP64)
