@@ -15,7 +15,8 @@ Also reported: filter-only H*X GFLOP/s in mixed and FP64, the density call
 (rho on the grid and its coefficients for the same 32 orbitals, both
 precisions, against the HBM and MFMA peaks), the per-stage rates of
 H*X on the 147-atom and 309-atom (projector) shapes, time to eigenpairs
-(all n_check eigenvalues within 1e-6 Ha of the stored oracle values) for both,
+(all n_check eigenvalues within 1e-6 Ha of the stored oracle values) for both
+precisions, and on the 147-atom workload against the FP64 GPU run,
 the roofline of the dominant kernel measured with HIP events (over a second
 run of the timed steps, so that the event records stay out of the step
 time), and the CPU oracle timed on a bounded sample.
@@ -201,6 +202,45 @@ def large_workload_rates(ces, torch, reps=5):
         torch.cuda.empty_cache()
     print(f"[bench] 147-atom H*X: mixed {out['mixed']['ms_per_HX']} ms, "
           f"fp64 {out['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def large_time_to_eigenpairs(ces, torch):
+    """Time to eigenpairs on the 147-atom workload (k = 400, n_check = 360,
+    degree 20) from the seeded random block, mixed and FP64, with the same
+    convergence test as the 13-atom run.  The CPU oracle would need hours at
+    this size, so the reference is the FP64 GPU run (its H*X matches the
+    oracle at this full size to 6e-15 relative); reported: seconds,
+    iterations and the mixed run's largest eigenvalue difference from it."""
+    w = si.C3
+    B = ces.Basis.for_workload(w)
+    r, wr, th, wt, ph = B.grid()
+    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
+    X0 = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
+    k = X0.shape[0]
+    v0 = torch.from_numpy(si.lanczos_start(B.d)).cuda()
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "orbitals": k, "n_check": w.n_check, "degree": w.degree,
+           "reference": "FP64 GPU run (CPU oracle infeasible at this size)"}
+    theta = {}
+    for name, prec in (("fp64", ces.CES_PREC_FP64), ("mixed", ces.CES_PREC_MIXED)):
+        work = H.workspace(k, prec)
+        X = X0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b = H.lanczos_bound(v0, work)
+        it = H.chefsi(X, w.degree, b, w.n_check, ev, rs, work, prec, max_iter=w.max_iter)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        theta[name] = ev.cpu().numpy()[:w.n_check].copy()
+        out[name] = {"seconds": round(sec, 3), "iterations": it,
+                     "converged": it < w.max_iter}
+        print(f"[bench] 147-atom time-to-eigenpairs {name}: {sec:.2f} s, {it} it",
+              file=sys.stderr, flush=True)
+        del work, X
+        torch.cuda.empty_cache()
+    out["max_eig_diff_mixed_vs_fp64_Ha"] = float(np.max(np.abs(theta["mixed"] - theta["fp64"])))
     return out
 
 
@@ -461,6 +501,9 @@ def main():
         torch.cuda.empty_cache()
         line["large_workload"] = large_workload_rates(ces, torch)
         torch.cuda.empty_cache()
+        if not args.no_tte:
+            line["time_to_eigenpairs_147"] = large_time_to_eigenpairs(ces, torch)
+            torch.cuda.empty_cache()
         try:
             line["kb_workload"] = kb_workload_rates(ces, torch)
         except Exception as e:   # reported, never fatal to the line
