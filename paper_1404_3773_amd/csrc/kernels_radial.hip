@@ -37,7 +37,7 @@ __host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 // X tile (N rows x 32 columns, zero-padded to a multiple of 16 rows) is staged
 // in LDS; the table operand is read in chunks of four k-steps, the next chunk
 // in flight while the current one runs.
-template <typename T, int MT, int CK>
+template <typename T, int MT, int CK, bool ONE>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
                                                              int64_t ldx, T* __restrict__ G,
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
   {
     // X tile: thread (column ii, rows n0 + 8 q), every load issued before the
     // LDS writes; N16 <= 4 CK rows in one chunk, N <= 192 otherwise
-    constexpr int XQ = CK > 4 ? CK / 2 : 24;
+    constexpr int XQ = ONE ? CK / 2 : 24;
     const T* Xl = X + static_cast<int64_t>(lm) * N;
     const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
     const bool iok = i0 + ii < k;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
       for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[nt], acc[u][nt]);
     }
   };
-  if constexpr (CK > 4) {                         // whole contraction in one chunk (N16 <= 4 CK)
+  if constexpr (ONE) {                            // whole contraction in one chunk (N16 <= 4 CK)
 #pragma unroll
     for (int t = 0; t < CK; ++t) {
       if (4 * t >= N16) break;                    // Xs holds N16 rows
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
 // each, repeated past the last and not stored); K = n_r in chunks of four
 // k-steps with the next chunk's operands in flight.  The projector term
 // (column-major d x k, ld d) is added in the epilogue when Zkb is given.
-template <typename T, int MT, int CK>
+template <typename T, int MT, int CK, bool ONE>
 __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
     const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   // epilogue operands (lanes along n, registers along i): in the one-chunk
   // form they are loaded with the contraction's, so the epilogue waits for
   // nothing new; indices clamped into the block, invalid entries not stored
-  constexpr int EP = CK > 4 ? 1 : 0;
+  constexpr int EP = ONE ? 1 : 0;
   T yin[MT][RI_NT][4 * EP + 1 - EP], yold[MT][RI_NT][4 * EP + 1 - EP];
   auto epi_load = [&](const T* Y, int64_t ld, T (*y)[RI_NT][4 * EP + 1 - EP]) {
 #pragma unroll
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     if (beta != T(0)) epi_load(Yold, ldold, yold);
   }
   __builtin_amdgcn_sched_barrier(0);   // issue every load of the chunk before the first MFMA
-  if constexpr (CK > 4) {   // whole contraction in one chunk (R4 <= 4 CK; rows past R4 are zero)
+  if constexpr (ONE) {      // whole contraction in one chunk (R4 <= 4 CK; rows past R4 are zero)
 #pragma unroll
     for (int t = 0; t < CK; ++t) step(4 * t + kk, ca[t], cb[t]);
   } else {
@@ -284,30 +284,31 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
 }  // namespace
 
 // Short contractions (N <= 64 for the inverse, n_r <= 96 for the forward)
-// load every operand fragment at once (CK > 4: one chunk of CK k-steps);
-// longer ones stream 16-row chunks (CK = 4) with the next chunk in flight.
-template <typename T, int CK>
+// load every operand fragment at once (ONE: one chunk of CK k-steps); longer
+// ones stream chunks of kStreamCK k-steps with the next chunk in flight.
+constexpr int kStreamCK = 4;
+template <typename T, int CK, bool ONE>
 void radial_inverse_ck(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx, T* G,
                        int k, int kp, hipStream_t s) {
   dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
   const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 1) * sizeof(T);
   const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
   switch (mt) {
-    case 1: k_radial_inverse_mfma<T, 1, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 2: k_radial_inverse_mfma<T, 2, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 3: k_radial_inverse_mfma<T, 3, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    default: k_radial_inverse_mfma<T, 4, CK><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 1: k_radial_inverse_mfma<T, 1, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 2: k_radial_inverse_mfma<T, 2, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 3: k_radial_inverse_mfma<T, 3, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    default: k_radial_inverse_mfma<T, 4, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
   }
 }
 
 template <typename T>
 void launch_radial_inverse(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx,
                            T* G, int k, int kp, hipStream_t s) {
-  if (rup(b.N, 16) <= 64) return radial_inverse_ck<T, 16>(b, tb, X, ldx, G, k, kp, s);
-  radial_inverse_ck<T, 4>(b, tb, X, ldx, G, k, kp, s);
+  if (rup(b.N, 16) <= 64) return radial_inverse_ck<T, 16, true>(b, tb, X, ldx, G, k, kp, s);
+  radial_inverse_ck<T, kStreamCK, false>(b, tb, X, ldx, G, k, kp, s);
 }
 
-template <typename T, int CK>
+template <typename T, int CK, bool ONE>
 void radial_forward_ck(const Basis& b, const DevTables<T>& tb, const T* A, const T* Yin,
                        int64_t ldin, const T* Yold, int64_t ldold, T* out, int64_t ldout,
                        T alpha, T cshift, T beta, bool kinetic, const T* Zkb, int k, int kp,
@@ -316,13 +317,13 @@ void radial_forward_ck(const Basis& b, const DevTables<T>& tb, const T* A, const
   const int mt = (rup(b.N, 16) / 16 + 3) / 4;   // N <= 192: at most 3 tiles per wave
   const int kin = kinetic ? 1 : 0;
   switch (mt) {
-    case 1: k_radial_forward_mfma<T, 1, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+    case 1: k_radial_forward_mfma<T, 1, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
                                                     ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
                                                     b.n_r, k, kp); break;
-    case 2: k_radial_forward_mfma<T, 2, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+    case 2: k_radial_forward_mfma<T, 2, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
                                                     ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
                                                     b.n_r, k, kp); break;
-    default: k_radial_forward_mfma<T, 3, CK><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
+    default: k_radial_forward_mfma<T, 3, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
                                                      ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
                                                      b.n_r, k, kp); break;
   }
@@ -335,15 +336,15 @@ void launch_radial_forward(const Basis& b, const DevTables<T>& tb, const T* A, c
                            hipStream_t s) {
   const int ks = rup(b.n_r, 4) / 4;   // k-steps of the contraction over r
   if (ks <= 8)
-    return radial_forward_ck<T, 8>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+    return radial_forward_ck<T, 8, true>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
                                    beta, kinetic, Zkb, k, kp, s);
   if (ks <= 16)
-    return radial_forward_ck<T, 16>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+    return radial_forward_ck<T, 16, true>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
                                     beta, kinetic, Zkb, k, kp, s);
   if (ks <= 24)
-    return radial_forward_ck<T, 24>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
+    return radial_forward_ck<T, 24, true>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift,
                                     beta, kinetic, Zkb, k, kp, s);
-  radial_forward_ck<T, 4>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift, beta,
+  radial_forward_ck<T, kStreamCK, false>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, cshift, beta,
                           kinetic, Zkb, k, kp, s);
 }
 
