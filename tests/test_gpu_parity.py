@@ -81,6 +81,9 @@ def setup(w, with_kb=False):
 SMALL = si.small(6, 8, R=9.0, k=5)
 ODD_THETA = si.small(5, 7, R=8.0, n_theta=11, n_phi=21, k=3)
 LONG_RADIAL = si.small(3, 70, R=12.0, n_r=100, k=4)
+# n_r 45 and N 30 (the one-chunk radial forms at 12 and 8 k-steps), n_theta 70 > 64 with
+# L <= 32 (the Legendre analysis streaming theta in chunks)
+MID_SHAPE = si.small(20, 30, R=11.0, n_r=45, n_theta=70, n_phi=80, k=17)
 
 
 def rel_err(got, ref):
@@ -88,9 +91,9 @@ def rel_err(got, ref):
 
 
 @pytest.mark.parametrize("w,k", [(SMALL, 1), (SMALL, 5), (SMALL, 17), (SMALL, 70),
-                                 (ODD_THETA, 3), (LONG_RADIAL, 4)],
+                                 (ODD_THETA, 3), (LONG_RADIAL, 4), (MID_SHAPE, 17)],
                          ids=["small_k1", "small_k5", "small_k17", "small_k70",
-                              "odd_theta", "N70"])
+                              "odd_theta", "N70", "L20_nr45_ntheta70"])
 def test_apply_H_fp64_and_mixed(w, k):
     _say(f"case apply_H {w.name} k={k}")
     s = setup(w)
@@ -385,10 +388,11 @@ def test_density_and_transforms_match_oracle():
 
 
 DENSITY_WIDE = si.small(18, 10, R=10.0, k=40)   # n_phi 72: five 16-point tiles; kp 48: 32 + 16
+DENSITY_L40 = si.small(40, 6, R=10.0, n_theta=80, k=20)   # 48 K-rows per half, ten phi tiles
 
 
-@pytest.mark.parametrize("w,k", [(DENSITY_WIDE, 40), (ODD_THETA, 3)],
-                         ids=["L18_k40", "odd_theta_odd_phi"])
+@pytest.mark.parametrize("w,k", [(DENSITY_WIDE, 40), (ODD_THETA, 3), (DENSITY_L40, 20)],
+                         ids=["L18_k40", "odd_theta_odd_phi", "L40_k20"])
 def test_density_column_blocks_and_phi_tiles_match_oracle(w, k):
     """Density over several 32-column blocks (the last one half full), several
     phi tiles per wave and an odd phi count, with uneven occupations, for both
