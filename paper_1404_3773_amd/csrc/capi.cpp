@@ -287,6 +287,24 @@ size_t solver_bytes_for(Ham& h, int k) {
   return h.solver_ws;
 }
 
+ces_status host_stage(Ham& h, size_t n) {
+  if (h.host_stage_n >= n) return CES_OK;
+  if (h.host_stage) (void)hipHostFree(h.host_stage);
+  h.host_stage = nullptr;
+  h.host_stage_n = 0;
+  const size_t want = std::max<size_t>(n, 1024);
+  CES_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.host_stage), want * sizeof(double),
+                        hipHostMallocDefault));
+  h.host_stage_n = want;
+  return CES_OK;
+}
+
+ces_status stage_read(Ham& h, size_t off, const void* src, size_t bytes, hipStream_t s) {
+  CES_TRY(host_stage(h, off + (bytes + 7) / 8));
+  CES_HIP(hipMemcpyAsync(h.host_stage + off, src, bytes, hipMemcpyDeviceToHost, s));
+  return CES_OK;
+}
+
 Layout layout_for(Ham& h, int k, int prec) {
   const Basis& b = *h.basis;
   Layout L;
@@ -530,9 +548,12 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     launch_copy2d_if(T2, d, X, ldx, d, k, info, s);
     return CES_OK;
   };
+  // read-backs go through the handle's pinned stage: info flags at offset 0,
+  // eigenvalues at 2, residual norms at 2 + k, behind one synchronisation
   auto read_info = [&](rocblas_int* h3) -> ces_status {
-    CES_HIP(hipMemcpyAsync(h3, info, 3 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    CES_TRY(stage_read(h, 0, info, 3 * sizeof(rocblas_int), s));
     CES_HIP(hipStreamSynchronize(s));
+    std::memcpy(h3, h.host_stage, 3 * sizeof(rocblas_int));
     return CES_OK;
   };
   // Rayleigh-Ritz on the (orthonormal) block; X and HX are written only if
@@ -572,9 +593,13 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     return CES_OK;
   };
   auto finish = [&](rocblas_int* h3) -> ces_status {
-    if (h_eval) CES_HIP(hipMemcpyAsync(h_eval, evals, size_t(k) * 8, hipMemcpyDeviceToHost, s));
-    if (h_res) CES_HIP(hipMemcpyAsync(h_res, res, size_t(k) * 8, hipMemcpyDeviceToHost, s));
-    return read_info(h3);
+    CES_TRY(host_stage(h, 2 + 2 * size_t(k)));
+    if (h_eval) CES_TRY(stage_read(h, 2, evals, size_t(k) * 8, s));
+    if (h_res) CES_TRY(stage_read(h, 2 + size_t(k), res, size_t(k) * 8, s));
+    CES_TRY(read_info(h3));
+    if (h_eval) std::memcpy(h_eval, h.host_stage + 2, size_t(k) * 8);
+    if (h_res) std::memcpy(h_res, h.host_stage + 2 + k, size_t(k) * 8);
+    return CES_OK;
   };
   CES_TRY(pass(0.0));
   CES_TRY(rayleigh());
@@ -808,6 +833,7 @@ ces_status ces_ham_destroy(ces_ham hh) {
   if (!hh) return CES_OK;
   if (hh->h.blas) rocblas_destroy_handle(hh->h.blas);
   if (hh->h.dev_block) (void)hipFree(hh->h.dev_block);
+  if (hh->h.host_stage) (void)hipHostFree(hh->h.host_stage);
   delete hh;
   return CES_OK;
 }
@@ -905,9 +931,9 @@ ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* 
   double* sc = Ptr<double>::at(d_work, ly.vec);
   CES_HIP(hipMemsetAsync(vp, 0, size_t(d) * 8, s));
   launch_dot(d_v0, d_v0, d, sc, sc + 64, s);
-  double nrm2 = 0;
-  CES_HIP(hipMemcpyAsync(&nrm2, sc, 8, hipMemcpyDeviceToHost, s));
+  CES_TRY(stage_read(h, 0, sc, 8, s));
   CES_HIP(hipStreamSynchronize(s));
+  const double nrm2 = h.host_stage[0];
   if (!(nrm2 > 0) || !std::isfinite(nrm2)) return fail(CES_ERR_INVALID_ARG, "bad Lanczos start vector");
   launch_axpby(1.0 / std::sqrt(nrm2), d_v0, 0.0, v, d, s);
   std::vector<double> al, be;
@@ -915,15 +941,15 @@ ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* 
   for (int j = 0; j < steps; ++j) {
     CES_TRY(h_step<double>(h, ly, d_work, 1, v, d, nullptr, 0, w, d, 1.0, 0.0, 0.0, s));
     launch_dot(v, w, d, sc, sc + 64, s);
-    double alpha = 0;
-    CES_HIP(hipMemcpyAsync(&alpha, sc, 8, hipMemcpyDeviceToHost, s));
+    CES_TRY(stage_read(h, 0, sc, 8, s));
     CES_HIP(hipStreamSynchronize(s));
+    const double alpha = h.host_stage[0];
     launch_axpby(-alpha, v, 1.0, w, d, s);
     if (j > 0) launch_axpby(-beta, vp, 1.0, w, d, s);
     launch_dot(w, w, d, sc, sc + 64, s);
-    double b2 = 0;
-    CES_HIP(hipMemcpyAsync(&b2, sc, 8, hipMemcpyDeviceToHost, s));
+    CES_TRY(stage_read(h, 0, sc, 8, s));
     CES_HIP(hipStreamSynchronize(s));
+    const double b2 = h.host_stage[0];
     beta = std::sqrt(std::max(b2, 0.0));
     al.push_back(alpha);
     if (j + 1 < steps) {

@@ -74,7 +74,16 @@ struct Ham {
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;
+  double* host_stage = nullptr;   // pinned host buffer for results read back by a call
+  size_t host_stage_n = 0;        // its length in doubles
 };
+
+// Pinned host staging of at least n doubles on h (grown as needed), so that a
+// call's read-backs are DMA copies behind one synchronisation.
+ces_status host_stage(Ham& h, size_t n);
+// Copies `bytes` from device `src` into the stage at double offset `off`
+// (asynchronous on s; read after synchronising s).
+ces_status stage_read(Ham& h, size_t off, const void* src, size_t bytes, hipStream_t s);
 
 // ------------------------------------------- shared by the C interface files
 
