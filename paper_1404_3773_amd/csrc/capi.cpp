@@ -511,7 +511,7 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   double* S1 = Ptr<double>::at(work, ly.S1);
   double* vec = Ptr<double>::at(work, ly.vec);
   double* dinv = vec;
-  double* evals = vec + k;
+  double* evals = eval ? eval : vec + k;   // eigenvalues straight into the caller's array
   double* Ework = vec + 2 * k;
   // info[0]: factorisation, info[1]: triangular inverse, info[2]: eigensolver
   rocblas_int* info = Ptr<rocblas_int>::at(work, ly.info);
@@ -523,7 +523,9 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   double* part = Ptr<double>::at(work, ly.part);
   const int64_t part_cap = int64_t(gram_chunks(d, k)) * k * k;   // doubles in the region
   const bool small = k <= kJacobiMax;
-  CES_HIP(hipMemsetAsync(info, 0, 4 * sizeof(rocblas_int), s));
+  // the one-workgroup Cholesky writes flags 0 and 1 and Jacobi flag 2 on every
+  // call; the library path clears them first
+  if (!small) CES_HIP(hipMemsetAsync(info, 0, 4 * sizeof(rocblas_int), s));
   // One Cholesky-QR pass: S = X^T X, D = diag(S)^{-1/2}, R^T R = D S D (+ shift I),
   // X <- X D R^{-1} (column scaling before factorising follows Section 3.1.1).
   // X is written only if the factorisation succeeded (checked on the device),
@@ -589,7 +591,6 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
       launch_copy2d_if(T2, d, HQ, ldhq, d, k, info, s);
       launch_residuals(HQ, ldhq, X, ldx, evals, res, d, k, part, part_cap, s);
     }
-    CES_HIP(hipMemcpyAsync(eval, evals, size_t(k) * sizeof(double), hipMemcpyDeviceToDevice, s));
     return CES_OK;
   };
   auto finish = [&](rocblas_int* h3) -> ces_status {

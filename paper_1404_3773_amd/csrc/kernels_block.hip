@@ -307,7 +307,10 @@ __global__ __launch_bounds__(NT) void k_chol(double* __restrict__ S, int k, int 
     const int c = e / ldw, i = e - c * ldw;
     S[e] = (c < k && i <= c) ? dv[i] * A[i][c] : 0.0;
   }
-  if (tid == 0) *info = bad;
+  if (tid == 0) {
+    info[0] = bad;
+    info[1] = 0;   // the triangular-inverse flag of the library path: nothing to report
+  }
 }
 
 // ------------------------------------------------- Jacobi eigensolver
