@@ -728,12 +728,11 @@ void launch_density_phi(const Basis& b, const T* gbuf, const double* occ, double
   const size_t lds = size_t(b.n_phi) * sizeof(double) + 2 * size_t(b.n_phi) * sizeof(T) +
                      size_t(2 * D.L16) * (16 * PS_NT + 1) * sizeof(T);
   auto go = [&](auto kern) {
-    static bool raised = false;   // large n_phi needs more than the default 64 KB
-    if (!raised && lds > 65536) {
+    // large n_phi needs more than the default 64 KB (set per kernel: the
+    // instantiations share one function-pointer type, so no static flag)
+    if (lds > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-      raised = true;
-    }
     kern<<<grid, 256, lds, s>>>(gbuf, occ, rho, b.dev_cs, D, b.n_phi, k, n_rows);
   };
   switch (D.L16) {   // L <= 96 (checked at basis creation)
