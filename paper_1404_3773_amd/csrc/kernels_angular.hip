@@ -447,7 +447,11 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 // the phi synthesis of each (r, theta_j) row as a GEMM on MFMA (M = phi
 // points, K = the cos and sin halves of the slots laid out as in the phi
 // stage, N = orbitals in 32-column blocks) with each psi tile squared,
-// weighted and summed over its columns in FP64.  Persistent workgroups walk
+// weighted and summed over its columns in FP64.  Only the points p <= n_phi/2
+// are formed, their cos part C and sin part S kept apart: since
+// cos(m (n - p)) = cos(m p) and sin(m (n - p)) = -sin(m p), the mirror point
+// has psi(n - p) = C - S next to psi(p) = C + S (p = 0 and p = n/2 are their
+// own mirrors).  Persistent workgroups walk
 // the rows; the (row, column block) g tile goes through LDS with the next one
 // in registers.  The A operand cos / sin(2 pi m p / n_phi) is read from a
 // table of the n_phi angles, its index (m p) mod n_phi advanced by 4p per
@@ -476,7 +480,8 @@ __global__ __launch_bounds__(256) void k_density_phi(const T* __restrict__ g,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
   const int ncb = (D.kp + 16 * PS_NT - 1) / (16 * PS_NT);
-  const int nMT = (n_phi + 15) / 16;
+  const int phalf = n_phi / 2;                  // points 0..phalf are formed
+  const int nMT = (phalf + 1 + 15) / 16;
   for (int e = tid; e < 2 * n_phi; e += 256) ct[e] = static_cast<T>(cs[e]);
   // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j)
   int sof[GPT];
@@ -521,11 +526,13 @@ __global__ __launch_bounds__(256) void k_density_phi(const T* __restrict__ g,
       }
       for (int mt = wave; mt < nMT; mt += 4) {
         const int p = mt * 16 + l16;
-        const int pc = p < n_phi ? p : 0;             // padded rows: any finite value
+        const int pc = p <= phalf ? p : 0;            // padded rows: any finite value
         const int d4 = (4 * pc) % n_phi;
-        acc_t acc[PS_NT];
+        acc_t acc[2][PS_NT];                          // [cos part, sin part]
 #pragma unroll
-        for (int nt = 0; nt < PS_NT; ++nt) acc[nt] = zero_acc<acc_t>();
+        for (int half = 0; half < 2; ++half)
+#pragma unroll
+          for (int nt = 0; nt < PS_NT; ++nt) acc[half][nt] = zero_acc<acc_t>();
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           // m = 4t + kk (cos half) or 4t + kk + 1 (sin half): u = (m p) mod n_phi
@@ -537,24 +544,34 @@ __global__ __launch_bounds__(256) void k_density_phi(const T* __restrict__ g,
             const T a = tb[u];
 #pragma unroll
             for (int nt = 0; nt < PS_NT; ++nt)
-              acc[nt] = MF<T>::mma(a, grow[4 * t * GW + nt * 16], acc[nt]);
+              acc[half][nt] = MF<T>::mma(a, grow[4 * t * GW + nt * 16], acc[half][nt]);
             u += d4;
             u -= u >= n_phi ? n_phi : 0;
           }
         }
-        // sum over this lane's columns, then over the 16 lanes of a row
+        // psi(p) = C + S and psi(n - p) = C - S: weighted squares summed over
+        // this lane's columns, then over the 16 lanes of a row
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double sum = 0.0;
+          double sp = 0.0, sm = 0.0;
 #pragma unroll
           for (int nt = 0; nt < PS_NT; ++nt) {
-            const double x = static_cast<double>(acc[nt][v]);
-            sum = fma(wcol[nt] * x, x, sum);
+            const double c = static_cast<double>(acc[0][nt][v]);
+            const double sn = static_cast<double>(acc[1][nt][v]);
+            const double xp = c + sn, xm = c - sn;
+            sp = fma(wcol[nt] * xp, xp, sp);
+            sm = fma(wcol[nt] * xm, xm, sm);
           }
 #pragma unroll
-          for (int off = 1; off < 16; off <<= 1) sum += __shfl_xor(sum, off, 64);
+          for (int off = 1; off < 16; off <<= 1) {
+            sp += __shfl_xor(sp, off, 64);
+            sm += __shfl_xor(sm, off, 64);
+          }
           const int pr = mt * 16 + MF<T>::row(lane, v);
-          if (l16 == 0 && pr < n_phi) racc[pr] += sum;
+          if (l16 == 0 && pr <= phalf) {
+            racc[pr] += sp;
+            if (pr > 0 && 2 * pr != n_phi) racc[n_phi - pr] += sm;
+          }
         }
       }
       __syncthreads();   // gs is refilled next; racc complete after the last block
