@@ -66,11 +66,13 @@ inline AngDims ang_dims(const Basis& b, int kp) {
 
 // ------------------------------------------------------- legendre_synth
 
-// Workgroup: one m-slot, 64 theta nodes (one 16-row tile per wave), 16 NT
-// columns i of one radial node r.  g[r][j][s][i] = sum_l Pm[m][l][j] G[r][lm][i].
+// Workgroup: one m-slot, JT groups of 64 theta nodes (one 16-row tile of each
+// group per wave), 16 NT columns i of one radial node r.
+// g[r][j][s][i] = sum_l Pm[m][l][j] G[r][lm][i].  A wave loads the G fragments
+// of a k-step once for all its JT theta tiles.
 // KS > 0 (L <= 4 KS): every operand of the K loop is loaded before the first
 // MFMA; KS = 0: the K loop streams its operands.
-template <typename T, int LS_NT, int KS>
+template <typename T, int LS_NT, int KS, int JT>
 __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm,
                                                         const T* __restrict__ G,
                                                         T* __restrict__ g, AngDims D,
@@ -84,12 +86,21 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
   const int nt_valid = min(LS_NT, (D.kp - i0) / 16);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kk = lane >> 4;
-  const int jt = blockIdx.y * 64 + wave * 16;
-  const T* Pa = Pm + (static_cast<int64_t>(m) * (D.L + 4)) * D.J64 + jt + l16;
-  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
-  acc_t acc[LS_NT];
+  // theta tiles of this wave; tiles past J64 (in the last workgroup) read the
+  // last tile and store nothing
+  int jt[JT];
+  const T* Pa[JT];
 #pragma unroll
-  for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = zero_acc<acc_t>();
+  for (int u = 0; u < JT; ++u) {
+    jt[u] = (blockIdx.y * JT + u) * 64 + wave * 16;
+    Pa[u] = Pm + (static_cast<int64_t>(m) * (D.L + 4)) * D.J64 + min(jt[u], D.J64 - 16) + l16;
+  }
+  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
+  acc_t acc[JT][LS_NT];
+#pragma unroll
+  for (int u = 0; u < JT; ++u)
+#pragma unroll
+    for (int nt = 0; nt < LS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
   const int K = D.L - m;
   // column of each N-tile clamped into the block (tiles past nt_valid are not stored)
   int col[LS_NT];
@@ -97,7 +108,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
   for (int nt = 0; nt < LS_NT; ++nt) col[nt] = min(nt * 16, D.kp - i0 - 16);
   if constexpr (KS > 0) {
     const int ks = (K + 3) >> 2;
-    T a[KS], b[KS][LS_NT];
+    T a[KS][JT], b[KS][LS_NT];
     // up to 8 k-steps the loops exit early; longer ones take uniform guards
     // instead, which keeps them unrolled (an early exit there leaves a rolled
     // loop indexing the operand arrays through scratch)
@@ -107,7 +118,8 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
       if (t < ks) {
         // rows l >= L read row L - 1 and are masked where used
         const int lc = min(m + 4 * t + kk, D.L - 1);
-        a[t] = Pa[lc * D.J64];
+#pragma unroll
+        for (int u = 0; u < JT; ++u) a[t][u] = Pa[u][lc * D.J64];
         const int off = (lc * lc + lc + sgn * m) * D.kp;
 #pragma unroll
         for (int nt = 0; nt < LS_NT; ++nt) b[t][nt] = Gr[off + col[nt]];
@@ -118,9 +130,13 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
     for (int t = 0; t < KS; ++t) {
       if (KS <= 8 && t >= ks) break;
       if (t < ks) {
-        const T av = m + 4 * t + kk < D.L ? a[t] : T(0);
+        const bool ok = m + 4 * t + kk < D.L;
 #pragma unroll
-        for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(av, b[t][nt], acc[nt]);
+        for (int u = 0; u < JT; ++u) {
+          const T av = ok ? a[t][u] : T(0);
+#pragma unroll
+          for (int nt = 0; nt < LS_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[t][nt], acc[u][nt]);
+        }
       }
     }
   } else {
@@ -132,39 +148,50 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
     int64_t off = static_cast<int64_t>(l * l + l + sgn * m) * D.kp;
     int64_t dof = static_cast<int64_t>(8 * l + 20) * D.kp;
     const int64_t ddof = 32 * static_cast<int64_t>(D.kp);
-    const T* pa = Pa + static_cast<int64_t>(l) * D.J64;
+    int64_t pofs = static_cast<int64_t>(l) * D.J64;
 #pragma unroll 4
     for (int t = 0; t < nfull; ++t) {
-      const T a = *pa;
-      T b[LS_NT];
+      T a[JT], b[LS_NT];
+#pragma unroll
+      for (int u = 0; u < JT; ++u) a[u] = Pa[u][pofs];
 #pragma unroll
       for (int nt = 0; nt < LS_NT; ++nt) b[nt] = Gr[off + col[nt]];
 #pragma unroll
-      for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(a, b[nt], acc[nt]);
-      pa += 4 * D.J64;
+      for (int u = 0; u < JT; ++u)
+#pragma unroll
+        for (int nt = 0; nt < LS_NT; ++nt) acc[u][nt] = MF<T>::mma(a[u], b[nt], acc[u][nt]);
+      pofs += 4 * D.J64;
       off += dof;
       dof += ddof;
     }
   }
   if (K & 3) {
     const int l = m + 4 * nfull + kk;
-    const T a = Pa[l * D.J64];                    // zero rows for l >= L
     const int lc = min(l, D.L - 1);
     const int off = (lc * lc + lc + sgn * m) * D.kp;
+    T b[LS_NT];
 #pragma unroll
-    for (int nt = 0; nt < LS_NT; ++nt) acc[nt] = MF<T>::mma(a, Gr[off + col[nt]], acc[nt]);
+    for (int nt = 0; nt < LS_NT; ++nt) b[nt] = Gr[off + col[nt]];
+#pragma unroll
+    for (int u = 0; u < JT; ++u) {
+      const T a = Pa[u][l * D.J64];                 // zero rows for l >= L
+#pragma unroll
+      for (int nt = 0; nt < LS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+    }
   }
   }
   T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
 #pragma unroll
-  for (int nt = 0; nt < LS_NT; ++nt) {
-    if (nt >= nt_valid) break;
+  for (int u = 0; u < JT; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = jt + MF<T>::row(lane, v);
-      if (j < D.n_theta) gr[static_cast<int64_t>(j) * D.S * D.kp + nt * 16] = acc[nt][v];
+    for (int nt = 0; nt < LS_NT; ++nt) {
+      if (nt >= nt_valid) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = jt[u] + MF<T>::row(lane, v);
+        if (j < D.n_theta) gr[static_cast<int64_t>(j) * D.S * D.kp + nt * 16] = acc[u][nt][v];
+      }
     }
-  }
 }
 
 // ------------------------------------------------------------ phi_stage
@@ -675,25 +702,45 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
   // two column tiles when the block is narrow (no idle MFMA columns), else four
   // (K loops of up to 8 k-steps, L <= 32, load all their operands at once;
   // up to 16 (L <= 64) in FP32, where the registers allow it)
-  auto go = [&](auto nt_tag, int n_ic) {
-    constexpr int NT = decltype(nt_tag)::value;
-    dim3 grid(b.n_r * n_ic, (b.n_theta + 63) / 64, D.S);
-    if (b.L <= 32) {
-      k_legendre_synth<T, NT, 8><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
-      return;
-    }
-    if constexpr (sizeof(T) == 4) {
-      if (b.L <= 64) {
-        k_legendre_synth<T, NT, 16><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+  // In FP32 with 32 < L <= 64, wide blocks (four column tiles) take up to four
+  // 64-row theta groups per workgroup, so each G fragment is read once per
+  // wave for all of them (measured faster there; slower in FP64 and for the
+  // streamed K loop, where the g stores rather than the G reads bound it).
+  const int ngrp = (b.n_theta + 63) / 64;
+  auto go = [&](auto nt_tag, auto jt_tag, int n_ic) {
+    constexpr int NT = decltype(nt_tag)::value, JT = decltype(jt_tag)::value;
+    dim3 grid(b.n_r * n_ic, (ngrp + JT - 1) / JT, D.S);
+    if constexpr (JT > 1) {
+      k_legendre_synth<T, NT, 16, JT><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+    } else {
+      if (b.L <= 32) {
+        k_legendre_synth<T, NT, 8, 1><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
         return;
       }
+      if constexpr (sizeof(T) == 4) {
+        if (b.L <= 64) {
+          k_legendre_synth<T, NT, 16, 1><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
+          return;
+        }
+      }
+      k_legendre_synth<T, NT, 0, 1><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
     }
-    k_legendre_synth<T, NT, 0><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic);
   };
-  if (kp <= 32)
-    go(std::integral_constant<int, 2>(), (kp + 31) / 32);
-  else
-    go(std::integral_constant<int, 4>(), (kp + 63) / 64);
+  using I = std::integral_constant<int, 1>;
+  if (kp <= 32) return go(std::integral_constant<int, 2>(), I(), (kp + 31) / 32);
+  const int n_ic = (kp + 63) / 64;
+  std::integral_constant<int, 4> nt4;
+  if constexpr (sizeof(T) == 4) {
+    if (b.L > 32 && b.L <= 64) {
+      switch (std::min(ngrp, 4)) {
+        case 1: return go(nt4, I(), n_ic);
+        case 2: return go(nt4, std::integral_constant<int, 2>(), n_ic);
+        case 3: return go(nt4, std::integral_constant<int, 3>(), n_ic);
+        default: return go(nt4, std::integral_constant<int, 4>(), n_ic);
+      }
+    }
+  }
+  go(nt4, I(), n_ic);
 }
 
 template <typename T>

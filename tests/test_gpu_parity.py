@@ -84,6 +84,9 @@ LONG_RADIAL = si.small(3, 70, R=12.0, n_r=100, k=4)
 # n_r 45 and N 30 (the one-chunk radial forms at 12 and 8 k-steps), n_theta 70 > 64 with
 # L <= 32 (the Legendre analysis streaming theta in chunks)
 MID_SHAPE = si.small(20, 30, R=11.0, n_r=45, n_theta=70, n_phi=80, k=17)
+# 32 < L <= 64 with four-tile column blocks and two 64-row theta groups (the FP32
+# synthesis taking both groups per workgroup)
+WIDE_L36 = si.small(36, 6, R=10.0, k=40)
 
 
 def rel_err(got, ref):
@@ -91,9 +94,10 @@ def rel_err(got, ref):
 
 
 @pytest.mark.parametrize("w,k", [(SMALL, 1), (SMALL, 5), (SMALL, 17), (SMALL, 70),
-                                 (ODD_THETA, 3), (LONG_RADIAL, 4), (MID_SHAPE, 17)],
+                                 (ODD_THETA, 3), (LONG_RADIAL, 4), (MID_SHAPE, 17),
+                                 (WIDE_L36, 40)],
                          ids=["small_k1", "small_k5", "small_k17", "small_k70",
-                              "odd_theta", "N70", "L20_nr45_ntheta70"])
+                              "odd_theta", "N70", "L20_nr45_ntheta70", "L36_k40"])
 def test_apply_H_fp64_and_mixed(w, k):
     _say(f"case apply_H {w.name} k={k}")
     s = setup(w)
