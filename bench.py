@@ -489,7 +489,9 @@ def main():
                    "grid": [w.n_r, w.n_theta, w.n_phi], "orbitals": k, "degree": w.degree,
                    "step": "mixed filter + FP64 Cholesky-QR/Rayleigh-Ritz"},
         "filter_gflops": {"mixed": round(gf_mixed, 3), "fp64": round(gf_fp64, 3),
-                          "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4)},
+                          "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4),
+                          "mixed_frac_fp32_peak": round(gf_mixed * 1e9 / PEAK_FP32, 4),
+                          "fp64_frac_fp64_peak": round(gf_fp64 * 1e9 / PEAK_FP64, 4)},
         "time_to_eigenpairs": tte,
         "density": dens,
         "stage_ms_avg": {s: round(v[0], 5) for s, v in stage_avg.items()},
