@@ -174,7 +174,10 @@ ces_status ces_chefsi(ces_ham h, int k, double* d_X, int64_t ldx, int degree, do
 /* rho(x_g) = 2 sum_i f_i psi_i(x_g)^2 with psi_i the inverse transform of
  * column i (Section 2.2.5); d_occ[k] device doubles f_i; d_rho_grid[n_grid]
  * ([r][theta][phi]); d_rho_coef[d] (may be NULL) = forward transform of rho
- * (same basis, the dualing choice of Section 2.2.5). */
+ * (same basis, the dualing choice of Section 2.2.5).  prec CES_PREC_FP64, or
+ * CES_PREC_MIXED: psi formed in FP32, its squares weighted and summed over
+ * the orbitals in FP64; rho and its coefficients are FP64 either way.
+ * Workspace: ces_workspace_size(h, k, prec). */
 ces_status ces_density(ces_ham h, int k, const double* d_X, int64_t ldx,
                        const double* d_occ, double* d_rho_grid, double* d_rho_coef,
                        int prec, void* d_work, size_t work_bytes, void* stream);
