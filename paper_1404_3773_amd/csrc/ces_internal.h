@@ -170,6 +170,12 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d);
 template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
                     int n_proj, int k, int kp, hipStream_t s);
+// part[c][q][i] (row-major k x kp per chunk c of the rows) = the chunk's share
+// of (A^T B)[q][i] for column-major rows x k blocks A, B, on FP64 MFMA with
+// the projector product's kernel; at most part_cap doubles of part are used.
+// Returns the number of chunks.
+int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ldb, double* part,
+                       int64_t part_cap, int64_t rows, int k, int kp, hipStream_t s);
 // Z[alpha][i] = sum_q P[q][alpha] C[q][i] (Z column-major d x k, ld d).
 template <typename T>
 void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,

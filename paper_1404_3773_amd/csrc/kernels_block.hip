@@ -136,57 +136,26 @@ __global__ __launch_bounds__(256) void k_gram_ts(const double* __restrict__ A, i
   }
 }
 
-// Large k: 64 x 64 output tiles on the vector units, rows split into chunks.
-constexpr int GR_T = 64, GR_K = 16;
+// Output tile edge used to size the Gram's partial-sum region for large k.
+constexpr int GR_T = 64;
 
-__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ Am, int64_t lda,
-                                                      const double* __restrict__ Bm, int64_t ldb,
-                                                      double* __restrict__ part, int64_t rows,
-                                                      int k, int64_t chunk) {
-  __shared__ double As[GR_K][GR_T + 1];
-  __shared__ double Bs[GR_K][GR_T + 1];
-  const int i0 = blockIdx.x * GR_T, j0 = blockIdx.y * GR_T;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.z) * chunk;
-  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int64_t q0 = r0; q0 < r1; q0 += GR_K) {
-    for (int e = tid; e < GR_K * GR_T; e += 256) {
-      const int kk = e % GR_K, cc = e / GR_K;
-      const int64_t row = q0 + kk;
-      As[kk][cc] = (row < r1 && i0 + cc < k) ? Am[static_cast<int64_t>(i0 + cc) * lda + row] : 0.0;
-      Bs[kk][cc] = (row < r1 && j0 + cc < k) ? Bm[static_cast<int64_t>(j0 + cc) * ldb + row] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GR_K; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
-    }
-    __syncthreads();
+// C (column-major k x k) = sum_c part[c] with part[c] row-major k x kp (the
+// large-k Gram's chunks), or with sym (S + S^T) / 2, bitwise symmetric; one
+// thread per element, chunks summed in order.
+__global__ __launch_bounds__(256) void k_gram_reduce_rm(const double* __restrict__ part,
+                                                        double* __restrict__ C, int k, int kp,
+                                                        int nchunk, int sym) {
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= kk) return;
+  const int64_t q = e % k, i = e / k;
+  const int64_t cs = static_cast<int64_t>(k) * kp;
+  double sv = 0.0, tv = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    sv += part[c * cs + q * kp + i];
+    if (sym) tv += part[c * cs + i * kp + q];
   }
-  double* P = part + static_cast<int64_t>(blockIdx.z) * k * k;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + tx + 16 * a;
-    if (i >= k) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + ty + 16 * c;
-      if (j < k) P[static_cast<int64_t>(j) * k + i] = acc[a][c];
-    }
-  }
+  C[e] = sym ? 0.5 * (sv + tv) : sv;
 }
 
 // C[i][j] = sum_c part[c][i][j], or with sym the symmetric part
@@ -687,9 +656,12 @@ void launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, dou
     k_gram_reduce<<<static_cast<unsigned>((kk + 3) / 4), 256, 0, s>>>(part, C, k, nb, sym ? 1 : 0);
     return;
   }
-  dim3 grid((k + GR_T - 1) / GR_T, (k + GR_T - 1) / GR_T, nch);
-  k_gram_partial<<<grid, 256, 0, s>>>(A, lda, B, ldb, part, rows, k, chunk);
-  k_gram_reduce<<<static_cast<unsigned>((kk + 3) / 4), 256, 0, s>>>(part, C, k, nch, sym ? 1 : 0);
+  // k > 64: the split-K FP64 MFMA GEMM of the projector products, in the
+  // region sized for gram_chunks(rows, k) chunks of k x k
+  const int kp = (k + 15) / 16 * 16;
+  const int nc = launch_atb_partial(A, lda, B, ldb, part, int64_t(nch) * kk, rows, k, kp, s);
+  k_gram_reduce_rm<<<static_cast<unsigned>((kk + 255) / 256), 256, 0, s>>>(part, C, k, kp, nc,
+                                                                           sym ? 1 : 0);
 }
 
 int small_ld(int k) { return (k + 15) / 16 * 16; }

@@ -38,7 +38,8 @@ constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_t d,
-                                                 const T* __restrict__ Y, int64_t ldy,
+                                                 int64_t ldp, const T* __restrict__ Y,
+                                                 int64_t ldy,
                                                  T* __restrict__ part, int n_proj, int k, int kp,
                                                  int64_t kchunk, int nM, int nN, int n_groups) {
   typedef typename MF<T>::acc acc_t;
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
       const int row = arow0 + RA * p;
-      ra[p] = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * d + kcl];
+      ra[p] = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * ldp + kcl];
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
@@ -276,11 +277,30 @@ void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, 
   const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
   const int per_xcd = (gr.n_groups + 7) / 8;   // groups per XCD (the last ones idle)
   const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
-  k_kb_gemm<T><<<nwg, 256, 0, s>>>(P, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM, gr.nN,
-                                   gr.n_groups);
+  k_kb_gemm<T><<<nwg, 256, 0, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
+                                   gr.nN, gr.n_groups);
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
   k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
+}
+
+int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ldb, double* part,
+                       int64_t part_cap, int64_t rows, int k, int kp, hipStream_t s) {
+  // the projector product's split-K grid, with no more chunks than `part` holds
+  KbGrid<double> gr = kb_grid<double>(k, k, rows);
+  const int64_t per_chunk = static_cast<int64_t>(k) * kp;
+  const int64_t maxc = std::max<int64_t>(1, part_cap / per_chunk);
+  if (gr.nchunk > maxc) {
+    constexpr int KB = KbShape<double>::KB;
+    gr.kchunk = round_up((rows + maxc - 1) / maxc, KB);
+    gr.nchunk = static_cast<int>((rows + gr.kchunk - 1) / gr.kchunk);
+    gr.n_groups = gr.nchunk * gr.nM;
+  }
+  const int per_xcd = (gr.n_groups + 7) / 8;
+  const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
+  k_kb_gemm<double><<<nwg, 256, 0, s>>>(A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM,
+                                        gr.nN, gr.n_groups);
+  return gr.nchunk;
 }
 
 template <typename T>

@@ -237,11 +237,12 @@ def test_rayleigh_ritz_matches_oracle():
     assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * np.max(np.abs(theta_ref))
 
 
-@pytest.mark.parametrize("k", [17, 33, 60, 64])
+@pytest.mark.parametrize("k", [17, 33, 60, 64, 100, 150])
 def test_rayleigh_ritz_block_sizes_match_oracle(k):
     # k = 17, 33, 60 run the one-workgroup Cholesky / Jacobi solvers with the
     # fused block rotation (16-, 48- and 64-wide rotation kernels, with and
-    # without fused residuals); k = 64 runs the rocSOLVER path
+    # without fused residuals); k = 64 runs the rocSOLVER path; k = 100, 150
+    # also the split-K MFMA Gram (several 128 x 64 tiles, a partial last one)
     w = SMALL
     _say(f"case rayleigh_ritz k={k}")
     s = setup(w)
@@ -268,6 +269,26 @@ def test_rayleigh_ritz_block_sizes_match_oracle(k):
         if with_hx:
             HXg = host(HXt, s.B.d)
             assert np.max(np.abs(HXg - s.oracle_apply(Xg))) < 1e-10 * scale
+
+
+def test_rayleigh_ritz_large_k_gram_over_row_chunks():
+    """k = 120 on a 630-row basis: the split-K Gram sums two row chunks."""
+    w = LONG_RADIAL
+    k = 120
+    _say(f"case rayleigh_ritz {w.name} k={k}")
+    s = setup(w)
+    X = si.random_block(s.B.d, k, 77) * np.linspace(0.5, 3.0, k)
+    theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
+    scale = np.max(np.abs(theta_ref))
+    work = s.H.workspace(k, FP64)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    Xt = dev(X, ld=s.B.d + 5)
+    s.H.rayleigh_ritz(Xt, ev, rs, work)
+    Xg = host(Xt, s.B.d)
+    assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * scale
+    assert np.max(np.abs(Xg.T @ Xg - np.eye(k))) < 1e-12
+    assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-9 * scale
 
 
 def test_rayleigh_ritz_rank_deficient_block_reports_error():
