@@ -438,6 +438,54 @@ def test_density_column_blocks_and_phi_tiles_match_oracle(w, k):
         assert rel_err(tau.cpu().numpy(), tau_ref) < tol, prec
 
 
+# Degenerate bases: s waves only (L = 1: one slot, no sine part, a one-row
+# Legendre contraction), one radial function per l (N = 1), and both at once
+# with a single orbital; phi grids of 4 points (below one 16-point tile).
+DEGENERATE = [si.small(1, 1, R=8.0, k=1, name="L1_N1"), si.small(1, 6, R=8.0, k=3, name="L1_N6"),
+              si.small(4, 1, R=8.0, k=2, name="L4_N1")]
+
+
+@pytest.mark.parametrize("w", DEGENERATE, ids=lambda w: w.name)
+def test_degenerate_bases_match_oracle(w):
+    """H X, the density and Rayleigh-Ritz on the smallest bases the method
+    allows, in both precisions where they apply."""
+    _say(f"case degenerate {w.name} k={w.k}")
+    s = setup(w)
+    k = w.k
+    X = si.random_block(s.B.d, k, 31) * np.linspace(1.0, 3.0, k)
+    Z = s.oracle_apply(X)
+    for prec, tol in ((FP64, TOL64), (MIXED, TOL32)):
+        work = s.H.workspace(k, prec)
+        Yt = torch.full((k, s.B.d), float("nan"), dtype=torch.float64, device="cuda")
+        s.H.apply_H(dev(X), Yt, prec, work)
+        torch.cuda.synchronize()
+        assert rel_err(host(Yt, s.B.d), Z) < tol, (prec, rel_err(host(Yt, s.B.d), Z))
+    occ = np.linspace(1.0, 0.5, k)
+    rho_ref = od.density_grid(s.bs, X, occ)
+    tau_ref = od.density_coefficients(s.bs, rho_ref)
+    for prec, tol in ((FP64, 1e-11), (MIXED, 5e-5)):
+        work = s.H.workspace(k, prec)
+        rho = torch.empty(s.B.n_grid, dtype=torch.float64, device="cuda")
+        tau = torch.empty(s.B.d, dtype=torch.float64, device="cuda")
+        s.H.density(dev(X), torch.from_numpy(occ).cuda(), rho, tau, prec, work)
+        torch.cuda.synchronize()
+        assert rel_err(rho.cpu().numpy().reshape(rho_ref.shape), rho_ref) < tol, prec
+        assert rel_err(tau.cpu().numpy(), tau_ref) < tol, prec
+    theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
+    work = s.H.workspace(k, FP64)
+    Xt = dev(X)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    s.H.rayleigh_ritz(Xt, ev, rs, work)
+    Xg = host(Xt, s.B.d)
+    scale = np.max(np.abs(theta_ref))
+    assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * scale
+    assert np.max(np.abs(Xg.T @ Xg - np.eye(k))) < 1e-12
+    sg = np.sign(np.sum(Xg * Xr, axis=0))
+    assert np.max(np.abs(Xg * sg - Xr)) < 1e-9
+    assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-10 * scale
+
+
 def test_invalid_arguments_rejected_before_launch():
     s = setup(SMALL)
     work = s.H.workspace(3, FP64)
@@ -446,6 +494,13 @@ def test_invalid_arguments_rejected_before_launch():
     with pytest.raises(ces.CesError) as e:       # workspace too small
         s.H.apply_H(X, Y, FP64, work[:1024])
     assert e.value.status == 4
+    with pytest.raises(ces.CesError) as e:       # empty block (k = 0)
+        s.H.apply_H(X[:0], Y[:0], FP64, work)
+    assert e.value.status == 1
+    with pytest.raises(ces.CesError) as e:       # leading dimension below d
+        short = torch.zeros((3, s.B.d - 1), dtype=torch.float64, device="cuda")
+        s.H.apply_H(short, Y, FP64, work)
+    assert e.value.status == 1
     with pytest.raises(ces.CesError) as e:       # bad filter bounds
         s.H.cheb_filter(X, 4, 1.0, 0.5, 0.0, FP64, work)
     assert e.value.status == 1
