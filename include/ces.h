@@ -23,7 +23,10 @@
  *  Index.  Coefficient alpha = (l*l + l + m) * N + n (0-based form of the
  *    paper's indexing map, Section 2.2.3).  d = L*L*N.
  *  Blocks.  Orbitals are columns; column-major; leading dimension ld >= d.
- *    All values crossing this interface are FP64.
+ *    All values crossing this interface are FP64.  A block has k >= 1
+ *    columns and n_r * n_theta * ceil(k16 / 32) < 2^31, k16 = k rounded up to
+ *    a multiple of 16 (the angular kernels' grid); otherwise, or with
+ *    ld < d or a null block, the call returns CES_ERR_INVALID_ARG.
  *  Grid.  n_r radial nodes (ascending r) x n_theta Gauss-Legendre nodes in
  *    cos(theta) (ascending theta) x n_phi uniform phi_p = 2 pi p / n_phi
  *    (Section 2.2.2).  Grid arrays are C-order [r][theta][phi].
@@ -34,6 +37,11 @@
  *  Workspace.  Calls that take (d_work, work_bytes) use only that device
  *    memory for scratch; query the size with ces_workspace_size.  Calls that
  *    run concurrently on different streams need distinct workspaces.
+ *  Threads.  A handle (ces_basis, ces_ham, ces_mlp) keeps mutable state: its
+ *    device tables are built on first use and ces_ham holds the pinned host
+ *    buffer through which the synchronising calls read their results.  Calls
+ *    on one handle from several host threads must be serialised by the
+ *    caller; distinct handles are independent.
  *  Errors.  Every call returns a ces_status; arguments are validated on the
  *    host before any launch.  Device faults surface as CES_ERR_DEVICE at the
  *    next synchronising call.  ces_last_error() gives a thread-local detail.

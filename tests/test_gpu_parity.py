@@ -497,6 +497,10 @@ def test_invalid_arguments_rejected_before_launch():
     with pytest.raises(ces.CesError) as e:       # empty block (k = 0)
         s.H.apply_H(X[:0], Y[:0], FP64, work)
     assert e.value.status == 1
+    with pytest.raises(ces.CesError) as e:       # k beyond what the angular grid can index
+        huge = X.as_strided((1 << 30, s.B.d), (0, 1))   # never dereferenced
+        s.H.apply_H(huge, huge, FP64, work)
+    assert e.value.status == 1 and "too large" in str(e.value)
     with pytest.raises(ces.CesError) as e:       # leading dimension below d
         short = torch.zeros((3, s.B.d - 1), dtype=torch.float64, device="cuda")
         s.H.apply_H(short, Y, FP64, work)
