@@ -553,6 +553,9 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
   // read-backs go through the handle's pinned stage: info flags at offset 0,
   // eigenvalues at 2, residual norms at 2 + k, behind one synchronisation
   auto read_info = [&](rocblas_int* h3) -> ces_status {
+    // a launch that never started leaves its status flag as an earlier call
+    // wrote it: report it before the flags are trusted
+    CES_HIP(hipGetLastError());
     CES_TRY(stage_read(h, 0, info, 3 * sizeof(rocblas_int), s));
     CES_HIP(hipStreamSynchronize(s));
     std::memcpy(h3, h.host_stage, 3 * sizeof(rocblas_int));

@@ -608,13 +608,13 @@ void rotate_kt(double* X, int64_t ldx, double* Y, int64_t ldy, const double* W, 
 template <int NP>
 void jacobi_np(double* S, int k, double* evals, int* info, hipStream_t s) {
   const size_t lds = jacobi_lds_bytes(k, NP);
-  static bool raised = false;   // allow more than 64 KB of LDS once per instantiation
-  if (!raised) {
+  // more than the default 64 KB of LDS (k > 50): raised on every such launch
+  // rather than behind a process-wide flag, so concurrent callers and other
+  // devices need no synchronisation; a refusal makes the launch fail, which
+  // the caller's launch check reports
+  if (lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_eig<NP>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(jacobi_lds_bytes(kJacobiMax, 64)));
-    raised = true;
-  }
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   k_jacobi_eig<NP><<<1, kJacobiThreads, lds, s>>>(S, k, small_ld(k), evals, info);
 }
 
