@@ -18,4 +18,13 @@ Modules
   hamiltonian  dense H (definition) and the paper's separable H*X
   eigensolver  Chebyshev filter, Cholesky-QR, Rayleigh-Ritz, CheFSI driver
   density      electron density, Hartree potential (closed form), Slater exchange
+  scf          Kohn-Sham potential, Anderson mixing, SAD start, SCF driver
+  mlp          the learned start's descriptors, network, loss and Adam step
+
+The tests in tests/test_oracle_*pins.py tie the oracle to things other than
+itself: closed forms, analytic spectra, invariants, finite differences, an
+independent radial solver, brute force on small cases.  Parity unpinned: the absolute eigenvalues
+of the cluster workloads (the paper prints none for these synthetic clusters;
+they rest on the operator pins and on oracle-GPU agreement), SCF iteration
+counts, and the learned start's reduction of them (measured, not pinned).
 """
