@@ -37,11 +37,16 @@
  *  Workspace.  Calls that take (d_work, work_bytes) use only that device
  *    memory for scratch; query the size with ces_workspace_size.  Calls that
  *    run concurrently on different streams need distinct workspaces.
- *  Threads.  A handle (ces_basis, ces_ham, ces_mlp) keeps mutable state: its
- *    device tables are built on first use and ces_ham holds the pinned host
- *    buffer through which the synchronising calls read their results.  Calls
- *    on one handle from several host threads must be serialised by the
- *    caller; distinct handles are independent.
+ *  Threads.  Apart from ces_ham_set_veff, calls do not change what a basis
+ *    or Hamiltonian handle represents, and calls on one handle may run from
+ *    several host threads at once (each on its own stream, with its own
+ *    workspace).  The handle's internal state (the one-time upload of the
+ *    basis tables, the rocBLAS handle, its workspace-size cache and the
+ *    pinned buffer for read-backs) is guarded by locks: Rayleigh-Ritz (also
+ *    inside ces_chefsi and ces_scf) and ces_lanczos_bound on one handle run
+ *    one at a time; H X, the filter and the density do not lock.
+ *    ces_ham_set_veff must not overlap other calls on its handle, and calls
+ *    on one ces_mlp handle must be serialised by the caller.
  *  Errors.  Every call returns a ces_status; arguments are validated on the
  *    host before any launch.  Device faults surface as CES_ERR_DEVICE at the
  *    next synchronising call.  ces_last_error() gives a thread-local detail.

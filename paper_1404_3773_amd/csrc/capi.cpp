@@ -185,6 +185,7 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
 
 // Upload device tables once (on the device current at first use).
 ces_status ensure_device(Basis& b) {
+  std::lock_guard<std::mutex> lock(b.dev_mu);
   int dev = 0;
   CES_HIP(hipGetDevice(&dev));
   if (b.dev_block) {
@@ -266,6 +267,7 @@ ces_status ensure_device(Basis& b) {
 
 
 size_t solver_bytes_for(Ham& h, int k) {
+  std::lock_guard<std::mutex> lock(h.mu);
   if (h.solver_ws_k == k) return h.solver_ws;
   size_t sz = 0;
   // Size query: no kernel runs while the handle is in query mode; the
@@ -506,6 +508,7 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& bb) 
 ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx, double* HX,
                    int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s,
                    double* h_eval = nullptr, double* h_res = nullptr) {
+  std::lock_guard<std::mutex> lock(h.mu);   // rocBLAS handle and host_stage
   const Basis& b = *h.basis;
   const int64_t d = b.d;
   double* S1 = Ptr<double>::at(work, ly.S1);
@@ -933,6 +936,7 @@ ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* 
   double* vp = v + d;
   double* w = v + 2 * d;
   double* sc = Ptr<double>::at(d_work, ly.vec);
+  std::lock_guard<std::mutex> lock(h.mu);   // host_stage
   CES_HIP(hipMemsetAsync(vp, 0, size_t(d) * 8, s));
   launch_dot(d_v0, d_v0, d, sc, sc + 64, s);
   CES_TRY(stage_read(h, 0, sc, 8, s));

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,7 @@ struct Basis {
   DevTables<double> t64;
   DevTables<float> t32;
   void* dev_block = nullptr;     // single allocation holding all device tables
+  std::mutex dev_mu;             // held while the device tables are uploaded
 };
 
 struct Ham {
@@ -76,6 +78,11 @@ struct Ham {
   void* dev_block = nullptr;
   double* host_stage = nullptr;   // pinned host buffer for results read back by a call
   size_t host_stage_n = 0;        // its length in doubles
+  // Held by every call that uses the rocBLAS handle, the solver-size cache or
+  // host_stage (workspace layout queries, Rayleigh-Ritz, the Lanczos bound),
+  // so concurrent calls on one handle from several threads stay correct; the
+  // H X, filter and density paths touch none of these and run unlocked.
+  std::mutex mu;
 };
 
 // Pinned host staging of at least n doubles on h (grown as needed), so that a

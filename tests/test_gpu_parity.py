@@ -486,6 +486,52 @@ def test_degenerate_bases_match_oracle(w):
     assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-10 * scale
 
 
+def test_concurrent_calls_on_one_handle_match_sequential():
+    """Two host threads, each with its own stream and workspace, apply H and
+    run Rayleigh-Ritz on one Hamiltonian handle at once (k = 6: one-workgroup
+    kernels; k = 100: rocBLAS/rocSOLVER on the handle's shared BLAS handle);
+    every result equals the same calls made one after another, bit for bit."""
+    import threading
+    s = setup(SMALL)
+    blocks = {k: si.random_block(s.B.d, k, 40 + k) * np.linspace(0.5, 4.0, k) for k in (6, 100)}
+
+    def run(k, stream, work):
+        with torch.cuda.stream(stream):
+            X = dev(blocks[k])
+            Y = torch.empty_like(X)
+            ev = torch.empty(k, dtype=torch.float64, device="cuda")
+            rs = torch.empty(k, dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                s.H.apply_H(X, Y, FP64, work, stream=stream)
+                s.H.rayleigh_ritz(X, ev, rs, work, stream=stream)
+            stream.synchronize()
+            return Y.cpu().numpy(), X.cpu().numpy(), ev.cpu().numpy(), rs.cpu().numpy()
+
+    streams = {k: torch.cuda.Stream() for k in blocks}
+    works = {k: s.H.workspace(k, FP64) for k in blocks}
+    _say("case concurrent handle: sequential reference")
+    ref = {k: run(k, streams[k], works[k]) for k in blocks}
+    _say("case concurrent handle: two threads")
+    out, errs = {}, []
+
+    def worker(k):
+        try:
+            out[k] = run(k, streams[k], works[k])
+        except Exception as e:   # reported by the main thread
+            errs.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in blocks]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errs, errs
+    assert not any(t.is_alive() for t in threads)
+    for k in blocks:
+        for a, b in zip(out[k], ref[k]):
+            assert np.array_equal(a, b), k
+
+
 def test_invalid_arguments_rejected_before_launch():
     s = setup(SMALL)
     work = s.H.workspace(3, FP64)
