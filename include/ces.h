@@ -35,7 +35,11 @@
  *  Streams.  `stream` is a hipStream_t passed as void* (NULL = default
  *    stream).  Calls are asynchronous on it unless stated otherwise.
  *  Workspace.  Calls that take (d_work, work_bytes) use only that device
- *    memory for scratch; query the size with ces_workspace_size.  Calls that
+ *    memory for scratch and allocate no device memory; query the size with
+ *    ces_workspace_size.  The only allocation after the handles are created
+ *    is the Hamiltonian's pinned host buffer for read-backs, made at
+ *    ces_ham_create for k <= 511 and grown once by the first
+ *    Rayleigh-Ritz call with a larger k.  Calls that
  *    run concurrently on different streams need distinct workspaces.
  *  Threads.  Apart from ces_ham_set_veff, calls do not change what a basis
  *    or Hamiltonian handle represents, and calls on one handle may run from

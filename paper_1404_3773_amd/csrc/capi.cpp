@@ -797,12 +797,16 @@ ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const 
   }
   auto cleanup = [&](ces_status st) {
     if (h.blas) rocblas_destroy_handle(h.blas);
+    if (h.host_stage) (void)hipHostFree(h.host_stage);
     (void)hipFree(blk);
     delete hh;
     return st;
   };
   if (rocblas_create_handle(&h.blas) != rocblas_status_success)
     return cleanup(fail(CES_ERR_DEVICE, "rocblas_create_handle failed"));
+  // the read-back buffer for k <= 511, so that later calls allocate only for
+  // larger blocks
+  if (const ces_status st = host_stage(h, 1024); st != CES_OK) return cleanup(st);
   if (hipMemcpyAsync(h.veff, d_veff, size_t(b.n_grid) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return cleanup(fail(CES_ERR_DEVICE, "copy of V_eff failed"));
   launch_veff_fourier(b, h.veff, h.ab64, h.ab32, s);
