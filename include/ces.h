@@ -117,6 +117,24 @@ ces_status ces_basis_grid(ces_basis b, double* h_r, double* h_wr, double* h_thet
 ces_status ces_basis_tables(ces_basis b, double* h_zeros, double* h_radial,
                             double* h_legendre);
 
+/* Coefficients in the paper's complex basis R_ln Y_l^m (Section 2.2.1,
+ * without the Condon-Shortley phase; same index alpha) to the real basis of
+ * this interface, and back.  For each (l, n) and mu = |m| > 0:
+ *   complex -> real  s_{l,mu}  = (f_{l,mu} + f_{l,-mu}) / sqrt2
+ *                    s_{l,-mu} = i (f_{l,mu} - f_{l,-mu}) / sqrt2
+ *   real -> complex  f_{l,mu}  = (s_{l,mu} - i s_{l,-mu}) / sqrt2
+ *                    f_{l,-mu} = (s_{l,mu} + i s_{l,-mu}) / sqrt2
+ * and s_{l,0} = f_{l,0}; the map is unitary, so norms and inner products
+ * carry over.  Both blocks are d x k column-major of interleaved complex
+ * doubles (re, im), leading dimension >= d in complex entries, 16-byte
+ * aligned, device memory, and must not overlap (CES_ERR_INVALID_ARG).  A
+ * real function has f_{l,-mu} = conj(f_{l,mu}) and real s (zero imaginary
+ * parts up to rounding).  Asynchronous on `stream`. */
+ces_status ces_coeffs_complex_to_real(ces_basis b, int k, const double* d_f, int64_t ldf,
+                                      double* d_s, int64_t lds, void* stream);
+ces_status ces_coeffs_real_to_complex(ces_basis b, int k, const double* d_s, int64_t lds,
+                                      double* d_f, int64_t ldf, void* stream);
+
 /* ------------------------------------------------------------ hamiltonian */
 
 /* H = 1/2 diag(Lambda) + B^T W diag(V_eff) B [+ P diag(h) P^T]
@@ -223,6 +241,12 @@ ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64
  * coefficients in the real layout; d_vh[n_grid] output. */
 ces_status ces_hartree(ces_ham h, const double* d_tau, double* d_vh, void* d_work,
                        size_t work_bytes, void* stream);
+
+/* Slater (LDA) exchange potential, elementwise over n grid values:
+ * d_vx = -(3 rho_+ / pi)^(1/3), rho_+ = max(d_rho, 0) (Section 2.1's V_x in
+ * its exchange-only local form).  d_vx may equal d_rho.  n = 0 does nothing;
+ * n < 0 or a null pointer is CES_ERR_INVALID_ARG.  Asynchronous. */
+ces_status ces_slater_x(int64_t n, const double* d_rho, double* d_vx, void* stream);
 
 /* d_v = V_ext + V_H[rho - rho_ion] + V_x[rho], V_x = -(3 rho_+ / pi)^(1/3),
  * rho_+ = max(rho, 0).  V_H uses the forward transform of rho - rho_ion in

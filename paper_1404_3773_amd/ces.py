@@ -26,6 +26,7 @@ EXPORTS = [
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
     "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
+    "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
@@ -73,6 +74,9 @@ def load() -> ctypes.CDLL:
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
         "ces_to_grid": [P, I, P, I64, P, P, SZ, P],
         "ces_from_grid": [P, I, P, P, I64, P, SZ, P],
+        "ces_coeffs_complex_to_real": [P, I, P, I64, P, I64, P],
+        "ces_coeffs_real_to_complex": [P, I, P, I64, P, I64, P],
+        "ces_slater_x": [I64, P, P, P],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
         "ces_anderson_workspace_size": [I64, I, ctypes.POINTER(SZ)],
@@ -152,6 +156,21 @@ def profile_read():
     _check(load().ces_profile_read(n, ms.ctypes.data_as(ctypes.c_void_p),
                                    cnt.ctypes.data_as(ctypes.c_void_p)), "ces_profile_read")
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def slater_x(rho, vx, stream=None):
+    """vx = -(3 max(rho, 0) / pi)^(1/3) elementwise (contiguous float64 tensors)."""
+    assert rho.dtype == vx.dtype and rho.is_contiguous() and vx.is_contiguous()
+    assert rho.numel() == vx.numel()
+    _check(load().ces_slater_x(rho.numel(), _ptr(rho), _ptr(vx), _stream(stream)),
+           "ces_slater_x")
+
+
+def _ldc(Z):
+    """Leading dimension (complex entries) of a (k, ld) complex128 block tensor."""
+    import torch
+    assert Z.dtype == torch.complex128 and Z.dim() == 2 and Z.stride(1) == 1
+    return Z.stride(0)
 
 
 def anderson_mix(V, F, oldest, beta, out, h_coef=None, stream=None):
@@ -308,6 +327,19 @@ class Basis:
                                                   for a in (z, rad, leg)]), "ces_basis_tables")
         return (z.reshape(self.L, self.N), rad.reshape(self.L, self.n_r, self.N),
                 leg.reshape(self.n_theta, -1))
+
+    def coeffs_complex_to_real(self, F, S, stream=None):
+        """S <- real-basis coefficients of the complex-basis block F; both
+        (k, ld) complex128 tensors on the GPU (row i = orbital i)."""
+        _check(load().ces_coeffs_complex_to_real(self._h, F.shape[0], _ptr(F), _ldc(F), _ptr(S),
+                                                 _ldc(S), _stream(stream)),
+               "ces_coeffs_complex_to_real")
+
+    def coeffs_real_to_complex(self, S, F, stream=None):
+        """F <- complex-basis coefficients of the real-basis block S."""
+        _check(load().ces_coeffs_real_to_complex(self._h, S.shape[0], _ptr(S), _ldc(S), _ptr(F),
+                                                 _ldc(F), _stream(stream)),
+               "ces_coeffs_real_to_complex")
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

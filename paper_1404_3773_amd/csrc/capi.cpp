@@ -737,6 +737,42 @@ ces_status ces_basis_info(ces_basis bb, int64_t* d, int64_t* n_grid) {
   return CES_OK;
 }
 
+namespace {
+// Validation shared by the two coefficient maps: sizes, 16-byte alignment of
+// the interleaved complex blocks, and no overlap between input and output.
+ces_status check_coeff_map(ces_basis bb, int k, const double* in, int64_t ldi, const double* out,
+                           int64_t ldo) {
+  if (!bb) return fail(CES_ERR_INVALID_ARG, "null basis");
+  const int64_t d = bb->b.d;
+  if (k < 1) return fail(CES_ERR_INVALID_ARG, "k must be >= 1");
+  if (!in || !out) return fail(CES_ERR_INVALID_ARG, "null coefficient block");
+  if (ldi < d || ldo < d) return fail(CES_ERR_INVALID_ARG, "leading dimension below d");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
+    return fail(CES_ERR_INVALID_ARG, "complex blocks must be 16-byte aligned");
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(in), b0 = reinterpret_cast<uintptr_t>(out);
+  const uintptr_t a1 = a0 + uintptr_t(16) * uintptr_t((k - 1) * ldi + d);
+  const uintptr_t b1 = b0 + uintptr_t(16) * uintptr_t((k - 1) * ldo + d);
+  if (a0 < b1 && b0 < a1) return fail(CES_ERR_INVALID_ARG, "input and output blocks overlap");
+  return CES_OK;
+}
+}  // namespace
+
+ces_status ces_coeffs_complex_to_real(ces_basis bb, int k, const double* d_f, int64_t ldf,
+                                      double* d_s, int64_t lds, void* stream) {
+  CES_TRY(check_coeff_map(bb, k, d_f, ldf, d_s, lds));
+  launch_coeffs_c2r(bb->b, d_f, ldf, d_s, lds, k, static_cast<hipStream_t>(stream));
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_coeffs_real_to_complex(ces_basis bb, int k, const double* d_s, int64_t lds,
+                                      double* d_f, int64_t ldf, void* stream) {
+  CES_TRY(check_coeff_map(bb, k, d_s, lds, d_f, ldf));
+  launch_coeffs_r2c(bb->b, d_s, lds, d_f, ldf, k, static_cast<hipStream_t>(stream));
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
 ces_status ces_basis_grid(ces_basis bb, double* h_r, double* h_wr, double* h_theta,
                           double* h_wtheta, double* h_phi) {
   if (!bb) return fail(CES_ERR_INVALID_ARG, "null basis");

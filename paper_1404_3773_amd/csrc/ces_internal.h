@@ -212,6 +212,14 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
 // v = vext + v - (3 rho / pi)^(1/3), v holding V_H on entry.
 void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
                       hipStream_t s);
+// vx = -(3 rho_+ / pi)^(1/3) elementwise (vx may be rho).
+void launch_slater_x(const double* rho, double* vx, int64_t n, hipStream_t s);
+// Complex <-> real harmonic coefficients (kernels.hip), d x k interleaved
+// complex blocks with leading dimensions in complex entries.
+void launch_coeffs_c2r(const Basis& b, const double* f, int64_t ldf, double* sr, int64_t lds,
+                       int k, hipStream_t s);
+void launch_coeffs_r2c(const Basis& b, const double* sr, int64_t lds, double* f, int64_t ldf,
+                       int k, hipStream_t s);
 // out = sum_i c_i (V_i + beta F_i) over m columns of ld-strided history.
 void launch_anderson_combine(const double* V, const double* F, int64_t ld, const double* c,
                              int m, double beta, double* out, int64_t n, hipStream_t s);

@@ -12,6 +12,8 @@
 // so they are computed once per V_eff and the per-orbital work needs no FFT.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ces_internal.h"
 
 namespace ces {
@@ -269,6 +271,46 @@ inline int grid1d(int64_t n) {
   return static_cast<int>(g > 4096 ? 4096 : (g < 1 ? 1 : g));
 }
 
+// Complex <-> real harmonic coefficients, one thread per output entry
+// (alpha, column i) of d x k interleaved complex blocks.  With alpha =
+// (l^2 + l + m) N + n and mu = |m| > 0, each (l, n) pairs f_{+mu} and f_{-mu}:
+//   complex -> real   s_{+mu} = (f_{+mu} + f_{-mu}) / sqrt2
+//                     s_{-mu} = i (f_{+mu} - f_{-mu}) / sqrt2
+//   real -> complex   f_{+mu} = (s_{+mu} - i s_{-mu}) / sqrt2
+//                     f_{-mu} = (s_{+mu} + i s_{-mu}) / sqrt2
+// and m = 0 is copied.  in and out do not overlap (checked by the caller).
+template <bool TO_REAL>
+__global__ void k_coeffs_map(const double2* __restrict__ in, int64_t ldi,
+                             double2* __restrict__ out, int64_t ldo, int L, int N, int64_t d,
+                             int k) {
+  const int64_t total = d * k;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = e / d, a = e - i * d;
+    const int lm = static_cast<int>(a / N), n = static_cast<int>(a - int64_t(lm) * N);
+    const int l = isqrt_lm(lm), m = lm - l * l - l, mu = m < 0 ? -m : m;
+    const double2* col = in + i * ldi;
+    double2 r;
+    if (m == 0) {
+      r = col[a];
+    } else {
+      const double2 p = col[int64_t(l * l + l + mu) * N + n];   // the +mu entry
+      const double2 q = col[int64_t(l * l + l - mu) * N + n];   // the -mu entry
+      const double h = 0.70710678118654752440;                 // 1 / sqrt2
+      if (TO_REAL) {
+        // s_{+mu} = (p + q) h;  s_{-mu} = i (p - q) h = (-(p - q).y, (p - q).x) h
+        r = m > 0 ? make_double2((p.x + q.x) * h, (p.y + q.y) * h)
+                  : make_double2(-(p.y - q.y) * h, (p.x - q.x) * h);
+      } else {
+        // here p = s_{+mu}, q = s_{-mu}; i q = (-q.y, q.x)
+        r = m > 0 ? make_double2((p.x + q.y) * h, (p.y - q.x) * h)     // (p - i q) h
+                  : make_double2((p.x - q.y) * h, (p.y + q.x) * h);    // (p + i q) h
+      }
+    }
+    out[i * ldo + a] = r;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -305,6 +347,22 @@ void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f,
 }
 
 
+
+void launch_coeffs_c2r(const Basis& b, const double* f, int64_t ldf, double* sr, int64_t lds,
+                       int k, hipStream_t s) {
+  const int64_t total = b.d * k;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 8192));
+  k_coeffs_map<true><<<g, 256, 0, s>>>(reinterpret_cast<const double2*>(f), ldf,
+                                        reinterpret_cast<double2*>(sr), lds, b.L, b.N, b.d, k);
+}
+
+void launch_coeffs_r2c(const Basis& b, const double* sr, int64_t lds, double* f, int64_t ldf,
+                       int k, hipStream_t s) {
+  const int64_t total = b.d * k;
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 8192));
+  k_coeffs_map<false><<<g, 256, 0, s>>>(reinterpret_cast<const double2*>(sr), lds,
+                                         reinterpret_cast<double2*>(f), ldf, b.L, b.N, b.d, k);
+}
 
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s) {
   k_scale_gram<<<1, 256, 0, s>>>(S, k, dinv);

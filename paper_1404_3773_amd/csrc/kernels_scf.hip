@@ -25,15 +25,25 @@ __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b
     out[e] = a[e] - b[e];
 }
 
-// v[g] = vext[g] + v[g] - (3 rho_+ / pi)^(1/3)   (v holds V_H on entry)
+// Slater (LDA) exchange potential V_x = -(3 rho_+ / pi)^(1/3), rho_+ =
+// max(rho, 0): negative densities from quadrature noise count as zero.
+__device__ __forceinline__ double slater_vx(double rho) {
+  return -cbrt((3.0 / M_PI) * (rho > 0.0 ? rho : 0.0));
+}
+
+// v[g] = vext[g] + v[g] + V_x(rho[g])   (v holds V_H on entry)
 __global__ void k_ks_finish(const double* __restrict__ vext, const double* __restrict__ rho,
                             double* __restrict__ v, int64_t n) {
-  const double c = 3.0 / M_PI;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double r = rho[e];
-    v[e] = vext[e] + v[e] - cbrt(c * (r > 0.0 ? r : 0.0));
-  }
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    v[e] = vext[e] + v[e] + slater_vx(rho[e]);
+}
+
+// vx[g] = V_x(rho[g]); vx may be rho (each element is read before it is written)
+__global__ void k_slater_x(const double* rho, double* vx, int64_t n) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    vx[e] = slater_vx(rho[e]);
 }
 
 // out[g] = sum_i c_i (V[g][i] + beta F[g][i]),  V, F column-major n x m.
@@ -100,6 +110,10 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
 void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
                       hipStream_t s) {
   k_ks_finish<<<grid1d(n), 256, 0, s>>>(vext, rho, v, n);
+}
+
+void launch_slater_x(const double* rho, double* vx, int64_t n, hipStream_t s) {
+  k_slater_x<<<grid1d(n), 256, 0, s>>>(rho, vx, n);
 }
 
 void launch_anderson_combine(const double* V, const double* F, int64_t ld, const double* c,

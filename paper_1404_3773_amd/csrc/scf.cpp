@@ -128,6 +128,15 @@ using namespace ces;
 
 extern "C" {
 
+ces_status ces_slater_x(int64_t n, const double* d_rho, double* d_vx, void* stream) {
+  if (n < 0) return fail(CES_ERR_INVALID_ARG, "negative length");
+  if (n == 0) return CES_OK;
+  if (!d_rho || !d_vx) return fail(CES_ERR_INVALID_ARG, "null density or output");
+  launch_slater_x(d_rho, d_vx, n, static_cast<hipStream_t>(stream));
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
 ces_status ces_hartree(ces_ham hh, const double* d_tau, double* d_vh, void* d_work,
                        size_t work_bytes, void* stream) {
   CES_TRY(check_ham(hh));

@@ -532,6 +532,55 @@ def test_concurrent_calls_on_one_handle_match_sequential():
             assert np.array_equal(a, b), k
 
 
+def _cblock(Z, ld):
+    """d x k complex numpy block -> (k, ld) complex128 cuda tensor."""
+    d, k = Z.shape
+    T = torch.zeros((k, ld), dtype=torch.complex128)
+    T[:, :d] = torch.from_numpy(np.ascontiguousarray(Z.T))
+    return T.cuda()
+
+
+@pytest.mark.parametrize("w", [SMALL, ODD_THETA, DEGENERATE[1]], ids=["L6_N8", "L5_N7", "L1_N6"])
+def test_coefficient_maps_match_oracle(w):
+    """Complex <-> real harmonic coefficients against the oracle's unitary
+    map, with ld > d on both sides; the round trip is the identity, and the
+    coefficients of a real function come out real."""
+    _say(f"case coefficient maps {w.name}")
+    s = setup(w)
+    d, k = s.B.d, 3
+    F = si.random_block(d, k, 51) + 1j * si.random_block(d, k, 52)
+    S_ref = np.column_stack([ob.complex_to_real(F[:, i], w.L, w.N) for i in range(k)])
+    Ft = _cblock(F, d + 3)
+    St = torch.full((k, d + 5), complex("nan"), dtype=torch.complex128, device="cuda")
+    s.B.coeffs_complex_to_real(Ft, St)
+    Fb = torch.full((k, d + 2), complex("nan"), dtype=torch.complex128, device="cuda")
+    s.B.coeffs_real_to_complex(St, Fb)
+    torch.cuda.synchronize()
+    S = St[:, :d].cpu().numpy().T
+    assert np.max(np.abs(S - S_ref)) < 4e-15 * np.max(np.abs(S_ref))
+    assert np.max(np.abs(Fb[:, :d].cpu().numpy().T - F)) < 1e-14 * np.max(np.abs(F))
+    assert torch.all(torch.isnan(St[:, d:].real)) and torch.all(torch.isnan(Fb[:, d:].real))
+    F_ref = np.column_stack([ob.real_to_complex(S_ref[:, i], w.L, w.N) for i in range(k)])
+    Fr = torch.empty((k, d), dtype=torch.complex128, device="cuda")
+    s.B.coeffs_real_to_complex(_cblock(S_ref, d), Fr)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(Fr.cpu().numpy().T - F_ref)) < 4e-15 * np.max(np.abs(F_ref))
+    # a real function: real coefficients s -> f with f_{-m} = conj(f_m) -> s again, real
+    Xr = si.random_block(d, k, 53).astype(np.complex128)
+    Fr = torch.empty((k, d), dtype=torch.complex128, device="cuda")
+    s.B.coeffs_real_to_complex(_cblock(Xr, d), Fr)
+    Sr = torch.empty((k, d), dtype=torch.complex128, device="cuda")
+    s.B.coeffs_complex_to_real(Fr, Sr)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(Sr.cpu().numpy().T - Xr)) < 1e-14 * np.max(np.abs(Xr))
+    Fc = Fr.cpu().numpy().T
+    for l in range(w.L):
+        for m in range(1, l + 1):
+            plus = Fc[(l * l + l + m) * w.N:(l * l + l + m + 1) * w.N]
+            minus = Fc[(l * l + l - m) * w.N:(l * l + l - m + 1) * w.N]
+            assert np.max(np.abs(minus - np.conj(plus))) < 1e-14 * np.max(np.abs(Xr))
+
+
 def test_invalid_arguments_rejected_before_launch():
     s = setup(SMALL)
     work = s.H.workspace(3, FP64)

@@ -77,6 +77,26 @@ def test_hartree_matches_oracle_quadrature(small):
     assert e < 1e-11
 
 
+def test_slater_exchange_matches_oracle():
+    """V_x = -(3 rho_+ / pi)^(1/3) elementwise against the oracle, with
+    negative, zero and positive densities, a length that is not a multiple
+    of the workgroup, and in place."""
+    _say("case slater_x")
+    rng = np.random.default_rng(61)
+    rho = rng.uniform(-0.2, 2.0, 100_003) ** 3
+    rho[:7] = [0.0, -0.0, -1e-12, 1e-300, 1.0, 8.0, -5.0]
+    ref = od.slater_exchange(rho)
+    r = _cuda(rho)
+    vx = torch.empty_like(r)
+    ces.slater_x(r, vx)
+    ces.slater_x(r, r)                  # in place
+    torch.cuda.synchronize()
+    for got in (vx.cpu().numpy(), r.cpu().numpy()):
+        # the two sides round 3 rho / pi in different orders and each cbrt is
+        # good to about an ulp: agreement to a few ulps
+        assert np.all(np.abs(got - ref) <= 2e-15 * np.abs(ref))
+
+
 def test_ks_potential_matches_oracle(small):
     _say("case ks_potential small")
     atoms = si.scf_cluster(3)[:6]

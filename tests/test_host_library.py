@@ -107,3 +107,25 @@ def test_scf_and_learned_calls_validate_on_the_host():
                                      1.0, None) == 1
     assert lib.ces_atom_descriptors(-1, None, None, None) == 1
     assert lib.ces_atom_descriptors(0, None, None, None) == 0
+    assert lib.ces_slater_x(-1, None, None, None) == 1
+    assert lib.ces_slater_x(0, None, None, None) == 0
+    assert lib.ces_slater_x(5, None, None, None) == 1
+
+
+def test_coefficient_maps_validate_on_the_host():
+    # the maps check sizes, alignment and overlap before any launch; the
+    # pointers below are never dereferenced
+    lib = ces.load()
+    B = ces.Basis(3, 4, 8.0, 6, 6, 12)       # L = 4, N = 4: d = 64
+    d, base = B.d, 1 << 20
+    c2r, r2c = lib.ces_coeffs_complex_to_real, lib.ces_coeffs_real_to_complex
+    far = base + 16 * 4 * d
+    assert c2r(None, 2, base, d, far, d, None) == 1                 # null basis
+    for fn in (c2r, r2c):
+        assert fn(B._h, 0, base, d, far, d, None) == 1              # k = 0
+        assert fn(B._h, 2, None, d, far, d, None) == 1              # null block
+        assert fn(B._h, 2, base, d - 1, far, d, None) == 1          # ld < d
+        assert fn(B._h, 2, base + 8, d, far, d, None) == 1          # not 16-byte aligned
+        assert fn(B._h, 2, base, d, base + 16 * (d + 5), d, None) == 1   # overlap
+        assert fn(B._h, 2, base + 16 * (d + 5), d, base, d, None) == 1   # overlap
+    B.close()
