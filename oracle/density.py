@@ -82,3 +82,43 @@ def hartree_grid(bs: Basis, tau: np.ndarray, zeta: np.ndarray | None = None) -> 
 def slater_exchange(rho: np.ndarray) -> np.ndarray:
     """V_x = -(3 rho / pi)^{1/3} (LDA exchange)."""
     return -np.cbrt(3.0 * np.maximum(rho, 0.0) / math.pi)
+
+
+# Perdew-Zunger (1981) fit of the Ceperley-Alder correlation energy per
+# electron of the unpolarised electron gas: the LDA parametrisation Section
+# 2.1 adopts.  Published constants (Hartree atomic units).
+PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334        # r_s >= 1
+PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116      # r_s < 1
+
+
+def pz81_correlation(rho: np.ndarray):
+    """Correlation energy per electron eps_c and potential v_c = d(rho eps_c)/drho
+    of the Perdew-Zunger parametrisation, r_s = (3 / (4 pi rho))^{1/3}:
+        r_s >= 1:  eps_c = gamma / (1 + beta1 sqrt(r_s) + beta2 r_s)
+        r_s < 1:   eps_c = A ln r_s + B + C r_s ln r_s + D r_s
+    and v_c = eps_c - (r_s / 3) d eps_c / d r_s (the chain rule through
+    d r_s / d rho = -r_s / (3 rho)), written out per branch.  rho <= 0 gives
+    0 for both (the r_s -> infinity limit).  Returns (eps_c, v_c)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    eps = np.zeros_like(rho)
+    v = np.zeros_like(rho)
+    pos = rho > 0.0
+    rs = np.cbrt(3.0 / (4.0 * math.pi * rho[pos]))
+    lo = rs >= 1.0
+    # low density: eps = gamma / den, d eps / d r_s = -gamma (beta1 / (2 sqrt r_s) + beta2) / den^2
+    sq = np.sqrt(rs[lo])
+    den = 1.0 + PZ_BETA1 * sq + PZ_BETA2 * rs[lo]
+    e_lo = PZ_GAMMA / den
+    de_lo = -PZ_GAMMA * (PZ_BETA1 / (2.0 * sq) + PZ_BETA2) / den ** 2
+    # high density: d eps / d r_s = A / r_s + C (ln r_s + 1) + D
+    r_hi = rs[~lo]
+    ln = np.log(r_hi)
+    e_hi = PZ_A * ln + PZ_B + PZ_C * r_hi * ln + PZ_D * r_hi
+    de_hi = PZ_A / r_hi + PZ_C * (ln + 1.0) + PZ_D
+    e_pos = np.empty_like(rs)
+    v_pos = np.empty_like(rs)
+    e_pos[lo], e_pos[~lo] = e_lo, e_hi
+    v_pos[lo] = e_lo - rs[lo] / 3.0 * de_lo
+    v_pos[~lo] = e_hi - r_hi / 3.0 * de_hi
+    eps[pos], v[pos] = e_pos, v_pos
+    return eps, v

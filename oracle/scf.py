@@ -24,6 +24,29 @@ from . import eigensolver as oe
 from . import hamiltonian as oh
 
 
+def fermi_dirac_occupations(eigs, n_electrons, kT):
+    """Fermi-Dirac smearing (Section 3.4.1, eq. Fermi_constraint):
+    f_i = 1 / (1 + exp((lambda_i - eF) / kT)), with eF fixed by
+    sum_i f_i = N_e / 2 over all the given states (each orbital doubly
+    occupied).  The sum runs over every computed state: with only N_e / 2
+    terms the constraint would force every f_i = 1.  eF is the root of the
+    monotone constraint, found by Brent's method (scipy.optimize.brentq)
+    on a bracket where the sum goes from below to above N_e / 2.
+    Returns (f, eF)."""
+    from scipy import optimize, special
+    lam = np.asarray(eigs, dtype=np.float64)
+    half = 0.5 * n_electrons
+    assert kT > 0 and 0 < half < lam.size
+
+    def excess(mu):
+        return special.expit((mu - lam) / kT).sum() - half
+
+    lo = lam.min() - 50.0 * kT - 1.0
+    hi = lam.max() + 50.0 * kT + 1.0
+    eF = optimize.brentq(excess, lo, hi, xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=500)
+    return special.expit((eF - lam) / kT), eF
+
+
 def anderson_step(V_hist, F_hist, beta):
     """Anderson mixing of potentials: with F = V_out - V_in and differences
     dV_i = V_{i+1} - V_i, dF_i = F_{i+1} - F_i over the stored history,

@@ -208,3 +208,66 @@ def test_scf_cluster_generator():
         d = np.linalg.norm(a[:, None] - a[None], axis=-1) + 1e9 * np.eye(len(a))
         assert d.min() >= si.SCF_MIN_SEP
     assert si.scf_occupation(8) == (8, 4) and si.scf_occupation(40) == (40, 8)
+
+
+# ------------------------------------------------- LDA correlation (PZ81)
+
+def test_pz_correlation_potential_is_the_density_derivative():
+    """v_c = d(rho eps_c)/d rho, checked by central differences in both
+    branches of the fit (r_s from 0.05 to 20)."""
+    for rs in (0.05, 0.3, 0.8, 0.999, 1.001, 1.5, 4.0, 20.0):
+        rho = 3.0 / (4.0 * math.pi * rs ** 3)
+        h = 1e-6 * rho
+        e_p, _ = od.pz81_correlation(np.array([rho + h]))
+        e_m, _ = od.pz81_correlation(np.array([rho - h]))
+        fd = ((rho + h) * e_p[0] - (rho - h) * e_m[0]) / (2.0 * h)
+        _, v = od.pz81_correlation(np.array([rho]))
+        assert abs(v[0] - fd) < 1e-8 * abs(v[0]), rs
+
+
+def test_pz_correlation_fit_is_continuous_and_has_its_limits():
+    """The two branches meet at r_s = 1 to the fit's own accuracy; eps_c -> 0
+    at vanishing density (and is 0 for rho <= 0); eps_c - A ln r_s -> B as
+    r_s -> 0 (the high-density form); eps_c ~ gamma / (beta2 r_s) at large r_s."""
+    rho1 = 3.0 / (4.0 * math.pi)
+    e, v = od.pz81_correlation(np.array([rho1 * (1 + 1e-12), rho1 * (1 - 1e-12)]))
+    assert abs(e[0] - e[1]) < 1e-4 and abs(v[0] - v[1]) < 1e-4
+    e, v = od.pz81_correlation(np.array([0.0, -1.0, 1e-30]))
+    assert e[0] == e[1] == v[0] == v[1] == 0.0 and abs(e[2]) < 1e-6
+    rs = 1e-6
+    e, _ = od.pz81_correlation(np.array([3.0 / (4.0 * math.pi * rs ** 3)]))
+    assert abs(e[0] - od.PZ_A * math.log(rs) - od.PZ_B) < 1e-6
+    rs = 1e8
+    e, _ = od.pz81_correlation(np.array([3.0 / (4.0 * math.pi * rs ** 3)]))
+    assert abs(e[0] * od.PZ_BETA2 * rs / od.PZ_GAMMA - 1.0) < 1e-3
+
+
+# ------------------------------------------------- Fermi-Dirac occupations
+
+def test_fermi_occupations_meet_the_electron_count():
+    rng = np.random.default_rng(71)
+    for kT in (1e-3, 0.01, 0.1):
+        lam = np.sort(rng.normal(0.0, 0.5, 30))
+        for ne in (2, 17, 40):
+            f, eF = osf.fermi_dirac_occupations(lam, ne, kT)
+            assert abs(2.0 * f.sum() - ne) < 1e-11
+            assert np.all(np.diff(f) <= 0) and np.all((f >= 0) & (f <= 1))
+            # f is the Fermi function of lambda at eF
+            with np.errstate(over="ignore"):     # exp -> inf gives f = 0, its limit
+                ref = 1.0 / (1.0 + np.exp((lam - eF) / kT))
+            assert np.allclose(f, ref, rtol=1e-12, atol=0)
+
+
+def test_fermi_occupations_closed_forms():
+    # levels symmetric about 0 with half of them filled: eF = 0 by symmetry
+    for kT in (0.01, 0.3):
+        f, eF = osf.fermi_dirac_occupations([-0.4, -0.1, 0.1, 0.4], 4, kT)
+        assert abs(eF) < 1e-12
+        assert np.allclose(f, [1 / (1 + math.exp(x / kT)) for x in (-0.4, -0.1, 0.1, 0.4)])
+    # a doubly degenerate level holding one pair: half filled, eF on the level
+    f, eF = osf.fermi_dirac_occupations([-1.0, 0.25, 0.25, 1.5], 4, 0.02)
+    assert abs(f[1] - 0.5) < 1e-12 and abs(f[2] - 0.5) < 1e-12 and abs(eF - 0.25) < 1e-9
+    # small kT against the gap: aufbau occupations
+    lam = np.array([-2.0, -1.5, -1.0, -0.2, 0.3, 0.8])
+    f, _ = osf.fermi_dirac_occupations(lam, 6, 1e-3)
+    assert np.max(np.abs(f - [1, 1, 1, 0, 0, 0])) < 1e-100
