@@ -119,6 +119,36 @@ def density_rates(ces, torch, H, w, X, work_mixed, reps=10):
     return out
 
 
+def pointwise_rates(ces, torch, n=1 << 26, reps=10):
+    """The grid-pointwise exchange-correlation kernels on n points (about a
+    147-atom grid's worth times 10): Perdew-Zunger correlation (rho in, v_c
+    and eps_c out: 24 B per point) and Slater exchange (16 B per point), as
+    HBM bandwidth against the peak.  Kernels run on torch's current stream,
+    timed with its events."""
+    rho = torch.rand(n, dtype=torch.float64, device="cuda")
+    vc, ec = torch.empty_like(rho), torch.empty_like(rho)
+    out = {}
+    for name, call, nbytes in (("pz_correlation", lambda: ces.pz_correlation(rho, vc, ec), 24),
+                               ("slater_x", lambda: ces.slater_x(rho, vc), 16)):
+        call()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            call()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        gbs = nbytes * n / (ms * 1e-3) / 1e9
+        out[name] = {"points": n, "ms": round(ms, 4), "GBps": round(gbs, 1),
+                     "hbm_frac": round(gbs * 1e9 / PEAK_HBM, 4)}
+        print(f"[bench] {name}: {ms:.3f} ms for {n} points, {gbs:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    del rho, vc, ec
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(kernel_prefix):
     """HBM bytes per launch of the kernel whose name starts with
     `kernel_prefix` (template arguments follow), from the committed
@@ -426,6 +456,9 @@ def main():
     # ---- density (rho and tau) for the same block
     dens = density_rates(ces, torch, H, w, X0, work)
 
+    # ---- grid-pointwise exchange-correlation kernels
+    pointwise = pointwise_rates(ces, torch)
+
     # ---- time to eigenpairs
     tte = {}
     ref = golden_eigenvalues(w)
@@ -494,6 +527,7 @@ def main():
                           "fp64_frac_fp64_peak": round(gf_fp64 * 1e9 / PEAK_FP64, 4)},
         "time_to_eigenpairs": tte,
         "density": dens,
+        "xc_pointwise": pointwise,
         "stage_ms_avg": {s: round(v[0], 5) for s, v in stage_avg.items()},
         "transform_gemm_frac_fp32_mfma": gemm_frac,
         "roofline": roof,

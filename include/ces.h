@@ -242,6 +242,28 @@ ces_status ces_from_grid(ces_ham h, int k, const double* d_f, double* d_X, int64
 ces_status ces_hartree(ces_ham h, const double* d_tau, double* d_vh, void* d_work,
                        size_t work_bytes, void* stream);
 
+/* Perdew-Zunger (1981) LDA correlation of the unpolarised electron gas (the
+ * parametrisation Section 2.1 adopts), elementwise over n grid values, with
+ * r_s = (3 / (4 pi rho))^(1/3):
+ *   r_s >= 1: eps_c = -0.1423 / (1 + 1.0529 sqrt(r_s) + 0.3334 r_s)
+ *   r_s < 1:  eps_c = 0.0311 ln r_s - 0.048 + 0.0020 r_s ln r_s - 0.0116 r_s
+ * d_vc = v_c = d(rho eps_c)/d rho; d_ec (may be NULL) = eps_c, the energy
+ * per electron.  rho <= 0 gives 0 for both.  d_vc may equal d_rho; d_ec must
+ * alias neither (CES_ERR_INVALID_ARG).  n = 0 does nothing.  Asynchronous. */
+ces_status ces_pz_correlation(int64_t n, const double* d_rho, double* d_vc, double* d_ec,
+                              void* stream);
+
+/* Fermi-Dirac occupations (Section 3.4.1, eq. Fermi_constraint), on the
+ * host: h_occ[i] = 1 / (1 + exp((h_eval[i] - eF) / kT)) for the k given
+ * eigenvalues (any order), with the Fermi level eF such that
+ * sum_i h_occ[i] = n_electrons / 2 (spin-unpolarised, every orbital doubly
+ * occupied), found by Brent's method to about machine precision in eF.  The
+ * sum runs over all k states.  kT (Hartree) > 0 and 0 < n_electrons / 2 < k,
+ * finite eigenvalues, else CES_ERR_INVALID_ARG.  h_occ feeds ces_density's
+ * d_occ.  Host pointers; no device work. */
+ces_status ces_fermi_dirac(int k, const double* h_eval, double n_electrons, double kT,
+                           double* h_occ, double* h_eF);
+
 /* Slater (LDA) exchange potential, elementwise over n grid values:
  * d_vx = -(3 rho_+ / pi)^(1/3), rho_+ = max(d_rho, 0) (Section 2.1's V_x in
  * its exchange-only local form).  d_vx may equal d_rho.  n = 0 does nothing;

@@ -27,6 +27,7 @@ EXPORTS = [
     "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
+    "ces_pz_correlation", "ces_fermi_dirac",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
@@ -77,6 +78,8 @@ def load() -> ctypes.CDLL:
         "ces_coeffs_complex_to_real": [P, I, P, I64, P, I64, P],
         "ces_coeffs_real_to_complex": [P, I, P, I64, P, I64, P],
         "ces_slater_x": [I64, P, P, P],
+        "ces_pz_correlation": [I64, P, P, P, P],
+        "ces_fermi_dirac": [I, P, D, D, P, ctypes.POINTER(D)],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
         "ces_anderson_workspace_size": [I64, I, ctypes.POINTER(SZ)],
@@ -164,6 +167,27 @@ def slater_x(rho, vx, stream=None):
     assert rho.numel() == vx.numel()
     _check(load().ces_slater_x(rho.numel(), _ptr(rho), _ptr(vx), _stream(stream)),
            "ces_slater_x")
+
+
+def pz_correlation(rho, vc, ec=None, stream=None):
+    """vc <- Perdew-Zunger v_c(rho), ec <- eps_c(rho) when given (contiguous
+    float64 tensors of equal length)."""
+    assert rho.is_contiguous() and vc.is_contiguous() and rho.numel() == vc.numel()
+    assert ec is None or (ec.is_contiguous() and ec.numel() == rho.numel())
+    _check(load().ces_pz_correlation(rho.numel(), _ptr(rho), _ptr(vc), _ptr(ec),
+                                     _stream(stream)), "ces_pz_correlation")
+
+
+def fermi_dirac(eigs, n_electrons, kT):
+    """Occupations f (numpy array) and Fermi level eF for the eigenvalues."""
+    lam = np.ascontiguousarray(eigs, dtype=np.float64)
+    f = np.zeros_like(lam)
+    eF = ctypes.c_double()
+    _check(load().ces_fermi_dirac(lam.size, lam.ctypes.data_as(ctypes.c_void_p),
+                                  float(n_electrons), float(kT),
+                                  f.ctypes.data_as(ctypes.c_void_p), ctypes.byref(eF)),
+           "ces_fermi_dirac")
+    return f, eF.value
 
 
 def _ldc(Z):

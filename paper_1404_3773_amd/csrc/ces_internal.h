@@ -212,6 +212,8 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
 // v = vext + v - (3 rho / pi)^(1/3), v holding V_H on entry.
 void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
                       hipStream_t s);
+// Perdew-Zunger LDA correlation: vc (and ec when not null) elementwise.
+void launch_pz_correlation(const double* rho, double* vc, double* ec, int64_t n, hipStream_t s);
 // vx = -(3 rho_+ / pi)^(1/3) elementwise (vx may be rho).
 void launch_slater_x(const double* rho, double* vx, int64_t n, hipStream_t s);
 // Complex <-> real harmonic coefficients (kernels.hip), d x k interleaved

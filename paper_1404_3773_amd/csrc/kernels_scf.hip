@@ -46,6 +46,43 @@ __global__ void k_slater_x(const double* rho, double* vx, int64_t n) {
     vx[e] = slater_vx(rho[e]);
 }
 
+// Perdew-Zunger (1981) fit of the Ceperley-Alder correlation energy per
+// electron of the unpolarised gas (the LDA of Section 2.1), r_s =
+// (3 / (4 pi rho))^(1/3):
+//   r_s >= 1:  eps = gamma / (1 + beta1 sqrt(r_s) + beta2 r_s)
+//   r_s < 1:   eps = A ln r_s + B + C r_s ln r_s + D r_s
+// v = d(rho eps)/d rho = eps - (r_s / 3) d eps / d r_s; rho <= 0 gives 0.
+__device__ __forceinline__ void pz81(double rho, double& eps, double& v) {
+  eps = 0.0;
+  v = 0.0;
+  if (!(rho > 0.0)) return;
+  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+  if (rs >= 1.0) {
+    const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+    const double sq = sqrt(rs), den = 1.0 + b1 * sq + b2 * rs;
+    eps = g / den;
+    // v = eps (1 + 7/6 b1 sqrt(r_s) + 4/3 b2 r_s) / den
+    v = eps * (1.0 + (7.0 / 6.0) * b1 * sq + (4.0 / 3.0) * b2 * rs) / den;
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    const double ln = log(rs);
+    eps = A * ln + B + C * rs * ln + D * rs;
+    v = A * ln + (B - A / 3.0) + (2.0 / 3.0) * C * rs * ln + ((2.0 * D - C) / 3.0) * rs;
+  }
+}
+
+// vc[g] = v_c(rho[g]) and, when ec is not null, ec[g] = eps_c(rho[g]); vc may
+// be rho (each element is read before it is written)
+__global__ void k_pz_correlation(const double* rho, double* vc, double* ec, int64_t n) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double eps, v;
+    pz81(rho[e], eps, v);
+    vc[e] = v;
+    if (ec) ec[e] = eps;
+  }
+}
+
 // out[g] = sum_i c_i (V[g][i] + beta F[g][i]),  V, F column-major n x m.
 __global__ void k_anderson_combine(const double* __restrict__ V, const double* __restrict__ F,
                                    int64_t ld, const double* __restrict__ c, int m, double beta,
@@ -110,6 +147,11 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
 void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
                       hipStream_t s) {
   k_ks_finish<<<grid1d(n), 256, 0, s>>>(vext, rho, v, n);
+}
+
+void launch_pz_correlation(const double* rho, double* vc, double* ec, int64_t n,
+                           hipStream_t s) {
+  k_pz_correlation<<<grid1d(n), 256, 0, s>>>(rho, vc, ec, n);
 }
 
 void launch_slater_x(const double* rho, double* vx, int64_t n, hipStream_t s) {

@@ -121,12 +121,119 @@ ces_status scf_layout(Ham& h, int k, int prec, int hist, ScfLayout& L) {
   return CES_OK;
 }
 
+
+// Fermi factor 1 / (1 + exp((lam - mu) / kT)) without overflow.
+double fermi_factor(double lam, double mu, double kT) {
+  const double x = (lam - mu) / kT;
+  if (x > 0.0) {
+    const double e = std::exp(-x);
+    return e / (1.0 + e);
+  }
+  return 1.0 / (1.0 + std::exp(x));
+}
+
+// Root of a continuous g on [a, b] with g(a) and g(b) of opposite signs by
+// Brent's method (Brent 1973, Algorithms for Minimization Without
+// Derivatives, ch. 4): each step tries inverse quadratic interpolation
+// through the last three iterates (a secant step when two coincide), and
+// falls back to bisection of the bracket [b, c] whenever the interpolated
+// step is not well inside it or the previous steps did not shrink enough;
+// stops when the bracket half-width is within 2 eps |b| + xtol / 2.
+template <typename G>
+double brent_root(G g, double a, double b, double ga, double gb, double xtol) {
+  double c = a, gc = ga, step = b - a, prev = step;
+  for (int it = 0; it < 400; ++it) {
+    if ((gb > 0.0) == (gc > 0.0)) {   // keep the root between b and c
+      c = a;
+      gc = ga;
+      step = prev = b - a;
+    }
+    if (std::fabs(gc) < std::fabs(gb)) {   // b is the best estimate
+      a = b;
+      b = c;
+      c = a;
+      ga = gb;
+      gb = gc;
+      gc = ga;
+    }
+    const double tol = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 0.5 * xtol;
+    const double half = 0.5 * (c - b);
+    if (std::fabs(half) <= tol || gb == 0.0) return b;
+    if (std::fabs(prev) >= tol && std::fabs(ga) > std::fabs(gb)) {
+      double p, q;
+      const double sb = gb / ga;
+      if (a == c) {   // secant through a and b
+        p = 2.0 * half * sb;
+        q = 1.0 - sb;
+      } else {        // inverse quadratic through a, b, c
+        const double qa = ga / gc, rb = gb / gc;
+        p = sb * (2.0 * half * qa * (qa - rb) - (b - a) * (rb - 1.0));
+        q = (qa - 1.0) * (rb - 1.0) * (sb - 1.0);
+      }
+      if (p > 0.0) q = -q;
+      else p = -p;
+      if (2.0 * p < std::min(3.0 * half * q - std::fabs(tol * q), std::fabs(prev * q))) {
+        prev = step;
+        step = p / q;
+      } else {
+        step = prev = half;
+      }
+    } else {
+      step = prev = half;
+    }
+    a = b;
+    ga = gb;
+    b += std::fabs(step) > tol ? step : (half > 0.0 ? tol : -tol);
+    gb = g(b);
+  }
+  return b;
+}
+
 }  // namespace
 }  // namespace ces
 
 using namespace ces;
 
 extern "C" {
+
+ces_status ces_pz_correlation(int64_t n, const double* d_rho, double* d_vc, double* d_ec,
+                              void* stream) {
+  if (n < 0) return fail(CES_ERR_INVALID_ARG, "negative length");
+  if (n == 0) return CES_OK;
+  if (!d_rho || !d_vc) return fail(CES_ERR_INVALID_ARG, "null density or output");
+  if (d_ec && (d_ec == d_vc || d_ec == d_rho))
+    return fail(CES_ERR_INVALID_ARG, "energy output must not alias the density or potential");
+  launch_pz_correlation(d_rho, d_vc, d_ec, n, static_cast<hipStream_t>(stream));
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+ces_status ces_fermi_dirac(int k, const double* h_eval, double n_electrons, double kT,
+                           double* h_occ, double* h_eF) {
+  if (k < 1 || !h_eval || !h_occ || !h_eF) return fail(CES_ERR_INVALID_ARG, "bad arguments");
+  if (!(kT > 0.0) || !std::isfinite(kT)) return fail(CES_ERR_INVALID_ARG, "kT must be > 0");
+  const double half = 0.5 * n_electrons;
+  if (!(half > 0.0) || !(half < k))
+    return fail(CES_ERR_INVALID_ARG, "need 0 < n_electrons / 2 < k");
+  double lo = h_eval[0], hi = h_eval[0];
+  for (int i = 0; i < k; ++i) {
+    if (!std::isfinite(h_eval[i])) return fail(CES_ERR_INVALID_ARG, "non-finite eigenvalue");
+    lo = std::min(lo, h_eval[i]);
+    hi = std::max(hi, h_eval[i]);
+  }
+  auto excess = [&](double mu) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += fermi_factor(h_eval[i], mu, kT);
+    return s - half;
+  };
+  // the count rises monotonically from ~0 to ~k across this bracket
+  lo -= 50.0 * kT + 1.0;
+  hi += 50.0 * kT + 1.0;
+  const double eF = brent_root(excess, lo, hi, excess(lo), excess(hi), 1e-15);
+  for (int i = 0; i < k; ++i) h_occ[i] = fermi_factor(h_eval[i], eF, kT);
+  *h_eF = eF;
+  return CES_OK;
+}
 
 ces_status ces_slater_x(int64_t n, const double* d_rho, double* d_vx, void* stream) {
   if (n < 0) return fail(CES_ERR_INVALID_ARG, "negative length");

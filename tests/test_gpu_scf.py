@@ -97,6 +97,32 @@ def test_slater_exchange_matches_oracle():
         assert np.all(np.abs(got - ref) <= 2e-15 * np.abs(ref))
 
 
+def test_pz_correlation_matches_oracle():
+    """Perdew-Zunger v_c and eps_c elementwise against the oracle over densities
+    spanning both branches (r_s from 0.01 to 100), with zero and negative
+    values, a ragged length, in place and without the energy output.  Samples
+    within 1e-9 of r_s = 1 are moved off it: there the fit's two branches
+    differ by 3e-5 and either side's cube root may round across."""
+    _say("case pz_correlation")
+    rng = np.random.default_rng(62)
+    rs = 10.0 ** rng.uniform(-2.0, 2.0, 50_001)
+    rs[np.abs(rs - 1.0) < 1e-9] = 1.01
+    rho = 3.0 / (4.0 * np.pi * rs ** 3)
+    rho[:4] = [0.0, -0.0, -1e-3, 1e-300]
+    e_ref, v_ref = od.pz81_correlation(rho)
+    r = _cuda(rho)
+    vc, ec = torch.empty_like(r), torch.empty_like(r)
+    ces.pz_correlation(r, vc, ec)
+    v2 = torch.empty_like(r)
+    ces.pz_correlation(r, v2)           # no energy output
+    ces.pz_correlation(r, r)            # in place
+    torch.cuda.synchronize()
+    scale = np.maximum(np.abs(v_ref), 1e-300)
+    for got in (vc.cpu().numpy(), v2.cpu().numpy(), r.cpu().numpy()):
+        assert np.all(np.abs(got - v_ref) <= 1e-13 * scale + 1e-300)
+    assert np.all(np.abs(ec.cpu().numpy() - e_ref) <= 1e-13 * np.maximum(np.abs(e_ref), 1e-300) + 1e-300)
+
+
 def test_ks_potential_matches_oracle(small):
     _say("case ks_potential small")
     atoms = si.scf_cluster(3)[:6]

@@ -129,3 +129,52 @@ def test_coefficient_maps_validate_on_the_host():
         assert fn(B._h, 2, base, d, base + 16 * (d + 5), d, None) == 1   # overlap
         assert fn(B._h, 2, base + 16 * (d + 5), d, base, d, None) == 1   # overlap
     B.close()
+
+
+def test_fermi_dirac_matches_oracle():
+    """Host Fermi-Dirac occupations (Brent's method in the library) against the
+    oracle's (scipy's brentq) on seeded spectra: occupations everywhere; the
+    Fermi level where the count pins it (inside a gap much wider than kT the
+    count is flat and eF is only fixed to the solvers' tolerances)."""
+    from oracle import scf as osf
+    rng = np.random.default_rng(81)
+    for trial in range(12):
+        k = int(rng.integers(2, 60))
+        lam = rng.normal(0.0, 0.6, k)
+        kT = float(10.0 ** rng.uniform(-3.5, -0.5))
+        ne = float(rng.integers(1, 2 * k))          # 0 < ne / 2 < k
+        f, eF = ces.fermi_dirac(lam, ne, kT)
+        fr, eFr = osf.fermi_dirac_occupations(lam, ne, kT)
+        assert np.max(np.abs(f - fr)) < 1e-12, trial
+        assert abs(2.0 * f.sum() - ne) < 1e-11
+        slope = np.sum(fr * (1.0 - fr)) / kT         # d(count) / d eF at the root
+        if slope > 1e-3:
+            assert abs(eF - eFr) < 1e-12 / min(slope, 1.0) + 1e-13, trial
+    # closed forms: symmetric spectrum half filled; a degenerate pair holding one pair
+    f, eF = ces.fermi_dirac([-0.4, -0.1, 0.1, 0.4], 4, 0.05)
+    assert abs(eF) < 1e-14
+    f, eF = ces.fermi_dirac([-1.0, 0.25, 0.25, 1.5], 4, 0.02)
+    assert abs(f[1] - 0.5) < 1e-13 and abs(eF - 0.25) < 1e-12
+
+
+def test_lda_and_fermi_calls_validate_on_the_host():
+    lib = ces.load()
+    e = ctypes.c_double()
+    lam = np.array([-1.0, 0.0, 1.0])
+    occ = np.zeros(3)
+    P = ctypes.c_void_p
+    lp, op = lam.ctypes.data_as(P), occ.ctypes.data_as(P)
+    assert lib.ces_fermi_dirac(3, lp, 2.0, 0.0, op, ctypes.byref(e)) == 1      # kT = 0
+    assert lib.ces_fermi_dirac(3, lp, 6.0, 0.1, op, ctypes.byref(e)) == 1      # all filled
+    assert lib.ces_fermi_dirac(3, lp, 0.0, 0.1, op, ctypes.byref(e)) == 1      # no electrons
+    assert lib.ces_fermi_dirac(0, lp, 2.0, 0.1, op, ctypes.byref(e)) == 1
+    assert lib.ces_fermi_dirac(3, None, 2.0, 0.1, op, ctypes.byref(e)) == 1
+    bad = np.array([-1.0, np.nan, 1.0])
+    assert lib.ces_fermi_dirac(3, bad.ctypes.data_as(P), 2.0, 0.1, op, ctypes.byref(e)) == 1
+    assert lib.ces_fermi_dirac(3, lp, 2.0, 0.1, op, ctypes.byref(e)) == 0
+    assert lib.ces_pz_correlation(-1, None, None, None, None) == 1
+    assert lib.ces_pz_correlation(0, None, None, None, None) == 0
+    assert lib.ces_pz_correlation(4, None, None, None, None) == 1
+    fake = 1 << 20                                   # never dereferenced: rejected first
+    assert lib.ces_pz_correlation(4, fake, fake + 64, fake + 64, None) == 1
+    assert lib.ces_pz_correlation(4, fake, fake + 64, fake, None) == 1
