@@ -70,7 +70,14 @@ class ClusterSCF:
 
     def __init__(self, bs: ob.Basis, atoms: np.ndarray, V_ext: np.ndarray,
                  rho_ion: np.ndarray, n_occ: int, n_guard: int, degree: int = 12,
-                 beta: float = 0.2, hist: int = 20, zeta: np.ndarray | None = None):
+                 beta: float = 0.2, hist: int = 20, zeta: np.ndarray | None = None,
+                 correlation: bool = False, kT: float = 0.0):
+        """correlation: add the Perdew-Zunger LDA correlation potential to
+        V_eff (Section 2.1); kT > 0: Fermi-Dirac occupations of all k states
+        at that temperature for 2 n_occ electrons, recomputed from each
+        step's Ritz values (Section 3.4.1), instead of n_occ filled states."""
+        self.correlation = correlation
+        self.kT = kT
         self.bs = bs
         self.atoms = atoms
         self.V_ext = V_ext
@@ -85,9 +92,12 @@ class ClusterSCF:
         self.occ[:n_occ] = 1.0
 
     def potential(self, rho):
-        """V_eff[rho] = V_ext + V_H[rho - rho_ion] + V_x[rho]."""
+        """V_eff[rho] = V_ext + V_H[rho - rho_ion] + V_x[rho] (+ V_c[rho])."""
         tau = od.density_coefficients(self.bs, rho - self.rho_ion)
-        return self.V_ext + od.hartree_grid(self.bs, tau, self.zeta) + od.slater_exchange(rho)
+        V = self.V_ext + od.hartree_grid(self.bs, tau, self.zeta) + od.slater_exchange(rho)
+        if self.correlation:
+            V = V + od.pz81_correlation(rho)[1]
+        return V
 
     def run(self, rho0, X0, v0=None, tol=1e-6, max_steps=60, first_iters=12, log=None):
         """Returns (eigenvalues, steps, rho, X); v0 starts the Lanczos bound
@@ -109,6 +119,8 @@ class ClusterSCF:
             else:
                 Y = oe.chebyshev_filter(app, X, self.degree, theta[-1], b, theta[0])
                 theta, X, _, _ = oe.rayleigh_ritz(app, Y)
+            if self.kT > 0.0:
+                self.occ = fermi_dirac_occupations(theta, 2 * self.n_occ, self.kT)[0]
             rho = od.density_grid(bs, X, self.occ)
             V_out = self.potential(rho)
             if log is not None:
