@@ -27,7 +27,7 @@ EXPORTS = [
     "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
-    "ces_pz_correlation", "ces_fermi_dirac",
+    "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
         "ces_coeffs_real_to_complex": [P, I, P, I64, P, I64, P],
         "ces_slater_x": [I64, P, P, P],
         "ces_pz_correlation": [I64, P, P, P, P],
+        "ces_ham_set_model": [P, I, D],
         "ces_fermi_dirac": [I, P, D, D, P, ctypes.POINTER(D)],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
@@ -396,6 +397,12 @@ class Ham:
                                   _stream(stream), ctypes.byref(h)), "ces_ham_create")
         self._h = h
         self.n_proj = n_proj
+
+    def set_model(self, correlation=False, smearing_kT=0.0):
+        """SCF model options: Perdew-Zunger correlation in V_eff, Fermi-Dirac
+        occupations at smearing_kT (Hartree; 0 = n_occ filled states)."""
+        _check(load().ces_ham_set_model(self._h, int(correlation), float(smearing_kT)),
+               "ces_ham_set_model")
 
     def set_veff(self, veff, stream=None):
         _check(load().ces_ham_set_veff(self._h, _ptr(veff.contiguous()), _stream(stream)),

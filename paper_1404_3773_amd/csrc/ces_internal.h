@@ -73,6 +73,8 @@ struct Ham {
   double* hproj64 = nullptr;
   float* hproj32 = nullptr;
   rocblas_handle blas = nullptr;
+  int xc_correlation = 0;    // ces_ks_potential adds the Perdew-Zunger v_c
+  double smear_kT = 0.0;     // ces_scf: Fermi-Dirac occupations at kT when > 0
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;
@@ -209,8 +211,8 @@ void launch_phi_synthesis_one(const Basis& b, const double* g, double* f, hipStr
 
 // Self-consistent field extras (kernels_scf.hip).
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
-// v = vext + v - (3 rho / pi)^(1/3), v holding V_H on entry.
-void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
+// v = vext + v + V_x(rho) [+ v_c(rho) when corr], v holding V_H on entry.
+void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n, int corr,
                       hipStream_t s);
 // Perdew-Zunger LDA correlation: vc (and ec when not null) elementwise.
 void launch_pz_correlation(const double* rho, double* vc, double* ec, int64_t n, hipStream_t s);

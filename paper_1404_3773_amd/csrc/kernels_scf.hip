@@ -31,14 +31,6 @@ __device__ __forceinline__ double slater_vx(double rho) {
   return -cbrt((3.0 / M_PI) * (rho > 0.0 ? rho : 0.0));
 }
 
-// v[g] = vext[g] + v[g] + V_x(rho[g])   (v holds V_H on entry)
-__global__ void k_ks_finish(const double* __restrict__ vext, const double* __restrict__ rho,
-                            double* __restrict__ v, int64_t n) {
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    v[e] = vext[e] + v[e] + slater_vx(rho[e]);
-}
-
 // vx[g] = V_x(rho[g]); vx may be rho (each element is read before it is written)
 __global__ void k_slater_x(const double* rho, double* vx, int64_t n) {
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
@@ -68,6 +60,23 @@ __device__ __forceinline__ void pz81(double rho, double& eps, double& v) {
     const double ln = log(rs);
     eps = A * ln + B + C * rs * ln + D * rs;
     v = A * ln + (B - A / 3.0) + (2.0 / 3.0) * C * rs * ln + ((2.0 * D - C) / 3.0) * rs;
+  }
+}
+
+// v[g] = vext[g] + v[g] + V_x(rho[g]) [+ v_c(rho[g]) when corr]   (v holds
+// V_H on entry)
+__global__ void k_ks_finish(const double* __restrict__ vext, const double* __restrict__ rho,
+                            double* __restrict__ v, int64_t n, int corr) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double r = rho[e];
+    double out = vext[e] + v[e] + slater_vx(r);
+    if (corr) {
+      double eps, vc;
+      pz81(r, eps, vc);
+      out += vc;
+    }
+    v[e] = out;
   }
 }
 
@@ -144,9 +153,9 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
   k_sub<<<grid1d(n), 256, 0, s>>>(a, b, out, n);
 }
 
-void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n,
+void launch_ks_finish(const double* vext, const double* rho, double* v, int64_t n, int corr,
                       hipStream_t s) {
-  k_ks_finish<<<grid1d(n), 256, 0, s>>>(vext, rho, v, n);
+  k_ks_finish<<<grid1d(n), 256, 0, s>>>(vext, rho, v, n, corr);
 }
 
 void launch_pz_correlation(const double* rho, double* vc, double* ec, int64_t n,

@@ -196,6 +196,17 @@ using namespace ces;
 
 extern "C" {
 
+ces_status ces_ham_set_model(ces_ham hh, int correlation, double smearing_kT) {
+  CES_TRY(check_ham(hh));
+  if (correlation != 0 && correlation != 1)
+    return fail(CES_ERR_INVALID_ARG, "correlation must be 0 or 1");
+  if (!(smearing_kT >= 0.0) || !std::isfinite(smearing_kT))
+    return fail(CES_ERR_INVALID_ARG, "smearing kT must be finite and >= 0");
+  hh->h.xc_correlation = correlation;
+  hh->h.smear_kT = smearing_kT;
+  return CES_OK;
+}
+
 ces_status ces_pz_correlation(int64_t n, const double* d_rho, double* d_vc, double* d_ec,
                               void* stream) {
   if (n < 0) return fail(CES_ERR_INVALID_ARG, "negative length");
@@ -278,7 +289,7 @@ ces_status ces_ks_potential(ces_ham hh, const double* d_rho, const double* d_rho
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, tau, b.d, 1.0, 0.0, 0.0,
                                 false, nullptr, 1, kColPad, s);
   hartree_to_grid(b, ly, d_work, tau, d_v, s);                      // d_v <- V_H
-  launch_ks_finish(d_vext, d_rho, d_v, b.n_grid, s);                // + V_ext + V_x
+  launch_ks_finish(d_vext, d_rho, d_v, b.n_grid, h.xc_correlation, s);   // + V_ext + V_xc
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -435,6 +446,12 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
       for (int it = 0; it < first_iters; ++it) CES_TRY(filter_rr());
     } else {
       CES_TRY(filter_rr());
+    }
+    if (h.smear_kT > 0.0) {   // Fermi-Dirac occupations of this step's Ritz values
+      double eF = 0.0;
+      CES_TRY(ces_fermi_dirac(k, theta.data(), 2.0 * n_occ, h.smear_kT, hocc.data(), &eF));
+      CES_HIP(hipMemcpyAsync(occ, hocc.data(), size_t(k) * 8, hipMemcpyHostToDevice, s));
+      CES_HIP(hipStreamSynchronize(s));   // hocc is reused next step
     }
     CES_TRY(ces_density(hh, k, d_X, ldx, occ, rho, nullptr, CES_PREC_FP64, ew, ewb, stream));
     CES_TRY(ces_ks_potential(hh, rho, d_rho_ion, d_vext, vout, nullptr, ew, ewb, stream));
