@@ -71,11 +71,15 @@ class ClusterSCF:
     def __init__(self, bs: ob.Basis, atoms: np.ndarray, V_ext: np.ndarray,
                  rho_ion: np.ndarray, n_occ: int, n_guard: int, degree: int = 12,
                  beta: float = 0.2, hist: int = 20, zeta: np.ndarray | None = None,
-                 correlation: bool = False, kT: float = 0.0):
+                 correlation: bool = False, kT: float = 0.0, mix_density: bool = False):
         """correlation: add the Perdew-Zunger LDA correlation potential to
         V_eff (Section 2.1); kT > 0: Fermi-Dirac occupations of all k states
         at that temperature for 2 n_occ electrons, recomputed from each
-        step's Ritz values (Section 3.4.1), instead of n_occ filled states."""
+        step's Ritz values (Section 3.4.1), instead of n_occ filled states.
+        mix_density: Anderson mixing of the electron density instead of the
+        potential (Section 3.4.1 allows either): the history holds
+        (rho_in, rho_out - rho_in) and each step's V_in is V_eff[rho_in]."""
+        self.mix_density = mix_density
         self.correlation = correlation
         self.kT = kT
         self.bs = bs
@@ -104,6 +108,7 @@ class ClusterSCF:
         (all ones if None)."""
         bs = self.bs
         v0 = np.ones(bs.d) if v0 is None else v0
+        rho_in = rho0
         V_in = self.potential(rho0)
         X = X0.copy()
         V_hist, F_hist = [], []
@@ -122,17 +127,24 @@ class ClusterSCF:
             if self.kT > 0.0:
                 self.occ = fermi_dirac_occupations(theta, 2 * self.n_occ, self.kT)[0]
             rho = od.density_grid(bs, X, self.occ)
-            V_out = self.potential(rho)
             if log is not None:
                 log(step, theta)
             if theta_old is not None and \
                     np.max(np.abs(theta[:self.n_occ] - theta_old[:self.n_occ])) < tol:
                 return theta, step, rho, X
             theta_old = theta
-            V_hist.append(V_in.reshape(-1))
-            F_hist.append((V_out - V_in).reshape(-1))
-            V_hist, F_hist = V_hist[-self.hist:], F_hist[-self.hist:]
-            V_in = anderson_step(V_hist, F_hist, self.beta).reshape(V_in.shape)
+            if self.mix_density:
+                V_hist.append(rho_in.reshape(-1))
+                F_hist.append((rho - rho_in).reshape(-1))
+                V_hist, F_hist = V_hist[-self.hist:], F_hist[-self.hist:]
+                rho_in = anderson_step(V_hist, F_hist, self.beta).reshape(rho.shape)
+                V_in = self.potential(rho_in)
+            else:
+                V_out = self.potential(rho)
+                V_hist.append(V_in.reshape(-1))
+                F_hist.append((V_out - V_in).reshape(-1))
+                V_hist, F_hist = V_hist[-self.hist:], F_hist[-self.hist:]
+                V_in = anderson_step(V_hist, F_hist, self.beta).reshape(V_in.shape)
         return theta, max_steps, rho, X
 
 

@@ -271,3 +271,23 @@ def test_fermi_occupations_closed_forms():
     lam = np.array([-2.0, -1.5, -1.0, -0.2, 0.3, 0.8])
     f, _ = osf.fermi_dirac_occupations(lam, 6, 1e-3)
     assert np.max(np.abs(f - [1, 1, 1, 0, 0, 0])) < 1e-100
+
+
+def test_density_and_potential_mixing_reach_the_same_fixed_point():
+    """Anderson mixing of rho or of V (Section 3.4.1 allows either) changes the
+    path, not the self-consistent solution: same converged eigenvalues."""
+    w = si.small(8, 16, R=16.0, n_r=24, n_theta=16, n_phi=32, potential="scf")
+    bs = ob.basis_for(w)
+    pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
+    atoms = si.scf_cluster(1)[:5]
+    n_occ, n_guard = si.scf_occupation(len(atoms))
+    rion = si.ion_density(pts, atoms)
+    out = []
+    for mix in (False, True):
+        s = osf.ClusterSCF(bs, atoms, si.gaussian_wells(pts, atoms), rion, n_occ, n_guard,
+                           degree=w.degree, mix_density=mix)
+        th, st, _, _ = s.run(rion, si.random_block(bs.d, n_occ + n_guard, 502),
+                             v0=si.lanczos_start(bs.d), tol=1e-10, max_steps=100)
+        assert st < 100
+        out.append(th[:n_occ])
+    assert np.max(np.abs(out[0] - out[1])) < 1e-8
