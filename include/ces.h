@@ -149,15 +149,17 @@ ces_status ces_ham_create(ces_basis b, const double* d_veff, int n_proj,
 /* Replace V_eff (same layout); asynchronous on `stream`. */
 ces_status ces_ham_set_veff(ces_ham h, const double* d_veff, void* stream);
 
-/* Model options of the handle's SCF calls (default 0, 0): correlation = 1
+/* Model options of the handle's SCF calls (default 0, 0, 0): correlation = 1
  * adds the Perdew-Zunger LDA correlation potential (ces_pz_correlation) to
  * ces_ks_potential's V_eff, and so to ces_scf's; smearing_kT > 0 (Hartree)
  * makes ces_scf occupy all k states by Fermi-Dirac (ces_fermi_dirac, 2 n_occ
- * electrons) from each step's Ritz values instead of filling n_occ states.
- * correlation not 0 or 1, or a negative or non-finite kT, is
- * CES_ERR_INVALID_ARG.  Like ces_ham_set_veff, must not overlap other calls
- * on the handle. */
-ces_status ces_ham_set_model(ces_ham h, int correlation, double smearing_kT);
+ * electrons) from each step's Ritz values instead of filling n_occ states;
+ * mix_density = 1 makes ces_scf Anderson-mix the electron density (history
+ * of rho_in, rho_out - rho_in; V_in = ks_potential(rho_in)) instead of the
+ * potential (Section 3.4.1 allows either).  correlation or mix_density not
+ * 0 or 1, or a negative or non-finite kT, is CES_ERR_INVALID_ARG.  Like
+ * ces_ham_set_veff, must not overlap other calls on the handle. */
+ces_status ces_ham_set_model(ces_ham h, int correlation, double smearing_kT, int mix_density);
 ces_status ces_ham_destroy(ces_ham h);
 
 /* Device bytes that any call below with k columns and precision `prec`

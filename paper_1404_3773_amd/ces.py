@@ -79,7 +79,7 @@ def load() -> ctypes.CDLL:
         "ces_coeffs_real_to_complex": [P, I, P, I64, P, I64, P],
         "ces_slater_x": [I64, P, P, P],
         "ces_pz_correlation": [I64, P, P, P, P],
-        "ces_ham_set_model": [P, I, D],
+        "ces_ham_set_model": [P, I, D, I],
         "ces_fermi_dirac": [I, P, D, D, P, ctypes.POINTER(D)],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
@@ -398,11 +398,12 @@ class Ham:
         self._h = h
         self.n_proj = n_proj
 
-    def set_model(self, correlation=False, smearing_kT=0.0):
+    def set_model(self, correlation=False, smearing_kT=0.0, mix_density=False):
         """SCF model options: Perdew-Zunger correlation in V_eff, Fermi-Dirac
-        occupations at smearing_kT (Hartree; 0 = n_occ filled states)."""
-        _check(load().ces_ham_set_model(self._h, int(correlation), float(smearing_kT)),
-               "ces_ham_set_model")
+        occupations at smearing_kT (Hartree; 0 = n_occ filled states), and
+        Anderson mixing of the density instead of the potential."""
+        _check(load().ces_ham_set_model(self._h, int(correlation), float(smearing_kT),
+                                        int(mix_density)), "ces_ham_set_model")
 
     def set_veff(self, veff, stream=None):
         _check(load().ces_ham_set_veff(self._h, _ptr(veff.contiguous()), _stream(stream)),

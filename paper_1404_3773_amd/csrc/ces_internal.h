@@ -75,6 +75,7 @@ struct Ham {
   rocblas_handle blas = nullptr;
   int xc_correlation = 0;    // ces_ks_potential adds the Perdew-Zunger v_c
   double smear_kT = 0.0;     // ces_scf: Fermi-Dirac occupations at kT when > 0
+  int mix_density = 0;       // ces_scf: Anderson-mix rho instead of V_eff
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;

@@ -196,14 +196,17 @@ using namespace ces;
 
 extern "C" {
 
-ces_status ces_ham_set_model(ces_ham hh, int correlation, double smearing_kT) {
+ces_status ces_ham_set_model(ces_ham hh, int correlation, double smearing_kT, int mix_density) {
   CES_TRY(check_ham(hh));
   if (correlation != 0 && correlation != 1)
     return fail(CES_ERR_INVALID_ARG, "correlation must be 0 or 1");
+  if (mix_density != 0 && mix_density != 1)
+    return fail(CES_ERR_INVALID_ARG, "mix_density must be 0 or 1");
   if (!(smearing_kT >= 0.0) || !std::isfinite(smearing_kT))
     return fail(CES_ERR_INVALID_ARG, "smearing kT must be finite and >= 0");
   hh->h.xc_correlation = correlation;
   hh->h.smear_kT = smearing_kT;
+  hh->h.mix_density = mix_density;
   return CES_OK;
 }
 
@@ -426,6 +429,12 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
   CES_HIP(hipStreamSynchronize(s));
 
   CES_TRY(ces_ks_potential(hh, d_rho0, d_rho_ion, d_vext, vin, nullptr, ew, ewb, stream));
+  // density mixing: the history holds (rho_in, rho_out - rho_in), and V_out is
+  // never formed, so its buffer holds rho_in
+  const bool mixrho = h.mix_density != 0;
+  double* rin = vout;
+  if (mixrho)
+    CES_HIP(hipMemcpyAsync(rin, d_rho0, size_t(ng) * 8, hipMemcpyDeviceToDevice, s));
   std::vector<double> theta(k), theta_old(k);
   int count = 0;   // pairs pushed into the history ring
   int step = 0;
@@ -454,7 +463,8 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
       CES_HIP(hipStreamSynchronize(s));   // hocc is reused next step
     }
     CES_TRY(ces_density(hh, k, d_X, ldx, occ, rho, nullptr, CES_PREC_FP64, ew, ewb, stream));
-    CES_TRY(ces_ks_potential(hh, rho, d_rho_ion, d_vext, vout, nullptr, ew, ewb, stream));
+    if (!mixrho)
+      CES_TRY(ces_ks_potential(hh, rho, d_rho_ion, d_vext, vout, nullptr, ew, ewb, stream));
     double dmax = std::numeric_limits<double>::infinity();
     if (step > 1) {
       dmax = 0.0;
@@ -465,13 +475,17 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
     theta_old = theta;
     if (step == max_steps) break;
     const int slot = count % hist;
-    launch_copy2d(vin, ng, Vh + size_t(slot) * ng, ng, ng, 1, s);
-    launch_sub(vout, vin, Fh + size_t(slot) * ng, ng, s);
+    double* xin = mixrho ? rin : vin;            // the mixed quantity, in
+    const double* xout = mixrho ? rho : vout;    // and out
+    launch_copy2d(xin, ng, Vh + size_t(slot) * ng, ng, ng, 1, s);
+    launch_sub(xout, xin, Fh + size_t(slot) * ng, ng, s);
     ++count;
     const int m = std::min(count, hist);
     const int oldest = count <= hist ? 0 : count % hist;
-    CES_TRY(ces_anderson_mix(ng, m, Vh, Fh, ng, oldest, beta, vin, nullptr, aw, L.anderson_bytes,
+    CES_TRY(ces_anderson_mix(ng, m, Vh, Fh, ng, oldest, beta, xin, nullptr, aw, L.anderson_bytes,
                              stream));
+    if (mixrho)
+      CES_TRY(ces_ks_potential(hh, rin, d_rho_ion, d_vext, vin, nullptr, ew, ewb, stream));
   }
   *h_steps = std::min(step, max_steps);
   CES_HIP(hipMemcpyAsync(d_rho, rho, size_t(ng) * 8, hipMemcpyDeviceToDevice, s));

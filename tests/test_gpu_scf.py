@@ -261,7 +261,7 @@ def test_scf_with_correlation_and_smearing_matches_oracle(small):
         ev, steps, dth, _ = gpu_scf(small, atoms, n_occ, n_guard, None, X0_SEED,
                                     ces.CES_PREC_FP64, 1e-10)
     finally:
-        small.H.set_model(False, 0.0)
+        small.H.set_model()
     e = np.max(np.abs(ev[:n_occ] - th[:n_occ]))
     _say(f"  max err {e:.2e} (gpu {steps} steps, oracle {st}); last dtheta {dth[-1]:.1e}")
     assert dth[-1] < 1e-10 and e < 1e-8
@@ -269,6 +269,34 @@ def test_scf_with_correlation_and_smearing_matches_oracle(small):
         small.H.set_model(correlation=2)
     with pytest.raises(ces.CesError):
         small.H.set_model(smearing_kT=-1.0)
+    with pytest.raises(ces.CesError):
+        small.H.set_model(mix_density=2)
+
+
+def test_scf_density_mixing_matches_oracle(small):
+    """Anderson mixing of the electron density instead of the potential
+    (Section 3.4.1 allows either), GPU SCF against the oracle SCF with the same
+    choice from the same ion-density start, FP64; the self-consistent
+    eigenvalues are those of potential mixing (an oracle pin)."""
+    _say("case scf density mixing")
+    atoms = si.scf_cluster(1)[:5]
+    n_occ, n_guard = si.scf_occupation(len(atoms))
+    bs = small.bs
+    rion = si.ion_density(small.opts, atoms)
+    s = osf.ClusterSCF(bs, atoms, si.gaussian_wells(small.opts, atoms), rion, n_occ, n_guard,
+                       degree=SMALL.degree, mix_density=True)
+    th, st, _, _ = s.run(rion, si.random_block(bs.d, n_occ + n_guard, X0_SEED),
+                         v0=si.lanczos_start(bs.d), tol=1e-10, max_steps=100)
+    assert st < 100
+    small.H.set_model(mix_density=True)
+    try:
+        ev, steps, dth, _ = gpu_scf(small, atoms, n_occ, n_guard, None, X0_SEED,
+                                    ces.CES_PREC_FP64, 1e-10)
+    finally:
+        small.H.set_model()
+    e = np.max(np.abs(ev[:n_occ] - th[:n_occ]))
+    _say(f"  max err {e:.2e} (gpu {steps} steps, oracle {st})")
+    assert dth[-1] < 1e-10 and e < 1e-8
 
 
 def _golden():
