@@ -35,11 +35,10 @@
  *  Streams.  `stream` is a hipStream_t passed as void* (NULL = default
  *    stream).  Calls are asynchronous on it unless stated otherwise.
  *  Workspace.  Calls that take (d_work, work_bytes) use only that device
- *    memory for scratch and allocate no device memory; query the size with
- *    ces_workspace_size.  The only allocation after the handles are created
- *    is the Hamiltonian's pinned host buffer for read-backs, made at
- *    ces_ham_create for k <= 511 and grown once by the first
- *    Rayleigh-Ritz call with a larger k.  Calls that
+ *    memory for scratch and allocate no device or host memory; query the size
+ *    with ces_workspace_size.  The Hamiltonian's pinned host buffer for
+ *    read-backs is allocated by ces_ham_create, sized for the largest block
+ *    Rayleigh-Ritz accepts (k <= min(d, 32768)).  Calls that
  *    run concurrently on different streams need distinct workspaces.
  *  Threads.  Apart from ces_ham_set_veff, calls do not change what a basis
  *    or Hamiltonian handle represents, and calls on one handle may run from
@@ -187,16 +186,20 @@ ces_status ces_cheb_filter(ces_ham h, int k, double* d_X, int64_t ldx, int degre
  * ldx) may be NULL.  d_eval[k], d_resnorm[k] device doubles; h_eval[k] (host,
  * may be NULL) receives a copy of the eigenvalues.  hx_prec selects
  * the precision of the H*Q product.  If factorising the scaled Gram matrix
- * meets a pivot not above 2 k eps (a numerically dependent column; for k > 60
- * a non-positive pivot), X is left as it was and one shifted Cholesky-QR pass
- * followed by two plain passes (shifted CholeskyQR3) orthonormalises it;
- * CES_ERR_NOT_POSITIVE_DEFINITE if one of these passes fails too (X then holds
- * the output of the last pass that succeeded).  The k x k eigenproblem is
+ * D S D (unit diagonal) meets a pivot not above 2 k eps (a numerically
+ * dependent column) or a non-positive one, X is left as it was and one
+ * shifted Cholesky-QR pass followed by two plain passes (shifted
+ * CholeskyQR3) orthonormalises it; CES_ERR_NOT_POSITIVE_DEFINITE if one of
+ * these passes fails too (X then holds the output of the last pass that
+ * succeeded).  *h_orth_path (host, may be NULL) receives which ran: 0 the
+ * plain pass, 1 the shifted CholeskyQR3 fallback.  The k x k eigenproblem is
  * solved by a one-workgroup Jacobi method for k <= 60, by rocSOLVER syevd
- * above; CES_ERR_EIGENSOLVER if it does not converge.  Synchronises `stream`. */
+ * above; CES_ERR_EIGENSOLVER if it does not converge.  1 <= k <= min(d,
+ * 32768).  Synchronises `stream`. */
 ces_status ces_rayleigh_ritz(ces_ham h, int k, double* d_X, int64_t ldx, double* d_HX,
-                             double* d_eval, double* d_resnorm, double* h_eval, int hx_prec,
-                             void* d_work, size_t work_bytes, void* stream);
+                             double* d_eval, double* d_resnorm, double* h_eval,
+                             int* h_orth_path, int hx_prec, void* d_work, size_t work_bytes,
+                             void* stream);
 
 /* Upper bound of the spectrum of H: `steps` Lanczos steps from the start
  * vector d_v0 (d doubles, not modified); bound = (largest Ritz value +

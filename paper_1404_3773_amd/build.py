@@ -7,6 +7,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -33,7 +34,7 @@ def build(verbose: bool = True) -> str:
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         path = os.path.join(CSRC, src)
@@ -41,8 +42,12 @@ def build(verbose: bool = True) -> str:
             cmd = [hipcc, "-x", "hip", *DEVICE_FLAGS, *COMMON, "-c", path, "-o", obj]
         else:
             cmd = [hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # one compiler process per source, at most 8 at once
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as pool:
+        for f in [pool.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", *DEVICE_FLAGS, "-o", tmp, *objs, f"-L{ROCM}/lib",
           "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"])

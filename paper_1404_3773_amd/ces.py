@@ -69,7 +69,7 @@ def load() -> ctypes.CDLL:
         "ces_workspace_size": [P, I, I, ctypes.POINTER(SZ)],
         "ces_apply_H": [P, I, P, I64, P, I64, I, P, SZ, P],
         "ces_cheb_filter": [P, I, P, I64, I, D, D, D, I, P, SZ, P],
-        "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, P, I, P, SZ, P],
+        "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, P, ctypes.POINTER(I), I, P, SZ, P],
         "ces_lanczos_bound": [P, P, I, ctypes.POINTER(D), P, SZ, P],
         "ces_chefsi": [P, I, P, I64, I, D, I, I, I, D, D, I, P, P, ctypes.POINTER(I), P, SZ, P],
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
@@ -430,15 +430,20 @@ class Ham:
                                       float(a), float(b), float(a0), int(prec), _ptr(work),
                                       work.numel(), _stream(stream)), "ces_cheb_filter")
 
-    def rayleigh_ritz(self, X, evals, res, work, HX=None, hx_prec=CES_PREC_FP64, stream=None):
+    def rayleigh_ritz(self, X, evals, res, work, HX=None, hx_prec=CES_PREC_FP64, stream=None,
+                      return_path=False):
         """Returns the eigenvalues as a host array (copied in the call's own
-        synchronisation); evals / res receive them on the device."""
+        synchronisation); evals / res receive them on the device.  With
+        return_path, returns (eigenvalues, path): 0 plain Cholesky-QR, 1 the
+        shifted CholeskyQR3 fallback."""
         h = np.zeros(X.shape[0])
+        path = ctypes.c_int(-1)
         _check(load().ces_rayleigh_ritz(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(HX),
                                         _ptr(evals), _ptr(res), h.ctypes.data_as(ctypes.c_void_p),
-                                        int(hx_prec), _ptr(work), work.numel(), _stream(stream)),
+                                        ctypes.byref(path), int(hx_prec), _ptr(work),
+                                        work.numel(), _stream(stream)),
                "ces_rayleigh_ritz")
-        return h
+        return (h, path.value) if return_path else h
 
     def lanczos_bound(self, v0, work, steps=20, stream=None) -> float:
         out = ctypes.c_double()

@@ -289,11 +289,14 @@ size_t solver_bytes_for(Ham& h, int k) {
   return h.solver_ws;
 }
 
+// The pinned read-back stage is allocated once, by ces_ham_create, for the
+// largest block a Rayleigh-Ritz call accepts; later calls only check that
+// what they read back fits.
 ces_status host_stage(Ham& h, size_t n) {
   if (h.host_stage_n >= n) return CES_OK;
-  if (h.host_stage) (void)hipHostFree(h.host_stage);
-  h.host_stage = nullptr;
-  h.host_stage_n = 0;
+  if (h.host_stage)
+    return fail(CES_ERR_INVALID_ARG, "read-back of " + std::to_string(n) +
+                                         " doubles exceeds the handle's pinned stage");
   const size_t want = std::max<size_t>(n, 1024);
   CES_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.host_stage), want * sizeof(double),
                         hipHostMallocDefault));
@@ -345,6 +348,35 @@ Layout layout_for(Ham& h, int k, int prec) {
   return L;
 }
 
+// Regions one H*X needs and nothing else (G, A, gbuf, the FP32 copies in
+// mixed precision, the projector products), each sized for the precision the
+// product runs in.
+Layout hx_layout(const Ham& h, int k, int prec) {
+  const Basis& b = *h.basis;
+  const size_t e = prec == CES_PREC_MIXED ? sizeof(float) : sizeof(double);
+  Layout L;
+  L.kp = round_up(k, kColPad);
+  const size_t LL = size_t(b.L) * b.L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align256(off);
+    const size_t at = off;
+    off += bytes + 4096;
+    return at;
+  };
+  L.G = take(size_t(b.n_r) * LL * L.kp * e);
+  L.A = take(size_t(b.n_r) * LL * L.kp * e);
+  L.gbuf = take(size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * e);
+  if (prec == CES_PREC_MIXED) {
+    L.F0 = take(size_t(b.d) * L.kp * sizeof(float));
+    L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
+  }
+  L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * e);
+  L.Cpart = take(kb_partial_bytes(h.n_proj, k, b.d));
+  L.Zkb = take(h.n_proj > 0 ? size_t(b.d) * L.kp * e : 0);
+  L.total = align256(off);
+  return L;
+}
 
 // -------------------------------------------------------------- one H step
 
@@ -407,6 +439,29 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
     launch_radial_forward<T>(b, tb, A, Yin, ldin, Yold, ldold, out, ldout, alpha, c, beta, true,
                              Zkb, k, kp, s);
   }
+  CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+template ces_status h_step<double>(Ham&, const Layout&, void*, int, const double*, int64_t,
+                                   const double*, int64_t, double*, int64_t, double, double,
+                                   double, hipStream_t);
+template ces_status h_step<float>(Ham&, const Layout&, void*, int, const float*, int64_t,
+                                  const float*, int64_t, float*, int64_t, float, float, float,
+                                  hipStream_t);
+
+// Y = H X on the regions of `ly` in `work` (FP64, or FP32 with the
+// conversions of the mixed precision).
+ces_status apply_H_impl(Ham& h, const Layout& ly, void* work, int k, const double* X,
+                        int64_t ldx, double* Y, int64_t ldy, int prec, hipStream_t s) {
+  const int64_t d = h.basis->d;
+  if (prec == CES_PREC_FP64)
+    return h_step<double>(h, ly, work, k, X, ldx, nullptr, 0, Y, ldy, 1.0, 0.0, 0.0, s);
+  float* F0 = Ptr<float>::at(work, ly.F0);
+  float* F1 = Ptr<float>::at(work, ly.F1);
+  launch_convert<double, float>(X, ldx, F0, d, d, k, s);
+  CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
+  launch_convert<float, double>(F1, d, Y, ldy, d, k, s);
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -507,7 +562,7 @@ double tridiag_max(const std::vector<double>& a, const std::vector<double>& bb) 
 // in the same synchronisation that checks the factorisation.
 ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx, double* HX,
                    int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s,
-                   double* h_eval = nullptr, double* h_res = nullptr) {
+                   double* h_eval, double* h_res, int* h_path) {
   std::lock_guard<std::mutex> lock(h.mu);   // rocBLAS handle and host_stage
   const Basis& b = *h.basis;
   const int64_t d = b.d;
@@ -543,6 +598,9 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     launch_scale_gram(S1, k, dinv, s);
     if (shift > 0) launch_add_diag(S1, k, shift, s);
     CES_BLAS(rocsolver_dpotrf(h.blas, rocblas_fill_upper, k, S1, k, info));
+    // the same failure test as the one-workgroup factorisation: a pivot of
+    // the unit-diagonal D S D at rounding level marks a dependent column
+    launch_check_pivots(S1, k, info, s);
     launch_zero_lower(S1, k, s);   // potrf leaves the Gram entries below the diagonal
     CES_BLAS(rocsolver_dtrtri(h.blas, rocblas_fill_upper, rocblas_diagonal_non_unit, k, S1, k,
                               info + 1));
@@ -608,11 +666,13 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
     if (h_res) std::memcpy(h_res, h.host_stage + 2 + k, size_t(k) * 8);
     return CES_OK;
   };
+  if (h_path) *h_path = 0;
   CES_TRY(pass(0.0));
   CES_TRY(rayleigh());
   rocblas_int h3[3] = {0, 0, 0};
   CES_TRY(finish(h3));
   if (h3[0] != 0 || h3[1] != 0) {
+    if (h_path) *h_path = 1;
     // The plain pass failed and X is unchanged: shifted Cholesky-QR (shift ~
     // 11 (d k + k(k+1)) u ||D S D||), then two plain passes restore
     // orthonormality (shifted CholeskyQR3); then Rayleigh-Ritz again.
@@ -840,9 +900,11 @@ ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const 
   };
   if (rocblas_create_handle(&h.blas) != rocblas_status_success)
     return cleanup(fail(CES_ERR_DEVICE, "rocblas_create_handle failed"));
-  // the read-back buffer for k <= 511, so that later calls allocate only for
-  // larger blocks
-  if (const ces_status st = host_stage(h, 1024); st != CES_OK) return cleanup(st);
+  // the read-back buffer for every block size Rayleigh-Ritz accepts on this
+  // basis (flags, eigenvalues and residual norms), so no later call allocates
+  if (const ces_status st = host_stage(h, 2 + 2 * size_t(std::min<int64_t>(b.d, kRRMax)));
+      st != CES_OK)
+    return cleanup(st);
   if (hipMemcpyAsync(h.veff, d_veff, size_t(b.n_grid) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return cleanup(fail(CES_ERR_DEVICE, "copy of V_eff failed"));
   launch_veff_fourier(b, h.veff, h.ab64, h.ab32, s);
@@ -903,17 +965,8 @@ ces_status ces_apply_H(ces_ham hh, int k, const double* d_X, int64_t ldx, double
   CES_TRY(check_block(h, k, d_Y, ldy, "Y"));
   Layout ly;
   CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t d = h.basis->d;
-  if (prec == CES_PREC_FP64)
-    return h_step<double>(h, ly, d_work, k, d_X, ldx, nullptr, 0, d_Y, ldy, 1.0, 0.0, 0.0, s);
-  float* F0 = Ptr<float>::at(d_work, ly.F0);
-  float* F1 = Ptr<float>::at(d_work, ly.F1);
-  launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
-  CES_TRY(h_step<float>(h, ly, d_work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
-  launch_convert<float, double>(F1, d, d_Y, ldy, d, k, s);
-  CES_HIP(hipGetLastError());
-  return CES_OK;
+  return apply_H_impl(h, ly, d_work, k, d_X, ldx, d_Y, ldy, prec,
+                      static_cast<hipStream_t>(stream));
 }
 
 ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, double a,
@@ -949,17 +1002,19 @@ ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degr
 }
 
 ces_status ces_rayleigh_ritz(ces_ham hh, int k, double* d_X, int64_t ldx, double* d_HX,
-                             double* d_eval, double* d_resnorm, double* h_eval, int hx_prec,
-                             void* d_work, size_t work_bytes, void* stream) {
+                             double* d_eval, double* d_resnorm, double* h_eval,
+                             int* h_orth_path, int hx_prec, void* d_work, size_t work_bytes,
+                             void* stream) {
   CES_TRY(check_ham(hh));
   Ham& h = hh->h;
   CES_TRY(check_block(h, k, d_X, ldx, "X"));
   if (!d_eval || !d_resnorm) return fail(CES_ERR_INVALID_ARG, "null eigenvalue/residual output");
   if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
+  if (k > kRRMax) return fail(CES_ERR_INVALID_ARG, "k above the Rayleigh-Ritz limit");
   Layout ly;
   CES_TRY(check_work(h, k, hx_prec, d_work, work_bytes, ly));
   return rr_impl(h, ly, d_work, k, d_X, ldx, d_HX, ldx, d_eval, d_resnorm, hx_prec,
-                 static_cast<hipStream_t>(stream), h_eval);
+                 static_cast<hipStream_t>(stream), h_eval, nullptr, h_orth_path);
 }
 
 ces_status ces_lanczos_bound(ces_ham hh, const double* d_v0, int steps, double* h_bound,
@@ -1024,13 +1079,14 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
   if (degree < 1 || n_check < 1 || n_check > k || max_iter < 1 || fixed_iter < 0)
     return fail(CES_ERR_INVALID_ARG, "bad iteration parameters");
   if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
+  if (k > kRRMax) return fail(CES_ERR_INVALID_ARG, "k above the Rayleigh-Ritz limit");
   Layout ly;
   CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t d = h.basis->d;
   std::vector<double> theta(k), theta_old(k), res(k);
   CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s,
-                  theta.data(), res.data()));
+                  theta.data(), res.data(), nullptr));
   int it = 0;
   while (true) {
     ++it;
@@ -1054,7 +1110,7 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
     }
     theta_old = theta;
     CES_TRY(rr_impl(h, ly, d_work, k, d_X, ldx, nullptr, ldx, d_eval, d_resnorm, CES_PREC_FP64, s,
-                    theta.data(), res.data()));
+                    theta.data(), res.data(), nullptr));
     if (fixed_iter > 0) {
       if (it >= fixed_iter) break;
       continue;

@@ -124,6 +124,24 @@ struct Layout {
 Layout layout_for(Ham& h, int k, int prec);
 ces_status check_work(Ham& h, int k, int prec, void* work, size_t bytes, Layout& ly);
 ces_status check_block(const Ham& h, int k, const void* X, int64_t ldx, const char* what);
+// The regions one H*X uses (G, A, gbuf, F0/F1 in mixed precision, projector
+// products), sized for the precision the product runs in.
+Layout hx_layout(const Ham& h, int k, int prec);
+// out = alpha (H Yin - c Yin) + beta Yold on the regions of ly in work.
+template <typename T>
+ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int64_t ldin,
+                  const T* Yold, int64_t ldold, T* out, int64_t ldout, T alpha, T c, T beta,
+                  hipStream_t s);
+// Y = H X (FP64, or the mixed-precision conversions around an FP32 product).
+ces_status apply_H_impl(Ham& h, const Layout& ly, void* work, int k, const double* X,
+                        int64_t ldx, double* Y, int64_t ldy, int prec, hipStream_t s);
+
+// Cholesky-QR + Rayleigh-Ritz on the block (see ces_rayleigh_ritz); h_eval /
+// h_res (host, may be null) receive the eigenvalues / residual norms, *h_path
+// (may be null) 0 for the plain pass, 1 for the shifted CholeskyQR3 fallback.
+ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx,
+                   double* HX, int64_t ldhx, double* eval, double* res, int hx_prec,
+                   hipStream_t s, double* h_eval, double* h_res, int* h_path);
 
 template <typename T>
 struct Ptr {
@@ -276,6 +294,12 @@ void launch_block_apply(double* X, int64_t ldx, const double* W, int k, int64_t 
 void launch_block_rotate(double* X, int64_t ldx, double* Y, int64_t ldy, const double* W, int k,
                          int64_t rows, const int* flags, const double* theta, double* res,
                          double* part, int64_t part_cap, hipStream_t s);
+// Largest block Rayleigh-Ritz accepts (its pinned read-back stage is sized
+// for it when the Hamiltonian is created).
+constexpr int kRRMax = 32768;
+// After potrf of the unit-diagonal D S D (upper factor R, ld k): if info[0]
+// is still 0 and some R_jj^2 <= 2 k eps, info[0] = j + 1 for the first such j.
+void launch_check_pivots(const double* R, int k, int* info, hipStream_t s);
 // S(i, j) *= dinv[i], k x k column-major.
 void launch_scale_rows_k(double* S, int k, const double* dinv, hipStream_t s);
 // dst <- src unless flags[0] or flags[1] is nonzero (checked on the device).

@@ -181,6 +181,19 @@ __global__ void k_zero_lower(double* S, int k) {
   }
 }
 
+// One wave: the first j with R_jj^2 <= 2 k eps (R from potrf of a matrix with
+// unit diagonal) fails the factorisation if potrf itself did not.
+__global__ void k_check_pivots(const double* R, int k, int* info) {
+  const double ptol = 2.0 * k * 2.220446049250313e-16;
+  int first = 0x7fffffff;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double r = R[int64_t(j) * k + j];
+    if (!(r * r > ptol) && j < first) first = j;
+  }
+  for (int o = 32; o > 0; o >>= 1) first = min(first, __shfl_down(first, o, 64));
+  if (threadIdx.x == 0 && first != 0x7fffffff && info[0] == 0) info[0] = first + 1;
+}
+
 __global__ void k_add_diag(double* S, int k, double shift) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
     S[int64_t(i) * k + i] += shift;
@@ -377,6 +390,9 @@ void launch_symmetrize(double* S, int k, hipStream_t s) {
 }
 void launch_zero_lower(double* S, int k, hipStream_t s) {
   k_zero_lower<<<grid1d(int64_t(k) * k), 256, 0, s>>>(S, k);
+}
+void launch_check_pivots(const double* R, int k, int* info, hipStream_t s) {
+  k_check_pivots<<<1, 64, 0, s>>>(R, k, info);
 }
 void launch_add_diag(double* S, int k, double shift, hipStream_t s) {
   k_add_diag<<<grid1d(k), 256, 0, s>>>(S, k, shift);

@@ -445,12 +445,12 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
     auto filter_rr = [&]() -> ces_status {
       CES_TRY(ces_cheb_filter(hh, k, d_X, ldx, degree, theta[k - 1], bnd, theta[0], prec, ew, ewb,
                               stream));
-      CES_TRY(ces_rayleigh_ritz(hh, k, d_X, ldx, nullptr, d_eval, res, theta.data(),
+      CES_TRY(ces_rayleigh_ritz(hh, k, d_X, ldx, nullptr, d_eval, res, theta.data(), nullptr,
                                 CES_PREC_FP64, ew, ewb, stream));
       return CES_OK;
     };
     if (step == 1) {
-      CES_TRY(ces_rayleigh_ritz(hh, k, d_X, ldx, nullptr, d_eval, res, theta.data(),
+      CES_TRY(ces_rayleigh_ritz(hh, k, d_X, ldx, nullptr, d_eval, res, theta.data(), nullptr,
                                 CES_PREC_FP64, ew, ewb, stream));
       for (int it = 0; it < first_iters; ++it) CES_TRY(filter_rr());
     } else {

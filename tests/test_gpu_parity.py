@@ -300,15 +300,54 @@ def test_rayleigh_ritz_rank_deficient_block_reports_error():
     Xt = dev(X)
     ev = torch.empty(4, dtype=torch.float64, device="cuda")
     rs = torch.empty(4, dtype=torch.float64, device="cuda")
-    # either reported as not positive definite, or recovered by the shifted
-    # Cholesky-QR2 fallback into an orthonormal block
+    # the plain pass must fail on the dependent column; then either the shifted
+    # CholeskyQR3 fallback recovers an orthonormal block or the call reports
+    # that it could not
     try:
-        s.H.rayleigh_ritz(Xt, ev, rs, work)
+        _, path = s.H.rayleigh_ritz(Xt, ev, rs, work, return_path=True)
     except ces.CesError as e:
-        assert e.value.status == 5
+        assert e.status == 5
         return
+    assert path == 1
     Xg = host(Xt, s.B.d)
     assert np.max(np.abs(Xg.T @ Xg - np.eye(4))) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["jacobi_k10", "rocsolver_k70"])
+def test_rayleigh_ritz_ill_conditioned_block_takes_the_fallback(case):
+    """A full-rank block with condition number 1e9 (Section 3.1.1: poorly
+    scaled blocks need care in the Cholesky factorisation): its Gram matrix
+    has pivots below rounding level, so the plain Cholesky-QR pass must fail
+    and the shifted CholeskyQR3 fallback must run, on the one-workgroup path
+    (k <= 60) and on the rocSOLVER path (k > 60).  The block spans an
+    invariant subspace (the lowest k eigenvectors of the oracle's dense H),
+    so its Ritz values are exactly the k lowest eigenvalues; the output block
+    must be orthonormal."""
+    w, k = (si.C1, 10) if case == "jacobi_k10" else (SMALL, 70)
+    _say(f"case rayleigh_ritz fallback {case}")
+    s = setup(w)
+    lam, U = np.linalg.eigh(oh.dense_H_real(s.bs, s.Vo))
+    rng = np.random.default_rng(91)
+    Qa, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    Qb, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    X = U[:, :k] @ (Qa * np.logspace(0.0, -9.0, k)[None, :]) @ Qb
+    assert np.linalg.cond(X) > 1e8
+    work = s.H.workspace(k, FP64)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    Xt = dev(X)
+    theta, path = s.H.rayleigh_ritz(Xt, ev, rs, work, return_path=True)
+    assert path == 1
+    scale = np.max(np.abs(lam))
+    err = np.max(np.abs(theta - lam[:k]))
+    _say(f"  Ritz values vs dense eigenvalues: {err / scale:.2e} of max|lambda|")
+    assert err < 1e-9 * scale
+    Xg = host(Xt, s.B.d)
+    assert np.max(np.abs(Xg.T @ Xg - np.eye(k))) < 1e-12
+    # a well-conditioned block takes the plain pass
+    Xt = dev(U[:, :k] @ Qb)
+    _, path = s.H.rayleigh_ritz(Xt, ev, rs, work, return_path=True)
+    assert path == 0
 
 
 def test_lanczos_bound_is_upper_bound():
