@@ -173,6 +173,21 @@ ces_status ces_apply_H(ces_ham h, int k, const double* d_X, int64_t ldx, double*
                        int64_t ldy, int prec, void* d_work, size_t work_bytes,
                        void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): Y = H X exactly as ces_apply_H
+ * computes it, with no workspace argument.  Its scratch is a fixed device
+ * array of CES_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ * from the first call on that GPU until the process ends; the call itself
+ * allocates nothing.  A block whose product needs more scratch than that
+ * returns CES_ERR_WORKSPACE before any launch (k = 32 on a basis of
+ * L_max = 30, N = 60 with a 90 x 62 x 124 grid fits in both precisions).
+ * Every call on one GPU uses the same array: calls that overlap in time on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller.  Arguments and errors as ces_apply_H; asynchronous on `stream`. */
+#define CES_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ces_status ces_apply_H_noalloc(ces_ham h, int k, const double* d_X, int64_t ldx, double* d_Y,
+                               int64_t ldy, int prec, void* stream);
+
 /* X <- p_m(H) X in place, p_m(t) = T_m((t-c)/e) / T_m((a0-c)/e), e = (b-a)/2,
  * c = (b+a)/2 (the scaled Chebyshev filter of Section 3.2), by the three-term
  * recurrence with per-step scaling.  Requires degree >= 1, a < b, a0 < a. */

@@ -24,7 +24,8 @@ CES_RADIAL_GAUSS_LEGENDRE = 1
 EXPORTS = [
     "ces_basis_create", "ces_basis_destroy", "ces_basis_info", "ces_basis_grid",
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
-    "ces_workspace_size", "ces_apply_H", "ces_cheb_filter", "ces_rayleigh_ritz",
+    "ces_workspace_size", "ces_apply_H", "ces_apply_H_noalloc", "ces_cheb_filter",
+    "ces_rayleigh_ritz",
     "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
     "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model",
@@ -68,6 +69,7 @@ def load() -> ctypes.CDLL:
         "ces_ham_destroy": [P],
         "ces_workspace_size": [P, I, I, ctypes.POINTER(SZ)],
         "ces_apply_H": [P, I, P, I64, P, I64, I, P, SZ, P],
+        "ces_apply_H_noalloc": [P, I, P, I64, P, I64, I, P],
         "ces_cheb_filter": [P, I, P, I64, I, D, D, D, I, P, SZ, P],
         "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, P, ctypes.POINTER(I), I, P, SZ, P],
         "ces_lanczos_bound": [P, P, I, ctypes.POINTER(D), P, SZ, P],
@@ -424,6 +426,12 @@ class Ham:
         k = X.shape[0]
         _check(load().ces_apply_H(self._h, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y), int(prec),
                                   _ptr(work), work.numel(), _stream(stream)), "ces_apply_H")
+
+    def apply_H_noalloc(self, X, Y, prec, stream=None):
+        """Y = H X with the library's fixed scratch (no workspace argument)."""
+        k = X.shape[0]
+        _check(load().ces_apply_H_noalloc(self._h, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y),
+                                          int(prec), _stream(stream)), "ces_apply_H_noalloc")
 
     def cheb_filter(self, X, degree, a, b, a0, prec, work, stream=None):
         _check(load().ces_cheb_filter(self._h, X.shape[0], _ptr(X), _ld(X), int(degree),
