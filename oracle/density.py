@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Density (eq. density_expression, Section 2.2.5): rho = 2 sum_i f_i |psi_i|^2,
 computed by inverse transforms to the grid, pointwise squares, and a forward
-transform for the coefficients tau (dualing: the same basis, Section 2.2.5).
+transform for the coefficients tau: in the orbitals' own basis (the dualing
+choice) or in the larger density basis with l' <= 2(L-1) that the product of
+two orbitals needs (Section 2.2.5's first comment, density_basis_for).
 
 Hartree (Section 2.3.1, eqs. Laplace_expansion, hartree_calc1, zeta_definition):
 V_H(x) = sum tau_lmn (4 pi / (2l+1)) Y_lm(x) Z_ln(r), with Z_ln the radial
@@ -36,6 +38,21 @@ def density_grid(bs: Basis, X: np.ndarray, occ: np.ndarray) -> np.ndarray:
 def density_coefficients(bs: Basis, rho: np.ndarray) -> np.ndarray:
     """tau = forward transform of rho (same basis as the orbitals)."""
     return from_grid_real(bs, rho[..., None])[:, 0]
+
+
+def density_basis_for(bs: Basis, N_rho: int | None = None) -> Basis:
+    """The larger basis for the density of Section 2.2.5 (the non-dualing
+    choice): the product of two orbitals holds angular degrees up to 2(L-1),
+    so l' <= 2(L-1), i.e. L' = 2L - 1; N_rho radial functions (default N), on
+    the orbitals' grid (same R, nodes and radial rule).  The grid integrates
+    the density against these functions exactly in angle when n_theta >=
+    2L - 1 and n_phi >= 4L - 3, which the usual n_theta = 2L, n_phi = 4L
+    satisfy."""
+    from .basis import make_basis
+    Lr = 2 * bs.L - 1
+    assert bs.n_theta >= Lr and bs.n_phi >= 2 * Lr - 1, "grid too coarse for the density basis"
+    return make_basis(Lr, bs.N if N_rho is None else N_rho, bs.R, bs.n_r, bs.n_theta,
+                      bs.n_phi, bs.rule)
 
 
 def integrate_grid(bs: Basis, f: np.ndarray) -> float:

@@ -71,14 +71,19 @@ class ClusterSCF:
     def __init__(self, bs: ob.Basis, atoms: np.ndarray, V_ext: np.ndarray,
                  rho_ion: np.ndarray, n_occ: int, n_guard: int, degree: int = 12,
                  beta: float = 0.2, hist: int = 20, zeta: np.ndarray | None = None,
-                 correlation: bool = False, kT: float = 0.0, mix_density: bool = False):
+                 correlation: bool = False, kT: float = 0.0, mix_density: bool = False,
+                 density_basis: ob.Basis | None = None):
         """correlation: add the Perdew-Zunger LDA correlation potential to
         V_eff (Section 2.1); kT > 0: Fermi-Dirac occupations of all k states
         at that temperature for 2 n_occ electrons, recomputed from each
         step's Ritz values (Section 3.4.1), instead of n_occ filled states.
         mix_density: Anderson mixing of the electron density instead of the
         potential (Section 3.4.1 allows either): the history holds
-        (rho_in, rho_out - rho_in) and each step's V_in is V_eff[rho_in]."""
+        (rho_in, rho_out - rho_in) and each step's V_in is V_eff[rho_in].
+        density_basis: expand rho - rho_ion for the Hartree potential in this
+        larger basis on the same grid (the non-dualing choice of Section
+        2.2.5) instead of the orbitals' basis."""
+        self.rho_bs = bs if density_basis is None else density_basis
         self.mix_density = mix_density
         self.correlation = correlation
         self.kT = kT
@@ -91,14 +96,14 @@ class ClusterSCF:
         self.degree = degree
         self.beta = beta
         self.hist = hist
-        self.zeta = od.zeta_table(bs) if zeta is None else zeta
+        self.zeta = od.zeta_table(self.rho_bs) if zeta is None else zeta
         self.occ = np.zeros(self.k)
         self.occ[:n_occ] = 1.0
 
     def potential(self, rho):
         """V_eff[rho] = V_ext + V_H[rho - rho_ion] + V_x[rho] (+ V_c[rho])."""
-        tau = od.density_coefficients(self.bs, rho - self.rho_ion)
-        V = self.V_ext + od.hartree_grid(self.bs, tau, self.zeta) + od.slater_exchange(rho)
+        tau = od.density_coefficients(self.rho_bs, rho - self.rho_ion)
+        V = self.V_ext + od.hartree_grid(self.rho_bs, tau, self.zeta) + od.slater_exchange(rho)
         if self.correlation:
             V = V + od.pz81_correlation(rho)[1]
         return V
