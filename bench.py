@@ -1,25 +1,28 @@
 """Benchmark of the Chebyshev-filtered subspace iteration hot path on one GPU.
 
-Workload: the 13-atom icosahedral cluster of Gaussian wells (R = 14 bohr,
-L_max = 30, 60 radial functions per l, d = 57,660; grid 90 x 62 x 124;
-32 orbitals; Chebyshev degree 16), synthetic and seeded.
+Headline workload: the 309-atom fcc cuboctahedron of Gaussian wells with
+Kleinman-Bylander projectors (l = 0, 1; 1236 projectors), R = 30 bohr,
+L_max = 80, 150 radial functions per l (d = 984,150), grid 225 x 162 x 324,
+1000 orbitals, Chebyshev degree 20: the largest configuration, synthetic and
+seeded.  V_eff and the projectors are sampled on the device by the seeded
+input generators; the projector coefficients come from the library's forward
+transform.
 
-A timed step is one outer CheFSI iteration in mixed precision: the degree-16
-FP32 filter (16 H*X), then FP64 Cholesky-QR + Rayleigh-Ritz (one FP64 H*X) and
-residuals, with the filter bounds taken from the previous Rayleigh-Ritz.
+A timed step is one outer CheFSI iteration in mixed precision: the degree-20
+FP32 filter (20 H*X), then FP64 Cholesky-QR + Rayleigh-Ritz (one FP64 H*X)
+and residuals, with the filter bounds taken from the previous Rayleigh-Ritz.
 `value` is the algorithmic H*X flop rate of the whole step:
 (degree + 1) * F / step_time, with F the separable method's algorithmic
-flops per H*X (phi stage counted at nominal real-FFT cost).
+flops per H*X (phi stage counted at nominal real-FFT cost, both projector
+products at 2 d n_proj k each).
 
-Also reported: filter-only H*X GFLOP/s in mixed and FP64, the density call
-(rho on the grid and its coefficients for the same 32 orbitals, both
-precisions, against the HBM and MFMA peaks), the per-stage rates of
-H*X on the 147-atom and 309-atom (projector) shapes, time to eigenpairs
-(all n_check eigenvalues within 1e-6 Ha of the stored oracle values) for both
-precisions, and on the 147-atom workload against the FP64 GPU run,
-the roofline of the dominant kernel measured with HIP events (over a second
-run of the timed steps, so that the event records stay out of the step
-time), and the CPU oracle timed on a bounded sample.
+Also reported: the same workload's mixed and FP64 H*X per stage, and, on the
+13-atom and 147-atom workloads, H*X rates, time to eigenpairs (13-atom: all
+n_check eigenvalues within 1e-6 Ha of the stored oracle values; 147-atom:
+mixed against the FP64 GPU run), the density call and the pointwise
+exchange-correlation kernels; the roofline of the dominant kernel measured
+with HIP events over further steps (kept out of the step time), and the CPU
+oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -41,7 +44,12 @@ PEAK_FP32 = 157.3e12   # MI355X FP32: vector (256 CUs x 2.4 GHz) = dense matrix,
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12      # B/s
 PMC_COPY_BYTES = 1 << 30      # calibration copy of --pmc-run (read and written once)
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "phi_stage_fp32_ico13_L31_N60_pmc.json")
+# kernel name prefix (as rocprofv3 reports it) of each H*X stage's FP32 launch
+STAGE_KERNEL = {"radial_inverse": "k_radial_inverse_mfma<float", "legendre_synth":
+                "k_legendre_synth<float", "phi_stage": "k_phi_stage<float",
+                "legendre_analysis": "k_legendre_analysis<float",
+                "radial_forward": "k_radial_forward_mfma<float",
+                "kb_project": "k_kb_gemm<float", "kb_apply": "k_kb_apply<float"}
 
 
 def algorithmic_flops(w, k, n_proj=0):
@@ -71,13 +79,25 @@ def stage_flops(w, k, n_proj=0):
             "phi_stage": f["phi"] + f["pointwise"],
             "legendre_analysis": f["legendre"] / 2,
             "radial_forward": f["radial"] / 2 + f["kinetic"],
-            "kb_gemm": f["kb"]}
+            "kb_project": f["kb"] / 2,
+            "kb_apply": f["kb"] / 2}
 
 
-def radial_bytes(w, k, elem):
-    """Algorithmic HBM bytes of one radial-inverse launch: read X (d k),
-    write G (n_r L^2 k); tables are L2-resident."""
-    return elem * (w.d * k + w.n_r * w.L * w.L * k)
+def stage_bytes(w, k, n_proj, elem):
+    """Algorithmic HBM bytes of one launch of each H*X stage (element size
+    elem): each stage reads its input block once and writes its output once
+    (the small basis tables are cache-resident); the phi stage also reads V's
+    halved Fourier sums; the projector products read P (d x n_proj) once."""
+    L2, S = w.L * w.L, 2 * w.L - 1
+    G = w.n_r * L2 * k                      # G or A
+    g = w.n_r * w.n_theta * S * k           # angular intermediate
+    return {"radial_inverse": elem * (w.d * k + G),
+            "legendre_synth": elem * (G + g),
+            "phi_stage": elem * (2 * g + 2 * w.n_r * w.n_theta * S),
+            "legendre_analysis": elem * (g + G),
+            "radial_forward": elem * (G + 3 * w.d * k + (w.d * k if n_proj else 0)),
+            "kb_project": elem * (w.d * n_proj + w.d * k),
+            "kb_apply": elem * (w.d * n_proj + w.d * k)}
 
 
 def density_rates(ces, torch, H, w, X, work_mixed, reps=10):
@@ -149,45 +169,111 @@ def pointwise_rates(ces, torch, n=1 << 26, reps=10):
     return out
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per launch of the kernel whose name starts with
-    `kernel_prefix` (template arguments follow), from the committed
-    FETCH_SIZE / WRITE_SIZE summary; None if absent or taken on other sources."""
-    if not os.path.exists(PMC_SUMMARY):
-        return None
-    with open(PMC_SUMMARY) as f:
-        pmc = json.load(f)
-    if not str(pmc.get("kernel", "")).startswith(kernel_prefix):
-        return None
+def measured_traffic(kernel_prefix, workload):
+    """(HBM bytes per launch, kernel name, summary file) of the kernel whose
+    name starts with kernel_prefix on `workload`, from a committed FETCH_SIZE /
+    WRITE_SIZE summary (profiles/*_pmc.json); None if there is none or it
+    was taken on other kernel sources."""
+    import glob
     from paper_1404_3773_amd import pmc_summary
-    if pmc_summary.source_digest(pmc["sources"]) != pmc["source_sha256"]:
-        return None
-    return pmc["traffic_bytes"]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.json"))):
+        with open(path) as f:
+            pmc = json.load(f)
+        if pmc.get("workload") != workload:
+            continue
+        for row in pmc.get("kernels", []):
+            if row["kernel"].startswith(kernel_prefix) and "traffic_bytes" in row:
+                if pmc_summary.source_digest(pmc["sources"]) != pmc["source_sha256"]:
+                    return None
+                return row["traffic_bytes"], row["kernel"], os.path.relpath(path, ROOT)
+    return None
+
+
+def x0_on_device(torch, w):
+    """The seeded start block of workload w as a (k, d) float64 device tensor,
+    streamed to the device in row chunks (row i = column i of the block)."""
+    X = torch.empty(w.k, w.d, dtype=torch.float64, device="cuda")
+    for i0, rows in si.x0_row_chunks(w, 64):
+        X[i0:i0 + rows.shape[0]] = torch.from_numpy(rows).cuda()
+    return X
+
+
+def kb_hamiltonian(ces, torch, w, B, atoms_per_chunk=16):
+    """Hamiltonian of a wells + projectors workload: V_eff and the projector
+    functions sampled on the grid by the seeded generators (on the device),
+    projector coefficients by the library's forward transform in chunks of
+    atoms.  Returns (H, n_proj, V, seconds)."""
+    t0 = time.perf_counter()
+    r, wr, th, wt, ph = B.grid()
+    pts = torch.from_numpy(si.spherical_to_cartesian(r, th, ph).reshape(-1, 3)).cuda()
+    atoms = si.atoms_for(w)
+    V = si.gaussian_wells_torch(pts, atoms)
+    H0 = ces.Ham(B, V)
+    n_proj = 4 * len(atoms)
+    P = torch.empty(n_proj, B.d, dtype=torch.float64, device="cuda")
+    energies = []
+    work = H0.workspace(4 * atoms_per_chunk, ces.CES_PREC_FP64)
+    for a0 in range(0, len(atoms), atoms_per_chunk):
+        vals, e = si.kb_projector_values_torch(pts, atoms[a0:a0 + atoms_per_chunk])
+        H0.from_grid(vals, P[4 * a0:4 * a0 + vals.shape[0]], work)
+        energies.append(e)
+        del vals
+    torch.cuda.synchronize()
+    del work, H0, pts
+    H = ces.Ham(B, V, P, np.concatenate(energies))
+    del P
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return H, n_proj, V, time.perf_counter() - t0
 
 
 def pmc_run():
-    """Short run for the counter passes: two mixed-precision filters on the
-    13-atom workload (32 H*X) and a plain elementwise copy of PMC_COPY_BYTES."""
+    """Short run for the counter passes on the 309-atom workload: two mixed
+    and one FP64 H*X of the 1000-orbital block, and a plain elementwise copy
+    of PMC_COPY_BYTES (read and written once) that calibrates the counters."""
     import torch
     from paper_1404_3773_amd import ces
-    w = si.C2
+    w = si.C4
     B = ces.Basis.for_workload(w)
-    r, wr, th, wt, ph = B.grid()
-    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
-    work = H.workspace(w.k, ces.CES_PREC_MIXED)
-    X = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
-    ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
-    rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
-    b = H.lanczos_bound(torch.from_numpy(si.lanczos_start(B.d)).cuda(), work)
-    theta = H.rayleigh_ritz(X, ev, rs, work)
-    for _ in range(2):
-        H.cheb_filter(X, w.degree, theta[-1], b, theta[0], ces.CES_PREC_MIXED, work)
+    H, n_proj, V, _ = kb_hamiltonian(ces, torch, w, B)
+    X = x0_on_device(torch, w)
+    Y = torch.empty_like(X)
+    print(f"[bench] pmc run: {w.name} setup done", flush=True)
+    for prec, reps in ((ces.CES_PREC_MIXED, 2), (ces.CES_PREC_FP64, 1)):
+        work = H.workspace(w.k, prec)
+        for _ in range(reps):
+            H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        del work
+        torch.cuda.empty_cache()
+        print(f"[bench] pmc run: {reps} H*X prec={prec}", flush=True)
+    del X, Y
+    torch.cuda.empty_cache()
     src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
-    print(f"[bench] pmc run done: 32 H*X, 3 copies of {PMC_COPY_BYTES} bytes", flush=True)
+    print(f"[bench] pmc run done: 3 copies of {PMC_COPY_BYTES} bytes", flush=True)
+
+
+def wells_on_device(torch, B, w):
+    """The workload's Gaussian-well V_eff on the basis grid, evaluated on the
+    device by the seeded generator (float64, flat [r][theta][phi])."""
+    r, wr, th, wt, ph = B.grid()
+    pts = torch.from_numpy(si.spherical_to_cartesian(r, th, ph).reshape(-1, 3)).cuda()
+    return si.gaussian_wells_torch(pts, si.atoms_for(w))
+
+
+def stage_rates(prof, sf, peak, prec_suffix):
+    """Per-stage average launch time and algorithmic rate from ces profiling."""
+    out = {}
+    for st, (ms, c) in prof.items():
+        if c and st.endswith(prec_suffix) and sf.get(st[:-5], 0) > 0:
+            rate = sf[st[:-5]] / (ms / c * 1e-3)
+            out[st[:-5]] = {"ms": round(ms / c, 4), "launches": c,
+                            "tflops": round(rate / 1e12, 2), "frac_peak": round(rate / peak, 4)}
+    return out
 
 
 def large_workload_rates(ces, torch, reps=5):
@@ -196,8 +282,7 @@ def large_workload_rates(ces, torch, reps=5):
     each stage's fraction of the FP32 / FP64 peak."""
     w = si.C3
     B = ces.Basis.for_workload(w)
-    r, wr, th, wt, ph = B.grid()
-    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
+    H = ces.Ham(B, wells_on_device(torch, B, w))
     F = algorithmic_flops(w, w.k)["total"]
     sf = stage_flops(w, w.k)
     out = {"workload": w.name, "d": w.d, "orbitals": w.k, "alg_flop_per_HX": F}
@@ -244,15 +329,16 @@ def large_time_to_eigenpairs(ces, torch):
     iterations and the mixed run's largest eigenvalue difference from it."""
     w = si.C3
     B = ces.Basis.for_workload(w)
-    r, wr, th, wt, ph = B.grid()
-    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
-    X0 = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
+    H = ces.Ham(B, wells_on_device(torch, B, w))
+    X0 = x0_on_device(torch, w)
     k = X0.shape[0]
     v0 = torch.from_numpy(si.lanczos_start(B.d)).cuda()
     ev = torch.empty(k, dtype=torch.float64, device="cuda")
     rs = torch.empty(k, dtype=torch.float64, device="cuda")
     out = {"workload": w.name, "orbitals": k, "n_check": w.n_check, "degree": w.degree,
-           "reference": "FP64 GPU run (CPU oracle infeasible at this size)"}
+           "reference": "FP64 GPU run (CPU oracle infeasible at this size); the absolute "
+                        "eigenvalues at this size are parity-unpinned: the FP64 H*X matches "
+                        "the oracle at this full size, the eigenvalues are not run there"}
     theta = {}
     for name, prec in (("fp64", ces.CES_PREC_FP64), ("mixed", ces.CES_PREC_MIXED)):
         work = H.workspace(k, prec)
@@ -274,62 +360,6 @@ def large_time_to_eigenpairs(ces, torch):
     return out
 
 
-def kb_workload_rates(ces, torch, reps=3):
-    """H*X on the 309-atom nonlocal shape (L_max = 80, N = 150, 225 x 162 x 324
-    grid, k = 1000, 1236 Kleinman-Bylander projectors) in mixed and FP64, per
-    stage.  Timing only: V_eff and the projector coefficients are seeded
-    random values of the real shapes (the kernels' work does not depend on
-    them); parity at this shape is tested with the physical projectors of a
-    few atoms."""
-    w = si.C4
-    n_proj = 4 * len(si.atoms_for(w))
-    B = ces.Basis.for_workload(w)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(3)
-    V = -0.5 + 0.1 * torch.rand(B.n_grid, dtype=torch.float64, device="cuda", generator=gen)
-    P = 1e-3 * torch.randn(n_proj, B.d, dtype=torch.float64, device="cuda", generator=gen)
-    H = ces.Ham(B, V, P, np.tile([1.5, -0.8, -0.8, -0.8], n_proj // 4))
-    del P
-    torch.cuda.empty_cache()
-    F = algorithmic_flops(w, w.k, n_proj)["total"]
-    sf = stage_flops(w, w.k, n_proj)
-    X = torch.randn(w.k, B.d, dtype=torch.float64, device="cuda", generator=gen)
-    Y = torch.empty_like(X)
-    out = {"workload": w.name, "d": w.d, "orbitals": w.k, "projectors": n_proj,
-           "values": "seeded random V_eff and projector coefficients (timing only)",
-           "alg_flop_per_HX": F}
-    for name, prec, peak in (("mixed", ces.CES_PREC_MIXED, PEAK_FP32),
-                             ("fp64", ces.CES_PREC_FP64, PEAK_FP64)):
-        work = H.workspace(w.k, prec)
-        H.apply_H(X, Y, prec, work)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            H.apply_H(X, Y, prec, work)
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t) / reps
-        ces.profile_enable(True, 1024)      # stage durations over a second pass
-        for _ in range(reps):
-            H.apply_H(X, Y, prec, work)
-        torch.cuda.synchronize()
-        prof = ces.profile_read()
-        ces.profile_enable(False)
-        suffix = "_fp32" if name == "mixed" else "_fp64"
-        stages = {}
-        for st, (ms, c) in prof.items():
-            if c and st.endswith(suffix) and sf[st[:-5]] > 0:
-                rate = sf[st[:-5]] / (ms / c * 1e-3)
-                stages[st[:-5]] = {"ms": round(ms / c, 3), "tflops": round(rate / 1e12, 2),
-                                   "frac_peak": round(rate / peak, 4)}
-        out[name] = {"ms_per_HX": round(sec * 1e3, 2), "tflops": round(F / sec / 1e12, 3),
-                     "stages": stages}
-        del work
-        torch.cuda.empty_cache()
-    print(f"[bench] 309-atom KB H*X: mixed {out['mixed']['ms_per_HX']} ms, "
-          f"fp64 {out['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
-    return out
-
-
 def golden_eigenvalues(w):
     path = os.path.join(ROOT, "tests", "golden", f"{w.name}_eigenvalues.txt")
     if not os.path.exists(path):
@@ -337,84 +367,71 @@ def golden_eigenvalues(w):
     return np.loadtxt(path, comments="#")[:, 1]
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """The FP64 oracle's H*X on the host cores, on a bounded sample: repeated
-    applications to the full k-column block until ~budget_s of work."""
+def cpu_baseline(w, V_grid, budget_s=20.0):
+    """The FP64 oracle's H*X on the host cores, on a bounded sample of the
+    headline workload: single columns of its start block through the oracle's
+    transforms, V_eff and kinetic term (the projector term left out, and out
+    of the flop count) until ~budget_s of work.  V_grid: the workload's V_eff
+    on the grid (host array from the seeded generator)."""
     from oracle import basis as ob
     from oracle import hamiltonian as oh
+    blas, threads = "unknown", os.cpu_count()
     try:
         import threadpoolctl
-        threads = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()),
-                      default=1)
+        info = threadpoolctl.threadpool_info()
+        blas = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info
+                                 if p.get("user_api") == "blas"})) or "unknown"
+        threads = max((p.get("num_threads", 1) for p in info), default=threads)
     except Exception:
-        threads = os.cpu_count()
+        pass
+    t0 = time.perf_counter()
     bs = ob.basis_for(w)
-    V = si.potential_on_grid(w, bs.r, bs.theta, bs.phi)
-    X = si.x0_block(w)
-    F = algorithmic_flops(w, w.k)["total"]
+    setup_s = time.perf_counter() - t0
+    V = V_grid.reshape(w.n_r, w.n_theta, w.n_phi)
+    F1 = algorithmic_flops(w, 1)["total"]
     n = 0
     t0 = time.perf_counter()
-    while True:
-        oh.apply_H_real(bs, V, X)
+    for _, rows in si.x0_row_chunks(w, 1):
+        oh.apply_H_real(bs, V, rows.T)
         n += 1
         if time.perf_counter() - t0 > budget_s or n >= 50:
             break
     dt = time.perf_counter() - t0
-    return {"value": round(F * n / dt / 1e9, 4), "unit": "GFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n} FP64 oracle H*X applications on the full {w.k}-orbital block "
-                      f"({w.name}), {dt:.1f} s; same algorithmic flop count as the GPU line"}
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except Exception:
+        ncpu = os.cpu_count()
+    return {"value": round(F1 * n / dt / 1e9, 4), "unit": "GFLOP/s", "cores": int(threads),
+            "kind": "oracle", "nproc": ncpu, "blas": blas,
+            "sample": f"{n} single-column FP64 oracle H*X on the {w.name} basis and grid "
+                      f"(columns 0..{n - 1} of the start block; transforms, V_eff and kinetic "
+                      f"term; projector term excluded from work and count), {dt:.1f} s after "
+                      f"{setup_s:.1f} s of oracle table setup"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 147-atom and 309-atom H*X rates")
-    ap.add_argument("--pmc-run", action="store_true",
-                    help="short run for rocprofv3 counter passes (no JSON line)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
-              f"got --gpus {args.gpus}", file=sys.stderr)
-        sys.exit(2)
-
-    if args.pmc_run:
-        pmc_run()
-        return
-
-    import torch
-    from paper_1404_3773_amd import ces
-
-    w = si.C2
-    k = w.k
+def headline_c4(ces, torch, args):
+    """The 309-atom workload: timed mixed CheFSI steps, then per-stage HIP-event
+    timings over further steps, and single H*X rates per precision."""
+    w = si.C4
     FP64, MIXED = ces.CES_PREC_FP64, ces.CES_PREC_MIXED
-    print(f"[bench] workload {w.name}: d={w.d} grid={w.n_r}x{w.n_theta}x{w.n_phi} k={k} "
+    print(f"[bench] workload {w.name}: d={w.d} grid={w.n_r}x{w.n_theta}x{w.n_phi} k={w.k} "
           f"degree={w.degree}", file=sys.stderr, flush=True)
     B = ces.Basis.for_workload(w)
-    r, wr, th, wt, ph = B.grid()
-    V = torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda()
-    H = ces.Ham(B, V)
-    work = H.workspace(k, MIXED)
-    X0 = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
+    H, n_proj, V, setup_s = kb_hamiltonian(ces, torch, w, B)
+    X = x0_on_device(torch, w)
+    print(f"[bench] setup: {setup_s:.1f} s ({n_proj} projectors)", file=sys.stderr, flush=True)
+    work = H.workspace(w.k, MIXED)
     v0 = torch.from_numpy(si.lanczos_start(B.d)).cuda()
     b = H.lanczos_bound(v0, work)
-    ev = torch.empty(k, dtype=torch.float64, device="cuda")
-    rs = torch.empty(k, dtype=torch.float64, device="cuda")
-    F = algorithmic_flops(w, k)["total"]
-
-    # ---- timed CheFSI steps (mixed filter + FP64 RR)
-    X = X0.clone()
+    ev = torch.empty(w.k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(w.k, dtype=torch.float64, device="cuda")
+    F = algorithmic_flops(w, w.k, n_proj)["total"]
     theta = H.rayleigh_ritz(X, ev, rs, work)
 
     def step():
         nonlocal theta
         H.cheb_filter(X, w.degree, theta[-1], b, theta[0], MIXED, work)
-        theta = H.rayleigh_ritz(X, ev, rs, work)  # synchronises; eigenvalues on the host
+        theta = H.rayleigh_ritz(X, ev, rs, work)   # synchronises
 
     for _ in range(args.warmup):
         step()
@@ -424,45 +441,115 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-kernel durations: HIP events around every launch, recorded on the
-    # library's stream over the same number of further steps (the two event
-    # records per launch cost host time, so they stay out of the step timing)
+    print(f"[bench] {args.steps} steps, {dt / args.steps * 1e3:.1f} ms/step",
+          file=sys.stderr, flush=True)
+    # per-kernel durations: HIP events around every launch on the library's
+    # stream, over further steps (kept out of the step timing)
     ces.profile_enable(True, 65536)
-    for _ in range(args.steps):
+    for _ in range(args.prof_steps):
         step()
     torch.cuda.synchronize()
     prof = ces.profile_read()
     ces.profile_enable(False)
-    ms_step = dt / args.steps * 1e3
-    value = (w.degree + 1) * F / (dt / args.steps) / 1e9
-    print(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+    res_max = float(rs[:w.n_check].max())
+    # single H*X per precision (mixed: FP32 transforms and projector products)
+    hx = {}
+    Y = torch.empty_like(X)
+    for name, prec, peak in (("mixed", MIXED, PEAK_FP32), ("fp64", FP64, PEAK_FP64)):
+        wk = work if prec == MIXED else H.workspace(w.k, prec)
+        H.apply_H(X, Y, prec, wk)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            H.apply_H(X, Y, prec, wk)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / 3
+        ces.profile_enable(True, 1024)
+        H.apply_H(X, Y, prec, wk)
+        torch.cuda.synchronize()
+        p1 = ces.profile_read()
+        ces.profile_enable(False)
+        hx[name] = {"ms_per_HX": round(sec * 1e3, 2), "tflops": round(F / sec / 1e12, 3),
+                    "frac_peak": round(F / sec / peak, 4),
+                    "stages": stage_rates(p1, stage_flops(w, w.k, n_proj), peak,
+                                          "_fp32" if name == "mixed" else "_fp64")}
+        if prec != MIXED:
+            del wk
+        torch.cuda.empty_cache()
+    print(f"[bench] {w.name} H*X: mixed {hx['mixed']['ms_per_HX']} ms, "
+          f"fp64 {hx['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
+    out = {"w": w, "n_proj": n_proj, "F": F, "dt": dt, "prof": prof, "hx": hx,
+           "setup_s": setup_s, "res_max_after_steps": res_max,
+           "theta_range": [float(theta[0]), float(theta[-1])], "bound": b}
+    V_host = V.cpu().numpy()
+    del work, X, Y, H, V
+    torch.cuda.empty_cache()
+    return out, V_host
 
-    # ---- filter-only throughput per precision
+
+def ico13_extras(ces, torch, args):
+    """The 13-atom workload: timed mixed CheFSI steps, filter rates, density,
+    and time to eigenpairs against the stored oracle eigenvalues."""
+    w = si.C2
+    k = w.k
+    FP64, MIXED = ces.CES_PREC_FP64, ces.CES_PREC_MIXED
+    B = ces.Basis.for_workload(w)
+    r, wr, th, wt, ph = B.grid()
+    H = ces.Ham(B, torch.from_numpy(si.potential_on_grid(w, r, th, ph).reshape(-1)).cuda())
+    work = H.workspace(k, MIXED)
+    X0 = torch.from_numpy(np.ascontiguousarray(si.x0_block(w).T)).cuda()
+    v0 = torch.from_numpy(si.lanczos_start(B.d)).cuda()
+    b = H.lanczos_bound(v0, work)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    F = algorithmic_flops(w, k)["total"]
+    X = X0.clone()
+    theta = H.rayleigh_ritz(X, ev, rs, work)
+
+    def step():
+        nonlocal theta
+        H.cheb_filter(X, w.degree, theta[-1], b, theta[0], MIXED, work)
+        theta = H.rayleigh_ritz(X, ev, rs, work)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    n = 20
+    t0 = time.perf_counter()
+    for _ in range(n):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ces.profile_enable(True, 65536)
+    for _ in range(n):
+        step()
+    torch.cuda.synchronize()
+    prof = ces.profile_read()
+    ces.profile_enable(False)
+
     def filter_rate(prec, reps=10):
-        Y = X.clone()
-        H.cheb_filter(Y, w.degree, theta[-1], b, theta[0], prec, work)
+        Yf = X.clone()
+        H.cheb_filter(Yf, w.degree, theta[-1], b, theta[0], prec, work)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
-            # filtering a converged Ritz block again keeps magnitudes near 1
-            H.cheb_filter(Y, w.degree, theta[-1], b, theta[0], prec, work)
+            H.cheb_filter(Yf, w.degree, theta[-1], b, theta[0], prec, work)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / reps
         return w.degree * F / sec / 1e9, sec * 1e3
 
     gf_mixed, ms_f_mixed = filter_rate(MIXED)
     gf_fp64, ms_f_fp64 = filter_rate(FP64)
-
-    # ---- density (rho and tau) for the same block
-    dens = density_rates(ces, torch, H, w, X0, work)
-
-    # ---- grid-pointwise exchange-correlation kernels
-    pointwise = pointwise_rates(ces, torch)
-
-    # ---- time to eigenpairs
-    tte = {}
-    ref = golden_eigenvalues(w)
+    out = {"workload": w.name, "d": w.d, "orbitals": k, "degree": w.degree,
+           "step_gflops": round((w.degree + 1) * F / (dt / n) / 1e9, 3),
+           "ms_per_step": round(dt / n * 1e3, 4),
+           "filter_gflops": {"mixed": round(gf_mixed, 3), "fp64": round(gf_fp64, 3),
+                             "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4)},
+           "stages_fp32": stage_rates(prof, stage_flops(w, k), PEAK_FP32, "_fp32")}
+    out["density"] = density_rates(ces, torch, H, w, X0, work)
     if not args.no_tte:
+        tte = {}
+        ref = golden_eigenvalues(w)
         for name, prec in (("mixed", MIXED), ("fp64", FP64)):
             Xs = X0.clone()
             torch.cuda.synchronize()
@@ -476,77 +563,100 @@ def main():
             tte[name] = {"seconds": round(sec, 4), "iterations": it,
                          "max_eig_err_vs_oracle_Ha": err,
                          "within_1e-6Ha": (err is not None and err < 1e-6)}
-            print(f"[bench] time-to-eigenpairs {name}: {sec:.3f} s, {it} it, err={err}",
+            print(f"[bench] 13-atom time-to-eigenpairs {name}: {sec:.3f} s, {it} it, err={err}",
                   file=sys.stderr, flush=True)
+        out["time_to_eigenpairs"] = tte
+    del work, X, X0, H
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prof-steps", type=int, default=2,
+                    help="further steps timed per kernel with HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no 13-atom / 147-atom extras)")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for rocprofv3 counter passes (no JSON line)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    if args.pmc_run:
+        pmc_run()
+        return
+
+    import torch
+    from paper_1404_3773_amd import ces
+
+    hd, V_host = headline_c4(ces, torch, args)
+    w, F, prof, n_proj = hd["w"], hd["F"], hd["prof"], hd["n_proj"]
+    ms_step = hd["dt"] / args.steps * 1e3
+    value = (w.degree + 1) * F / (hd["dt"] / args.steps) / 1e9
 
     # ---- roofline of the dominant kernel: the FP32 launch class with the
-    # largest total time over the profiled steps (HIP events around each
-    # launch, a second run of the timed steps).
-    # The phi stage (synthesis, V, analysis) is credited at nominal real-FFT
-    # flops and priced against the FP32 ALU peak; the transform GEMM stages
-    # (radial, Legendre) against the FP32 MFMA peak (the same 157.3 TFLOP/s).
-    stage_avg = {s: (ms / c if c else 0.0, c) for s, (ms, c) in prof.items()}
-    fp32 = [s for s in prof if s.endswith("_fp32")]
-    dom = max(fp32, key=lambda s: prof[s][0])
-    avg_ms, launches = stage_avg[dom]
-    sf = stage_flops(w, k)
-    alg = sf[dom[:-5]]
+    # largest total time over the profiled steps
+    fp32 = [st for st in prof if st.endswith("_fp32") and prof[st][1]]
+    dom = max(fp32, key=lambda st: prof[st][0])
+    tot_ms, launches = prof[dom]
+    avg_ms = tot_ms / launches
+    stage = dom[:-5]
+    alg = stage_flops(w, w.k, n_proj)[stage]
+    alg_b = stage_bytes(w, w.k, n_proj, 4)[stage]
     achieved = alg / (avg_ms * 1e-3)
-    kernel_name = {"phi_stage_fp32": "k_phi_stage<float"}.get(dom)
-    traffic = measured_traffic(kernel_name) if kernel_name else None
-    roof = {"bound": "alu" if dom.startswith("phi") else "mfma",
-            "achieved": round(achieved / 1e12, 4),
+    tr = measured_traffic(STAGE_KERNEL[stage], w.name)
+    # every H*X stage runs its contraction on FP32 MFMA (the phi stage as an
+    # exact Toeplitz + Hankel product, credited at real-FFT flops only)
+    roof = {"bound": "mfma", "achieved": round(achieved / 1e12, 3),
             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32, 5),
-            "traffic": None if traffic is None else round(traffic),
-            "kernel": dom, "avg_launch_ms": round(avg_ms, 5), "launches": launches,
-            "kernel_timing": f"HIP events around each launch over {args.steps} further steps "
-                             "of the same workload (kept out of the step timing)",
-            "alg_flop_per_launch": alg}
-    if traffic is not None:
-        roof["hbm_GBps_measured"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
-        roof["hbm_frac_measured"] = round(traffic / (avg_ms * 1e-3) / PEAK_HBM, 4)
-    gemm_frac = {}
-    for st in ("radial_inverse", "legendre_synth", "legendre_analysis", "radial_forward"):
-        ms_, c_ = stage_avg.get(st + "_fp32", (0.0, 0))
-        if c_:
-            gemm_frac[st] = round(sf[st] / (ms_ * 1e-3) / PEAK_FP32, 4)
+            "frac": round(achieved / PEAK_FP32, 4),
+            "traffic": None if tr is None else round(tr[0]),
+            "kernel": tr[1] if tr else STAGE_KERNEL[stage], "stage": dom,
+            "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "alg_flop_per_launch": alg, "alg_bytes_per_launch": alg_b,
+            "kernel_timing": f"HIP events around each launch over {args.prof_steps} further "
+                             "steps of the same workload (kept out of the step timing)"}
+    if tr is not None:
+        roof["traffic_source"] = tr[2]
+        roof["hbm_GBps_measured"] = round(tr[0] / (avg_ms * 1e-3) / 1e9, 1)
+    gemm_frac = {st: v["frac_peak"] for st, v in
+                 stage_rates(prof, stage_flops(w, w.k, n_proj), PEAK_FP32, "_fp32").items()}
 
     line = {
         "metric": "Chebyshev-filter H*X GFLOP/s & time-to-eigenpairs@1e-6Ha: mixed vs FP64",
         "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": w.name, "atoms": 13, "R_bohr": w.R, "L_max": w.L - 1,
-                   "radial_per_l": w.N, "d": w.d,
-                   "grid": [w.n_r, w.n_theta, w.n_phi], "orbitals": k, "degree": w.degree,
-                   "step": "mixed filter + FP64 Cholesky-QR/Rayleigh-Ritz"},
-        "filter_gflops": {"mixed": round(gf_mixed, 3), "fp64": round(gf_fp64, 3),
-                          "mixed_ms": round(ms_f_mixed, 4), "fp64_ms": round(ms_f_fp64, 4),
-                          "mixed_frac_fp32_peak": round(gf_mixed * 1e9 / PEAK_FP32, 4),
-                          "fp64_frac_fp64_peak": round(gf_fp64 * 1e9 / PEAK_FP64, 4)},
-        "time_to_eigenpairs": tte,
-        "density": dens,
-        "xc_pointwise": pointwise,
-        "stage_ms_avg": {s: round(v[0], 5) for s, v in stage_avg.items()},
-        "transform_gemm_frac_fp32_mfma": gemm_frac,
+        "config": {"workload": w.name, "atoms": 309, "projectors": n_proj, "R_bohr": w.R,
+                   "L_max": w.L - 1, "radial_per_l": w.N, "d": w.d,
+                   "grid": [w.n_r, w.n_theta, w.n_phi], "orbitals": w.k, "degree": w.degree,
+                   "step": "mixed degree-20 filter + FP64 Cholesky-QR/Rayleigh-Ritz"},
+        "setup_seconds": round(hd["setup_s"], 1),
+        "HX": hd["hx"],
+        "mixed_vs_fp64_HX_speedup": round(hd["hx"]["fp64"]["ms_per_HX"] /
+                                          hd["hx"]["mixed"]["ms_per_HX"], 3),
+        "stage_frac_fp32_peak": gemm_frac,
         "roofline": roof,
+        "after_steps": {"max_residual_first_n_check": hd["res_max_after_steps"],
+                        "ritz_range_Ha": hd["theta_range"], "upper_bound_Ha": hd["bound"]},
     }
-    if not args.no_large:
-        del work
-        torch.cuda.empty_cache()
-        line["large_workload"] = large_workload_rates(ces, torch)
+    if not args.no_extras:
+        line["ico13"] = ico13_extras(ces, torch, args)
+        line["xc_pointwise"] = pointwise_rates(ces, torch)
+        line["mackay147_HX"] = large_workload_rates(ces, torch)
         torch.cuda.empty_cache()
         if not args.no_tte:
-            line["time_to_eigenpairs_147"] = large_time_to_eigenpairs(ces, torch)
+            line["mackay147_time_to_eigenpairs"] = large_time_to_eigenpairs(ces, torch)
             torch.cuda.empty_cache()
-        try:
-            line["kb_workload"] = kb_workload_rates(ces, torch)
-        except Exception as e:   # reported, never fatal to the line
-            line["kb_workload"] = {"error": f"{type(e).__name__}: {e}"}
-        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
+        line["cpu_baseline"] = cpu_baseline(w, V_host)
     print(json.dumps(line), flush=True)
 
 

@@ -234,6 +234,36 @@ ces_status ces_chefsi(ces_ham h, int k, double* d_X, int64_t ldx, int degree, do
                       double dtheta_tol, int prec, double* d_eval, double* d_resnorm,
                       int* h_iters, void* d_work, size_t work_bytes, void* stream);
 
+/* Lowest eigenpairs of H by block LOBPCG (Section 3.1, following the
+ * published method of Knyazev et al. that the paper adopts) from the block in
+ * d_X: column-scaled Cholesky orthonormalisation of every search block;
+ * soft locking (a column whose residual r_i = ||H x_i - theta_i x_i|| <=
+ * res_tol * max(1, |theta_i|) leaves the residual and conjugate-direction
+ * blocks; its Ritz vector still takes part in the Rayleigh-Ritz step); hard
+ * locking against the n_lock orthonormal constraint columns d_Y (d x n_lock,
+ * ld ldy; may be NULL with n_lock = 0): the start block and every residual
+ * block are projected against them; on a failed factorisation of the
+ * conjugate directions or of the projected pencil the iteration goes on
+ * without them, and on a failed factorisation of the residual block it
+ * restarts from the current Ritz vectors.  With precondition = 1 each
+ * residual y is multiplied coefficient-wise by the Teter-Payne-Allan factor
+ * (Section 3.1.2) T(g) = (27 + 18g + 12g^2 + 8g^3) / (27 + 18g + 12g^2 + 8g^3
+ * + 16g^4), g = g_scale * Lambda_alpha / KE(y), KE(y) = (1/2) sum Lambda |y|^2
+ * / sum |y|^2 (g_scale = 1 is the printed formula read per unit norm of y;
+ * 0.5 is Teter, Payne and Allan's own variable).  H W runs in `prec`; the
+ * Gram products, factorisations and updates in FP64.  Stops when the first
+ * n_check columns have converged or after max_iter iterations.  On return
+ * d_X holds the Ritz vectors after a final FP64 Rayleigh-Ritz, d_eval /
+ * d_resnorm (k device doubles) their values and residual norms, *h_iters the
+ * iterations, *h_restarts (may be NULL) the restarts.  Requires 3k + n_lock
+ * <= d, k <= 32768, 1 <= n_check <= k, res_tol > 0, g_scale > 0.
+ * Workspace: ces_lobpcg_workspace_size.  Synchronous. */
+ces_status ces_lobpcg_workspace_size(ces_ham h, int k, int n_lock, int prec, size_t* bytes);
+ces_status ces_lobpcg(ces_ham h, int k, double* d_X, int64_t ldx, int n_lock, const double* d_Y,
+                      int64_t ldy, int n_check, int max_iter, double res_tol, double g_scale,
+                      int precondition, int prec, double* d_eval, double* d_resnorm, int* h_iters,
+                      int* h_restarts, void* d_work, size_t work_bytes, void* stream);
+
 /* ---------------------------------------------------------------- density */
 
 /* rho(x_g) = 2 sum_i f_i psi_i(x_g)^2 with psi_i the inverse transform of
@@ -446,13 +476,14 @@ ces_status ces_cluster_quad_loss(int n_clusters, int max_atoms, const int64_t* d
  * kernels on the caller's stream.  Stage ids: 0 radial inverse (eq. G_lmr),
  * 1 Legendre synthesis, 2 phi stage with V_eff, 3 Legendre quadrature
  * (eq. Ar_lm), 4 radial quadrature with the kinetic / projector / Chebyshev
- * epilogue (eq. Arlm_to_coeff), 5 projector GEMM; ids 6..11 are the same
- * stages in FP64 (0..5 are FP32).  ces_profile_enable(1, n) starts
+ * epilogue (eq. Arlm_to_coeff), 5 projector product C = diag(h) P^T Y,
+ * 6 projector product P C; ids 7..13 are the same stages in FP64 (0..6 are
+ * FP32).  ces_profile_enable(1, n) starts
  * recording into a pool of n event pairs (launches beyond the pool are not
  * recorded) and clears the totals; ces_profile_enable(0, 0) stops and frees
  * the pool.  Process-wide, not thread-safe; meant for benchmarking. */
 ces_status ces_profile_enable(int on, int max_records);
-/* Synchronise the recorded events and return, per stage s < n_stages (<= 12),
+/* Synchronise the recorded events and return, per stage s < n_stages (<= 14),
  * the summed milliseconds h_ms[s] and launch count h_count[s]. */
 ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count);
 

@@ -26,7 +26,8 @@ EXPORTS = [
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
     "ces_workspace_size", "ces_apply_H", "ces_apply_H_noalloc", "ces_cheb_filter",
     "ces_rayleigh_ritz",
-    "ces_lanczos_bound", "ces_chefsi", "ces_density", "ces_to_grid", "ces_from_grid",
+    "ces_lanczos_bound", "ces_chefsi", "ces_lobpcg_workspace_size", "ces_lobpcg",
+    "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
     "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
@@ -74,6 +75,9 @@ def load() -> ctypes.CDLL:
         "ces_rayleigh_ritz": [P, I, P, I64, P, P, P, P, ctypes.POINTER(I), I, P, SZ, P],
         "ces_lanczos_bound": [P, P, I, ctypes.POINTER(D), P, SZ, P],
         "ces_chefsi": [P, I, P, I64, I, D, I, I, I, D, D, I, P, P, ctypes.POINTER(I), P, SZ, P],
+        "ces_lobpcg_workspace_size": [P, I, I, I, ctypes.POINTER(SZ)],
+        "ces_lobpcg": [P, I, P, I64, I, P, I64, I, I, D, D, I, I, P, P, ctypes.POINTER(I),
+                       ctypes.POINTER(I), P, SZ, P],
         "ces_density": [P, I, P, I64, P, P, P, I, P, SZ, P],
         "ces_to_grid": [P, I, P, I64, P, P, SZ, P],
         "ces_from_grid": [P, I, P, P, I64, P, SZ, P],
@@ -145,7 +149,7 @@ def _ld(X):
 
 
 _STAGE_NAMES = ("radial_inverse", "legendre_synth", "phi_stage", "legendre_analysis",
-                "radial_forward", "kb_gemm")
+                "radial_forward", "kb_project", "kb_apply")
 STAGES = tuple(f"{n}_fp32" for n in _STAGE_NAMES) + tuple(f"{n}_fp64" for n in _STAGE_NAMES)
 
 
@@ -469,6 +473,29 @@ class Ham:
                                  ctypes.byref(it), _ptr(work), work.numel(), _stream(stream)),
                "ces_chefsi")
         return it.value
+
+    def lobpcg_workspace(self, k, n_lock=0, prec=CES_PREC_FP64):
+        import torch
+        n = ctypes.c_size_t()
+        _check(load().ces_lobpcg_workspace_size(self._h, int(k), int(n_lock), int(prec),
+                                                ctypes.byref(n)), "ces_lobpcg_workspace_size")
+        return torch.empty(n.value, dtype=torch.uint8, device="cuda")
+
+    def lobpcg(self, X, evals, res, work, n_check=None, max_iter=200, res_tol=1e-6,
+               g_scale=1.0, precondition=True, prec=CES_PREC_FP64, Y=None, stream=None):
+        """Block LOBPCG in place on X ((k, ld) block); Y: (n_lock, ld) constraint
+        block or None.  Returns (iterations, restarts)."""
+        k = X.shape[0]
+        it, rs = ctypes.c_int(), ctypes.c_int()
+        n_lock = 0 if Y is None else Y.shape[0]
+        _check(load().ces_lobpcg(self._h, k, _ptr(X), _ld(X), n_lock, _ptr(Y),
+                                 _ld(Y) if Y is not None else 0,
+                                 int(k if n_check is None else n_check), int(max_iter),
+                                 float(res_tol), float(g_scale), 1 if precondition else 0,
+                                 int(prec), _ptr(evals), _ptr(res), ctypes.byref(it),
+                                 ctypes.byref(rs), _ptr(work), work.numel(), _stream(stream)),
+               "ces_lobpcg")
+        return it.value, rs.value
 
     def density(self, X, occ, rho_grid, rho_coef, prec, work, stream=None):
         _check(load().ces_density(self._h, X.shape[0], _ptr(X), _ld(X), _ptr(occ),

@@ -35,12 +35,13 @@ ces_status fail(ces_status s, const std::string& msg) {
   } while (0)
 
 
-// Stage timing (ces_profile_enable / ces_profile_read): stage ids 0..5 for
-// FP32 launches, 6..11 for FP64 launches.
-constexpr int kStages = 12;
-enum { ST_RADIAL_INV = 0, ST_LEG_SYNTH, ST_PHI, ST_LEG_ANALYSIS, ST_RADIAL_FWD, ST_KB_GEMM };
+// Stage timing (ces_profile_enable / ces_profile_read): stage ids 0..6 for
+// FP32 launches, 7..13 for FP64 launches.
+enum { ST_RADIAL_INV = 0, ST_LEG_SYNTH, ST_PHI, ST_LEG_ANALYSIS, ST_RADIAL_FWD, ST_KB_C, ST_KB_Z,
+       ST_PER_PREC };
+constexpr int kStages = 2 * ST_PER_PREC;
 template <typename T>
-constexpr int stage_id(int st) { return st + (sizeof(T) == 8 ? 6 : 0); }
+constexpr int stage_id(int st) { return st + (sizeof(T) == 8 ? ST_PER_PREC : 0); }
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> ev;     // 2 per record
@@ -412,9 +413,13 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
     // C = diag(h) P^T Yin (n_proj x kp, row-major), then Zkb = P C (d x k)
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
-    StageTimer t(stage_id<T>(ST_KB_GEMM), s);
-    launch_kb_gemm<T>(Pd, b.d, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k, kp, s);
+    {
+      StageTimer t(stage_id<T>(ST_KB_C), s);
+      launch_kb_gemm<T>(Pd, b.d, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k, kp,
+                        s);
+    }
     Zkb = Ptr<T>::at(work, ly.Zkb);
+    StageTimer t(stage_id<T>(ST_KB_Z), s);
     launch_kb_apply<T>(Pd, b.d, C, Zkb, h.n_proj, k, kp, s);
   }
   T* gbuf = Ptr<T>::at(work, ly.gbuf);
@@ -564,6 +569,13 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
                    int64_t ldhx, double* eval, double* res, int hx_prec, hipStream_t s,
                    double* h_eval, double* h_res, int* h_path) {
   std::lock_guard<std::mutex> lock(h.mu);   // rocBLAS handle and host_stage
+  return rr_locked(h, ly, work, k, X, ldx, HX, ldhx, eval, res, hx_prec, s, h_eval, h_res,
+                   h_path);
+}
+
+ces_status rr_locked(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx,
+                     double* HX, int64_t ldhx, double* eval, double* res, int hx_prec,
+                     hipStream_t s, double* h_eval, double* h_res, int* h_path) {
   const Basis& b = *h.basis;
   const int64_t d = b.d;
   double* S1 = Ptr<double>::at(work, ly.S1);

@@ -213,10 +213,19 @@ def gaussian_wells(points: np.ndarray, atoms: np.ndarray,
     import torch   # multithreaded CPU elementwise work; float64 throughout
     shape = points.shape[:-1]
     p = torch.from_numpy(np.ascontiguousarray(points.reshape(-1, 3), dtype=np.float64))
+    return gaussian_wells_torch(p, atoms, depth, sigma).numpy().reshape(shape)
+
+
+def gaussian_wells_torch(p, atoms: np.ndarray, depth: float = WELL_DEPTH,
+                         sigma: float = WELL_SIGMA):
+    """gaussian_wells on a float64 torch tensor of points (n, 3), on the
+    tensor's device; returns a float64 tensor (n,)."""
+    import torch
     a = torch.from_numpy(np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3)))
-    v = torch.zeros(p.shape[0], dtype=torch.float64)
+    a = a.to(p.device)
+    v = torch.zeros(p.shape[0], dtype=torch.float64, device=p.device)
     if a.shape[0] == 0:
-        return v.numpy().reshape(shape)
+        return v
     cut2 = 2.0 * sigma * sigma * 92.1   # exp(-92.1) = 1e-40
     chunk = max(1, int(2.0e8 // a.shape[0]))
     for s in range(0, p.shape[0], chunk):
@@ -225,7 +234,7 @@ def gaussian_wells(points: np.ndarray, atoms: np.ndarray,
         e = torch.exp(-d2 / (2.0 * sigma * sigma))
         e = torch.where(d2 < cut2, e, torch.zeros_like(e))
         v[s:s + chunk] = -depth * e.sum(1)
-    return v.numpy().reshape(shape)
+    return v
 
 
 def harmonic(points: np.ndarray, omega: float) -> np.ndarray:
@@ -269,6 +278,34 @@ def kb_projector_values(points: np.ndarray, atoms: np.ndarray,
     if not cols:
         return np.zeros((p.shape[0], 0)), np.zeros(0)
     return np.stack(cols, axis=1), np.array(energies)
+
+
+def kb_projector_values_torch(p, atoms: np.ndarray, width: float = KB_WIDTH):
+    """kb_projector_values on a float64 torch tensor of points (n, 3), on the
+    tensor's device, transposed: returns (values [n_proj, n], energies
+    [n_proj]) with the same projector order and normalisation."""
+    import torch
+    n0 = 1.0 / math.sqrt(math.gamma(1.5) * width ** 3 / 2.0) / math.sqrt(4.0 * math.pi)
+    n1 = (1.0 / math.sqrt(math.gamma(2.5) * width ** 5 / 2.0)) * math.sqrt(3.0 / (4.0 * math.pi))
+    out = torch.empty(4 * len(atoms), p.shape[0], dtype=torch.float64, device=p.device)
+    energies = []
+    for j, a in enumerate(np.asarray(atoms, dtype=np.float64)):
+        rho = p - torch.from_numpy(a).to(p.device)
+        g = torch.exp(-(rho * rho).sum(1) / (2.0 * width ** 2))
+        out[4 * j] = n0 * g
+        for c, comp in enumerate((1, 2, 0)):
+            out[4 * j + 1 + c] = n1 * g * rho[:, comp]
+        energies += [KB_ENERGY[0]] + [KB_ENERGY[1]] * 3
+    return out, np.array(energies)
+
+
+def x0_row_chunks(w: Workload, chunk: int):
+    """The rows of x0_block(w).T (row i = column i of the start block) in
+    consecutive chunks of at most `chunk` rows: the same draws in the same
+    order, without holding the whole block."""
+    rng = np.random.default_rng(w.x0_seed)
+    for i0 in range(0, w.k, chunk):
+        yield i0, rng.standard_normal((min(chunk, w.k - i0), w.d))
 
 
 def x0_block(w: Workload, k: int | None = None, d: int | None = None,
