@@ -330,11 +330,29 @@ ces_status ces_fermi_dirac(int k, const double* h_eval, double n_electrons, doub
  * n < 0 or a null pointer is CES_ERR_INVALID_ARG.  Asynchronous. */
 ces_status ces_slater_x(int64_t n, const double* d_rho, double* d_vx, void* stream);
 
+/* Non-dualing density (Section 2.2.5): the density of orbitals with
+ * l <= lmax holds angular degrees up to 2 lmax, so the paper lets it be
+ * expanded in a larger basis than the orbitals.  After this call the
+ * handle's ces_ks_potential (and so ces_scf) expands rho - rho_ion in the
+ * basis `rho_basis` for the Hartree potential; NULL restores the orbitals'
+ * own basis (the dualing choice).  rho_basis must use the orbitals' grid
+ * (same R, n_r, n_theta, n_phi and radial rule) and lmax_rho >= lmax;
+ * lmax_rho = 2 lmax holds the density exactly in angle, and the grid
+ * integrates the density against it exactly in angle when 2 n_theta - 1 >=
+ * 2 lmax + lmax_rho and n_phi > 2 lmax + lmax_rho (with lmax_rho = 2 lmax:
+ * n_theta >= 2 lmax + 1, n_phi >= 4 lmax + 1; the n_theta = 2L, n_phi = 4L
+ * grids qualify).  The handle borrows rho_basis: keep it alive while set.
+ * Workspace sizes queried afterwards include the density basis; like
+ * ces_ham_set_veff, must not overlap other calls on the handle. */
+ces_status ces_ham_set_density_basis(ces_ham h, ces_basis rho_basis);
+
 /* d_v = V_ext + V_H[rho - rho_ion] + V_x[rho], V_x = -(3 rho_+ / pi)^(1/3),
  * rho_+ = max(rho, 0).  V_H uses the forward transform of rho - rho_ion in
- * the orbital basis (the dualing choice, Section 2.2.5) and ces_hartree.
- * d_tau[d] (may be NULL) receives those coefficients.  d_v must not alias an
- * input (CES_ERR_INVALID_ARG). */
+ * the orbital basis (the dualing choice, Section 2.2.5), or in the density
+ * basis set by ces_ham_set_density_basis, and the Hartree closed form of
+ * ces_hartree on that basis.  d_tau (may be NULL) receives those
+ * coefficients: d doubles of that basis.  d_v must not alias an input
+ * (CES_ERR_INVALID_ARG). */
 ces_status ces_ks_potential(ces_ham h, const double* d_rho, const double* d_rho_ion,
                             const double* d_vext, double* d_v, double* d_tau, void* d_work,
                             size_t work_bytes, void* stream);

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libces.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["kernels.hip", "kernels_angular.hip", "kernels_radial.hip", "kernels_scf.hip",
-           "kernels_mlp.hip", "kernels_block.hip", "kernels_kb.hip", "noalloc.hip", "capi.cpp", "scf.cpp", "learned.cpp", "setup_tables.cpp"]
+           "kernels_mlp.hip", "kernels_block.hip", "kernels_kb.hip", "kernels_lobpcg.hip", "noalloc.hip", "capi.cpp", "lobpcg.cpp", "scf.cpp", "learned.cpp", "setup_tables.cpp"]
 
 # Device code: gfx950 only; packed-FP32 instructions disabled.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -29,7 +29,7 @@ EXPORTS = [
     "ces_lanczos_bound", "ces_chefsi", "ces_lobpcg_workspace_size", "ces_lobpcg",
     "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
-    "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model",
+    "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model", "ces_ham_set_density_basis",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
         "ces_slater_x": [I64, P, P, P],
         "ces_pz_correlation": [I64, P, P, P, P],
         "ces_ham_set_model": [P, I, D, I],
+        "ces_ham_set_density_basis": [P, P],
         "ces_fermi_dirac": [I, P, D, D, P, ctypes.POINTER(D)],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
@@ -410,6 +411,14 @@ class Ham:
         Anderson mixing of the density instead of the potential."""
         _check(load().ces_ham_set_model(self._h, int(correlation), float(smearing_kT),
                                         int(mix_density)), "ces_ham_set_model")
+
+    def set_density_basis(self, basis):
+        """Expand the density for the Hartree potential in `basis` (a Basis on
+        the same grid, typically lmax = 2 lmax of this one); None restores the
+        orbitals' basis.  The handle keeps a reference to the basis."""
+        _check(load().ces_ham_set_density_basis(self._h, None if basis is None else basis._h),
+               "ces_ham_set_density_basis")
+        self._rho_basis = basis
 
     def set_veff(self, veff, stream=None):
         _check(load().ces_ham_set_veff(self._h, _ptr(veff.contiguous()), _stream(stream)),

@@ -316,7 +316,15 @@ Layout layout_for(Ham& h, int k, int prec) {
   Layout L;
   L.kp = round_up(k, kColPad);
   const size_t LL = size_t(b.L) * b.L;
-  const size_t gbytes = size_t(b.n_r) * LL * L.kp * sizeof(double);
+  size_t gbytes = size_t(b.n_r) * LL * L.kp * sizeof(double);
+  size_t gbuf = size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * sizeof(double);
+  size_t v3 = size_t(b.d) * 3 * sizeof(double);
+  if (const Basis* bd = h.rho_basis) {   // one-column transforms on the density basis
+    gbytes = std::max(gbytes, size_t(bd->n_r) * bd->L * bd->L * kColPad * sizeof(double));
+    gbuf = std::max(gbuf, size_t(bd->n_r) * bd->n_theta * (2 * size_t(bd->L) - 1) * kColPad *
+                              sizeof(double));
+    v3 = std::max(v3, size_t(bd->d) * sizeof(double));
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     off = align256(off);
@@ -326,10 +334,10 @@ Layout layout_for(Ham& h, int k, int prec) {
   };
   L.G = take(gbytes);
   L.A = take(gbytes);
-  L.gbuf = take(size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * sizeof(double));
+  L.gbuf = take(gbuf);
   L.B1 = take(size_t(b.d) * k * sizeof(double));
   L.B2 = take(size_t(b.d) * k * sizeof(double));
-  L.V3 = take(size_t(b.d) * 3 * sizeof(double));
+  L.V3 = take(v3);
   if (prec == CES_PREC_MIXED) {
     L.F0 = take(size_t(b.d) * L.kp * sizeof(float));
     L.F1 = take(size_t(b.d) * L.kp * sizeof(float));

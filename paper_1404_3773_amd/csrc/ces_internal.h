@@ -76,6 +76,7 @@ struct Ham {
   int xc_correlation = 0;    // ces_ks_potential adds the Perdew-Zunger v_c
   double smear_kT = 0.0;     // ces_scf: Fermi-Dirac occupations at kT when > 0
   int mix_density = 0;       // ces_scf: Anderson-mix rho instead of V_eff
+  Basis* rho_basis = nullptr;  // density basis on the same grid (non-dualing), or null
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;
@@ -142,6 +143,13 @@ ces_status apply_H_impl(Ham& h, const Layout& ly, void* work, int k, const doubl
 ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx,
                    double* HX, int64_t ldhx, double* eval, double* res, int hx_prec,
                    hipStream_t s, double* h_eval, double* h_res, int* h_path);
+// rr_impl for a caller that already holds h.mu.
+ces_status rr_locked(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx,
+                     double* HX, int64_t ldhx, double* eval, double* res, int hx_prec,
+                     hipStream_t s, double* h_eval, double* h_res, int* h_path);
+// Device bytes rocSOLVER needs for potrf/trtri/syevd of order k (cached per
+// handle; takes h.mu).
+size_t solver_bytes_for(Ham& h, int k);
 
 template <typename T>
 struct Ptr {
@@ -294,6 +302,21 @@ void launch_block_apply(double* X, int64_t ldx, const double* W, int k, int64_t 
 void launch_block_rotate(double* X, int64_t ldx, double* Y, int64_t ldy, const double* W, int k,
                          int64_t rows, const int* flags, const double* theta, double* res,
                          double* part, int64_t part_cap, hipStream_t s);
+// LOBPCG (kernels_lobpcg.hip).  W[:, j] = AX[:, act[j]] - theta[act[j]] X[:, act[j]]
+// for j < na, and ke[j] = the kinetic energy per unit norm of W[:, j]
+// (sum (Lambda/2) w^2 / sum w^2, lamh the [l][N] table of Lambda / 2); part:
+// 2 * 64 * na doubles of scratch.
+void launch_active_residual(const double* X, int64_t ldx, const double* AX, int64_t ldax,
+                            const double* theta, const int* act, int na, double* W, int64_t ldw,
+                            const double* lamh, int N, int64_t rows, double* part, double* ke,
+                            hipStream_t s);
+// W[alpha, j] *= T(g_scale Lambda_alpha / ke[j]) (Teter-Payne-Allan factor).
+void launch_tpa_scale(double* W, int64_t ldw, int na, const double* ke, const double* lamh, int N,
+                      double g_scale, int64_t rows, hipStream_t s);
+// dst[:, j] = src[:, list[j]] for j < n.
+void launch_gather_cols(const double* src, int64_t lds, const int* list, int n, double* dst,
+                        int64_t ldd, int64_t rows, hipStream_t s);
+
 // Largest block Rayleigh-Ritz accepts (its pinned read-back stage is sized
 // for it when the Hamiltonian is created).
 constexpr int kRRMax = 32768;
@@ -335,4 +358,5 @@ struct ces_ham_s {
 
 namespace ces {
 ces_status check_ham(ces_ham hh);   // non-null and on the current device
+ces_status ensure_device(Basis& b);  // uploads the basis tables once (current device)
 }  // namespace ces
