@@ -210,6 +210,27 @@ ces_status ces_ham_set_model(ces_ham hh, int correlation, double smearing_kT, in
   return CES_OK;
 }
 
+ces_status ces_ham_set_density_basis(ces_ham hh, ces_basis bb) {
+  CES_TRY(check_ham(hh));
+  Ham& h = hh->h;
+  if (!bb) {
+    h.rho_basis = nullptr;
+    return CES_OK;
+  }
+  Basis& bd = bb->b;
+  const Basis& b = *h.basis;
+  if (bd.n_r != b.n_r || bd.n_theta != b.n_theta || bd.n_phi != b.n_phi || bd.R != b.R ||
+      bd.rule != b.rule)
+    return fail(CES_ERR_INVALID_ARG, "the density basis must use the orbitals' grid "
+                                     "(same R, n_r, n_theta, n_phi and radial rule)");
+  if (bd.L < b.L) return fail(CES_ERR_INVALID_ARG, "the density basis must have lmax >= the "
+                                                  "orbitals' lmax");
+  CES_TRY(ensure_device(bd));
+  if (bd.device != b.device) return fail(CES_ERR_INVALID_ARG, "bases on different devices");
+  h.rho_basis = &bd;
+  return CES_OK;
+}
+
 ces_status ces_pz_correlation(int64_t n, const double* d_rho, double* d_vc, double* d_ec,
                               void* stream) {
   if (n < 0) return fail(CES_ERR_INVALID_ARG, "negative length");
@@ -282,12 +303,14 @@ ces_status ces_ks_potential(ces_ham hh, const double* d_rho, const double* d_rho
   Layout ly;
   CES_TRY(check_work(h, 1, CES_PREC_FP64, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Basis& b = *h.basis;
+  // the density's coefficients in the orbitals' basis (dualing) or in the
+  // larger density basis on the same grid (Section 2.2.5)
+  const Basis& b = h.rho_basis ? *h.rho_basis : *h.basis;
   double* tau = d_tau ? d_tau : Ptr<double>::at(d_work, ly.V3);
   double* A = Ptr<double>::at(d_work, ly.A);
   double* gh = Ptr<double>::at(d_work, ly.gbuf);
   launch_sub(d_rho, d_rho_ion, d_v, b.n_grid, s);                  // d_v <- rho - rho_ion
-  launch_phi_analysis_one(b, d_v, gh, s);                          // dualing forward transform
+  launch_phi_analysis_one(b, d_v, gh, s);                          // forward transform
   launch_legendre_analysis<double>(b, b.t64, gh, A, kColPad, s);
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, tau, b.d, 1.0, 0.0, 0.0,
                                 false, nullptr, 1, kColPad, s);

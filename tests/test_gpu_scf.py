@@ -327,3 +327,76 @@ def test_scf_full_basis_heldout_cluster_matches_stored_oracle(prec):
     e = np.max(np.abs(ev[:n_occ] - ref[:n_occ]))
     _say(f"  atom err {e1:.2e} ({st1} steps); cluster max err {e:.2e} ({steps} steps)")
     assert e1 < 1e-6 and e < 1e-6
+
+
+# --------------------------------------------- non-dualing density basis
+
+def _density_basis(S):
+    """Library and oracle density bases on the orbitals' grid, l' <= 2(L-1)."""
+    w = S.w
+    Bd = ces.Basis(2 * (w.L - 1), w.N, w.R, w.n_r, w.n_theta, w.n_phi, w.radial_rule)
+    return Bd, od.density_basis_for(S.bs)
+
+
+def test_ks_potential_with_density_basis_matches_oracle(small):
+    """Section 2.2.5's larger density basis: the coefficients of rho - rho_ion
+    on it (l' up to 2(L-1)) and the potential built from them, against the
+    oracle's."""
+    _say("case ks_potential density basis")
+    Bd, bsd = _density_basis(small)
+    atoms = si.scf_cluster(3)[:6]
+    X = si.random_block(small.B.d, 6, 8) * 0.05
+    rho = od.density_grid(small.bs, X, np.ones(6))
+    vext = si.gaussian_wells(small.opts, atoms)
+    rion = si.ion_density(small.opts, atoms)
+    scf = osf.ClusterSCF(small.bs, atoms, vext, rion, 6, 4, density_basis=bsd)
+    ref = scf.potential(rho)
+    tau_ref = od.density_coefficients(bsd, rho - rion)
+    small.H.set_density_basis(Bd)
+    try:
+        work = small.H.workspace(1)
+        assert work.numel() >= small.work.numel()
+        v = torch.empty(small.B.n_grid, dtype=torch.float64, device="cuda")
+        tau = torch.empty(Bd.d, dtype=torch.float64, device="cuda")
+        small.H.ks_potential(_cuda(rho), _cuda(rion), _cuda(vext), v, work, tau=tau)
+        torch.cuda.synchronize()
+    finally:
+        small.H.set_density_basis(None)
+    ev = rel(v.cpu().numpy().reshape(ref.shape), ref)
+    et = rel(tau.cpu().numpy(), tau_ref)
+    hi = np.max(np.abs(tau_ref[(small.w.L ** 2) * small.w.N:]))
+    _say(f"  potential rel err {ev:.2e}, coefficients {et:.2e}, largest l' >= L part {hi:.2e}")
+    assert ev < 1e-11 and et < 1e-11
+    assert hi > 1e-6 * np.max(np.abs(tau_ref))     # the degrees beyond the orbital cutoff
+    # a basis on another grid is rejected
+    Bbad = ces.Basis(2 * (small.w.L - 1), small.w.N, small.w.R, small.w.n_r + 1,
+                     small.w.n_theta, small.w.n_phi, small.w.radial_rule)
+    with pytest.raises(ces.CesError) as e:
+        small.H.set_density_basis(Bbad)
+    assert e.value.status == 1
+
+
+def test_scf_with_density_basis_matches_oracle(small):
+    """SCF with the non-dualing density basis for the Hartree potential, GPU
+    against the oracle SCF with the same choice from the same ion-density
+    start, FP64, both converged to 1e-10."""
+    _say("case scf density basis")
+    Bd, bsd = _density_basis(small)
+    atoms = si.scf_cluster(1)[:5]
+    n_occ, n_guard = si.scf_occupation(len(atoms))
+    bs = small.bs
+    rion = si.ion_density(small.opts, atoms)
+    s = osf.ClusterSCF(bs, atoms, si.gaussian_wells(small.opts, atoms), rion, n_occ, n_guard,
+                       degree=SMALL.degree, density_basis=bsd)
+    th, st, _, _ = s.run(rion, si.random_block(bs.d, n_occ + n_guard, X0_SEED),
+                         v0=si.lanczos_start(bs.d), tol=1e-10, max_steps=100)
+    assert st < 100
+    small.H.set_density_basis(Bd)
+    try:
+        ev, steps, dth, _ = gpu_scf(small, atoms, n_occ, n_guard, None, X0_SEED,
+                                    ces.CES_PREC_FP64, 1e-10)
+    finally:
+        small.H.set_density_basis(None)
+    e = np.max(np.abs(ev[:n_occ] - th[:n_occ]))
+    _say(f"  max err {e:.2e} (gpu {steps} steps, oracle {st})")
+    assert dth[-1] < 1e-10 and e < 1e-8
