@@ -11,8 +11,9 @@ loss); this module sequences the calls and moves arrays.
             recomputed when training).
   train     fits the per-atom network to those clusters with Adam.
   evaluate  runs the SCF from SAD and from the learned start on held-out
-            clusters: step counts, converged-eigenvalue differences and the
-            start density's error relative to SAD's.
+            clusters, both to |delta theta| < 1e-8: step counts (also at
+            1e-6), converged-eigenvalue differences and the start density's
+            error relative to SAD's.
 
   python -m paper_1404_3773_amd.learned_start generate --first 0 --count 1000 --out a.npz
   python -m paper_1404_3773_amd.learned_start train --data a.npz b.npz --out w.npz
@@ -264,8 +265,21 @@ def learned_density(ctx, net, atoms, rho_sad=None):
 
 # ---------------------------------------------------------------- evaluate
 
-def evaluate(weights, first, count, out, data_out=None):
-    ctx = Context()
+def steps_to(dtheta, tol):
+    """SCF steps until the largest occupied eigenvalue change first fell below
+    tol (the run's own step count if it never did before it stopped)."""
+    for i, v in enumerate(dtheta):
+        if v < tol:
+            return i + 1
+    return len(dtheta)
+
+
+def evaluate(weights, first, count, out, data_out=None, tol=1e-8, count_tol=1e-6):
+    """Both SCFs (SAD start, learned start) run to |delta theta| < tol; the
+    step counts are reported at tol and at count_tol (the first step whose
+    change fell below it), and the converged eigenvalues of the two runs are
+    compared at tol."""
+    ctx = Context(tol=tol)
     net = load_network(weights)
     rows = []
     rec = {k: [] for k in ("seed", "n", "atoms", "p", "t", "steps", "eig", "last_dtheta")}
@@ -282,6 +296,9 @@ def evaluate(weights, first, count, out, data_out=None):
         c = coef.cpu().numpy().astype(np.float64).reshape(-1)
         rel_err = (c @ M @ c - 2 * p @ c + t) / t
         rows.append({"seed": s, "n": len(atoms), "steps_sad": st_s, "steps_learned": st_l,
+                     "steps_sad_at_count_tol": steps_to(dth_s, count_tol),
+                     "steps_learned_at_count_tol": steps_to(dth_l, count_tol),
+                     "converged": bool(dth_s[-1] < tol and dth_l[-1] < tol),
                      "max_eig_diff": float(np.max(np.abs(ev_s[:n_occ] - ev_l[:n_occ]))),
                      "start_rel_sq_err": float(rel_err)})
         for k, v in (("seed", s), ("n", len(atoms)), ("atoms", atoms.reshape(-1)), ("p", p),
@@ -293,13 +310,20 @@ def evaluate(weights, first, count, out, data_out=None):
                  f"{np.mean([r['steps_learned'] for r in rows]):.2f}")
     ss = np.array([r["steps_sad"] for r in rows])
     sl = np.array([r["steps_learned"] for r in rows])
+    cs = np.array([r["steps_sad_at_count_tol"] for r in rows])
+    cl = np.array([r["steps_learned_at_count_tol"] for r in rows])
+    diffs = np.array([r["max_eig_diff"] for r in rows])
     summary = {
-        "clusters": count, "tol": ctx.tol,
+        "clusters": count, "tol": ctx.tol, "count_tol": count_tol,
+        "all_converged": bool(all(r["converged"] for r in rows)),
         "mean_steps_sad": float(ss.mean()), "mean_steps_learned": float(sl.mean()),
         "median_steps_sad": float(np.median(ss)), "median_steps_learned": float(np.median(sl)),
         "fraction_fewer": float(np.mean(sl < ss)), "fraction_more": float(np.mean(sl > ss)),
+        "mean_steps_sad_at_count_tol": float(cs.mean()),
+        "mean_steps_learned_at_count_tol": float(cl.mean()),
         "hist_sad": np.bincount(ss).tolist(), "hist_learned": np.bincount(sl).tolist(),
-        "max_eig_diff": float(max(r["max_eig_diff"] for r in rows)),
+        "max_eig_diff": float(diffs.max()),
+        "clusters_eig_diff_above_1e-6": int(np.sum(diffs > 1e-6)),
         "median_start_rel_sq_err": float(np.median([r["start_rel_sq_err"] for r in rows])),
         "per_cluster": rows,
     }
@@ -334,13 +358,15 @@ def main(argv=None):
     e.add_argument("--count", type=int, default=200)
     e.add_argument("--out", required=True)
     e.add_argument("--data-out")
+    e.add_argument("--tol", type=float, default=1e-8)
+    e.add_argument("--count-tol", type=float, default=1e-6)
     a = ap.parse_args(argv)
     if a.cmd == "generate":
         generate(a.first, a.count, a.out)
     elif a.cmd == "train":
         train(a.data, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr, val_file=a.val)
     else:
-        evaluate(a.weights, a.first, a.count, a.out, a.data_out)
+        evaluate(a.weights, a.first, a.count, a.out, a.data_out, a.tol, a.count_tol)
 
 
 if __name__ == "__main__":

@@ -196,36 +196,33 @@ def _weights():
 
 @pytest.mark.timeout(600)
 def test_learned_start_cuts_scf_steps_with_unchanged_eigenvalues():
+    """Eight held-out clusters, both SCFs (SAD start and learned start)
+    converged to |delta theta| < 1e-8 Ha: the learned start takes fewer steps
+    in total, and on every cluster the converged occupied eigenvalues of the
+    two runs agree within 1e-6 Ha (the same stopping rule for both)."""
     import os
     from paper_1404_3773_amd import learned_start as ls
     if not os.path.exists(_weights()):
         pytest.skip("trained network weights not present")
-    ctx = ls.Context()
+    ctx = ls.Context(tol=1e-8)
     net = ls.load_network(_weights())
     seeds = [si.HELDOUT_SEED0 + i for i in range(8)]
-    steps_sad, steps_learned = [], []
+    steps_sad, steps_learned, diffs = [], [], []
     for s in seeds:
         atoms = si.scf_cluster(s)
         fields = ctx.fields(atoms)
         rho_sad = ctx.sad(atoms)
         n_occ, _ = si.scf_occupation(len(atoms))
-        ev_s, st_s, _, _ = ctx.scf(atoms, rho_sad, fields=fields)
+        ev_s, st_s, dth_s, _ = ctx.scf(atoms, rho_sad, fields=fields)
         rho_l, _, _ = ls.learned_density(ctx, net, atoms, rho_sad)
-        ev_l, st_l, _, _ = ctx.scf(atoms, rho_l, fields=fields)
-        _say(f"case held-out seed {s} ({len(atoms)} atoms): steps SAD {st_s}, learned {st_l}, "
-             f"max eigenvalue difference {np.max(np.abs(ev_s[:n_occ] - ev_l[:n_occ])):.1e}")
+        ev_l, st_l, dth_l, _ = ctx.scf(atoms, rho_l, fields=fields)
+        d = float(np.max(np.abs(ev_s[:n_occ] - ev_l[:n_occ])))
+        _say(f"case held-out seed {s} ({len(atoms)} atoms): steps SAD {st_s}, learned {st_l} "
+             f"(to 1e-6: {ls.steps_to(dth_s, 1e-6)}, {ls.steps_to(dth_l, 1e-6)}); "
+             f"max eigenvalue difference {d:.1e}")
+        assert dth_s[-1] < 1e-8 and dth_l[-1] < 1e-8
         steps_sad.append(st_s)
         steps_learned.append(st_l)
+        diffs.append(d)
     assert sum(steps_learned) < sum(steps_sad)
-    # converged to 1e-10, both starts give the same eigenvalues
-    tight = ls.Context(tol=1e-10)
-    atoms = si.scf_cluster(seeds[0])
-    fields = tight.fields(atoms)
-    rho_sad = tight.sad(atoms)
-    n_occ, _ = si.scf_occupation(len(atoms))
-    ev_s, _, _, _ = tight.scf(atoms, rho_sad, fields=fields)
-    ev_l, _, _, _ = tight.scf(atoms, ls.learned_density(tight, net, atoms, rho_sad)[0],
-                              fields=fields)
-    d = np.max(np.abs(ev_s[:n_occ] - ev_l[:n_occ]))
-    _say(f"  tight: max eigenvalue difference {d:.1e}")
-    assert d < 1e-8
+    assert max(diffs) <= 1e-6
