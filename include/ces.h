@@ -330,6 +330,16 @@ ces_status ces_fermi_dirac(int k, const double* h_eval, double n_electrons, doub
  * n < 0 or a null pointer is CES_ERR_INVALID_ARG.  Asynchronous. */
 ces_status ces_slater_x(int64_t n, const double* d_rho, double* d_vx, void* stream);
 
+/* Eigensolver of the handle's ces_scf: mode 0 (default) Chebyshev-filtered
+ * subspace iteration in every step, started with Rayleigh-Ritz and
+ * first_iters filters; mode 1 LOBPCG (ces_lobpcg with the preconditioner,
+ * all k states to res_tol, at most max_iter iterations) in the first SCF
+ * step and the filter afterwards (the paper's strategy for large systems,
+ * Section 3.2); mode 2 LOBPCG in every step (its strategy for small ones,
+ * Section 3.1).  Workspace sizes queried afterwards include LOBPCG's.  Like
+ * ces_ham_set_veff, must not overlap other calls on the handle. */
+ces_status ces_ham_set_scf_eigensolver(ces_ham h, int mode, double res_tol, int max_iter);
+
 /* Non-dualing density (Section 2.2.5): the density of orbitals with
  * l <= lmax holds angular degrees up to 2 lmax, so the paper lets it be
  * expanded in a larger basis than the orbitals.  After this call the
@@ -391,7 +401,8 @@ ces_status ces_sad_density(ces_ham h, int n_atoms, const double* h_atoms,
  *   V_eff = V_in; b = ces_lanczos_bound(d_v0, 20 steps);
  *   step 1: Rayleigh-Ritz of d_X, then first_iters x (filter + RR);
  *   later steps: one filter (degree, prec; a = theta_k, a0 = theta_1) + RR
- *   (Rayleigh-Ritz always with FP64 H*X);
+ *   (Rayleigh-Ritz always with FP64 H*X); or LOBPCG in the first or in
+ *   every step (ces_ham_set_scf_eigensolver);
  *   rho = density of d_X; V_out = ks_potential(rho);
  *   stop when max_{i < n_occ} |theta_i - theta_i(previous step)| < tol;
  *   else V_in = ces_anderson_mix over the last `hist` pairs (V_in, V_out - V_in).

@@ -30,6 +30,7 @@ EXPORTS = [
     "ces_density", "ces_to_grid", "ces_from_grid",
     "ces_coeffs_complex_to_real", "ces_coeffs_real_to_complex", "ces_slater_x",
     "ces_pz_correlation", "ces_fermi_dirac", "ces_ham_set_model", "ces_ham_set_density_basis",
+    "ces_ham_set_scf_eigensolver",
     "ces_hartree", "ces_ks_potential", "ces_anderson_workspace_size", "ces_anderson_mix",
     "ces_sad_density", "ces_scf_workspace_size", "ces_scf",
     "ces_atom_descriptors", "ces_density_fit_workspace_size", "ces_density_fit_gram",
@@ -87,6 +88,7 @@ def load() -> ctypes.CDLL:
         "ces_pz_correlation": [I64, P, P, P, P],
         "ces_ham_set_model": [P, I, D, I],
         "ces_ham_set_density_basis": [P, P],
+        "ces_ham_set_scf_eigensolver": [P, I, D, I],
         "ces_fermi_dirac": [I, P, D, D, P, ctypes.POINTER(D)],
         "ces_hartree": [P, P, P, P, SZ, P],
         "ces_ks_potential": [P, P, P, P, P, P, P, SZ, P],
@@ -411,6 +413,12 @@ class Ham:
         Anderson mixing of the density instead of the potential."""
         _check(load().ces_ham_set_model(self._h, int(correlation), float(smearing_kT),
                                         int(mix_density)), "ces_ham_set_model")
+
+    def set_scf_eigensolver(self, mode=0, res_tol=1e-6, max_iter=200):
+        """ces_scf eigensolver: 0 CheFSI, 1 LOBPCG in the first step, 2 LOBPCG
+        in every step."""
+        _check(load().ces_ham_set_scf_eigensolver(self._h, int(mode), float(res_tol),
+                                                  int(max_iter)), "ces_ham_set_scf_eigensolver")
 
     def set_density_basis(self, basis):
         """Expand the density for the Hartree potential in `basis` (a Basis on

@@ -77,6 +77,9 @@ struct Ham {
   double smear_kT = 0.0;     // ces_scf: Fermi-Dirac occupations at kT when > 0
   int mix_density = 0;       // ces_scf: Anderson-mix rho instead of V_eff
   Basis* rho_basis = nullptr;  // density basis on the same grid (non-dualing), or null
+  int scf_solver = 0;         // ces_scf eigensolver: 0 CheFSI, 1 LOBPCG first step, 2 LOBPCG
+  double lobpcg_tol = 1e-6;   // LOBPCG residual tolerance inside ces_scf
+  int lobpcg_max_iter = 200;
   size_t solver_ws = 0;     // device bytes rocSOLVER needs for k = kmax_query
   int solver_ws_k = 0;
   void* dev_block = nullptr;
@@ -147,6 +150,8 @@ ces_status rr_impl(Ham& h, const Layout& ly, void* work, int k, double* X, int64
 ces_status rr_locked(Ham& h, const Layout& ly, void* work, int k, double* X, int64_t ldx,
                      double* HX, int64_t ldhx, double* eval, double* res, int hx_prec,
                      hipStream_t s, double* h_eval, double* h_res, int* h_path);
+// Workspace bytes of ces_lobpcg for k columns (takes h.mu).
+size_t lobpcg_workspace_bytes(Ham& h, int k, int n_lock, int prec);
 // Device bytes rocSOLVER needs for potrf/trtri/syevd of order k (cached per
 // handle; takes h.mu).
 size_t solver_bytes_for(Ham& h, int k);

@@ -177,6 +177,11 @@ struct Lob {
 };
 
 }  // namespace
+
+size_t lobpcg_workspace_bytes(Ham& h, int k, int n_lock, int prec) {
+  return lob_layout(h, k, n_lock, prec).total;
+}
+
 }  // namespace ces
 
 using namespace ces;

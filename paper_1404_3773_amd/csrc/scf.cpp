@@ -100,6 +100,7 @@ ces_status scf_layout(Ham& h, int k, int prec, int hist, ScfLayout& L) {
   b1 = layout_for(h, k, prec).total;
   b2 = layout_for(h, k, CES_PREC_FP64).total;
   b3 = layout_for(h, 1, CES_PREC_FP64).total;
+  if (h.scf_solver != 0) b3 = std::max(b3, lobpcg_workspace_bytes(h, k, 0, prec));
   const size_t ng = size_t(h.basis->n_grid);
   size_t off = align256(std::max(b1, std::max(b2, b3)));
   L.base = off;
@@ -207,6 +208,17 @@ ces_status ces_ham_set_model(ces_ham hh, int correlation, double smearing_kT, in
   hh->h.xc_correlation = correlation;
   hh->h.smear_kT = smearing_kT;
   hh->h.mix_density = mix_density;
+  return CES_OK;
+}
+
+ces_status ces_ham_set_scf_eigensolver(ces_ham hh, int mode, double res_tol, int max_iter) {
+  CES_TRY(check_ham(hh));
+  if (mode < 0 || mode > 2) return fail(CES_ERR_INVALID_ARG, "eigensolver mode must be 0, 1 or 2");
+  if (!(res_tol > 0) || !std::isfinite(res_tol) || max_iter < 1)
+    return fail(CES_ERR_INVALID_ARG, "LOBPCG tolerance must be > 0 and max_iter >= 1");
+  hh->h.scf_solver = mode;
+  hh->h.lobpcg_tol = res_tol;
+  hh->h.lobpcg_max_iter = max_iter;
   return CES_OK;
 }
 
@@ -472,7 +484,18 @@ ces_status ces_scf(ces_ham hh, int k, double* d_X, int64_t ldx, int n_occ, const
                                 CES_PREC_FP64, ew, ewb, stream));
       return CES_OK;
     };
-    if (step == 1) {
+    // LOBPCG to the handle's residual tolerance on all k states (Section 3.1):
+    // in the first step only (h.scf_solver == 1), or in every step (2)
+    auto lobpcg = [&]() -> ces_status {
+      int its = 0;
+      CES_TRY(ces_lobpcg(hh, k, d_X, ldx, 0, nullptr, 0, k, h.lobpcg_max_iter, h.lobpcg_tol, 1.0,
+                         1, prec, d_eval, res, &its, nullptr, ew, ewb, stream));
+      CES_HIP(hipMemcpy(theta.data(), d_eval, size_t(k) * 8, hipMemcpyDeviceToHost));
+      return CES_OK;
+    };
+    if (h.scf_solver == 2 || (step == 1 && h.scf_solver == 1)) {
+      CES_TRY(lobpcg());
+    } else if (step == 1) {
       CES_TRY(ces_rayleigh_ritz(hh, k, d_X, ldx, nullptr, d_eval, res, theta.data(), nullptr,
                                 CES_PREC_FP64, ew, ewb, stream));
       for (int it = 0; it < first_iters; ++it) CES_TRY(filter_rr());

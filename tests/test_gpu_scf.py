@@ -400,3 +400,31 @@ def test_scf_with_density_basis_matches_oracle(small):
     e = np.max(np.abs(ev[:n_occ] - th[:n_occ]))
     _say(f"  max err {e:.2e} (gpu {steps} steps, oracle {st})")
     assert dth[-1] < 1e-10 and e < 1e-8
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_scf_with_lobpcg_reaches_the_oracle_fixed_point(small, mode):
+    """ces_scf with LOBPCG in the first SCF step (mode 1, then the filter) or
+    in every step (mode 2) (Sections 3.1, 3.2): the self-consistent
+    eigenvalues do not depend on the eigensolver, so they equal the oracle
+    SCF's (Chebyshev filter) within 1e-8 Ha, both converged to 1e-10."""
+    _say(f"case scf lobpcg mode={mode}")
+    atoms = si.scf_cluster(1)[:5]
+    n_occ, n_guard = si.scf_occupation(len(atoms))
+    bs = small.bs
+    rion = si.ion_density(small.opts, atoms)
+    s = osf.ClusterSCF(bs, atoms, si.gaussian_wells(small.opts, atoms), rion, n_occ, n_guard,
+                       degree=SMALL.degree)
+    th, st, _, _ = s.run(rion, si.random_block(bs.d, n_occ + n_guard, X0_SEED),
+                         v0=si.lanczos_start(bs.d), tol=1e-10, max_steps=100)
+    small.H.set_scf_eigensolver(mode, res_tol=1e-9, max_iter=300)
+    try:
+        ev, steps, dth, _ = gpu_scf(small, atoms, n_occ, n_guard, None, X0_SEED,
+                                    ces.CES_PREC_FP64, 1e-10)
+    finally:
+        small.H.set_scf_eigensolver(0)
+    e = np.max(np.abs(ev[:n_occ] - th[:n_occ]))
+    _say(f"  max err {e:.2e} (gpu {steps} steps, oracle {st})")
+    assert dth[-1] < 1e-10 and e < 1e-8
+    with pytest.raises(ces.CesError):
+        small.H.set_scf_eigensolver(3)
