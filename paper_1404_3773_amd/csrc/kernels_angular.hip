@@ -194,6 +194,129 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
     }
 }
 
+// Folded form (L > 32).  The theta nodes come in mirror pairs t_{n-1-j} = -t_j
+// and P_l^m(-t) = (-1)^{l+m} P_l^m(t), so with E(j) the sum over l + m even
+// and O(j) over l + m odd, g(j) = E(j) + O(j) and g(n-1-j) = E(j) - O(j) for
+// the nodes j < nh = ceil(n_theta / 2): half the MFMA work and half the table
+// reads of the direct sum.  Workgroup: one m-slot, 4 waves x JT 16-row tiles
+// of the first half, 16 NT columns of one radial node; a k-step takes four l
+// of one parity, l = m + par + 2 (4t + kk); steps go in chunks of CH with the
+// next chunk's operands in flight while the current one runs on MFMA.
+template <typename T, int NT, int JT, int CH>
+__global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict__ Pm,
+                                                             const T* __restrict__ G,
+                                                             T* __restrict__ g, AngDims D,
+                                                             int n_ic, int nh) {
+  typedef typename MF<T>::acc acc_t;
+  const int s = blockIdx.z;
+  int m, sgn;
+  slot_to_m(s, D.L, m, sgn);
+  const int r = blockIdx.x / n_ic;
+  const int i0 = (blockIdx.x - r * n_ic) * (16 * NT);
+  const int nt_valid = min(NT, (D.kp - i0) / 16);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int tile0 = (blockIdx.y * 4 + wave) * JT;
+  if (tile0 * 16 >= nh) return;   // no barriers in this kernel
+  int jt[JT];
+  const T* Pa[JT];
+#pragma unroll
+  for (int u = 0; u < JT; ++u) {
+    jt[u] = (tile0 + u) * 16;
+    Pa[u] = Pm + (static_cast<int64_t>(m) * (D.L + 4)) * D.J64 + min(jt[u], D.J64 - 16) + l16;
+  }
+  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
+  int col[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) col[nt] = min(nt * 16, D.kp - i0 - 16);
+  acc_t E[JT][NT], O[JT][NT];
+#pragma unroll
+  for (int u = 0; u < JT; ++u)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      E[u][nt] = zero_acc<acc_t>();
+      O[u][nt] = zero_acc<acc_t>();
+    }
+  const int K = D.L - m;
+  const int nE = ((K + 1) / 2 + 3) / 4, nO = (K / 2 + 3) / 4;
+  const int nst = nE + nO;
+  // step st: parity par = (st >= nE), t = st - par nE; rows l >= L read row
+  // L - 1 and are masked at the MFMA
+  auto lrow = [&](int st) {
+    const int par = st >= nE ? 1 : 0;
+    const int t = st - par * nE;
+    return m + par + 8 * t + 2 * kk;
+  };
+  auto load = [&](int st, T (&a)[JT], T (&b)[NT]) __attribute__((always_inline)) {
+    const int lc = min(lrow(st), D.L - 1);
+#pragma unroll
+    for (int u = 0; u < JT; ++u) a[u] = Pa[u][lc * D.J64];
+    const int64_t off = static_cast<int64_t>(lc * lc + lc + sgn * m) * D.kp;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = Gr[off + col[nt]];
+  };
+  // CH steps per chunk, all loaded before the chunk's MFMAs; the next chunk
+  // is in flight while the current one runs
+  auto mma_step = [&](int st, const T (&a)[JT], const T (&b)[NT]) __attribute__((always_inline)) {
+    const bool ok = st < nst && lrow(st) < D.L;
+    if (st < nE) {
+#pragma unroll
+      for (int u = 0; u < JT; ++u) {
+        const T av = ok ? a[u] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) E[u][nt] = MF<T>::mma(av, b[nt], E[u][nt]);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < JT; ++u) {
+        const T av = ok ? a[u] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) O[u][nt] = MF<T>::mma(av, b[nt], O[u][nt]);
+      }
+    }
+  };
+  const int nch = (nst + CH - 1) / CH;
+  T ca[CH][JT], cb[CH][NT], na[CH][JT], nb[CH][NT];
+#pragma unroll
+  for (int t = 0; t < CH; ++t) load(min(t, nst - 1), ca[t], cb[t]);
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) load(min((c + 1) * CH + t, nst - 1), na[t], nb[t]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) mma_step(c * CH + t, ca[t], cb[t]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+#pragma unroll
+      for (int u = 0; u < JT; ++u) ca[t][u] = na[t][u];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) cb[t][nt] = nb[t][nt];
+    }
+  }
+  T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
+  const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
+#pragma unroll
+  for (int u = 0; u < JT; ++u)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (nt >= nt_valid) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = jt[u] + MF<T>::row(lane, v);
+        if (j < nh) {
+          const T e = E[u][nt][v], o = O[u][nt][v];
+          gr[j * jstride + nt * 16] = e + o;
+          const int jm = D.n_theta - 1 - j;
+          if (jm != j) gr[jm * jstride + nt * 16] = e - o;
+        }
+      }
+    }
+}
+
 // ------------------------------------------------------------ phi_stage
 
 // Coupling of input slot s into output slot so of the phi stage: with
@@ -466,6 +589,137 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
   }
 }
 
+// Folded form (L > 32).  With mirror nodes t_{n-1-j} = -t_j, equal weights
+// and P_l^m(-t) = (-1)^{l+m} P_l^m(t),
+//   A(l,m) = sum_{j < nh} w_j P_l^m(t_j) [gh(j) + (-1)^{l+m} gh(n-1-j)],
+// (the middle node of an odd n_theta taken once), so the l + m even rows
+// contract the sums u(j) = gh(j) + gh(n-1-j) and the odd rows the differences
+// v(j) over the first half of the nodes: half the MFMA work of the direct
+// sum.  One m-slot per wave; ME / MO 16-row l-tiles of each parity (rows
+// l = m + par + 2 (16 tile + lane row)); theta in k-steps of four, CH steps
+// per chunk with the next chunk's operands in flight.
+template <typename T, int MH, int CH>
+__global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restrict__ PwT,
+                                                                const T* __restrict__ g,
+                                                                T* __restrict__ A, AngDims D,
+                                                                int n_ic, int nh) {
+  typedef typename MF<T>::acc acc_t;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = blockIdx.y * LA_SW + wave;
+  if (s >= D.S) return;
+  int m, sgn;
+  slot_to_m(s, D.L, m, sgn);
+  const int r = blockIdx.x / n_ic;
+  const int l16 = lane & 15, kk = lane >> 4;
+  const int i0 = (blockIdx.x - r * n_ic) * (16 * LA_NT);
+  const int nt_valid = min(LA_NT, (D.kp - i0) / 16);
+  const int K = D.L - m;
+  const int nme = ((K + 1) / 2 + 15) / 16, nmo = (K / 2 + 15) / 16;   // <= MH each
+  const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
+  const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp;
+  int col[LA_NT];
+#pragma unroll
+  for (int nt = 0; nt < LA_NT; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
+  // table entry [m][j][q] = w_j P_{m+q}^m(t_j); row q = par + 2 (16 u + l16),
+  // clamped into the padded row and masked where q >= K
+  const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16;
+  int qe[MH], qo[MH];
+#pragma unroll
+  for (int u = 0; u < MH; ++u) {
+    qe[u] = 2 * (16 * u + l16);
+    qo[u] = qe[u] + 1;
+  }
+  acc_t ae[MH][LA_NT], ao[MH][LA_NT];
+#pragma unroll
+  for (int u = 0; u < MH; ++u)
+#pragma unroll
+    for (int nt = 0; nt < LA_NT; ++nt) {
+      ae[u][nt] = zero_acc<acc_t>();
+      ao[u][nt] = zero_acc<acc_t>();
+    }
+  const int nst = (nh + 3) / 4;
+  // step t: node j = 4t + kk (rows past nh read node nh - 1, zero weight)
+  auto load = [&](int t, T (&a)[2][MH], T (&bu)[LA_NT], T (&bv)[LA_NT])
+      __attribute__((always_inline)) {
+    const int j = min(4 * t + kk, nh - 1);
+    const int jm = D.n_theta - 1 - j;
+#pragma unroll
+    for (int u = 0; u < MH; ++u) {
+      if (u < nme) a[0][u] = Pa[j * D.L16 + min(qe[u], D.L16 - 1)];
+      if (u < nmo) a[1][u] = Pa[j * D.L16 + min(qo[u], D.L16 - 1)];
+    }
+#pragma unroll
+    for (int nt = 0; nt < LA_NT; ++nt) {
+      const T x = gb[j * jstride + col[nt]];
+      const T y = gb[jm * jstride + col[nt]];
+      const bool mid = jm == j;
+      bu[nt] = mid ? x : x + y;
+      bv[nt] = mid ? T(0) : x - y;
+    }
+  };
+  auto mma_step = [&](int t, const T (&a)[2][MH], const T (&bu)[LA_NT], const T (&bv)[LA_NT])
+      __attribute__((always_inline)) {
+    const bool okj = 4 * t + kk < nh;
+#pragma unroll
+    for (int u = 0; u < MH; ++u) {
+      if (u < nme) {
+        const T av = okj && qe[u] < K ? a[0][u] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < LA_NT; ++nt) ae[u][nt] = MF<T>::mma(av, bu[nt], ae[u][nt]);
+      }
+      if (u < nmo) {
+        const T av = okj && qo[u] < K ? a[1][u] : T(0);
+#pragma unroll
+        for (int nt = 0; nt < LA_NT; ++nt) ao[u][nt] = MF<T>::mma(av, bv[nt], ao[u][nt]);
+      }
+    }
+  };
+  // CH steps per chunk, loaded together, the next chunk in flight
+  const int nch = (nst + CH - 1) / CH;
+  T ca[CH][2][MH], cu[CH][LA_NT], cv[CH][LA_NT], na[CH][2][MH], nu[CH][LA_NT], nv[CH][LA_NT];
+#pragma unroll
+  for (int t = 0; t < CH; ++t) load(t, ca[t], cu[t], cv[t]);
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) load((c + 1) * CH + t, na[t], nu[t], nv[t]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) mma_step(c * CH + t, ca[t], cu[t], cv[t]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+#pragma unroll
+      for (int u = 0; u < MH; ++u) {
+        ca[t][0][u] = na[t][0][u];
+        ca[t][1][u] = na[t][1][u];
+      }
+#pragma unroll
+      for (int nt = 0; nt < LA_NT; ++nt) {
+        cu[t][nt] = nu[t][nt];
+        cv[t][nt] = nv[t][nt];
+      }
+    }
+  }
+  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
+#pragma unroll
+  for (int u = 0; u < MH; ++u) {
+#pragma unroll
+    for (int nt = 0; nt < LA_NT; ++nt) {
+      if (nt >= nt_valid) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = 2 * (16 * u + MF<T>::row(lane, v));
+        const int le = m + q, lo = le + 1;
+        if (u < nme && le < D.L) Ar[(le * le + le + sgn * m) * D.kp + i0 + nt * 16] = ae[u][nt][v];
+        if (u < nmo && lo < D.L) Ar[(lo * lo + lo + sgn * m) * D.kp + i0 + nt * 16] = ao[u][nt][v];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- density
 
 // Density from the Legendre-synthesis output g[r][j][s][i] (Section 2.2.5):
@@ -699,6 +953,19 @@ template <typename T>
 void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* gbuf, int kp,
                            hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
+  if (b.L > 32) {
+    // folded in theta: one 16-row tile of the first half of the nodes per wave
+    const int nh = (b.n_theta + 1) / 2;
+    const int ntile = (nh + 15) / 16;
+    constexpr int CH = sizeof(T) == 4 ? 8 : 4;
+    auto go = [&](auto nt_tag, int n_ic) {
+      constexpr int NT = decltype(nt_tag)::value;
+      dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
+      k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+    };
+    if (kp <= 32) return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
+    return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
+  }
   // two column tiles when the block is narrow (no idle MFMA columns), else four
   // (K loops of up to 8 k-steps, L <= 32, load all their operands at once;
   // up to 16 (L <= 64) in FP32, where the registers allow it)
@@ -770,6 +1037,16 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   constexpr bool f32 = sizeof(T) == 4;
+  if (b.L > 32) {   // folded in theta; l-tiles of each parity cover ceil(L/2)
+    const int nh = (b.n_theta + 1) / 2;
+    if (b.L <= 64)
+      k_legendre_analysis_fold<T, 2, f32 ? 4 : 2><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic,
+                                                                       nh);
+    else
+      k_legendre_analysis_fold<T, 3, f32 ? 4 : 2><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic,
+                                                                       nh);
+    return;
+  }
   // l-tiles per slot cover L; theta chunks sized to the registers left
   if (b.L <= 32) {
     if (b.n_theta <= 64)

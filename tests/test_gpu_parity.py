@@ -87,6 +87,10 @@ MID_SHAPE = si.small(20, 30, R=11.0, n_r=45, n_theta=70, n_phi=80, k=17)
 # 32 < L <= 64 with four-tile column blocks and two 64-row theta groups (the FP32
 # synthesis taking both groups per workgroup)
 WIDE_L36 = si.small(36, 6, R=10.0, k=40)
+# L > 32 with an odd n_theta: the theta-folded Legendre kernels' middle node,
+# five 16-row tiles of the first half (two per wave), 3 l-tiles per parity
+ODD_L81 = si.small(81, 3, R=10.0, n_r=6, n_theta=163, n_phi=324, k=9)
+ODD_L40 = si.small(40, 5, R=10.0, n_r=8, n_theta=81, n_phi=160, k=20)
 
 
 def rel_err(got, ref):
@@ -95,9 +99,10 @@ def rel_err(got, ref):
 
 @pytest.mark.parametrize("w,k", [(SMALL, 1), (SMALL, 5), (SMALL, 17), (SMALL, 70),
                                  (ODD_THETA, 3), (LONG_RADIAL, 4), (MID_SHAPE, 17),
-                                 (WIDE_L36, 40)],
+                                 (WIDE_L36, 40), (ODD_L40, 20), (ODD_L81, 9)],
                          ids=["small_k1", "small_k5", "small_k17", "small_k70",
-                              "odd_theta", "N70", "L20_nr45_ntheta70", "L36_k40"])
+                              "odd_theta", "N70", "L20_nr45_ntheta70", "L36_k40",
+                              "L40_odd_theta", "L81_odd_theta"])
 def test_apply_H_fp64_and_mixed(w, k):
     _say(f"case apply_H {w.name} k={k}")
     s = setup(w)
