@@ -229,6 +229,23 @@ def basis_for(w) -> Basis:
     return make_basis(w.L, w.N, w.R, w.n_r, w.n_theta, w.n_phi, w.radial_rule)
 
 
+def ke_cutoff_counts(bs: Basis, e_cut: float) -> np.ndarray:
+    """Radial functions kept per l by a kinetic-energy cutoff (the non-uniform
+    basis of the footnote in Section 2.2.1): N_l = #{n < N : Lambda_ln / 2 <=
+    e_cut}.  Lambda_ln grows with n, so the kept ones are n = 0 .. N_l - 1."""
+    return np.array([int(np.sum(0.5 * (bs.b[l] / bs.R) ** 2 <= e_cut)) for l in range(bs.L)])
+
+
+def ke_cutoff_index(bs: Basis, e_cut: float) -> np.ndarray:
+    """Positions, in the uniform layout, of the functions the cutoff keeps, in
+    the order of the cutoff basis's own layout (l, then m, then n, as in the
+    uniform one): a coefficient vector of the cutoff basis is the uniform one
+    restricted to these entries."""
+    Nl = ke_cutoff_counts(bs, e_cut)
+    return np.array([index(l, m, n, bs.N) for l in range(bs.L) for m in range(-l, l + 1)
+                     for n in range(Nl[l])], dtype=np.int64)
+
+
 def basis_matrix_complex(bs: Basis) -> np.ndarray:
     """B[g, alpha] = F_alpha(x_g) on the grid (flattened [r][theta][phi]);
     small bases only."""

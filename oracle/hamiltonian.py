@@ -135,6 +135,18 @@ def apply_H_real(bs: Basis, V: np.ndarray, X: np.ndarray,
     return Z[:, 0] if one else Z
 
 
+def apply_H_subset(bs: Basis, V: np.ndarray, kept: np.ndarray, X: np.ndarray,
+                   proj: np.ndarray | None = None, h=None) -> np.ndarray:
+    """H X in the basis of the functions `kept` (uniform-layout positions, e.g.
+    a kinetic-energy cutoff): the operator of a subset of an orthonormal basis
+    is the submatrix of H, so X is placed at those positions, H is applied and
+    the same positions are read back.  proj: uniform-layout projector
+    coefficients (their restriction is the subset's own)."""
+    Xf = np.zeros((bs.d, X.shape[1]))
+    Xf[kept] = X
+    return apply_H_real(bs, V, Xf, proj=proj, h=h)[kept]
+
+
 def to_grid_real(bs: Basis, X: np.ndarray) -> np.ndarray:
     """Real-layout coefficients -> real grid values (n_r, n_theta, n_phi, k)."""
     f = inverse_transform(bs, real_to_complex(np.atleast_2d(X.T).T, bs.L, bs.N))
