@@ -36,7 +36,10 @@ struct KbShape<double> {  // wave tile 64 x 32, workgroup 128 x 64, 32 alpha per
 };
 constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 
-template <typename T>
+// With DB the P and Y tiles are double-buffered in (dynamic) LDS: a step
+// computes from one buffer while the next step's tiles are written into the
+// other, so it takes one barrier instead of two.
+template <typename T, bool DB>
 __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_t d,
                                                  int64_t ldp, const T* __restrict__ Y,
                                                  int64_t ldy,
@@ -48,8 +51,9 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   constexpr int KW = KB + 1;                     // padded LDS row
   constexpr int RA = 256 / KB;                   // tile rows loaded per pass
   constexpr int LA = BM / RA, LB = BN / RA;      // passes for the P and Y tiles
-  __shared__ T As[BM * KW];
-  __shared__ T Bs[BN * KW];
+  constexpr int STAGE = (BM + BN) * KW;          // one buffer: A tile then B tile
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  T* const lds = reinterpret_cast<T*>(kb_smem);
   // workgroup id -> (XCD x, position j on it) -> (group g = chunk and M tile, N tile)
   const int id = blockIdx.x;
   const int x = id & 7, j = id >> 3;
@@ -89,10 +93,10 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   for (int u = 0; u < TM; ++u)
 #pragma unroll
     for (int v = 0; v < TN; ++v) acc[u][v] = zero_acc<acc_t>();
-  const T* Aw = As + (wm * 16 * TM + c16) * KW + kk;
-  const T* Bw = Bs + (wn * 16 * TN + c16) * KW + kk;
-  if (k0 < k1) fetch(k0);
-  for (int64_t kb = k0; kb < k1; kb += KB) {
+  // the staged tiles of step kb into buffer `buf`
+  auto stage = [&](int64_t kb, int buf) __attribute__((always_inline)) {
+    T* As = lds + buf * STAGE;
+    T* Bs = As + BM * KW;
     const bool okk = kb + kc < k1;
 #pragma unroll
     for (int p = 0; p < LA; ++p)
@@ -100,8 +104,10 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 #pragma unroll
     for (int p = 0; p < LB; ++p)
       Bs[(r0 + RA * p) * KW + kc] = okk && bcol0 + RA * p < k ? rb[p] : T(0);
-    __syncthreads();
-    if (kb + KB < k1) fetch(kb + KB);          // next step's tiles, in flight
+  };
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const T* Aw = lds + buf * STAGE + (wm * 16 * TM + c16) * KW + kk;
+    const T* Bw = lds + buf * STAGE + BM * KW + (wn * 16 * TN + c16) * KW + kk;
 #pragma unroll
     for (int st = 0; st < KB / 4; ++st) {
       T a[TM], b[TN];
@@ -114,7 +120,33 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 #pragma unroll
         for (int v = 0; v < TN; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
     }
+  };
+  if (k0 < k1) fetch(k0);
+  if constexpr (DB) {
+    if (k0 < k1) {
+      stage(k0, 0);
+      if (k0 + KB < k1) fetch(k0 + KB);
+    }
     __syncthreads();
+    int buf = 0;
+    for (int64_t kb = k0; kb < k1; kb += KB) {
+      compute(buf);
+      // the other buffer was last read in the previous step, before its barrier
+      if (kb + KB < k1) {
+        stage(kb + KB, buf ^ 1);
+        if (kb + 2 * KB < k1) fetch(kb + 2 * KB);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int64_t kb = k0; kb < k1; kb += KB) {
+      stage(kb, 0);
+      __syncthreads();
+      if (kb + KB < k1) fetch(kb + KB);          // next step's tiles, in flight
+      compute(0);
+      __syncthreads();
+    }
   }
   T* pc = part + static_cast<int64_t>(chunk) * n_proj * kp;
 #pragma unroll
@@ -135,7 +167,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 // result lane holds 16 consecutive alpha of one column, so stores are
 // coalesced.  Workgroups that read the same P tile (same alpha tile) share
 // an XCD.
-template <typename T>
+template <typename T, bool DB>
 __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64_t d,
                                                   const T* __restrict__ C, int n_proj, int k,
                                                   int kp, T* __restrict__ Z, int nI, int nA) {
@@ -145,8 +177,9 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
   constexpr int KW = KB + 1;
   constexpr int RC = 256 / BM, RP = 256 / BN;    // q rows per staging pass
   constexpr int LC = KB / RC, LP = KB / RP;
-  __shared__ T Cs[BM * KW];                       // [i][q]
-  __shared__ T Ps[BN * KW];                       // [alpha][q]
+  constexpr int STAGE = (BM + BN) * KW;          // one buffer: Cs [i][q] then Ps [alpha][q]
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  T* const lds = reinterpret_cast<T*>(kb_smem);
   const int id = blockIdx.x;
   const int x = id & 7, j = id >> 3;
   const int ga = x + 8 * (j / nI), itb = j - (j / nI) * nI;
@@ -182,18 +215,19 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
   for (int u = 0; u < TN; ++u)
 #pragma unroll
     for (int v = 0; v < TM; ++v) acc[u][v] = zero_acc<acc_t>();
-  const T* Aw = Cs + (wm * 16 * TN + c16) * KW + kk;
-  const T* Bw = Ps + (wn * 16 * TM + c16) * KW + kk;
-  fetch(0);
-  for (int q0 = 0; q0 < n_proj; q0 += KB) {
+  auto stage = [&](int q0, int buf) __attribute__((always_inline)) {
+    T* Cs = lds + buf * STAGE;
+    T* Ps = Cs + BM * KW;
 #pragma unroll
     for (int p = 0; p < LC; ++p)
       Cs[ci * KW + cq + RC * p] = iok && q0 + cq + RC * p < n_proj ? rc[p] : T(0);
 #pragma unroll
     for (int p = 0; p < LP; ++p)
       Ps[pa_ * KW + pq + RP * p] = aok && q0 + pq + RP * p < n_proj ? rp[p] : T(0);
-    __syncthreads();
-    if (q0 + KB < n_proj) fetch(q0 + KB);
+  };
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    const T* Aw = lds + buf * STAGE + (wm * 16 * TN + c16) * KW + kk;
+    const T* Bw = lds + buf * STAGE + BM * KW + (wn * 16 * TM + c16) * KW + kk;
 #pragma unroll
     for (int st = 0; st < KB / 4; ++st) {
       T a[TN], b[TM];
@@ -206,7 +240,30 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
 #pragma unroll
         for (int v = 0; v < TM; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
     }
+  };
+  fetch(0);
+  if constexpr (DB) {
+    stage(0, 0);
+    if (KB < n_proj) fetch(KB);
     __syncthreads();
+    int buf = 0;
+    for (int q0 = 0; q0 < n_proj; q0 += KB) {
+      compute(buf);
+      if (q0 + KB < n_proj) {
+        stage(q0 + KB, buf ^ 1);
+        if (q0 + 2 * KB < n_proj) fetch(q0 + 2 * KB);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int q0 = 0; q0 < n_proj; q0 += KB) {
+      stage(q0, 0);
+      __syncthreads();
+      if (q0 + KB < n_proj) fetch(q0 + KB);
+      compute(0);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int u = 0; u < TN; ++u)
@@ -271,14 +328,37 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
   return std::max(c32, c64) * size_t(n_proj) * size_t(kp);
 }
 
+// LDS bytes of the projector kernels: one (A tile + B tile) stage, or two when
+// double-buffered.  Measured on MI355X (309-atom shape): double buffering
+// takes the FP32 C = P^T Y product from 28.3 to 25.4 ms and makes P C slower
+// (22.3 -> 24.3 ms), so only the former uses it (2 x 33.8 KB, two workgroups
+// per CU still fit).
+template <typename T>
+constexpr size_t kb_lds_bytes(bool db) {
+  return (db ? 2 : 1) *
+         size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * (KbShape<T>::KB + 1) * sizeof(T);
+}
+
+// Allow more than the default 64 KB of dynamic LDS for a kernel that needs it
+// (set per kernel on each launch: no process-wide state).
+template <typename K>
+void allow_lds(K kern, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
 template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
                     int n_proj, int k, int kp, hipStream_t s) {
   const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
   const int per_xcd = (gr.n_groups + 7) / 8;   // groups per XCD (the last ones idle)
   const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
-  k_kb_gemm<T><<<nwg, 256, 0, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
-                                   gr.nN, gr.n_groups);
+  constexpr bool DB = sizeof(T) == 4;
+  constexpr size_t lds = kb_lds_bytes<T>(DB);
+  allow_lds(&k_kb_gemm<T, DB>, lds);
+  k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
+                                         gr.nN, gr.n_groups);
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
   k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
@@ -298,8 +378,8 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
   }
   const int per_xcd = (gr.n_groups + 7) / 8;
   const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
-  k_kb_gemm<double><<<nwg, 256, 0, s>>>(A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM,
-                                        gr.nN, gr.n_groups);
+  k_kb_gemm<double, false><<<nwg, 256, kb_lds_bytes<double>(false), s>>>(
+      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.n_groups);
   return gr.nchunk;
 }
 
@@ -310,7 +390,9 @@ void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k,
   const int nI = (k + BM - 1) / BM;
   const int nA = static_cast<int>((d + BN - 1) / BN);
   const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
-  k_kb_apply<T><<<nwg, 256, 0, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
+  constexpr size_t lds = kb_lds_bytes<T>(false);
+  allow_lds(&k_kb_apply<T, false>, lds);
+  k_kb_apply<T, false><<<nwg, 256, lds, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
 }
 
 template void launch_kb_apply<float>(const float*, int64_t, const float*, float*, int, int, int,
