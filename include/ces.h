@@ -21,7 +21,10 @@
  *    s_m = (f_m + f_{-m})/sqrt2, s_{-m} = i (f_m - f_{-m})/sqrt2; eigenvalues,
  *    densities and residual norms are the same in both.
  *  Index.  Coefficient alpha = (l*l + l + m) * N + n (0-based form of the
- *    paper's indexing map, Section 2.2.3).  d = L*L*N.
+ *    paper's indexing map, Section 2.2.3).  d = L*L*N.  A basis built with a
+ *    kinetic-energy cutoff (ces_basis_create_ke) keeps N_l <= N radial
+ *    functions for each l; then alpha = off_l + (l + m) * N_l + n with
+ *    off_l = sum_{l' < l} (2l' + 1) N_l', and d = sum_l (2l + 1) N_l.
  *  Blocks.  Orbitals are columns; column-major; leading dimension ld >= d.
  *    All values crossing this interface are FP64.  A block has k >= 1
  *    columns and n_r * n_theta * ceil(k16 / 32) < 2^31, k16 = k rounded up to
@@ -101,8 +104,21 @@ typedef struct ces_ham_s* ces_ham;
  * (CES_ERR_INVALID_ARG beyond them). */
 ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
                             int n_phi, int radial_rule, ces_basis* out);
+/* The non-uniform basis of the footnote in Section 2.2.1: the spherical
+ * waves of the uniform basis above whose kinetic energy Lambda_ln / 2 =
+ * b_ln^2 / (2 R^2) is at most e_cut (Hartree), i.e. N_l = #{n < n_rad :
+ * Lambda_ln / 2 <= e_cut} radial functions for each l (n = 0 .. N_l - 1;
+ * N_l does not grow with l), with the coefficient layout given under
+ * "Index".  The grid, tables and limits are those of ces_basis_create; every
+ * call works on either kind of basis.  e_cut must be finite and > 0 and keep
+ * at least one l = 0 function (CES_ERR_INVALID_ARG). */
+ces_status ces_basis_create_ke(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
+                               int radial_rule, double e_cut, ces_basis* out);
+/* h_nl[L] = N_l, the radial functions kept for each l (n_rad for a basis
+ * without a cutoff). */
+ces_status ces_basis_radial_counts(ces_basis b, int* h_nl);
 ces_status ces_basis_destroy(ces_basis b);
-/* d = L*L*N and n_grid = n_r*n_theta*n_phi. */
+/* d (L*L*N, or sum (2l+1) N_l with a cutoff) and n_grid = n_r*n_theta*n_phi. */
 ces_status ces_basis_info(ces_basis b, int64_t* d, int64_t* n_grid);
 /* Host copies of the grid: h_r[n_r], h_wr[n_r] (weights include r^2),
  * h_theta[n_theta], h_wtheta[n_theta] (Gauss weights in cos theta),
@@ -387,9 +403,10 @@ ces_status ces_anderson_mix(int64_t n, int m, const double* d_V, const double* d
 /* Superposition of atomic densities (Section 3.2): d_rho(x_g) = sum_a
  * rho_at(|x_g - a|), with the spherical atomic density
  *   rho_at(r) = S_00 sum_n tau00[n] R_0n(r)  (r < R; 0 for r >= R),
- * tau00[N] the l = 0 coefficients (alpha = n) of one atom's density in this
+ * tau00[N_0] the l = 0 coefficients (alpha = n) of one atom's density in this
  * basis (from ces_ks_potential's d_tau or ces_density of a one-atom SCF).
- * h_atoms[3 n_atoms] host xyz (bohr).  Synchronous. */
+ * h_atoms[3 n_atoms] host xyz (bohr); tau00 holds N_0 values (n_rad for a
+ * basis without a cutoff).  Synchronous. */
 ces_status ces_sad_density(ces_ham h, int n_atoms, const double* h_atoms,
                            const double* h_tau00, double* d_rho, void* d_work,
                            size_t work_bytes, void* stream);

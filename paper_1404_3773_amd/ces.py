@@ -22,7 +22,8 @@ CES_RADIAL_GAUSS_JACOBI_R2 = 0
 CES_RADIAL_GAUSS_LEGENDRE = 1
 
 EXPORTS = [
-    "ces_basis_create", "ces_basis_destroy", "ces_basis_info", "ces_basis_grid",
+    "ces_basis_create", "ces_basis_create_ke", "ces_basis_radial_counts",
+    "ces_basis_destroy", "ces_basis_info", "ces_basis_grid",
     "ces_basis_tables", "ces_ham_create", "ces_ham_set_veff", "ces_ham_destroy",
     "ces_workspace_size", "ces_apply_H", "ces_apply_H_noalloc", "ces_cheb_filter",
     "ces_rayleigh_ritz",
@@ -62,6 +63,8 @@ def load() -> ctypes.CDLL:
                         ctypes.c_size_t)
     sig = {
         "ces_basis_create": [I, I, D, I, I, I, I, ctypes.POINTER(P)],
+        "ces_basis_create_ke": [I, I, D, I, I, I, I, D, ctypes.POINTER(P)],
+        "ces_basis_radial_counts": [P, P],
         "ces_basis_destroy": [P],
         "ces_basis_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
         "ces_basis_grid": [P, P, P, P, P, P],
@@ -328,11 +331,20 @@ class MLP:
 class Basis:
     """Handle of ces_basis (host tables; device upload on first Ham)."""
 
-    def __init__(self, lmax, n_rad, R, n_r, n_theta, n_phi, rule=CES_RADIAL_GAUSS_JACOBI_R2):
+    def __init__(self, lmax, n_rad, R, n_r, n_theta, n_phi, rule=CES_RADIAL_GAUSS_JACOBI_R2,
+                 e_cut=None):
+        """e_cut (Hartree): keep only the radial functions with Lambda / 2 <=
+        e_cut (the kinetic-energy-cutoff basis); None keeps all n_rad."""
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.ces_basis_create(int(lmax), int(n_rad), float(R), int(n_r), int(n_theta),
-                                    int(n_phi), int(rule), ctypes.byref(h)), "ces_basis_create")
+        if e_cut is None:
+            _check(lib.ces_basis_create(int(lmax), int(n_rad), float(R), int(n_r), int(n_theta),
+                                        int(n_phi), int(rule), ctypes.byref(h)),
+                   "ces_basis_create")
+        else:
+            _check(lib.ces_basis_create_ke(int(lmax), int(n_rad), float(R), int(n_r),
+                                           int(n_theta), int(n_phi), int(rule), float(e_cut),
+                                           ctypes.byref(h)), "ces_basis_create_ke")
         self._h = h
         self.L, self.N = lmax + 1, n_rad
         self.R = R
@@ -340,10 +352,19 @@ class Basis:
         d, g = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.ces_basis_info(h, ctypes.byref(d), ctypes.byref(g)), "ces_basis_info")
         self.d, self.n_grid = d.value, g.value
+        self.e_cut = e_cut
+        self.Nl = self.radial_counts()
 
     @classmethod
-    def for_workload(cls, w):
-        return cls(w.L - 1, w.N, w.R, w.n_r, w.n_theta, w.n_phi, w.radial_rule)
+    def for_workload(cls, w, e_cut=None):
+        return cls(w.L - 1, w.N, w.R, w.n_r, w.n_theta, w.n_phi, w.radial_rule, e_cut=e_cut)
+
+    def radial_counts(self):
+        """N_l for each l (numpy int array)."""
+        out = np.zeros(self.L, dtype=np.int32)
+        _check(load().ces_basis_radial_counts(self._h, out.ctypes.data_as(ctypes.c_void_p)),
+               "ces_basis_radial_counts")
+        return out
 
     def grid(self):
         r, wr = np.zeros(self.n_r), np.zeros(self.n_r)
@@ -542,7 +563,7 @@ class Ham:
     def sad_density(self, atoms, tau00, rho, work, stream=None):
         a = np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3))
         t = np.ascontiguousarray(np.asarray(tau00, dtype=np.float64))
-        assert t.shape == (self.basis.N,)
+        assert t.shape == (int(self.basis.Nl[0]),)
         _check(load().ces_sad_density(self._h, a.shape[0], a.ctypes.data_as(ctypes.c_void_p),
                                       t.ctypes.data_as(ctypes.c_void_p), _ptr(rho), _ptr(work),
                                       work.numel(), _stream(stream)), "ces_sad_density")

@@ -132,10 +132,10 @@ void build_host_tables(Basis& b) {
 }
 
 template <typename T>
-void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std::vector<T>& Pleg,
-                 std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& trig,
-                 std::vector<T>& Pm, std::vector<T>& PwT) {
-  const int L = b.L, N = b.N, LP = L * (L + 1) / 2, S = 2 * L - 1;
+void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd,
+                 std::vector<T>& lamh, std::vector<T>& wt, std::vector<T>& Pm,
+                 std::vector<T>& PwT) {
+  const int L = b.L, N = b.N, LP = L * (L + 1) / 2;
   // zero-padded MFMA operand tables (see kernels_radial.hip)
   const int N4 = int(round_up(N, 4)), R16 = int(round_up(b.n_r, 16));
   const int R4 = int(round_up(b.n_r, 4)), N16 = int(round_up(N, 16));
@@ -148,13 +148,6 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
         Rinv[(static_cast<size_t>(l) * N4 + n) * R16 + kk] = static_cast<T>(v);
         Rfwd[(static_cast<size_t>(l) * R4 + kk) * N16 + n] = static_cast<T>(b.wr[kk] * v);
       }
-  const int npairs = (b.n_theta + 1) / 2;
-  Pleg.resize(static_cast<size_t>(npairs) * LP);
-  for (int jp = 0; jp < npairs; ++jp)
-    for (int l = 0; l < L; ++l)
-      for (int m = 0; m <= l; ++m)
-        Pleg[size_t(jp) * LP + l * (l + 1) / 2 + m] = static_cast<T>(
-            b.legendre[size_t(jp) * LP + l * (l + 1) / 2 + m] * (m > 0 ? std::sqrt(2.0) : 1.0));
   lamh.resize(static_cast<size_t>(L) * N);
   for (int l = 0; l < L; ++l)
     for (int n = 0; n < N; ++n) {
@@ -174,14 +167,6 @@ void fill_tables(const Basis& b, std::vector<T>& Rinv, std::vector<T>& Rfwd, std
         Pm[(size_t(m) * (L + 4) + l) * J64 + j] = static_cast<T>(v);
         PwT[(size_t(m) * J4 + j) * L16 + (l - m)] = static_cast<T>(b.wt[j] * v);
       }
-  trig.resize(static_cast<size_t>(S) * b.n_phi);
-  for (int s = 0; s < S; ++s)
-    for (int p = 0; p < b.n_phi; ++p) {
-      const int m = s < L ? s : s - L + 1;
-      const long long u = (static_cast<long long>(m) * p) % b.n_phi;
-      const double ang = 2.0 * M_PI * static_cast<double>(u) / b.n_phi;
-      trig[size_t(s) * b.n_phi + p] = static_cast<T>(s < L ? std::cos(ang) : std::sin(ang));
-    }
 }
 
 // Upload device tables once (on the device current at first use).
@@ -193,10 +178,10 @@ ces_status ensure_device(Basis& b) {
     if (dev != b.device) return fail(CES_ERR_INVALID_ARG, "basis tables live on another device");
     return CES_OK;
   }
-  std::vector<double> R64, F64, P64, l64, w64, t64, M64, W64;
-  std::vector<float> R32, F32, P32, l32, w32, t32, M32, W32;
-  fill_tables(b, R64, F64, P64, l64, w64, t64, M64, W64);
-  fill_tables(b, R32, F32, P32, l32, w32, t32, M32, W32);
+  std::vector<double> R64, F64, l64, w64, M64, W64;
+  std::vector<float> R32, F32, l32, w32, M32, W32;
+  fill_tables(b, R64, F64, l64, w64, M64, W64);
+  fill_tables(b, R32, F32, l32, w32, M32, W32);
   std::vector<double> cs(2 * static_cast<size_t>(b.n_phi));
   for (int u = 0; u < b.n_phi; ++u) {
     cs[u] = std::cos(2.0 * M_PI * u / b.n_phi);
@@ -221,6 +206,17 @@ ces_status ensure_device(Basis& b) {
             4.0 * M_PI / (2 * l + 1) * c0 * b.R * std::pow(b.r[kk] / b.R, l) / k;
       }
     }
+  std::vector<int> lay(2 * size_t(b.L));
+  std::vector<double> lam(b.d);
+  for (int l = 0; l < b.L; ++l) {
+    lay[2 * l] = static_cast<int>(b.off[l]);
+    lay[2 * l + 1] = b.Nl[l];
+    for (int mm = 0; mm < 2 * l + 1; ++mm)
+      for (int n = 0; n < b.Nl[l]; ++n) {
+        const double kk = b.zeros[size_t(l) * b.N + n] / b.R;
+        lam[b.off[l] + int64_t(mm) * b.Nl[l] + n] = kk * kk;
+      }
+  }
   std::vector<double> cth(b.n_theta), sth(b.n_theta);
   for (int j = 0; j < b.n_theta; ++j) {
     cth[j] = b.t[j];
@@ -233,11 +229,9 @@ ces_status ensure_device(Basis& b) {
   };
   std::vector<Piece> pieces = {
       {R64.data(), R64.size() * 8, (void**)&b.t64.RiT}, {F64.data(), F64.size() * 8, (void**)&b.t64.RfT},
-      {P64.data(), P64.size() * 8, (void**)&b.t64.Pleg}, {l64.data(), l64.size() * 8, (void**)&b.t64.lamh},
-      {w64.data(), w64.size() * 8, (void**)&b.t64.wt},   {t64.data(), t64.size() * 8, (void**)&b.t64.trig},
+      {l64.data(), l64.size() * 8, (void**)&b.t64.lamh}, {w64.data(), w64.size() * 8, (void**)&b.t64.wt},
       {R32.data(), R32.size() * 4, (void**)&b.t32.RiT}, {F32.data(), F32.size() * 4, (void**)&b.t32.RfT},
-      {P32.data(), P32.size() * 4, (void**)&b.t32.Pleg}, {l32.data(), l32.size() * 4, (void**)&b.t32.lamh},
-      {w32.data(), w32.size() * 4, (void**)&b.t32.wt},   {t32.data(), t32.size() * 4, (void**)&b.t32.trig},
+      {l32.data(), l32.size() * 4, (void**)&b.t32.lamh}, {w32.data(), w32.size() * 4, (void**)&b.t32.wt},
       {M64.data(), M64.size() * 8, (void**)&b.t64.Pm},   {W64.data(), W64.size() * 8, (void**)&b.t64.PwT},
       {M32.data(), M32.size() * 4, (void**)&b.t32.Pm},   {W32.data(), W32.size() * 4, (void**)&b.t32.PwT},
       {cs.data(), cs.size() * 8, (void**)&b.dev_cs},
@@ -245,7 +239,9 @@ ces_status ensure_device(Basis& b) {
       {b.r.data(), b.r.size() * 8, (void**)&b.dev_rnode},
       {b.wr.data(), b.wr.size() * 8, (void**)&b.dev_wr},
       {cth.data(), cth.size() * 8, (void**)&b.dev_cth},
-      {sth.data(), sth.size() * 8, (void**)&b.dev_sth}};
+      {sth.data(), sth.size() * 8, (void**)&b.dev_sth},
+      {lay.data(), lay.size() * sizeof(int), (void**)&b.dev_lay},
+      {lam.data(), lam.size() * 8, (void**)&b.dev_lam}};
   size_t total = 0;
   for (auto& p : pieces) total += align256(p.bytes);
   void* blk = nullptr;
@@ -767,8 +763,11 @@ ces_status ces_profile_read(int n_stages, double* h_ms, int64_t* h_count) {
   return CES_OK;
 }
 
-ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
-                            int radial_rule, ces_basis* out) {
+namespace {
+// Shared by the uniform and the cutoff constructors; e_cut <= 0 keeps every
+// radial function (N_l = N).
+ces_status basis_create(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
+                        int radial_rule, double e_cut, ces_basis* out) {
   if (!out) return fail(CES_ERR_INVALID_ARG, "null output handle");
   *out = nullptr;
   if (lmax < 0 || n_rad < 1 || !(R > 0) || n_r < 1 || n_theta < 1)
@@ -791,7 +790,6 @@ ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
   b.n_theta = n_theta;
   b.n_phi = n_phi;
   b.rule = radial_rule;
-  b.d = int64_t(b.L) * b.L * b.N;
   b.n_grid = int64_t(n_r) * n_theta * n_phi;
   try {
     build_host_tables(b);
@@ -799,7 +797,49 @@ ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta,
     delete bb;
     return fail(CES_ERR_INVALID_ARG, e.what());
   }
+  // coefficient layout: N_l = #{n < N : Lambda_ln / 2 <= e_cut} (all N without
+  // a cutoff); Lambda grows with n, so the kept functions are n < N_l
+  b.e_cut = e_cut > 0 ? e_cut : 0.0;
+  b.Nl.assign(b.L, b.N);
+  b.off.assign(b.L, 0);
+  int64_t d = 0;
+  for (int l = 0; l < b.L; ++l) {
+    if (e_cut > 0) {
+      int cnt = 0;
+      for (int n = 0; n < b.N; ++n) {
+        const double kk = b.zeros[size_t(l) * b.N + n] / b.R;
+        if (0.5 * kk * kk <= e_cut) ++cnt;
+      }
+      b.Nl[l] = cnt;
+    }
+    b.off[l] = d;
+    d += int64_t(2 * l + 1) * b.Nl[l];
+  }
+  if (b.Nl[0] < 1) {
+    delete bb;
+    return fail(CES_ERR_INVALID_ARG, "the kinetic-energy cutoff keeps no radial function");
+  }
+  b.d = d;
   *out = bb;
+  return CES_OK;
+}
+}  // namespace
+
+ces_status ces_basis_create(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
+                            int radial_rule, ces_basis* out) {
+  return basis_create(lmax, n_rad, R, n_r, n_theta, n_phi, radial_rule, 0.0, out);
+}
+
+ces_status ces_basis_create_ke(int lmax, int n_rad, double R, int n_r, int n_theta, int n_phi,
+                               int radial_rule, double e_cut, ces_basis* out) {
+  if (!(e_cut > 0) || !std::isfinite(e_cut))
+    return fail(CES_ERR_INVALID_ARG, "the kinetic-energy cutoff must be finite and > 0");
+  return basis_create(lmax, n_rad, R, n_r, n_theta, n_phi, radial_rule, e_cut, out);
+}
+
+ces_status ces_basis_radial_counts(ces_basis bb, int* h_nl) {
+  if (!bb || !h_nl) return fail(CES_ERR_INVALID_ARG, "null argument");
+  std::memcpy(h_nl, bb->b.Nl.data(), bb->b.Nl.size() * sizeof(int));
   return CES_OK;
 }
 
@@ -840,6 +880,7 @@ ces_status check_coeff_map(ces_basis bb, int k, const double* in, int64_t ldi, c
 ces_status ces_coeffs_complex_to_real(ces_basis bb, int k, const double* d_f, int64_t ldf,
                                       double* d_s, int64_t lds, void* stream) {
   CES_TRY(check_coeff_map(bb, k, d_f, ldf, d_s, lds));
+  CES_TRY(ensure_device(bb->b));   // the coefficient layout table
   launch_coeffs_c2r(bb->b, d_f, ldf, d_s, lds, k, static_cast<hipStream_t>(stream));
   CES_HIP(hipGetLastError());
   return CES_OK;
@@ -848,6 +889,7 @@ ces_status ces_coeffs_complex_to_real(ces_basis bb, int k, const double* d_f, in
 ces_status ces_coeffs_real_to_complex(ces_basis bb, int k, const double* d_s, int64_t lds,
                                       double* d_f, int64_t ldf, void* stream) {
   CES_TRY(check_coeff_map(bb, k, d_s, lds, d_f, ldf));
+  CES_TRY(ensure_device(bb->b));   // the coefficient layout table
   launch_coeffs_r2c(bb->b, d_s, lds, d_f, ldf, k, static_cast<hipStream_t>(stream));
   CES_HIP(hipGetLastError());
   return CES_OK;
@@ -1157,8 +1199,11 @@ ces_status ces_to_grid(ces_ham hh, int k, const double* d_X, int64_t ldx, double
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Basis& b = *h.basis;
   double* G = Ptr<double>::at(d_work, ly.G);
-  launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, static_cast<int>(ly.kp), s);
-  launch_angular_synth<double>(b, b.t64, G, d_f, k, static_cast<int>(ly.kp), s);
+  double* gbuf = Ptr<double>::at(d_work, ly.gbuf);
+  const int kp = static_cast<int>(ly.kp);
+  launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, kp, s);
+  launch_legendre_synth<double>(b, b.t64, G, gbuf, kp, s);
+  launch_phi_synthesis_cols(b, gbuf, k, kp, d_f, b.n_grid, s);
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -1174,8 +1219,10 @@ ces_status ces_from_grid(ces_ham hh, int k, const double* d_f, double* d_X, int6
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Basis& b = *h.basis;
   double* A = Ptr<double>::at(d_work, ly.A);
+  double* gh = Ptr<double>::at(d_work, ly.gbuf);
   const int kp = static_cast<int>(ly.kp);
-  launch_angular_analysis<double>(b, b.t64, d_f, A, k, kp, s);
+  launch_phi_analysis_cols(b, d_f, b.n_grid, k, kp, gh, s);
+  launch_legendre_analysis<double>(b, b.t64, gh, A, kp, s);
   launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_X, ldx, 1.0, 0.0, 0.0,
                                 false, nullptr, k, kp, s);
   CES_HIP(hipGetLastError());

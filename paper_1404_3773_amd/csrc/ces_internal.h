@@ -4,8 +4,6 @@
 //   G, A       [r][lm][i]            per radial node and (l,m), i padded to kp
 //   RiT        [l][N4][R16]          R_ln(r_k) at [l][n][r]
 //   RfT        [l][R4][N16]          w_k R_ln(r_k) at [l][r][n]
-//   Pleg       [jp][l(l+1)/2 + m]    c_lm P_l^m(t_jp) * (sqrt2 for m > 0),
-//                                    jp over the nodes with t >= 0
 //   Pm, PwT, RiT, RfT                zero-padded MFMA operand tables (shapes
 //                                    in kernels_angular.hip / kernels_radial.hip)
 //   ab         [r][j][2][S]          halved phi-Fourier cosine / sine sums of
@@ -34,10 +32,8 @@ template <typename T>
 struct DevTables {
   T* RiT = nullptr;
   T* RfT = nullptr;
-  T* Pleg = nullptr;
   T* lamh = nullptr;   // [l][n] Lambda_ln / 2
   T* wt = nullptr;     // [n_theta]
-  T* trig = nullptr;   // [S][n_phi]: slot s < L cos(s phi_p), else sin((s-L+1) phi_p)
   T* Pm = nullptr;     // [m][L+4][J64]  c_lm P_l^m(t_j) (* sqrt2, m > 0); 0 for l < m
   T* PwT = nullptr;    // [m][J4][L16]   w_j * Pm[m][m + ll][j] at [m][j][ll]
 };
@@ -46,6 +42,14 @@ struct Basis {
   int L = 0, N = 0, n_r = 0, n_theta = 0, n_phi = 0, rule = 0;
   double R = 0;
   int64_t d = 0, n_grid = 0;
+  // Coefficient layout: N_l radial functions kept for each l (N for the
+  // uniform basis; fewer under a kinetic-energy cutoff) and the first index
+  // off_l of each l, so alpha(l, m, n) = off_l + (l + m) N_l + n.
+  std::vector<int> Nl;
+  std::vector<int64_t> off;
+  double e_cut = 0.0;            // the cutoff (0: uniform basis)
+  int* dev_lay = nullptr;        // [L][2] off_l, N_l (device)
+  double* dev_lam = nullptr;     // [d] Lambda of each coefficient (device)
   std::vector<double> zeros, r, wr, theta, t, wt, phi;
   std::vector<double> radial;    // [l][k][n]
   std::vector<double> legendre;  // [j][l(l+1)/2 + m]
@@ -222,13 +226,13 @@ template <typename T>
 void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,
                      hipStream_t s);
 
-// Transforms for grids of k functions (column i at offset i*n_grid).
-template <typename T>
-void launch_angular_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* f, int k,
-                          int kp, hipStream_t s);
-template <typename T>
-void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f, T* A, int k,
-                             int kp, hipStream_t s);
+// Phi transforms of k grid functions (column i at f + i ldf, [r][j][p]) to /
+// from the Legendre stages' layout g[r][j][s][c] with kp columns (columns k ..
+// kp-1 of the analysis output zeroed).
+void launch_phi_synthesis_cols(const Basis& b, const double* g, int k, int kp, double* f,
+                               int64_t ldf, hipStream_t s);
+void launch_phi_analysis_cols(const Basis& b, const double* f, int64_t ldf, int k, int kp,
+                              double* gh, hipStream_t s);
 // rho[r][j][p] = 2 sum_i occ_i psi_i(r, j, p)^2 from the Legendre-synthesis
 // output gbuf (n_r x n_theta x S x kp), accumulated in FP64.
 template <typename T>
@@ -313,10 +317,11 @@ void launch_block_rotate(double* X, int64_t ldx, double* Y, int64_t ldy, const d
 // 2 * 64 * na doubles of scratch.
 void launch_active_residual(const double* X, int64_t ldx, const double* AX, int64_t ldax,
                             const double* theta, const int* act, int na, double* W, int64_t ldw,
-                            const double* lamh, int N, int64_t rows, double* part, double* ke,
+                            const double* lam, int64_t rows, double* part, double* ke,
                             hipStream_t s);
-// W[alpha, j] *= T(g_scale Lambda_alpha / ke[j]) (Teter-Payne-Allan factor).
-void launch_tpa_scale(double* W, int64_t ldw, int na, const double* ke, const double* lamh, int N,
+// W[alpha, j] *= T(g_scale Lambda_alpha / ke[j]) (Teter-Payne-Allan factor);
+// lam[alpha] = Lambda_alpha.
+void launch_tpa_scale(double* W, int64_t ldw, int na, const double* ke, const double* lam,
                       double g_scale, int64_t rows, hipStream_t s);
 // dst[:, j] = src[:, list[j]] for j < n.
 void launch_gather_cols(const double* src, int64_t lds, const int* list, int n, double* dst,

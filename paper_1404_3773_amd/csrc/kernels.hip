@@ -1,6 +1,6 @@
-// HIP kernels (gfx950): V_eff phi-Fourier sums, grid synthesis / analysis
-// for to_grid / from_grid / density, and small FP64 helpers of Cholesky-QR,
-// Rayleigh-Ritz and Lanczos.  The H*X stages are in kernels_radial.hip and
+// HIP kernels (gfx950): V_eff phi-Fourier sums, the complex <-> real
+// coefficient maps, and small FP64 helpers of Cholesky-QR, Rayleigh-Ritz and
+// Lanczos.  The H*X stages are in kernels_radial.hip and
 // kernels_angular.hip.
 //
 // phi stage of H*X.  With f(phi) = sum_m g^c_m cos(m phi) + g^s_m sin(m phi), the
@@ -19,13 +19,6 @@
 namespace ces {
 
 namespace {
-
-__device__ __forceinline__ int isqrt_lm(int lm) {
-  int l = static_cast<int>(sqrtf(static_cast<float>(lm)));
-  while (l * l > lm) --l;
-  while ((l + 1) * (l + 1) <= lm) ++l;
-  return l;
-}
 
 // ab[r][j][0][q] = (pi/N_phi) sum_p V cos(q phi_p), ab[..][1][q] the sine sums;
 // cs holds cos / sin(2 pi u / N_phi), u < N_phi, indexed by (q p) mod N_phi.
@@ -48,86 +41,6 @@ __global__ void k_veff_fourier(const double* __restrict__ V, const double* __res
     ab64[rj * 2 * S + q] = scale * acc;
     ab32[rj * 2 * S + q] = static_cast<float>(scale * acc);
   }
-}
-
-// ---------------------------------------------------- grid synthesis/analysis
-
-template <typename T>
-__device__ __forceinline__ T pleg_at(const T* Pleg, int n_theta, int LP, int j, int l, int m) {
-  const int jn = n_theta - 1 - j;
-  if (j <= jn) return Pleg[static_cast<int64_t>(j) * LP + l * (l + 1) / 2 + m];
-  const T v = Pleg[static_cast<int64_t>(jn) * LP + l * (l + 1) / 2 + m];
-  return ((l + m) & 1) ? -v : v;
-}
-
-// f[i][r][j][p] from G, one workgroup per (r, j), loop over columns.
-template <typename T>
-__global__ __launch_bounds__(256) void k_angular_synth(const T* __restrict__ G, T* __restrict__ f,
-                                                       const T* __restrict__ Pleg,
-                                                       const T* __restrict__ trig, int L,
-                                                       int n_theta, int n_phi, int64_t n_grid,
-                                                       int k, int kp) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* gs = reinterpret_cast<T*>(smem_raw);
-  const int r = blockIdx.x, j = blockIdx.y;
-  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
-  for (int i = 0; i < k; ++i) {
-    for (int s = threadIdx.x; s < S; s += blockDim.x) {
-      const bool sn = s >= L;
-      const int m = sn ? s - L + 1 : s;
-      T acc = T(0);
-      for (int l = m; l < L; ++l)
-        acc += pleg_at(Pleg, n_theta, LP, j, l, m) *
-               G[(static_cast<int64_t>(r) * LL + l * l + l + (sn ? -m : m)) * kp + i];
-      gs[s] = acc;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < n_phi; p += blockDim.x) {
-      T acc = T(0);
-      for (int s = 0; s < S; ++s) acc += gs[s] * trig[static_cast<int64_t>(s) * n_phi + p];
-      f[static_cast<int64_t>(i) * n_grid + (static_cast<int64_t>(r) * n_theta + j) * n_phi + p] = acc;
-    }
-    __syncthreads();
-  }
-}
-
-// A[r][lm][i] = sum_j w_j Pbar_lm(t_j) (2 pi / N_phi) sum_p f trig, one
-// workgroup per (r, column).
-template <typename T>
-__global__ __launch_bounds__(256) void k_angular_analysis(const T* __restrict__ f,
-                                                          T* __restrict__ A,
-                                                          const T* __restrict__ Pleg,
-                                                          const T* __restrict__ trig,
-                                                          const T* __restrict__ wt, int L,
-                                                          int n_theta, int n_phi,
-                                                          int64_t n_grid, int kp) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* As = reinterpret_cast<T*>(smem_raw);
-  const int r = blockIdx.x, i = blockIdx.y;
-  const int LL = L * L, S = 2 * L - 1, LP = L * (L + 1) / 2;
-  T* gh = As + LL;
-  const T dphi = T(2.0 * M_PI / n_phi);
-  for (int e = threadIdx.x; e < LL; e += blockDim.x) As[e] = T(0);
-  const T* fi = f + static_cast<int64_t>(i) * n_grid;
-  for (int j = 0; j < n_theta; ++j) {
-    for (int s = threadIdx.x; s < S; s += blockDim.x) {
-      T acc = T(0);
-      const T* row = fi + (static_cast<int64_t>(r) * n_theta + j) * n_phi;
-      for (int p = 0; p < n_phi; ++p) acc += row[p] * trig[static_cast<int64_t>(s) * n_phi + p];
-      gh[s] = acc * dphi;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-      const int l = isqrt_lm(e);
-      const int ms = e - l * l - l;
-      const int m = ms < 0 ? -ms : ms;
-      const int s = ms >= 0 ? m : L - 1 + m;
-      As[e] += wt[j] * pleg_at(Pleg, n_theta, LP, j, l, m) * gh[s];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < LL; e += blockDim.x)
-    A[(static_cast<int64_t>(r) * LL + e) * kp + i] = As[e];
 }
 
 // --------------------------------------------------------------- utilities
@@ -285,30 +198,41 @@ inline int grid1d(int64_t n) {
 }
 
 // Complex <-> real harmonic coefficients, one thread per output entry
-// (alpha, column i) of d x k interleaved complex blocks.  With alpha =
-// (l^2 + l + m) N + n and mu = |m| > 0, each (l, n) pairs f_{+mu} and f_{-mu}:
+// (alpha, column i) of d x k interleaved complex blocks.  With mu = |m| > 0,
+// each (l, n) pairs f_{+mu} and f_{-mu}:
 //   complex -> real   s_{+mu} = (f_{+mu} + f_{-mu}) / sqrt2
 //                     s_{-mu} = i (f_{+mu} - f_{-mu}) / sqrt2
 //   real -> complex   f_{+mu} = (s_{+mu} - i s_{-mu}) / sqrt2
 //                     f_{-mu} = (s_{+mu} + i s_{-mu}) / sqrt2
 // and m = 0 is copied.  in and out do not overlap (checked by the caller).
+// The layout gives each l its first index off_l and N_l radial functions
+// (lay[2l], lay[2l+1]): alpha = off_l + (l + m) N_l + n.
 template <bool TO_REAL>
 __global__ void k_coeffs_map(const double2* __restrict__ in, int64_t ldi,
-                             double2* __restrict__ out, int64_t ldo, int L, int N, int64_t d,
-                             int k) {
+                             double2* __restrict__ out, int64_t ldo,
+                             const int* __restrict__ lay, int L, int64_t d, int k) {
   const int64_t total = d * k;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t i = e / d, a = e - i * d;
-    const int lm = static_cast<int>(a / N), n = static_cast<int>(a - int64_t(lm) * N);
-    const int l = isqrt_lm(lm), m = lm - l * l - l, mu = m < 0 ? -m : m;
+    // l: the last l with off_l <= a (binary search over the offsets)
+    int lo = 0, hi = L - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lay[2 * mid] <= a) lo = mid; else hi = mid - 1;
+    }
+    const int l = lo, Nl = lay[2 * l + 1];
+    const int64_t off = lay[2 * l];
+    const int lmi = static_cast<int>((a - off) / Nl);       // l + m
+    const int n = static_cast<int>(a - off - int64_t(lmi) * Nl);
+    const int m = lmi - l, mu = m < 0 ? -m : m;
     const double2* col = in + i * ldi;
     double2 r;
     if (m == 0) {
       r = col[a];
     } else {
-      const double2 p = col[int64_t(l * l + l + mu) * N + n];   // the +mu entry
-      const double2 q = col[int64_t(l * l + l - mu) * N + n];   // the -mu entry
+      const double2 p = col[off + int64_t(l + mu) * Nl + n];   // the +mu entry
+      const double2 q = col[off + int64_t(l - mu) * Nl + n];   // the -mu entry
       const double h = 0.70710678118654752440;                 // 1 / sqrt2
       if (TO_REAL) {
         // s_{+mu} = (p + q) h;  s_{-mu} = i (p - q) h = (-(p - q).y, (p - q).x) h
@@ -342,31 +266,12 @@ void launch_convert(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t
   k_convert<Tin, Tout><<<grid, 256, 0, s>>>(src, lds, dst, ldd, rows, cols);
 }
 
-template <typename T>
-void launch_angular_synth(const Basis& b, const DevTables<T>& tb, const T* G, T* f, int k,
-                          int kp, hipStream_t s) {
-  dim3 grid(b.n_r, b.n_theta);
-  k_angular_synth<T><<<grid, 256, (2 * b.L - 1) * sizeof(T), s>>>(
-      G, f, tb.Pleg, tb.trig, b.L, b.n_theta, b.n_phi, b.n_grid, k, kp);
-}
-
-template <typename T>
-void launch_angular_analysis(const Basis& b, const DevTables<T>& tb, const T* f, T* A, int k,
-                             int kp, hipStream_t s) {
-  dim3 grid(b.n_r, k);
-  const size_t lds = (size_t(b.L) * b.L + 2 * b.L - 1) * sizeof(T);
-  k_angular_analysis<T><<<grid, 256, lds, s>>>(f, A, tb.Pleg, tb.trig, tb.wt, b.L, b.n_theta,
-                                               b.n_phi, b.n_grid, kp);
-}
-
-
-
 void launch_coeffs_c2r(const Basis& b, const double* f, int64_t ldf, double* sr, int64_t lds,
                        int k, hipStream_t s) {
   const int64_t total = b.d * k;
   const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 8192));
   k_coeffs_map<true><<<g, 256, 0, s>>>(reinterpret_cast<const double2*>(f), ldf,
-                                        reinterpret_cast<double2*>(sr), lds, b.L, b.N, b.d, k);
+                                        reinterpret_cast<double2*>(sr), lds, b.dev_lay, b.L, b.d, k);
 }
 
 void launch_coeffs_r2c(const Basis& b, const double* sr, int64_t lds, double* f, int64_t ldf,
@@ -374,7 +279,7 @@ void launch_coeffs_r2c(const Basis& b, const double* sr, int64_t lds, double* f,
   const int64_t total = b.d * k;
   const unsigned g = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 8192));
   k_coeffs_map<false><<<g, 256, 0, s>>>(reinterpret_cast<const double2*>(sr), lds,
-                                         reinterpret_cast<double2*>(f), ldf, b.L, b.N, b.d, k);
+                                         reinterpret_cast<double2*>(f), ldf, b.dev_lay, b.L, b.d, k);
 }
 
 void launch_scale_gram(double* S, int k, double* dinv, hipStream_t s) {
@@ -431,14 +336,6 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hip
   k_axpby<<<grid1d(n), 256, 0, s>>>(a, x, b, y, n);
 }
 
-#define CES_INST(T)                                                                           \
-  template void launch_angular_synth<T>(const Basis&, const DevTables<T>&, const T*, T*, int, \
-                                        int, hipStream_t);                                    \
-  template void launch_angular_analysis<T>(const Basis&, const DevTables<T>&, const T*, T*,   \
-                                           int, int, hipStream_t);
-CES_INST(float)
-CES_INST(double)
-#undef CES_INST
 
 template void launch_convert<double, float>(const double*, int64_t, float*, int64_t, int64_t,
                                             int, hipStream_t);

@@ -863,30 +863,36 @@ __global__ __launch_bounds__(256) void k_density_phi(const T* __restrict__ g,
   }
 }
 
-// One-column phi transforms (the SCF potential and the density coefficients).
-// A workgroup takes four (r, theta_j) rows, one per wave; the angle table
-// cos | sin(2 pi u / n_phi) sits in LDS, and with n_phi <= kOneRowLds also the
-// wave's input row, so the inner loops read LDS only.
+// Column-block phi transforms between grid functions (column i at f + i ldf,
+// [r][theta_j][p]) and the Legendre stages' slot layout g[r][j][s][kp]: the
+// SCF potential and density coefficients (one column, kp = 16) and
+// ces_to_grid / ces_from_grid (k columns).  A workgroup takes four (r, theta_j)
+// rows of one column, one per wave; the angle table cos | sin(2 pi u / n_phi)
+// sits in LDS, and with n_phi <= kOneRowLds also the wave's input row, so the
+// inner loops read LDS only.
 constexpr int kOneRowLds = 1024;
 
-// f[r][j][p] = sum_s g[r][j][s][0] trig[s][p] from the Legendre-synthesis
-// output with 16 columns; lane p walks the slots with index (m p) mod n_phi.
-__global__ __launch_bounds__(256) void k_phi_synthesis_one(const double* __restrict__ g,
-                                                           double* __restrict__ f,
-                                                           const double* __restrict__ cs,
-                                                           int L, int n_phi, int64_t n_rows) {
+// f_i[r][j][p] = sum_s g[r][j][s][i] trig[s][p]; lane p walks the slots with
+// index (m p) mod n_phi.
+__global__ __launch_bounds__(256) void k_phi_synthesis_cols(const double* __restrict__ g,
+                                                            int kp, double* __restrict__ f,
+                                                            int64_t ldf,
+                                                            const double* __restrict__ cs,
+                                                            int L, int n_phi, int64_t n_rows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ct = reinterpret_cast<double*>(smem_raw);           // [2][n_phi]
   double* gw = ct + 2 * n_phi;                                 // [4][S] slot values per wave
   const int S = 2 * L - 1;
+  const int i = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < 2 * n_phi; e += 256) ct[e] = cs[e];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave;
   double* gv = gw + wave * S;
   if (row < n_rows)
-    for (int e = lane; e < S; e += 64) gv[e] = g[(row * S + e) * 16];
+    for (int e = lane; e < S; e += 64) gv[e] = g[(row * S + e) * kp + i];
   __syncthreads();
   if (row >= n_rows) return;
+  double* fo = f + static_cast<int64_t>(i) * ldf + row * n_phi;
   for (int p = lane; p < n_phi; p += 64) {
     double acc = 0.0;
     int u = 0;                                   // cos part, m = 0..L-1
@@ -903,26 +909,28 @@ __global__ __launch_bounds__(256) void k_phi_synthesis_one(const double* __restr
       u += p;
       u -= u >= n_phi ? n_phi : 0;
     }
-    f[row * n_phi + p] = acc;
+    fo[p] = acc;
   }
 }
 
-// gh[r][j][s][0] = (2 pi / n_phi) sum_p f[p] trig[s][p], in the Legendre
-// analysis' layout with 16 columns (columns 1..15 zero); lane s walks p with
-// index (m p) mod n_phi.
-__global__ __launch_bounds__(256) void k_phi_analysis_one(const double* __restrict__ f,
-                                                          double* __restrict__ gh,
-                                                          const double* __restrict__ cs,
-                                                          int L, int n_phi, int64_t n_rows) {
+// g[r][j][s][i] = (2 pi / n_phi) sum_p f_i[r][j][p] trig[s][p] for the k
+// columns; the workgroups of the last column also zero columns k .. kp-1.
+// Lane s walks p with index (m p) mod n_phi.
+__global__ __launch_bounds__(256) void k_phi_analysis_cols(const double* __restrict__ f,
+                                                           int64_t ldf, int k, int kp,
+                                                           double* __restrict__ gh,
+                                                           const double* __restrict__ cs,
+                                                           int L, int n_phi, int64_t n_rows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ct = reinterpret_cast<double*>(smem_raw);           // [2][n_phi]
   double* fw = ct + 2 * n_phi;                                 // [4][n_phi] when staged
   const int S = 2 * L - 1;
+  const int i = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool staged = n_phi <= kOneRowLds;
   for (int e = threadIdx.x; e < 2 * n_phi; e += 256) ct[e] = cs[e];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wave;
-  const double* fr = f + row * n_phi;
+  const double* fr = f + static_cast<int64_t>(i) * ldf + row * n_phi;
   if (staged && row < n_rows)
     for (int e = lane; e < n_phi; e += 64) fw[wave * n_phi + e] = fr[e];
   __syncthreads();
@@ -940,10 +948,10 @@ __global__ __launch_bounds__(256) void k_phi_analysis_one(const double* __restri
       u += m;
       u -= u >= n_phi ? n_phi : 0;
     }
-    double* o = gh + (row * S + s) * 16;
-    o[0] = dphi * acc;
-#pragma unroll
-    for (int c = 1; c < 16; ++c) o[c] = 0.0;
+    double* o = gh + (row * S + s) * kp;
+    o[i] = dphi * acc;
+    if (i == k - 1)
+      for (int c = k; c < kp; ++c) o[c] = 0.0;
   }
 }
 
@@ -1086,19 +1094,29 @@ void launch_density_phi(const Basis& b, const T* gbuf, const double* occ, double
   }
 }
 
-void launch_phi_synthesis_one(const Basis& b, const double* g, double* f, hipStream_t s) {
+void launch_phi_synthesis_cols(const Basis& b, const double* g, int k, int kp, double* f,
+                               int64_t ldf, hipStream_t s) {
   const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
   const size_t lds = (2 * size_t(b.n_phi) + 4 * (2 * size_t(b.L) - 1)) * sizeof(double);
-  k_phi_synthesis_one<<<static_cast<unsigned>((n_rows + 3) / 4), 256, lds, s>>>(
-      g, f, b.dev_cs, b.L, b.n_phi, n_rows);
+  k_phi_synthesis_cols<<<dim3(static_cast<unsigned>((n_rows + 3) / 4), k), 256, lds, s>>>(
+      g, kp, f, ldf, b.dev_cs, b.L, b.n_phi, n_rows);
 }
 
-void launch_phi_analysis_one(const Basis& b, const double* f, double* gh, hipStream_t s) {
+void launch_phi_analysis_cols(const Basis& b, const double* f, int64_t ldf, int k, int kp,
+                              double* gh, hipStream_t s) {
   const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
   const size_t lds = (2 * size_t(b.n_phi) + (b.n_phi <= kOneRowLds ? 4 * size_t(b.n_phi) : 0)) *
                      sizeof(double);
-  k_phi_analysis_one<<<static_cast<unsigned>((n_rows + 3) / 4), 256, lds, s>>>(
-      f, gh, b.dev_cs, b.L, b.n_phi, n_rows);
+  k_phi_analysis_cols<<<dim3(static_cast<unsigned>((n_rows + 3) / 4), k), 256, lds, s>>>(
+      f, ldf, k, kp, gh, b.dev_cs, b.L, b.n_phi, n_rows);
+}
+
+void launch_phi_synthesis_one(const Basis& b, const double* g, double* f, hipStream_t s) {
+  launch_phi_synthesis_cols(b, g, 1, kColPad, f, b.n_grid, s);
+}
+
+void launch_phi_analysis_one(const Basis& b, const double* f, double* gh, hipStream_t s) {
+  launch_phi_analysis_cols(b, f, b.n_grid, 1, kColPad, gh, s);
 }
 
 #define CES_INST(T)                                                                          \

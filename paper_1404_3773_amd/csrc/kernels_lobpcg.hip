@@ -19,23 +19,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Laplacian eigenvalue Lambda of coefficient alpha = (l^2 + l + m) N + n:
-// 2 * lamh[l][n] (lamh holds Lambda / 2).
-__device__ __forceinline__ double lambda_of(int64_t alpha, int N, const double* lamh) {
-  const int64_t lm = alpha / N;
-  const int n = static_cast<int>(alpha - lm * N);
-  int l = static_cast<int>(sqrt(static_cast<double>(lm)));
-  while (int64_t(l + 1) * (l + 1) <= lm) ++l;
-  while (int64_t(l) * l > lm) --l;
-  return 2.0 * lamh[static_cast<int64_t>(l) * N + n];
-}
-
 // W[:, j] = AX[:, a_j] - theta[a_j] X[:, a_j] for the active list a; per block
 // partial sums of |r|^2 and (Lambda / 2) |r|^2 into part[j][0 or 1][block].
 __global__ __launch_bounds__(kThreads) void k_active_residual(
     const double* __restrict__ X, int64_t ldx, const double* __restrict__ AX, int64_t ldax,
     const double* __restrict__ theta, const int* __restrict__ act, double* __restrict__ W,
-    int64_t ldw, const double* __restrict__ lamh, int N, int64_t rows,
+    int64_t ldw, const double* __restrict__ lam, int64_t rows,
     double* __restrict__ part) {
   __shared__ double red[2][kThreads / 64];
   const int j = blockIdx.y, nb = gridDim.x;
@@ -51,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_active_residual(
     w[e] = r;
     const double r2 = r * r;
     s2 += r2;
-    sk += 0.5 * lambda_of(e, N, lamh) * r2;
+    sk += 0.5 * lam[e] * r2;
   }
   s2 = wave_sum(s2);
   sk = wave_sum(sk);
@@ -90,7 +79,7 @@ __global__ void k_kinetic_per_norm(const double* __restrict__ part, int nb, int 
 // T(g) = (27 + 18 g + 12 g^2 + 8 g^3) / (27 + 18 g + 12 g^2 + 8 g^3 + 16 g^4).
 __global__ __launch_bounds__(kThreads) void k_tpa_scale(double* __restrict__ W, int64_t ldw,
                                                         const double* __restrict__ ke,
-                                                        const double* __restrict__ lamh, int N,
+                                                        const double* __restrict__ lam,
                                                         double g_scale, int64_t rows) {
   const int j = blockIdx.y;
   const double kej = ke[j];
@@ -99,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_tpa_scale(double* __restrict__ W, 
   double* w = W + j * ldw;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; e < rows;
        e += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double g = lambda_of(e, N, lamh) * inv;
+    const double g = lam[e] * inv;
     const double num = 27.0 + g * (18.0 + g * (12.0 + 8.0 * g));
     const double g2 = g * g;
     w[e] *= num / (num + 16.0 * g2 * g2);
@@ -133,17 +122,17 @@ int lobpcg_residual_blocks(int64_t rows, int na) {
 
 void launch_active_residual(const double* X, int64_t ldx, const double* AX, int64_t ldax,
                             const double* theta, const int* act, int na, double* W, int64_t ldw,
-                            const double* lamh, int N, int64_t rows, double* part, double* ke,
+                            const double* lam, int64_t rows, double* part, double* ke,
                             hipStream_t s) {
   const int nb = lobpcg_residual_blocks(rows, na);
   k_active_residual<<<dim3(nb, na), kThreads, 0, s>>>(X, ldx, AX, ldax, theta, act, W, ldw,
-                                                      lamh, N, rows, part);
+                                                      lam, rows, part);
   k_kinetic_per_norm<<<(na + 255) / 256, 256, 0, s>>>(part, nb, na, ke);
 }
 
-void launch_tpa_scale(double* W, int64_t ldw, int na, const double* ke, const double* lamh, int N,
+void launch_tpa_scale(double* W, int64_t ldw, int na, const double* ke, const double* lam,
                       double g_scale, int64_t rows, hipStream_t s) {
-  k_tpa_scale<<<dim3(stream_blocks(rows, na), na), kThreads, 0, s>>>(W, ldw, ke, lamh, N, g_scale,
+  k_tpa_scale<<<dim3(stream_blocks(rows, na), na), kThreads, 0, s>>>(W, ldw, ke, lam, g_scale,
                                                                     rows);
 }
 

@@ -41,15 +41,20 @@ template <typename T, int MT, int CK, bool ONE>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
                                                              int64_t ldx, T* __restrict__ G,
+                                                             const int* __restrict__ lay,
                                                              int L, int N, int n_r, int k,
                                                              int kp) {
   typedef typename MF<T>::acc acc_t;
   constexpr int CW = 16 * RI_NT, XW = CW + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Xs = reinterpret_cast<T*>(smem_raw);  // [N16][XW]  X[n][i]
-  const int N4 = rup(N, 4), N16 = rup(N, 16), R16 = rup(n_r, 16);
+  const int N4 = rup(N, 4), R16 = rup(n_r, 16);
   const int lm = blockIdx.y;
   const int l = isqrt_lm(lm);
+  // this l's radial functions: N_l of them from coefficient off_l + (l + m) N_l
+  const int Nl = lay[2 * l + 1];
+  const int64_t xbase = lay[2 * l] + static_cast<int64_t>(lm - l * l) * Nl;
+  const int N16l = rup(Nl, 16);
   const int i0 = blockIdx.x * CW;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -77,17 +82,20 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
     // X tile: thread (column ii, rows n0 + 8 q), every load issued before the
     // LDS writes; N16 <= 4 CK rows in one chunk, N <= 192 otherwise
     constexpr int XQ = ONE ? CK / 2 : 24;
-    const T* Xl = X + static_cast<int64_t>(lm) * N;
+    // an l with no radial functions (N_l = 0) reads coefficient 0 and stores
+    // only zeros
+    const T* Xl = X + (Nl > 0 ? xbase : 0);
     const int ii = threadIdx.x >> 3, n0 = threadIdx.x & 7;
     const bool iok = i0 + ii < k;
     const T* xc = Xl + static_cast<int64_t>(min(i0 + ii, k - 1)) * ldx;
+    const int nlast = max(Nl - 1, 0);
     T xv[XQ];
 #pragma unroll
-    for (int q = 0; q < XQ; ++q) xv[q] = xc[min(n0 + 8 * q, N - 1)];
+    for (int q = 0; q < XQ; ++q) xv[q] = xc[min(n0 + 8 * q, nlast)];
 #pragma unroll
     for (int q = 0; q < XQ; ++q) {
       const int n = n0 + 8 * q;
-      if (n < N16) Xs[n * XW + ii] = (iok && n < N) ? xv[q] : T(0);
+      if (n < N16l) Xs[n * XW + ii] = (iok && n < Nl) ? xv[q] : T(0);
     }
   }
   __syncthreads();
@@ -108,20 +116,21 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
       for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = MF<T>::mma(av, b[nt], acc[u][nt]);
     }
   };
+  // the contraction runs over the N16l rows Xs holds (zero past N_l)
   if constexpr (ONE) {                            // whole contraction in one chunk (N16 <= 4 CK)
 #pragma unroll
     for (int t = 0; t < CK; ++t) {
-      if (4 * t >= N16) break;                    // Xs holds N16 rows
+      if (4 * t >= N16l) break;
       step(t * 4 + kk, ca[t]);
     }
   } else {
-    const int nch = (N16 + 4 * CK - 1) / (4 * CK);
+    const int nch = (N16l + 4 * CK - 1) / (4 * CK);
     T na[CK][MT];
     for (int c = 0; c < nch; ++c) {
       if (c + 1 < nch) load(c + 1, na);
 #pragma unroll
       for (int t = 0; t < CK; ++t) {
-        if (c * 4 * CK + 4 * t >= N16) break;
+        if (c * 4 * CK + 4 * t >= N16l) break;
         step(c * 4 * CK + t * 4 + kk, ca[t]);
       }
 #pragma unroll
@@ -157,16 +166,21 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
     const T* __restrict__ Yin, int64_t ldin, const T* __restrict__ Yold, int64_t ldold,
     T* __restrict__ out, int64_t ldout, T alpha, T cshift, T beta, int kinetic,
-    const T* __restrict__ Zkb, int64_t d, int L, int N, int n_r, int k, int kp) {
+    const T* __restrict__ Zkb, const int* __restrict__ lay, int64_t d, int L, int N, int n_r,
+    int k, int kp) {
   typedef typename MF<T>::acc acc_t;
   const int R4 = rup(n_r, 4), N16 = rup(N, 16);
   const int lm = blockIdx.y;
   const int l = isqrt_lm(lm);
+  // this l's radial functions: rows n < N_l at coefficient off_l + (l + m) N_l + n
+  const int Nl = lay[2 * l + 1];
+  if (Nl == 0) return;   // no coefficients for this l
+  const int64_t obase = lay[2 * l] + static_cast<int64_t>(lm - l * l) * Nl;
   const int i0 = blockIdx.x * (16 * RI_NT);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
-  const int nmt = N16 / 16;
+  const int nmt = rup(Nl, 16) / 16;
   int mrow[MT];
 #pragma unroll
   for (int u = 0; u < MT; ++u) mrow[u] = min(wave + 4 * u, nmt - 1) * 16;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   auto epi_load = [&](const T* Y, int64_t ld, T (*y)[RI_NT][4 * EP + 1 - EP]) {
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
-      const int64_t row = static_cast<int64_t>(lm) * N + min(mrow[u] + l16, N - 1);
+      const int64_t row = obase + min(mrow[u] + l16, Nl - 1);
 #pragma unroll
       for (int nt = 0; nt < RI_NT; ++nt)
 #pragma unroll
@@ -259,8 +273,8 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
     const int n = mt * 16 + l16;
-    if (n >= N) continue;
-    const int64_t row = static_cast<int64_t>(lm) * N + n;
+    if (n >= Nl) continue;
+    const int64_t row = obase + n;
     const T kin = kinetic ? lamh[static_cast<int64_t>(l) * N + n] - cshift : T(0);
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) {
@@ -294,10 +308,10 @@ void radial_inverse_ck(const Basis& b, const DevTables<T>& tb, const T* X, int64
   const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 1) * sizeof(T);
   const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
   switch (mt) {
-    case 1: k_radial_inverse_mfma<T, 1, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 2: k_radial_inverse_mfma<T, 2, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    case 3: k_radial_inverse_mfma<T, 3, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
-    default: k_radial_inverse_mfma<T, 4, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.L, b.N, b.n_r, k, kp); break;
+    case 1: k_radial_inverse_mfma<T, 1, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+    case 2: k_radial_inverse_mfma<T, 2, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+    case 3: k_radial_inverse_mfma<T, 3, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+    default: k_radial_inverse_mfma<T, 4, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
   }
 }
 
@@ -318,13 +332,13 @@ void radial_forward_ck(const Basis& b, const DevTables<T>& tb, const T* A, const
   const int kin = kinetic ? 1 : 0;
   switch (mt) {
     case 1: k_radial_forward_mfma<T, 1, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                    ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                    ldout, alpha, cshift, beta, kin, Zkb, b.dev_lay, b.d, b.L, b.N,
                                                     b.n_r, k, kp); break;
     case 2: k_radial_forward_mfma<T, 2, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                    ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                    ldout, alpha, cshift, beta, kin, Zkb, b.dev_lay, b.d, b.L, b.N,
                                                     b.n_r, k, kp); break;
     default: k_radial_forward_mfma<T, 3, CK, ONE><<<grid, 256, 0, s>>>(tb.RfT, A, tb.lamh, Yin, ldin, Yold, ldold, out,
-                                                     ldout, alpha, cshift, beta, kin, Zkb, b.d, b.L, b.N,
+                                                     ldout, alpha, cshift, beta, kin, Zkb, b.dev_lay, b.d, b.L, b.N,
                                                      b.n_r, k, kp); break;
   }
 }

@@ -175,7 +175,7 @@ void launch_anderson_combine(const double* V, const double* F, int64_t ld, const
 void launch_sad_density(const Basis& b, const double* atoms, int n_atoms, const double* cn,
                         double* rho, hipStream_t s) {
   k_sad_density<<<grid1d(b.n_grid), 256, 0, s>>>(b.dev_rnode, b.dev_cth, b.dev_sth, b.dev_cs,
-                                                 atoms, n_atoms, cn, b.N, b.R, b.n_theta,
+                                                 atoms, n_atoms, cn, b.Nl[0], b.R, b.n_theta,
                                                  b.n_phi, b.n_grid, rho);
 }
 

@@ -286,9 +286,9 @@ ces_status ces_lobpcg(ces_ham hh, int k, double* d_X, int64_t ldx, int n_lock, c
     CES_HIP(hipMemsetAsync(L.info, 0, 8 * sizeof(int), s));
     double* W = S + int64_t(k) * d;
     double* AW = AS + int64_t(k) * d;
-    launch_active_residual(S, d, AS, d, evm, act_d, na, W, d, b.t64.lamh, b.N, d,
+    launch_active_residual(S, d, AS, d, evm, act_d, na, W, d, b.dev_lam, d,
                            L.at<double>(ly.rpart), L.at<double>(ly.ke), s);
-    if (precondition) launch_tpa_scale(W, d, na, L.at<double>(ly.ke), b.t64.lamh, b.N, g_scale, d, s);
+    if (precondition) launch_tpa_scale(W, d, na, L.at<double>(ly.ke), b.dev_lam, g_scale, d, s);
     CES_TRY(L.project_out(W, na, d_Y, ldy, n_lock));
     CES_TRY(L.cholqr(W, nullptr, na, L.info));
     bool use_p = have_p;

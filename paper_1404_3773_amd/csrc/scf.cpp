@@ -390,11 +390,12 @@ ces_status ces_sad_density(ces_ham hh, int n_atoms, const double* h_atoms,
     return fail(CES_ERR_INVALID_ARG, "bad SAD arguments");
   Layout ly;
   CES_TRY(check_work(h, 1, CES_PREC_FP64, d_work, work_bytes, ly));
-  if (3 * int64_t(n_atoms) + b.N > 3 * b.d) return fail(CES_ERR_INVALID_ARG, "too many atoms");
+  const int N0 = b.Nl[0];   // the l = 0 radial functions of the layout
+  if (3 * int64_t(n_atoms) + N0 > 3 * b.d) return fail(CES_ERR_INVALID_ARG, "too many atoms");
   // rho_at(r) = Y_00 sum_n tau00[n] R_0n(r); R_0n = sqrt(2/R^3) j0(k_n r) / j1(b_0n)
-  std::vector<double> buf(3 * size_t(n_atoms) + b.N);
+  std::vector<double> buf(3 * size_t(n_atoms) + N0);
   const double c0 = std::sqrt(2.0 / (b.R * b.R * b.R)) / std::sqrt(4.0 * M_PI);
-  for (int n = 0; n < b.N; ++n) {
+  for (int n = 0; n < N0; ++n) {
     const double z = b.zeros[n];
     if (std::fabs(z - (n + 1) * M_PI) > 1e-9 * z)
       return fail(CES_ERR_DEVICE, "l = 0 radial zeros are not multiples of pi");

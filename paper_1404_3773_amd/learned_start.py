@@ -66,7 +66,7 @@ class Context:
         _, self.atom_steps, _, rho1 = self.scf(a1, None, ATOM_X0_SEED, n_occ=1, n_guard=4)
         coef = torch.empty((1, self.B.d), dtype=torch.float64, device="cuda")
         self.H.from_grid(rho1, coef, self.work)
-        self.tau00 = coef.cpu().numpy()[0, :self.B.N].copy()
+        self.tau00 = coef.cpu().numpy()[0, :int(self.B.Nl[0])].copy()
 
     def _dev(self, a):
         return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()

@@ -65,6 +65,34 @@ def test_basis_argument_validation():
     assert lib.ces_status_string(5) == b"CES_ERR_NOT_POSITIVE_DEFINITE"
 
 
+@pytest.mark.parametrize("e_cut", [0.31, 1.07, 2.9, 40.0])
+def test_ke_cutoff_basis_layout_matches_oracle(e_cut):
+    """N_l and d of the cutoff basis equal the oracle's count of the spherical
+    waves with Lambda / 2 <= e_cut (cutoffs chosen away from every level, so
+    the comparison is exact)."""
+    w = si.C1
+    bs = ob.basis_for(w)
+    half_lam = 0.5 * (bs.b / bs.R) ** 2
+    assert np.min(np.abs(half_lam - e_cut)) > 1e-6 * e_cut
+    B = ces.Basis.for_workload(w, e_cut=e_cut)
+    Nl = ob.ke_cutoff_counts(bs, e_cut)
+    assert np.array_equal(B.radial_counts(), Nl)
+    assert B.d == len(ob.ke_cutoff_index(bs, e_cut))
+    assert np.array_equal(ces.Basis.for_workload(w).radial_counts(), np.full(w.L, w.N))
+
+
+def test_ke_cutoff_basis_argument_validation():
+    lib = ces.load()
+    h = ctypes.c_void_p()
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.ces_basis_create_ke(8, 12, 10.0, 24, 18, 36, 0, bad, ctypes.byref(h)) == 1
+        assert b"cutoff" in lib.ces_last_error()
+    # below the lowest level (b_00^2 / (2 R^2) = 0.049 Ha at R = 10): nothing kept
+    assert lib.ces_basis_create_ke(8, 12, 10.0, 24, 18, 36, 0, 0.01, ctypes.byref(h)) == 1
+    assert b"keeps no" in lib.ces_last_error()
+    assert lib.ces_basis_radial_counts(None, None) == 1
+
+
 def test_large_basis_tables_are_finite():
     # L_max = 80, 150 radial functions: the deepest tables of the workloads
     B = ces.Basis(80, 150, 30.0, 225, 162, 324)
