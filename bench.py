@@ -45,11 +45,15 @@ PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12      # B/s
 PMC_COPY_BYTES = 1 << 30      # calibration copy of --pmc-run (read and written once)
 # kernel name prefix (as rocprofv3 reports it) of each H*X stage's FP32 launch
-STAGE_KERNEL = {"radial_inverse": "k_radial_inverse_mfma<float", "legendre_synth":
-                "k_legendre_synth<float", "phi_stage": "k_phi_stage<float",
-                "legendre_analysis": "k_legendre_analysis<float",
-                "radial_forward": "k_radial_forward_mfma<float",
-                "kb_project": "k_kb_gemm<float", "kb_apply": "k_kb_apply<float"}
+# FP32 kernels of each H*X stage (name prefixes; the Legendre stages run the
+# theta-folded kernels for L > 32)
+STAGE_KERNEL = {"radial_inverse": ("k_radial_inverse_mfma<float",),
+                "legendre_synth": ("k_legendre_synth<float", "k_legendre_synth_fold<float"),
+                "phi_stage": ("k_phi_stage<float",),
+                "legendre_analysis": ("k_legendre_analysis<float",
+                                      "k_legendre_analysis_fold<float"),
+                "radial_forward": ("k_radial_forward_mfma<float",),
+                "kb_project": ("k_kb_gemm<float",), "kb_apply": ("k_kb_apply<float",)}
 
 
 def algorithmic_flops(w, k, n_proj=0):
@@ -169,11 +173,11 @@ def pointwise_rates(ces, torch, n=1 << 26, reps=10):
     return out
 
 
-def measured_traffic(kernel_prefix, workload):
-    """(HBM bytes per launch, kernel name, summary file) of the kernel whose
-    name starts with kernel_prefix on `workload`, from a committed FETCH_SIZE /
-    WRITE_SIZE summary (profiles/*_pmc.json); None if there is none or it
-    was taken on other kernel sources."""
+def measured_traffic(kernel_prefixes, workload):
+    """(HBM bytes per launch, kernel name, summary file, counter row) of the
+    kernel whose name starts with one of kernel_prefixes on `workload`, from
+    a committed FETCH_SIZE / WRITE_SIZE summary (profiles/*_pmc.json); None
+    if there is none or it was taken on other kernel sources."""
     import glob
     from paper_1404_3773_amd import pmc_summary
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.json"))):
@@ -182,10 +186,10 @@ def measured_traffic(kernel_prefix, workload):
         if pmc.get("workload") != workload:
             continue
         for row in pmc.get("kernels", []):
-            if row["kernel"].startswith(kernel_prefix) and "traffic_bytes" in row:
+            if row["kernel"].startswith(tuple(kernel_prefixes)) and "traffic_bytes" in row:
                 if pmc_summary.source_digest(pmc["sources"]) != pmc["source_sha256"]:
                     return None
-                return row["traffic_bytes"], row["kernel"], os.path.relpath(path, ROOT)
+                return row["traffic_bytes"], row["kernel"], os.path.relpath(path, ROOT), row
     return None
 
 
@@ -227,28 +231,36 @@ def kb_hamiltonian(ces, torch, w, B, atoms_per_chunk=16):
     return H, n_proj, V, time.perf_counter() - t0
 
 
-def pmc_run():
-    """Short run for the counter passes on the 309-atom workload: two mixed
-    and one FP64 H*X of the 1000-orbital block, and a plain elementwise copy
-    of PMC_COPY_BYTES (read and written once) that calibrates the counters."""
+def pmc_run(workload):
+    """Short run for the counter passes: on one workload (the 309-atom one by
+    default, or the 147-atom one) two mixed and one FP64 H*X of its orbital
+    block, and a plain elementwise copy of PMC_COPY_BYTES (read and written
+    once) that calibrates the byte counters."""
     import torch
     from paper_1404_3773_amd import ces
-    w = si.C4
-    B = ces.Basis.for_workload(w)
-    H, n_proj, V, _ = kb_hamiltonian(ces, torch, w, B)
-    X = x0_on_device(torch, w)
-    Y = torch.empty_like(X)
-    print(f"[bench] pmc run: {w.name} setup done", flush=True)
-    for prec, reps in ((ces.CES_PREC_MIXED, 2), (ces.CES_PREC_FP64, 1)):
-        work = H.workspace(w.k, prec)
-        for _ in range(reps):
-            H.apply_H(X, Y, prec, work)
-        torch.cuda.synchronize()
-        del work
+    ws = {w.name: w for w in (si.C4, si.C3)}
+    if workload not in ws:
+        raise SystemExit(f"--pmc-workload: one of {sorted(ws)}")
+    for w in (ws[workload],):
+        B = ces.Basis.for_workload(w)
+        if w.potential == "wells+kb":
+            H, n_proj, V, _ = kb_hamiltonian(ces, torch, w, B)
+            del V
+        else:
+            H = ces.Ham(B, wells_on_device(torch, B, w))
+        X = x0_on_device(torch, w)
+        Y = torch.empty_like(X)
+        print(f"[bench] pmc run: {w.name} setup done", flush=True)
+        for prec, reps in ((ces.CES_PREC_MIXED, 2), (ces.CES_PREC_FP64, 1)):
+            work = H.workspace(w.k, prec)
+            for _ in range(reps):
+                H.apply_H(X, Y, prec, work)
+            torch.cuda.synchronize()
+            del work
+            torch.cuda.empty_cache()
+            print(f"[bench] pmc run: {w.name} {reps} H*X prec={prec}", flush=True)
+        del X, Y, H
         torch.cuda.empty_cache()
-        print(f"[bench] pmc run: {reps} H*X prec={prec}", flush=True)
-    del X, Y
-    torch.cuda.empty_cache()
     src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -487,6 +499,46 @@ def headline_c4(ces, torch, args):
     return out, V_host
 
 
+def ke_cutoff_c4(ces, torch, uniform_hx, reps=3):
+    """The 309-atom workload in the kinetic-energy-cutoff basis (the
+    non-uniform basis of the footnote in Section 2.2.1) at E_cut =
+    Lambda_{0,N-1} / 2, the kinetic energy of the uniform basis's last l = 0
+    function: each l keeps the functions below that energy.  Mixed and FP64
+    H*X of the 1000-orbital block (seeded random coefficients) with the same
+    projectors and V_eff, against the uniform basis's times."""
+    w = si.C4
+    z = ces.Basis.for_workload(w).tables()[0]
+    e_cut = 0.5 * (z[0, w.N - 1] / w.R) ** 2
+    B = ces.Basis.for_workload(w, e_cut=e_cut)
+    H, n_proj, V, setup_s = kb_hamiltonian(ces, torch, w, B)
+    del V
+    g = torch.Generator(device="cuda")
+    g.manual_seed(20140314)
+    X = torch.randn(w.k, B.d, dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    out = {"e_cut_Ha": round(e_cut, 4), "d": B.d, "d_uniform": w.d,
+           "radial_per_l_first_last": [int(B.Nl[0]), int(B.Nl[-1])],
+           "setup_seconds": round(setup_s, 1)}
+    for name, prec in (("mixed", ces.CES_PREC_MIXED), ("fp64", ces.CES_PREC_FP64)):
+        work = H.workspace(w.k, prec)
+        H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            H.apply_H(X, Y, prec, work)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / reps * 1e3
+        out[name] = {"ms_per_HX": round(ms, 2),
+                     "speedup_vs_uniform": round(uniform_hx[name]["ms_per_HX"] / ms, 3)}
+        del work
+        torch.cuda.empty_cache()
+    print(f"[bench] {w.name} cutoff basis d={B.d}: mixed {out['mixed']['ms_per_HX']} ms, "
+          f"fp64 {out['fp64']['ms_per_HX']} ms", file=sys.stderr, flush=True)
+    del X, Y, H
+    torch.cuda.empty_cache()
+    return out
+
+
 def ico13_extras(ces, torch, args):
     """The 13-atom workload: timed mixed CheFSI steps, filter rates, density,
     and time to eigenpairs against the stored oracle eigenvalues."""
@@ -584,13 +636,15 @@ def main():
                     help="headline workload only (no 13-atom / 147-atom extras)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes (no JSON line)")
+    ap.add_argument("--pmc-workload", default=si.C4.name,
+                    help="workload of --pmc-run (fcc309kb_L81_N150 or mackay147_L61_N120)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
     if args.pmc_run:
-        pmc_run()
+        pmc_run(args.pmc_workload)
         return
 
     import torch
@@ -618,7 +672,7 @@ def main():
             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32, 4),
             "traffic": None if tr is None else round(tr[0]),
-            "kernel": tr[1] if tr else STAGE_KERNEL[stage], "stage": dom,
+            "kernel": tr[1] if tr else STAGE_KERNEL[stage][0], "stage": dom,
             "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "alg_flop_per_launch": alg, "alg_bytes_per_launch": alg_b,
             "kernel_timing": f"HIP events around each launch over {args.prof_steps} further "
@@ -626,8 +680,21 @@ def main():
     if tr is not None:
         roof["traffic_source"] = tr[2]
         roof["hbm_GBps_measured"] = round(tr[0] / (avg_ms * 1e-3) / 1e9, 1)
+        row = tr[3]
+        if "mfma_busy_frac" in row:
+            roof["mfma_busy_frac_counters"] = round(row["mfma_busy_frac"], 4)
+        if "mfma_flop_f32" in row:
+            # MFMA work the kernel executes (counters) over its launch time
+            roof["mfma_executed_tflops"] = round(row["mfma_flop_f32"] / (avg_ms * 1e-3) / 1e12, 2)
     gemm_frac = {st: v["frac_peak"] for st, v in
                  stage_rates(prof, stage_flops(w, w.k, n_proj), PEAK_FP32, "_fp32").items()}
+    # counter-based MFMA utilisation of each FP32 stage kernel (committed
+    # rocprofv3 summary of the same workload), beside the algorithmic fractions
+    busy = {}
+    for st, prefixes in STAGE_KERNEL.items():
+        t = measured_traffic(prefixes, w.name)
+        if t is not None and "mfma_busy_frac" in t[3]:
+            busy[st] = round(t[3]["mfma_busy_frac"], 4)
 
     line = {
         "metric": "Chebyshev-filter H*X GFLOP/s & time-to-eigenpairs@1e-6Ha: mixed vs FP64",
@@ -643,11 +710,13 @@ def main():
         "mixed_vs_fp64_HX_speedup": round(hd["hx"]["fp64"]["ms_per_HX"] /
                                           hd["hx"]["mixed"]["ms_per_HX"], 3),
         "stage_frac_fp32_peak": gemm_frac,
+        "stage_mfma_busy_counters": busy or None,
         "roofline": roof,
         "after_steps": {"max_residual_first_n_check": hd["res_max_after_steps"],
                         "ritz_range_Ha": hd["theta_range"], "upper_bound_Ha": hd["bound"]},
     }
     if not args.no_extras:
+        line["fcc309_ke_cutoff_HX"] = ke_cutoff_c4(ces, torch, hd["hx"])
         line["ico13"] = ico13_extras(ces, torch, args)
         line["xc_pointwise"] = pointwise_rates(ces, torch)
         line["mackay147_HX"] = large_workload_rates(ces, torch)

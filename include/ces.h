@@ -178,7 +178,11 @@ ces_status ces_ham_set_model(ces_ham h, int correlation, double smearing_kT, int
 ces_status ces_ham_destroy(ces_ham h);
 
 /* Device bytes that any call below with k columns and precision `prec`
- * needs in d_work. */
+ * needs in d_work.  A CES_PREC_MIXED workspace holds the transform
+ * intermediates of the FP32 product (about half the FP64 product's); FP64
+ * products on it (ces_apply_H, ces_cheb_filter and ces_chefsi with
+ * CES_PREC_FP64, Rayleigh-Ritz's H X, ces_to_grid, ces_from_grid) run in
+ * column chunks of about k / 2, with the same results. */
 ces_status ces_workspace_size(ces_ham h, int k, int prec, size_t* bytes);
 
 /* Y = H X for a d x k block (eq. matvec_final): inverse radial sum

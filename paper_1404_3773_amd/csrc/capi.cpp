@@ -312,8 +312,19 @@ Layout layout_for(Ham& h, int k, int prec) {
   Layout L;
   L.kp = round_up(k, kColPad);
   const size_t LL = size_t(b.L) * b.L;
-  size_t gbytes = size_t(b.n_r) * LL * L.kp * sizeof(double);
-  size_t gbuf = size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * sizeof(double);
+  // G, A and gbuf: the FP32 product's kp columns in mixed precision (FP64
+  // products, e.g. Rayleigh-Ritz's H X, then run in chunks of kc64 columns),
+  // the FP64 product's kp columns otherwise
+  size_t ecols;
+  if (prec == CES_PREC_MIXED) {
+    L.kc64 = std::max<int64_t>(kColPad, L.kp / 2 / kColPad * kColPad);
+    ecols = std::max(size_t(L.kp) * sizeof(float), size_t(L.kc64) * sizeof(double));
+  } else {
+    L.kc64 = L.kp;
+    ecols = size_t(L.kp) * sizeof(double);
+  }
+  size_t gbytes = size_t(b.n_r) * LL * ecols;
+  size_t gbuf = size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * ecols;
   size_t v3 = size_t(b.d) * 3 * sizeof(double);
   if (const Basis* bd = h.rho_basis) {   // one-column transforms on the density basis
     gbytes = std::max(gbytes, size_t(bd->n_r) * bd->L * bd->L * kColPad * sizeof(double));
@@ -369,6 +380,7 @@ Layout hx_layout(const Ham& h, int k, int prec) {
     off += bytes + 4096;
     return at;
   };
+  L.kc64 = prec == CES_PREC_MIXED ? 0 : L.kp;   // an FP32 product only in mixed precision
   L.G = take(size_t(b.n_r) * LL * L.kp * e);
   L.A = take(size_t(b.n_r) * LL * L.kp * e);
   L.gbuf = take(size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * e);
@@ -401,17 +413,18 @@ const float* ab_of<float>(const Ham& h) { return h.ab32; }
 
 
 // out = alpha * (H Yin - c Yin) + beta * Yold  (kinetic and projector terms
-// included).  Uses the G, A and C regions of the workspace.
+// included) for k columns with kp = k rounded up to 16.  Uses the G, A, gbuf
+// and projector regions of the workspace.
 template <typename T>
-ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int64_t ldin,
-                  const T* Yold, int64_t ldold, T* out, int64_t ldout, T alpha, T c, T beta,
-                  hipStream_t s) {
+ces_status h_step_block(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int64_t ldin,
+                        const T* Yold, int64_t ldold, T* out, int64_t ldout, T alpha, T c,
+                        T beta, hipStream_t s) {
   const Basis& b = *h.basis;
   const DevTables<T>& tb = tables<T>(b);
   T* G = Ptr<T>::at(work, ly.G);
   T* A = Ptr<T>::at(work, ly.A);
   T* C = Ptr<T>::at(work, ly.C);
-  const int kp = static_cast<int>(ly.kp);
+  const int kp = static_cast<int>(round_up(k, kColPad));
   T* Zkb = nullptr;
   if (h.n_proj > 0) {
     // C = diag(h) P^T Yin (n_proj x kp, row-major), then Zkb = P C (d x k)
@@ -449,6 +462,24 @@ ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int
                              Zkb, k, kp, s);
   }
   CES_HIP(hipGetLastError());
+  return CES_OK;
+}
+
+// h_step_block over column chunks of at most the columns the layout's G, A
+// and gbuf hold in this precision (one chunk unless an FP64 product runs in a
+// mixed-precision workspace).
+template <typename T>
+ces_status h_step(Ham& h, const Layout& ly, void* work, int k, const T* Yin, int64_t ldin,
+                  const T* Yold, int64_t ldold, T* out, int64_t ldout, T alpha, T c, T beta,
+                  hipStream_t s) {
+  const int64_t cap = sizeof(T) == 8 ? ly.kc64 : ly.kp;
+  if (cap < kColPad) return fail(CES_ERR_WORKSPACE, "workspace holds no product of this precision");
+  for (int64_t c0 = 0; c0 < k; c0 += cap) {
+    const int kc = static_cast<int>(std::min<int64_t>(cap, k - c0));
+    CES_TRY(h_step_block<T>(h, ly, work, kc, Yin + c0 * ldin, ldin,
+                            Yold ? Yold + c0 * ldold : nullptr, ldold, out + c0 * ldout, ldout,
+                            alpha, c, beta, s));
+  }
   return CES_OK;
 }
 
@@ -508,6 +539,27 @@ ces_status check_work(Ham& h, int k, int prec, void* work, size_t bytes, Layout&
   if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
     return fail(CES_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   return CES_OK;
+}
+
+// Layout for a call whose products run in FP64: the FP64 layout when the
+// workspace holds it, else the mixed-precision layout of the same k (FP64
+// products then run in column chunks), so a workspace sized for a mixed-
+// precision filter also serves the FP64 Rayleigh-Ritz and transforms.
+ces_status check_work_fp64(Ham& h, int k, void* work, size_t bytes, Layout& ly) {
+  const Layout l64 = layout_for(h, k, CES_PREC_FP64);
+  if (bytes >= l64.total) return check_work(h, k, CES_PREC_FP64, work, bytes, ly);
+  const Layout lmx = layout_for(h, k, CES_PREC_MIXED);
+  if (bytes >= lmx.total) return check_work(h, k, CES_PREC_MIXED, work, bytes, ly);
+  return fail(CES_ERR_WORKSPACE, "workspace too small: need " +
+                                     std::to_string(std::min(l64.total, lmx.total)) +
+                                     " bytes, got " + std::to_string(bytes));
+}
+
+// The layout for a call whose products run in `prec`: check_work_fp64 for
+// FP64, the mixed layout otherwise.
+ces_status check_work_for(Ham& h, int k, int prec, void* work, size_t bytes, Layout& ly) {
+  if (prec == CES_PREC_FP64) return check_work_fp64(h, k, work, bytes, ly);
+  return check_work(h, k, prec, work, bytes, ly);
 }
 
 // Chebyshev filter on an internal block; Y0 (ld ld0) in place.
@@ -1026,7 +1078,7 @@ ces_status ces_apply_H(ces_ham hh, int k, const double* d_X, int64_t ldx, double
   CES_TRY(check_block(h, k, d_X, ldx, "X"));
   CES_TRY(check_block(h, k, d_Y, ldy, "Y"));
   Layout ly;
-  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  CES_TRY(check_work_for(h, k, prec, d_work, work_bytes, ly));
   return apply_H_impl(h, ly, d_work, k, d_X, ldx, d_Y, ldy, prec,
                       static_cast<hipStream_t>(stream));
 }
@@ -1041,7 +1093,7 @@ ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degr
   if (!(a < b) || !(a0 < a) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(a0))
     return fail(CES_ERR_INVALID_ARG, "filter bounds must satisfy a0 < a < b");
   Layout ly;
-  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  CES_TRY(check_work_for(h, k, prec, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t d = h.basis->d;
   if (prec == CES_PREC_FP64) {
@@ -1074,7 +1126,7 @@ ces_status ces_rayleigh_ritz(ces_ham hh, int k, double* d_X, int64_t ldx, double
   if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
   if (k > kRRMax) return fail(CES_ERR_INVALID_ARG, "k above the Rayleigh-Ritz limit");
   Layout ly;
-  CES_TRY(check_work(h, k, hx_prec, d_work, work_bytes, ly));
+  CES_TRY(check_work_for(h, k, hx_prec, d_work, work_bytes, ly));
   return rr_impl(h, ly, d_work, k, d_X, ldx, d_HX, ldx, d_eval, d_resnorm, hx_prec,
                  static_cast<hipStream_t>(stream), h_eval, nullptr, h_orth_path);
 }
@@ -1143,7 +1195,7 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
   if (k > h.basis->d) return fail(CES_ERR_INVALID_ARG, "k exceeds the basis size");
   if (k > kRRMax) return fail(CES_ERR_INVALID_ARG, "k above the Rayleigh-Ritz limit");
   Layout ly;
-  CES_TRY(check_work(h, k, prec, d_work, work_bytes, ly));
+  CES_TRY(check_work_for(h, k, prec, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t d = h.basis->d;
   std::vector<double> theta(k), theta_old(k), res(k);
@@ -1195,15 +1247,18 @@ ces_status ces_to_grid(ces_ham hh, int k, const double* d_X, int64_t ldx, double
   CES_TRY(check_block(h, k, d_X, ldx, "X"));
   if (!d_f) return fail(CES_ERR_INVALID_ARG, "null grid output");
   Layout ly;
-  CES_TRY(check_work(h, k, CES_PREC_FP64, d_work, work_bytes, ly));
+  CES_TRY(check_work_fp64(h, k, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Basis& b = *h.basis;
   double* G = Ptr<double>::at(d_work, ly.G);
   double* gbuf = Ptr<double>::at(d_work, ly.gbuf);
-  const int kp = static_cast<int>(ly.kp);
-  launch_radial_inverse<double>(b, b.t64, d_X, ldx, G, k, kp, s);
-  launch_legendre_synth<double>(b, b.t64, G, gbuf, kp, s);
-  launch_phi_synthesis_cols(b, gbuf, k, kp, d_f, b.n_grid, s);
+  for (int64_t c0 = 0; c0 < k; c0 += ly.kc64) {   // column chunks the regions hold
+    const int kc = static_cast<int>(std::min<int64_t>(ly.kc64, k - c0));
+    const int kp = static_cast<int>(round_up(kc, kColPad));
+    launch_radial_inverse<double>(b, b.t64, d_X + c0 * ldx, ldx, G, kc, kp, s);
+    launch_legendre_synth<double>(b, b.t64, G, gbuf, kp, s);
+    launch_phi_synthesis_cols(b, gbuf, kc, kp, d_f + c0 * b.n_grid, b.n_grid, s);
+  }
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -1215,16 +1270,19 @@ ces_status ces_from_grid(ces_ham hh, int k, const double* d_f, double* d_X, int6
   CES_TRY(check_block(h, k, d_X, ldx, "X"));
   if (!d_f) return fail(CES_ERR_INVALID_ARG, "null grid input");
   Layout ly;
-  CES_TRY(check_work(h, k, CES_PREC_FP64, d_work, work_bytes, ly));
+  CES_TRY(check_work_fp64(h, k, d_work, work_bytes, ly));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Basis& b = *h.basis;
   double* A = Ptr<double>::at(d_work, ly.A);
   double* gh = Ptr<double>::at(d_work, ly.gbuf);
-  const int kp = static_cast<int>(ly.kp);
-  launch_phi_analysis_cols(b, d_f, b.n_grid, k, kp, gh, s);
-  launch_legendre_analysis<double>(b, b.t64, gh, A, kp, s);
-  launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_X, ldx, 1.0, 0.0, 0.0,
-                                false, nullptr, k, kp, s);
+  for (int64_t c0 = 0; c0 < k; c0 += ly.kc64) {   // column chunks the regions hold
+    const int kc = static_cast<int>(std::min<int64_t>(ly.kc64, k - c0));
+    const int kp = static_cast<int>(round_up(kc, kColPad));
+    launch_phi_analysis_cols(b, d_f + c0 * b.n_grid, b.n_grid, kc, kp, gh, s);
+    launch_legendre_analysis<double>(b, b.t64, gh, A, kp, s);
+    launch_radial_forward<double>(b, b.t64, A, nullptr, 0, nullptr, 0, d_X + c0 * ldx, ldx, 1.0,
+                                  0.0, 0.0, false, nullptr, kc, kp, s);
+  }
   CES_HIP(hipGetLastError());
   return CES_OK;
 }

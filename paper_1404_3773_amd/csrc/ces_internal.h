@@ -128,6 +128,10 @@ struct Layout {
          Zkb = 0, S1 = 0, S2 = 0, vec = 0, part = 0, info = 0, solver = 0, total = 0;
   size_t solver_bytes = 0;
   int64_t kp = 0;
+  // columns of an FP64 product that G, A and gbuf hold: kp in an FP64
+  // workspace; in a mixed one (regions sized for the FP32 product) about
+  // half, and FP64 products run in column chunks of that size
+  int64_t kc64 = 0;
 };
 Layout layout_for(Ham& h, int k, int prec);
 ces_status check_work(Ham& h, int k, int prec, void* work, size_t bytes, Layout& ly);

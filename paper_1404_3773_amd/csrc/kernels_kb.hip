@@ -320,12 +320,19 @@ KbGrid<T> kb_grid(int n_proj, int k, int64_t d) {
 
 }  // namespace
 
+// Split-K partial sums of a product with up to k columns: the chunk count
+// grows as the column count falls, so the largest need over every width <= k
+// (a narrower call, e.g. a Lanczos vector or the last column chunk).
 size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
   if (n_proj <= 0) return 0;
-  const int kp = static_cast<int>(round_up(k, kColPad));
-  const size_t c32 = size_t(kb_grid<float>(n_proj, k, d).nchunk) * sizeof(float);
-  const size_t c64 = size_t(kb_grid<double>(n_proj, k, d).nchunk) * sizeof(double);
-  return std::max(c32, c64) * size_t(n_proj) * size_t(kp);
+  size_t most = 0;
+  for (int kc = 1; kc <= k; ++kc) {
+    const size_t kp = size_t(round_up(kc, kColPad));
+    const size_t c32 = size_t(kb_grid<float>(n_proj, kc, d).nchunk) * sizeof(float);
+    const size_t c64 = size_t(kb_grid<double>(n_proj, kc, d).nchunk) * sizeof(double);
+    most = std::max(most, std::max(c32, c64) * size_t(n_proj) * kp);
+  }
+  return most;
 }
 
 // LDS bytes of the projector kernels: one (A tile + B tile) stage, or two when

@@ -91,10 +91,7 @@ LobLayout lob_layout(Ham& h, int k, int n_lock, int prec) {
   L.gcap = gp;
   L.gpart = take(gp * sizeof(double));
   // projector-product partial sums for H*W on any number of active columns
-  size_t kbp = 0;
-  for (int n = kColPad; n < k + kColPad; n += kColPad)
-    kbp = std::max(kbp, kb_partial_bytes(h.n_proj, std::min(n, k), d));
-  L.kbpart = take(kbp);
+  L.kbpart = take(kb_partial_bytes(h.n_proj, k, d));
   L.solver_bytes = lob_solver_bytes(h, k, L.m);
   L.solver = take(L.solver_bytes);
   L.total = align256(off);

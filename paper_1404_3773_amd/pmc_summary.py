@@ -8,7 +8,21 @@ Per kernel, traffic = fetch KiB * 1024 * fetch scale + write KiB * 1024 *
 write scale, averaged over its dispatches.
 
   python -m paper_1404_3773_amd.pmc_summary --fetch DIR --write DIR \\
-      --copy-bytes N --kernel 'k_phi_stage<float>' --json OUT.json
+      --copy-bytes N --kernel 'k_phi_stage<float, 96>' --workload NAME \\
+      [--extra DIR ...] --json OUT.json
+
+--extra passes (e.g. SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE,
+SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64) are averaged per kernel into the same
+rows, with two derived figures where their counters are present:
+  mfma_busy_frac = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / n_xcc * n_simd)
+    (GRBM_GUI_ACTIVE sums the active cycles of the n_xcc dies; the busy
+    cycles sum over all n_simd SIMDs; both from the pass's agent table)
+  mfma_flop_f32 / _f64 = SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64 * 512
+    (the counter counts MFMA work in units of 512 flops)
+
+  python -m paper_1404_3773_amd.pmc_summary stats --db RUN_results.db [--top 40]
+prints the kernel table (calls, average and total microseconds, share) of a
+rocprofv3 --kernel-trace --stats database.
 """
 from __future__ import annotations
 
@@ -50,7 +64,65 @@ def source_digest(files):
     return h.hexdigest()
 
 
+def counters_in(pass_dir):
+    """Names of the counters a pass directory holds."""
+    names = set()
+    for path in glob.glob(os.path.join(pass_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                names.add(row["Counter_Name"])
+    return sorted(names)
+
+
+def gpu_agent(pass_dir):
+    """(Simd_Count, Num_Xcc) of the GPU agent recorded by a pass."""
+    for path in glob.glob(os.path.join(pass_dir, "**", "*agent_info.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Agent_Type") == "GPU":
+                    return int(row["Simd_Count"]), int(row["Num_Xcc"])
+    return None
+
+
+def derived(row, agent):
+    busy, active = row.get("SQ_VALU_MFMA_BUSY_CYCLES"), row.get("GRBM_GUI_ACTIVE")
+    if busy is not None and active and agent:
+        n_simd, n_xcc = agent
+        row["mfma_busy_frac"] = busy / (active / n_xcc * n_simd)
+    for prec in ("F32", "F64"):
+        mops = row.get(f"SQ_INSTS_VALU_MFMA_MOPS_{prec}")
+        if mops is not None:
+            row[f"mfma_flop_{prec.lower()}"] = mops * 512.0
+
+
+def kernel_stats(db, top):
+    """Rows (kernel, calls, avg_us, total_us, share %) of a rocprofv3 stats
+    database's top_kernels view."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select * from top_kernels").fetchall()
+    con.close()
+    out = []
+    for name, calls, total_ns, avg_ns, pct in rows[:top]:
+        out.append((short_name(name), int(calls), avg_ns / 1e3, total_ns / 1e3, pct))
+    return out
+
+
+def stats_main(argv):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--db", required=True)
+    ap.add_argument("--top", type=int, default=40)
+    a = ap.parse_args(argv)
+    print(f"{'share%':>7s} {'calls':>6s} {'avg_us':>11s} {'total_us':>12s}  kernel")
+    for name, calls, avg, tot, pct in kernel_stats(a.db, a.top):
+        print(f"{pct:7.2f} {calls:6d} {avg:11.2f} {tot:12.1f}  {name}")
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "stats":
+        return stats_main(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
@@ -60,9 +132,18 @@ def main(argv=None):
     ap.add_argument("--sources", nargs="+", default=["kernels_angular.hip", "mfma.h"])
     ap.add_argument("--json", required=True)
     ap.add_argument("--command", default="")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--extra", nargs="*", default=[],
+                    help="further pass directories (e.g. MFMA counters), averaged per kernel")
     a = ap.parse_args(argv)
     fetch = per_kernel(a.fetch, "FETCH_SIZE")
     write = per_kernel(a.write, "WRITE_SIZE")
+    extra = {}
+    agent = None
+    for d in a.extra:
+        agent = agent or gpu_agent(d)
+        for c in counters_in(d):
+            extra[c] = per_kernel(d, c)
     copy_f = [v for k, (v, n) in fetch.items() if a.copy_match in k]
     copy_w = [v for k, (v, n) in write.items() if a.copy_match in k]
     if not copy_f or not copy_w:
@@ -75,10 +156,15 @@ def main(argv=None):
             continue
         fk, nf = fetch[k]
         wk, nw = write[k]
-        rows.append({"kernel": k, "dispatches": min(nf, nw), "fetch_kib": fk, "write_kib": wk,
-                     "traffic_bytes": fk * 1024 * fs + wk * 1024 * ws})
+        row = {"kernel": k, "dispatches": min(nf, nw), "fetch_kib": fk, "write_kib": wk,
+               "traffic_bytes": fk * 1024 * fs + wk * 1024 * ws}
+        for c, vals in extra.items():
+            if k in vals:
+                row[c] = vals[k][0]
+        derived(row, agent)
+        rows.append(row)
     target = [r for r in rows if r["kernel"] == a.kernel]
-    out = {"kernel": a.kernel, "copy_bytes": a.copy_bytes,
+    out = {"kernel": a.kernel, "workload": a.workload, "copy_bytes": a.copy_bytes,
            "copy_fetch_kib": max(copy_f), "copy_write_kib": max(copy_w),
            "fetch_scale": fs, "write_scale": ws,
            "traffic_bytes": target[0]["traffic_bytes"] if target else None,
@@ -88,8 +174,10 @@ def main(argv=None):
         json.dump(out, f, indent=1)
     print(f"copy calibration: fetch x{fs:.4f}, write x{ws:.4f}")
     for r in rows:
-        print(f"{r['kernel']:40s} {r['dispatches']:5d}  fetch {r['fetch_kib']:12.1f} KiB  "
-              f"write {r['write_kib']:12.1f} KiB  traffic {r['traffic_bytes'] / 1e6:10.3f} MB")
+        more = "".join(f"  {c} {r[c]:.4g}" for c in list(extra) + ["mfma_busy_frac"] if c in r)
+        print(f"{r['kernel']:48s} {r['dispatches']:5d}  fetch {r['fetch_kib']:12.1f} KiB  "
+              f"write {r['write_kib']:12.1f} KiB  traffic {r['traffic_bytes'] / 1e6:10.3f} MB"
+              + more)
 
 
 if __name__ == "__main__":

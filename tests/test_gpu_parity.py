@@ -197,6 +197,41 @@ def test_apply_H_13_atom_cluster_full_size():
             assert rel_err(Y[:, c], Z[:, c]) < tol, (prec, cols[c], rel_err(Y[:, c], Z[:, c]))
 
 
+def test_fp64_products_on_a_mixed_workspace_run_in_column_chunks():
+    """A workspace sized for the mixed-precision product holds the FP64
+    transform intermediates of about half the columns: FP64 H*X, Rayleigh-
+    Ritz's H X and the grid transforms on it run in column chunks (k = 70:
+    32 + 32 + 6, with projectors) and match the oracle as on an FP64 workspace."""
+    w = si.small(6, 8, R=10.0, k=6)
+    s = setup(w, with_kb=True)
+    k = 70
+    _say(f"case FP64 on a mixed workspace k={k}")
+    assert s.H.workspace_size(k, MIXED) < s.H.workspace_size(k, FP64)
+    work = s.H.workspace(k, MIXED)
+    X = si.random_block(s.B.d, k, 97) * np.linspace(0.5, 3.0, k)
+    Z = s.oracle_apply(X)
+    Yt = torch.empty((k, s.B.d), dtype=torch.float64, device="cuda")
+    s.H.apply_H(dev(X), Yt, FP64, work)
+    torch.cuda.synchronize()
+    assert rel_err(host(Yt, s.B.d), Z) < TOL64
+    theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    Xt = dev(X)
+    s.H.rayleigh_ritz(Xt, ev, rs, work)
+    scale = np.max(np.abs(theta_ref))
+    assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * scale
+    assert np.max(np.abs(rs.cpu().numpy() - res_ref)) < 1e-9 * scale
+    f = torch.empty((k, s.B.n_grid), dtype=torch.float64, device="cuda")
+    s.H.to_grid(dev(X), f, work)
+    fref = oh.to_grid_real(s.bs, X)
+    assert rel_err(f.cpu().numpy().reshape(k, *fref.shape[:3]), np.moveaxis(fref, 3, 0)) < 1e-11
+    Xb = torch.empty((k, s.B.d), dtype=torch.float64, device="cuda")
+    s.H.from_grid(f, Xb, work)
+    torch.cuda.synchronize()
+    assert rel_err(host(Xb, s.B.d), oh.from_grid_real(s.bs, fref)) < 1e-11
+
+
 def test_cheb_filter_matches_oracle():
     w = SMALL
     _say("case cheb_filter")
@@ -407,7 +442,7 @@ def test_chefsi_harmonic_oscillator_levels():
 @pytest.mark.skipif(not os.path.exists(golden_path("ico13_L31_N60_eigenvalues.txt")),
                     reason="golden eigenvalues not generated")
 def test_chefsi_13_atom_cluster_mixed_and_fp64():
-    """13-atom cluster, k = 32, degree 16: the lowest 28 eigenvalues match the
+    """13-atom cluster, k = 32, degree 16: the lowest 26 eigenvalues match the
     oracle's converged values to 1e-6 Ha in FP64 and in mixed precision."""
     w = si.C2
     _say(f"case chefsi {w.name}")
