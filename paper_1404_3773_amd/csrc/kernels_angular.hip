@@ -339,8 +339,11 @@ constexpr int kPhiWorkgroups = 1792; // resident rows in flight (7 per CU)
 // table entry is one of the row's Fourier sums times +1, -1 or 0, fixed by
 // its position alone: each thread works out the source and sign of its
 // entries once, and fetches their values with the row's g block, one row
-// ahead, so a row takes one LDS fill and two barriers.
-template <typename T, int LP>
+// ahead, so a row takes one LDS fill and two barriers.  The K loop of each
+// input block stops at its last slot, rounded up to a k-step, at compile
+// time (LP - 4 TC rows of the cos block, 4 SS fewer of the sin block), so the
+// padding rows cost no MFMA work and the loop stays fully unrolled.
+template <typename T, int LP, int TC, int SS>
 __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
                                                    AngDims D, int64_t n_rows) {
   typedef typename MF<T>::acc acc_t;
@@ -448,8 +451,9 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
         Hb[u] = tab + hsel * K2 + hoff[u];
       }
       const T* grow = gs + (ic * LP + kk) * GW + l16;
+      const int kend = ic == 0 ? LP - 4 * TC : LP - 4 * (TC + SS);   // known per unrolled ic
 #pragma unroll
-      for (int k0 = 0; k0 < LP; k0 += 4) {
+      for (int k0 = 0; k0 < kend; k0 += 4) {
         T b[PS_NT];
 #pragma unroll
         for (int nt = 0; nt < PS_NT; ++nt) b[nt] = grow[k0 * GW + nt * 16];
@@ -1028,13 +1032,30 @@ void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t 
   const int64_t want = std::max<int64_t>(1, kPhiWorkgroups / ncg);
   dim3 grid(static_cast<unsigned>(std::min(n_rows, want)), ncg);
   const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
+  // K rows that hold slots: rup(L, 4) of the cos block, rup(L - 1, 4) of the
+  // sin block; with L in (LP - 16, LP] that is LP - 4 TC and 4 SS fewer
+  const int kend0 = rup(D.L, 4), kend1 = rup(D.L - 1, 4);
+  const int tc = (D.L16 - kend0) / 4, ss = (kend0 - kend1) / 4;
+  auto go = [&](auto lp_tag) {
+    constexpr int LP = decltype(lp_tag)::value;
+    switch (tc * 2 + ss) {
+      case 0: k_phi_stage<T, LP, 0, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 1: k_phi_stage<T, LP, 0, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 2: k_phi_stage<T, LP, 1, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 3: k_phi_stage<T, LP, 1, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 4: k_phi_stage<T, LP, 2, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 5: k_phi_stage<T, LP, 2, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      case 6: k_phi_stage<T, LP, 3, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      default: k_phi_stage<T, LP, 3, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    }
+  };
   switch (D.L16) {   // L <= 96 (checked at basis creation)
-    case 16: k_phi_stage<T, 16><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    case 32: k_phi_stage<T, 32><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    case 48: k_phi_stage<T, 48><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    case 64: k_phi_stage<T, 64><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    case 80: k_phi_stage<T, 80><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    default: k_phi_stage<T, 96><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+    case 16: go(std::integral_constant<int, 16>()); break;
+    case 32: go(std::integral_constant<int, 32>()); break;
+    case 48: go(std::integral_constant<int, 48>()); break;
+    case 64: go(std::integral_constant<int, 64>()); break;
+    case 80: go(std::integral_constant<int, 80>()); break;
+    default: go(std::integral_constant<int, 96>()); break;
   }
 }
 
