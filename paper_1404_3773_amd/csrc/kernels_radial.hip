@@ -225,23 +225,40 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   };
   T ca[CK][MT], cb[CK][RI_NT];
   load(0, ca, cb);
-  // epilogue operands (lanes along n, registers along i): in the one-chunk
-  // form they are loaded with the contraction's, so the epilogue waits for
-  // nothing new; indices clamped into the block, invalid entries not stored
-  constexpr int EP = ONE ? 1 : 0;
-  T yin[MT][RI_NT][4 * EP + 1 - EP], yold[MT][RI_NT][4 * EP + 1 - EP];
-  auto epi_load = [&](const T* Y, int64_t ld, T (*y)[RI_NT][4 * EP + 1 - EP]) {
+  // epilogue operands (lanes along n, registers along i), indices clamped
+  // into the block, invalid entries not stored: in the one-chunk form they
+  // are loaded with the contraction's, so the epilogue waits for nothing new;
+  // in the streamed FP32 form (with the projector term too) they are loaded
+  // with the last chunk, in flight while its MFMAs run (in FP64 the registers
+  // would cost a wave per SIMD, so there they are read in the epilogue)
+  constexpr int EPR = (ONE || sizeof(T) == 4) ? 1 : 0;
+  constexpr int ZP = (!ONE && sizeof(T) == 4) ? 1 : 0;
+  T yin[MT][RI_NT][4 * EPR + 1 - EPR], yold[MT][RI_NT][4 * EPR + 1 - EPR];
+  T zk[MT][RI_NT][4 * ZP + 1 - ZP];
+  auto epi_load = [&](const T* Y, int64_t ld, T (*y)[RI_NT][4 * EPR + 1 - EPR])
+      __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
       const int64_t row = obase + min(mrow[u] + l16, Nl - 1);
 #pragma unroll
       for (int nt = 0; nt < RI_NT; ++nt)
 #pragma unroll
-        for (int v = 0; v < 4 * EP; ++v)
+        for (int v = 0; v < 4 * EPR; ++v)
           y[u][nt][v] = Y[min(i0 + nt * 16 + MF<T>::row(lane, v), k - 1) * ld + row];
     }
   };
-  if constexpr (EP) {
+  auto zkb_load = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < MT; ++u) {
+      const int64_t row = obase + min(mrow[u] + l16, Nl - 1);
+#pragma unroll
+      for (int nt = 0; nt < RI_NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4 * ZP; ++v)
+          zk[u][nt][v] = Zkb[static_cast<int64_t>(min(i0 + nt * 16 + MF<T>::row(lane, v), k - 1)) * d + row];
+    }
+  };
+  if constexpr (ONE) {
     if (kinetic) epi_load(Yin, ldin, yin);
     if (beta != T(0)) epi_load(Yold, ldold, yold);
   }
@@ -252,13 +269,11 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   } else {
     const int nch = (R4 + 4 * CK - 1) / (4 * CK);
     T na[CK][MT], nb[CK][RI_NT];
-    for (int c = 0; c < nch; ++c) {
-      if (c + 1 < nch) load(c + 1, na, nb);
+    // every chunk but the last is full
+    for (int c = 0; c + 1 < nch; ++c) {
+      load(c + 1, na, nb);
 #pragma unroll
-      for (int t = 0; t < CK; ++t) {
-        if (c * 4 * CK + 4 * t >= R4) break;
-        step(c * 4 * CK + 4 * t + kk, ca[t], cb[t]);
-      }
+      for (int t = 0; t < CK; ++t) step(c * 4 * CK + 4 * t + kk, ca[t], cb[t]);
 #pragma unroll
       for (int t = 0; t < CK; ++t) {
 #pragma unroll
@@ -266,6 +281,18 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
 #pragma unroll
         for (int nt = 0; nt < RI_NT; ++nt) cb[t][nt] = nb[t][nt];
       }
+    }
+    if constexpr (EPR) {
+      if (kinetic) epi_load(Yin, ldin, yin);
+      if (beta != T(0)) epi_load(Yold, ldold, yold);
+      if (Zkb) zkb_load();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int c = nch - 1;
+#pragma unroll
+    for (int t = 0; t < CK; ++t) {
+      if (c * 4 * CK + 4 * t >= R4) break;
+      step(c * 4 * CK + 4 * t + kk, ca[t], cb[t]);
     }
   }
 #pragma unroll
@@ -284,11 +311,12 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
         const int i = i0 + nt * 16 + MF<T>::row(lane, v);
         if (i >= k || i0 + nt * 16 >= kp) continue;
         T z = acc[u][nt][v];
-        if (Zkb) z += Zkb[static_cast<int64_t>(i) * d + row];
-        if (kinetic) z += kin * (EP ? yin[u][nt][v * EP] : Yin[static_cast<int64_t>(i) * ldin + row]);
+        if (Zkb) z += ZP ? zk[u][nt][v * ZP] : Zkb[static_cast<int64_t>(i) * d + row];
+        if (kinetic)
+          z += kin * (EPR ? yin[u][nt][v * EPR] : Yin[static_cast<int64_t>(i) * ldin + row]);
         T val = alpha * z;
         if (beta != T(0))
-          val += beta * (EP ? yold[u][nt][v * EP] : Yold[static_cast<int64_t>(i) * ldold + row]);
+          val += beta * (EPR ? yold[u][nt][v * EPR] : Yold[static_cast<int64_t>(i) * ldold + row]);
         out[static_cast<int64_t>(i) * ldout + row] = val;
       }
     }
