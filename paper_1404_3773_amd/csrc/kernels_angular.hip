@@ -599,10 +599,10 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 // (the middle node of an odd n_theta taken once), so the l + m even rows
 // contract the sums u(j) = gh(j) + gh(n-1-j) and the odd rows the differences
 // v(j) over the first half of the nodes: half the MFMA work of the direct
-// sum.  One m-slot per wave; ME / MO 16-row l-tiles of each parity (rows
-// l = m + par + 2 (16 tile + lane row)); theta in k-steps of four, CH steps
-// per chunk with the next chunk's operands in flight.
-template <typename T, int MH, int CH>
+// sum.  One m-slot per wave, NTA 16-column tiles; ME / MO 16-row l-tiles of
+// each parity (rows l = m + par + 2 (16 tile + lane row)); theta in k-steps
+// of four, CH steps per chunk with the next chunk's operands in flight.
+template <typename T, int MH, int CH, int NTA>
 __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restrict__ PwT,
                                                                 const T* __restrict__ g,
                                                                 T* __restrict__ A, AngDims D,
@@ -616,15 +616,15 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
   slot_to_m(s, D.L, m, sgn);
   const int r = blockIdx.x / n_ic;
   const int l16 = lane & 15, kk = lane >> 4;
-  const int i0 = (blockIdx.x - r * n_ic) * (16 * LA_NT);
-  const int nt_valid = min(LA_NT, (D.kp - i0) / 16);
+  const int i0 = (blockIdx.x - r * n_ic) * (16 * NTA);
+  const int nt_valid = min(NTA, (D.kp - i0) / 16);
   const int K = D.L - m;
   const int nme = ((K + 1) / 2 + 15) / 16, nmo = (K / 2 + 15) / 16;   // <= MH each
   const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
   const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp;
-  int col[LA_NT];
+  int col[NTA];
 #pragma unroll
-  for (int nt = 0; nt < LA_NT; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
+  for (int nt = 0; nt < NTA; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
   // table entry [m][j][q] = w_j P_{m+q}^m(t_j); row q = par + 2 (16 u + l16),
   // clamped into the padded row and masked where q >= K
   const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16;
@@ -634,17 +634,17 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
     qe[u] = 2 * (16 * u + l16);
     qo[u] = qe[u] + 1;
   }
-  acc_t ae[MH][LA_NT], ao[MH][LA_NT];
+  acc_t ae[MH][NTA], ao[MH][NTA];
 #pragma unroll
   for (int u = 0; u < MH; ++u)
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) {
+    for (int nt = 0; nt < NTA; ++nt) {
       ae[u][nt] = zero_acc<acc_t>();
       ao[u][nt] = zero_acc<acc_t>();
     }
   const int nst = (nh + 3) / 4;
   // step t: node j = 4t + kk (rows past nh read node nh - 1, zero weight)
-  auto load = [&](int t, T (&a)[2][MH], T (&bu)[LA_NT], T (&bv)[LA_NT])
+  auto load = [&](int t, T (&a)[2][MH], T (&bu)[NTA], T (&bv)[NTA])
       __attribute__((always_inline)) {
     const int j = min(4 * t + kk, nh - 1);
     const int jm = D.n_theta - 1 - j;
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
       if (u < nmo) a[1][u] = Pa[j * D.L16 + min(qo[u], D.L16 - 1)];
     }
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) {
+    for (int nt = 0; nt < NTA; ++nt) {
       const T x = gb[j * jstride + col[nt]];
       const T y = gb[jm * jstride + col[nt]];
       const bool mid = jm == j;
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
       bv[nt] = mid ? T(0) : x - y;
     }
   };
-  auto mma_step = [&](int t, const T (&a)[2][MH], const T (&bu)[LA_NT], const T (&bv)[LA_NT])
+  auto mma_step = [&](int t, const T (&a)[2][MH], const T (&bu)[NTA], const T (&bv)[NTA])
       __attribute__((always_inline)) {
     const bool okj = 4 * t + kk < nh;
 #pragma unroll
@@ -670,18 +670,18 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
       if (u < nme) {
         const T av = okj && qe[u] < K ? a[0][u] : T(0);
 #pragma unroll
-        for (int nt = 0; nt < LA_NT; ++nt) ae[u][nt] = MF<T>::mma(av, bu[nt], ae[u][nt]);
+        for (int nt = 0; nt < NTA; ++nt) ae[u][nt] = MF<T>::mma(av, bu[nt], ae[u][nt]);
       }
       if (u < nmo) {
         const T av = okj && qo[u] < K ? a[1][u] : T(0);
 #pragma unroll
-        for (int nt = 0; nt < LA_NT; ++nt) ao[u][nt] = MF<T>::mma(av, bv[nt], ao[u][nt]);
+        for (int nt = 0; nt < NTA; ++nt) ao[u][nt] = MF<T>::mma(av, bv[nt], ao[u][nt]);
       }
     }
   };
   // CH steps per chunk, loaded together, the next chunk in flight
   const int nch = (nst + CH - 1) / CH;
-  T ca[CH][2][MH], cu[CH][LA_NT], cv[CH][LA_NT], na[CH][2][MH], nu[CH][LA_NT], nv[CH][LA_NT];
+  T ca[CH][2][MH], cu[CH][NTA], cv[CH][NTA], na[CH][2][MH], nu[CH][NTA], nv[CH][NTA];
 #pragma unroll
   for (int t = 0; t < CH; ++t) load(t, ca[t], cu[t], cv[t]);
   for (int c = 0; c < nch; ++c) {
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
         ca[t][1][u] = na[t][1][u];
       }
 #pragma unroll
-      for (int nt = 0; nt < LA_NT; ++nt) {
+      for (int nt = 0; nt < NTA; ++nt) {
         cu[t][nt] = nu[t][nt];
         cv[t][nt] = nv[t][nt];
       }
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
 #pragma unroll
   for (int u = 0; u < MH; ++u) {
 #pragma unroll
-    for (int nt = 0; nt < LA_NT; ++nt) {
+    for (int nt = 0; nt < NTA; ++nt) {
       if (nt >= nt_valid) break;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -966,14 +966,17 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
                            hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
   if (b.L > 32) {
-    // folded in theta: one 16-row tile of the first half of the nodes per wave
+    // folded in theta: JT 16-row tiles of the first half of the nodes per wave
     const int nh = (b.n_theta + 1) / 2;
     const int ntile = (nh + 15) / 16;
-    constexpr int CH = sizeof(T) == 4 ? 8 : 4;
+    // FP32: two theta tiles per wave share each G fragment (measured 13.3 ->
+    // 12.6 ms at 309 atoms); FP64 keeps one for its registers
+    constexpr int JT = sizeof(T) == 4 ? 2 : 1;
+    constexpr int CH = 4;
     auto go = [&](auto nt_tag, int n_ic) {
       constexpr int NT = decltype(nt_tag)::value;
-      dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
-      k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      dim3 grid(b.n_r * n_ic, (ntile + 4 * JT - 1) / (4 * JT), D.S);
+      k_legendre_synth_fold<T, NT, JT, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
     };
     if (kp <= 32) return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
     return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
@@ -1067,13 +1070,18 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   constexpr bool f32 = sizeof(T) == 4;
   if (b.L > 32) {   // folded in theta; l-tiles of each parity cover ceil(L/2)
+    // FP32: 64 columns per wave share each table fragment (measured 8.85 ->
+    // 8.0 ms at 309 atoms); FP64 keeps 32 (64 measured slower)
+    constexpr int NTA = f32 ? 4 : 2;
+    const int n_icf = (kp + 16 * NTA - 1) / (16 * NTA);
+    dim3 gridf(b.n_r * n_icf, (D.S + LA_SW - 1) / LA_SW);
     const int nh = (b.n_theta + 1) / 2;
     if (b.L <= 64)
-      k_legendre_analysis_fold<T, 2, f32 ? 4 : 2><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic,
-                                                                       nh);
+      k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
+                                                                             n_icf, nh);
     else
-      k_legendre_analysis_fold<T, 3, f32 ? 4 : 2><<<grid, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_ic,
-                                                                       nh);
+      k_legendre_analysis_fold<T, 3, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
+                                                                             n_icf, nh);
     return;
   }
   // l-tiles per slot cover L; theta chunks sized to the registers left
