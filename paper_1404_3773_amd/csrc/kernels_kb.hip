@@ -167,12 +167,12 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 // result lane holds 16 consecutive alpha of one column, so stores are
 // coalesced.  Workgroups that read the same P tile (same alpha tile) share
 // an XCD.
-template <typename T, bool DB>
+template <typename T, bool DB, int KB>
 __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64_t d,
                                                   const T* __restrict__ C, int n_proj, int k,
                                                   int kp, T* __restrict__ Z, int nI, int nA) {
   typedef typename MF<T>::acc acc_t;
-  constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
+  constexpr int TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TN, BN = 32 * TM;      // i tile, alpha tile (2 x 2 waves)
   constexpr int KW = KB + 1;
   constexpr int RC = 256 / BM, RP = 256 / BN;    // q rows per staging pass
@@ -341,9 +341,8 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
 // (22.3 -> 24.3 ms), so only the former uses it (2 x 33.8 KB, two workgroups
 // per CU still fit).
 template <typename T>
-constexpr size_t kb_lds_bytes(bool db) {
-  return (db ? 2 : 1) *
-         size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * (KbShape<T>::KB + 1) * sizeof(T);
+constexpr size_t kb_lds_bytes(bool db, int kb = KbShape<T>::KB) {
+  return (db ? 2 : 1) * size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * (kb + 1) * sizeof(T);
 }
 
 // Allow more than the default 64 KB of dynamic LDS for a kernel that needs it
@@ -397,9 +396,10 @@ void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k,
   const int nI = (k + BM - 1) / BM;
   const int nA = static_cast<int>((d + BN - 1) / BN);
   const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
-  constexpr size_t lds = kb_lds_bytes<T>(false);
-  allow_lds(&k_kb_apply<T, false>, lds);
-  k_kb_apply<T, false><<<nwg, 256, lds, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
+  constexpr int KBA = KbShape<T>::KB;   // projectors per staged step
+  constexpr size_t lds = kb_lds_bytes<T>(false, KBA);
+  allow_lds(&k_kb_apply<T, false, KBA>, lds);
+  k_kb_apply<T, false, KBA><<<nwg, 256, lds, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
 }
 
 template void launch_kb_apply<float>(const float*, int64_t, const float*, float*, int, int, int,
