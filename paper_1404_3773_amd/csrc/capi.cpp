@@ -317,7 +317,8 @@ Layout layout_for(Ham& h, int k, int prec) {
   // the FP64 product's kp columns otherwise
   size_t ecols;
   if (prec == CES_PREC_MIXED) {
-    L.kc64 = std::max<int64_t>(kColPad, L.kp / 2 / kColPad * kColPad);
+    // half the columns (rounded up to 16), so an FP64 product takes two chunks
+    L.kc64 = round_up((L.kp + 1) / 2, kColPad);
     ecols = std::max(size_t(L.kp) * sizeof(float), size_t(L.kc64) * sizeof(double));
   } else {
     L.kc64 = L.kp;

@@ -969,14 +969,21 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
     // folded in theta: JT 16-row tiles of the first half of the nodes per wave
     const int nh = (b.n_theta + 1) / 2;
     const int ntile = (nh + 15) / 16;
-    // FP32: two theta tiles per wave share each G fragment (measured 13.3 ->
-    // 12.6 ms at 309 atoms); FP64 keeps one for its registers
-    constexpr int JT = sizeof(T) == 4 ? 2 : 1;
+    // FP32 with more than four tiles: two theta tiles per wave share each G
+    // fragment (309 atoms, six tiles: 13.3 -> 12.4 ms; with four tiles, as
+    // at 147 atoms, it would idle half of each workgroup's waves); FP64
+    // keeps one for its registers
     constexpr int CH = 4;
+    const bool jt2 = sizeof(T) == 4 && ntile > 4;
     auto go = [&](auto nt_tag, int n_ic) {
       constexpr int NT = decltype(nt_tag)::value;
-      dim3 grid(b.n_r * n_ic, (ntile + 4 * JT - 1) / (4 * JT), D.S);
-      k_legendre_synth_fold<T, NT, JT, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      if (jt2) {
+        dim3 grid(b.n_r * n_ic, (ntile + 7) / 8, D.S);
+        k_legendre_synth_fold<T, NT, 2, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      } else {
+        dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
+        k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      }
     };
     if (kp <= 32) return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
     return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
@@ -1070,18 +1077,25 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   constexpr bool f32 = sizeof(T) == 4;
   if (b.L > 32) {   // folded in theta; l-tiles of each parity cover ceil(L/2)
-    // FP32: 64 columns per wave share each table fragment (measured 8.85 ->
-    // 8.0 ms at 309 atoms); FP64 keeps 32 (64 measured slower)
-    constexpr int NTA = f32 ? 4 : 2;
-    const int n_icf = (kp + 16 * NTA - 1) / (16 * NTA);
-    dim3 gridf(b.n_r * n_icf, (D.S + LA_SW - 1) / LA_SW);
+    // FP32 on wide blocks: 64 columns per wave share each table fragment
+    // (309 atoms, kp = 1008: 8.85 -> 8.0 ms; 147 atoms, kp = 400, measured
+    // slower); FP64 keeps 32 (64 measured slower)
     const int nh = (b.n_theta + 1) / 2;
-    if (b.L <= 64)
-      k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
-                                                                             n_icf, nh);
+    auto go = [&](auto nta_tag) {
+      constexpr int NTA = decltype(nta_tag)::value;
+      const int n_icf = (kp + 16 * NTA - 1) / (16 * NTA);
+      dim3 gridf(b.n_r * n_icf, (D.S + LA_SW - 1) / LA_SW);
+      if (b.L <= 64)
+        k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
+                                                                               n_icf, nh);
+      else
+        k_legendre_analysis_fold<T, 3, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
+                                                                               n_icf, nh);
+    };
+    if (f32 && kp >= 512)
+      go(std::integral_constant<int, 4>());
     else
-      k_legendre_analysis_fold<T, 3, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
-                                                                             n_icf, nh);
+      go(std::integral_constant<int, 2>());
     return;
   }
   // l-tiles per slot cover L; theta chunks sized to the registers left

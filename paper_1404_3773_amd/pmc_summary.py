@@ -21,8 +21,12 @@ rows, with two derived figures where their counters are present:
     (the counter counts MFMA work in units of 512 flops)
 
   python -m paper_1404_3773_amd.pmc_summary stats --db RUN_results.db [--top 40]
-prints the kernel table (calls, average and total microseconds, share) of a
-rocprofv3 --kernel-trace --stats database.
+prints the kernel table (calls, average and total milliseconds, share) of a
+rocprofv3 --kernel-trace --stats database, and
+
+  python -m paper_1404_3773_amd.pmc_summary table SUMMARY.json [...]
+the MFMA kernels of summaries written by the first form: launches, MFMA busy,
+executed MFMA flop and traffic per launch.
 """
 from __future__ import annotations
 
@@ -56,11 +60,30 @@ def per_kernel(pass_dir, counter):
     return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
 
 
+def kernel_source(text, name):
+    """The source of the __global__ function `name` in `text`: from the
+    template line (if any) before its declaration to the closing brace at
+    the start of a line."""
+    m = re.search(r"__global__[^;{]*?\b" + re.escape(name) + r"\s*\(", text)
+    if not m:
+        raise SystemExit(f"kernel {name} not found")
+    start = m.start()
+    t = text.rfind("template", 0, start)
+    if t != -1 and text[t:start].count("\n") <= 1:
+        start = t
+    end = text.index("\n}\n", m.end()) + 3
+    return text[start:end]
+
+
 def source_digest(files):
+    """SHA-256 over the listed sources in csrc/: a whole file, or `file#kernel`
+    for one kernel's own source."""
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path, _, kern = f.partition("#")
+        with open(os.path.join(HERE, "csrc", path), encoding="utf-8") as fh:
+            text = fh.read()
+        h.update((kernel_source(text, kern) if kern else text).encode())
     return h.hexdigest()
 
 
@@ -96,15 +119,15 @@ def derived(row, agent):
 
 
 def kernel_stats(db, top):
-    """Rows (kernel, calls, avg_us, total_us, share %) of a rocprofv3 stats
-    database's top_kernels view."""
+    """Rows (kernel, calls, avg_ms, total_ms, share %) of a rocprofv3 stats
+    database's top_kernels view (which holds microseconds)."""
     import sqlite3
     con = sqlite3.connect(db)
     rows = con.execute("select * from top_kernels").fetchall()
     con.close()
     out = []
-    for name, calls, total_ns, avg_ns, pct in rows[:top]:
-        out.append((short_name(name), int(calls), avg_ns / 1e3, total_ns / 1e3, pct))
+    for name, calls, total_us, avg_us, pct in rows[:top]:
+        out.append((short_name(name), int(calls), avg_us / 1e3, total_us / 1e3, pct))
     return out
 
 
@@ -113,9 +136,23 @@ def stats_main(argv):
     ap.add_argument("--db", required=True)
     ap.add_argument("--top", type=int, default=40)
     a = ap.parse_args(argv)
-    print(f"{'share%':>7s} {'calls':>6s} {'avg_us':>11s} {'total_us':>12s}  kernel")
+    print(f"{'share%':>7s} {'calls':>6s} {'avg_ms':>11s} {'total_ms':>12s}  kernel")
     for name, calls, avg, tot, pct in kernel_stats(a.db, a.top):
-        print(f"{pct:7.2f} {calls:6d} {avg:11.2f} {tot:12.1f}  {name}")
+        print(f"{pct:7.2f} {calls:6d} {avg:11.3f} {tot:12.1f}  {name}")
+
+
+def table_main(paths):
+    print(f"# {'workload':18s}  {'kernel':44s}  {'launches':>8s}  {'mfma_busy':>9s}  "
+          f"{'mfma_Tflop':>10s}  {'traffic_GB':>10s}")
+    for path in paths:
+        with open(path) as f:
+            d = json.load(f)
+        for r in d["kernels"]:
+            fl = r.get("mfma_flop_f32", 0) + r.get("mfma_flop_f64", 0)
+            if "mfma_busy_frac" in r and fl > 0:
+                print(f"  {d['workload']:18s}  {r['kernel']:44s}  {r['dispatches']:8d}  "
+                      f"{r['mfma_busy_frac']:9.3f}  {fl / 1e12:10.3f}  "
+                      f"{r['traffic_bytes'] / 1e9:10.2f}")
 
 
 def main(argv=None):
@@ -123,13 +160,16 @@ def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "stats":
         return stats_main(argv[1:])
+    if argv and argv[0] == "table":
+        return table_main(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-bytes", type=float, required=True)
     ap.add_argument("--copy-match", default="elementwise")
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--sources", nargs="+", default=["kernels_angular.hip", "mfma.h"])
+    ap.add_argument("--sources", nargs="+", default=["kernels_angular.hip#k_phi_stage", "mfma.h"],
+                    help="sources the summary is valid for: files in csrc/, or file#kernel")
     ap.add_argument("--json", required=True)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")

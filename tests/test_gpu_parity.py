@@ -201,7 +201,7 @@ def test_fp64_products_on_a_mixed_workspace_run_in_column_chunks():
     """A workspace sized for the mixed-precision product holds the FP64
     transform intermediates of about half the columns: FP64 H*X, Rayleigh-
     Ritz's H X and the grid transforms on it run in column chunks (k = 70:
-    32 + 32 + 6, with projectors) and match the oracle as on an FP64 workspace."""
+    48 + 22, with projectors) and match the oracle as on an FP64 workspace."""
     w = si.small(6, 8, R=10.0, k=6)
     s = setup(w, with_kb=True)
     k = 70
