@@ -372,6 +372,60 @@ def large_time_to_eigenpairs(ces, torch):
     return out
 
 
+def c4_time_to_eigenpairs(ces, torch, max_iter=200):
+    """Time to eigenpairs on the 309-atom workload (k = 1000, n_check = 900,
+    degree 20, 1236 projectors) from the seeded start block, FP64 and mixed:
+    the Lanczos bound, a Rayleigh-Ritz of the start block, then filter +
+    Rayleigh-Ritz steps until the n_check lowest pairs meet res <= 1e-4
+    max(1, |theta|) and |delta theta| < 1e-7 (the test of ces_chefsi, run
+    step by step here so that every few steps report progress; about 1.5 and
+    1 minute).  The reference is the FP64 run (the CPU oracle cannot run this
+    size)."""
+    w = si.C4
+    B = ces.Basis.for_workload(w)
+    H, n_proj, V, setup_s = kb_hamiltonian(ces, torch, w, B)
+    del V
+    X0 = x0_on_device(torch, w)
+    k, nc = X0.shape[0], w.n_check
+    v0 = torch.from_numpy(si.lanczos_start(B.d)).cuda()
+    ev = torch.empty(k, dtype=torch.float64, device="cuda")
+    rs = torch.empty(k, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "orbitals": k, "n_check": nc, "degree": w.degree,
+           "projectors": n_proj, "setup_seconds": round(setup_s, 1)}
+    theta_end = {}
+    for name, prec in (("fp64", ces.CES_PREC_FP64), ("mixed", ces.CES_PREC_MIXED)):
+        work = H.workspace(k, prec)
+        X = X0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b = H.lanczos_bound(v0, work)
+        theta = H.rayleigh_ritz(X, ev, rs, work)
+        it, done = 0, False
+        while not done and it < max_iter:
+            it += 1
+            a0 = theta[0] if theta[0] < theta[-1] else theta[-1] - 1e-6 * max(1.0, abs(theta[-1]))
+            H.cheb_filter(X, w.degree, theta[-1], b, a0, prec, work)
+            old = theta
+            theta = H.rayleigh_ritz(X, ev, rs, work)
+            res = rs.cpu().numpy()
+            done = bool(np.all(res[:nc] <= 1e-4 * np.maximum(1.0, np.abs(theta[:nc])))
+                        and np.all(np.abs(theta[:nc] - old[:nc]) < 1e-7))
+            if it % 5 == 0 or done:
+                print(f"[bench] 309-atom eigenpairs {name}: step {it}, "
+                      f"{time.perf_counter() - t:.1f} s, max res {float(res[:nc].max()):.2e}",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        theta_end[name] = np.array(theta[:nc])
+        out[name] = {"seconds": round(sec, 2), "iterations": it, "converged": done}
+        del work, X
+        torch.cuda.empty_cache()
+    out["max_eig_diff_mixed_vs_fp64_Ha"] = float(np.max(np.abs(theta_end["mixed"] -
+                                                               theta_end["fp64"])))
+    out["mixed_speedup"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    return out
+
+
 def golden_eigenvalues(w):
     path = os.path.join(ROOT, "tests", "golden", f"{w.name}_eigenvalues.txt")
     if not os.path.exists(path):
@@ -707,11 +761,14 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=2,
                     help="further steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tte", action="store_true", help="skip time-to-eigenpairs runs")
+    ap.add_argument("--no-tte", action="store_true",
+                    help="skip the 147- and 309-atom time-to-eigenpairs runs")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no 13-atom / 147-atom extras)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes (no JSON line)")
+    ap.add_argument("--c4-tte", action="store_true",
+                    help="only the 309-atom time to eigenpairs, mixed and FP64 (minutes)")
     ap.add_argument("--pmc-workload", default=si.C4.name,
                     help="workload of --pmc-run (fcc309kb_L81_N150 or mackay147_L61_N120)")
     args = ap.parse_args()
@@ -726,6 +783,10 @@ def main():
     import torch
     from paper_1404_3773_amd import ces
 
+    if args.c4_tte:
+        print(json.dumps({"fcc309_time_to_eigenpairs": c4_time_to_eigenpairs(ces, torch)}),
+              flush=True)
+        return
     hd, V_host = headline_c4(ces, torch, args)
     w, F, prof, n_proj = hd["w"], hd["F"], hd["prof"], hd["n_proj"]
     ms_step = hd["dt"] / args.steps * 1e3
@@ -800,6 +861,8 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_tte:
             line["mackay147_time_to_eigenpairs"] = large_time_to_eigenpairs(ces, torch)
+            torch.cuda.empty_cache()
+            line["fcc309_time_to_eigenpairs"] = c4_time_to_eigenpairs(ces, torch)
             torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, V_host)
