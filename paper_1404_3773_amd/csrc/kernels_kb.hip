@@ -105,11 +105,12 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
     for (int p = 0; p < LB; ++p)
       Bs[(r0 + RA * p) * KW + kc] = okk && bcol0 + RA * p < k ? rb[p] : T(0);
   };
-  auto compute = [&](int buf) __attribute__((always_inline)) {
+  // k-steps [s0, s1) of the staged tiles in buffer `buf`
+  auto compute_steps = [&](int buf, int s0, int s1) __attribute__((always_inline)) {
     const T* Aw = lds + buf * STAGE + (wm * 16 * TM + c16) * KW + kk;
     const T* Bw = lds + buf * STAGE + BM * KW + (wn * 16 * TN + c16) * KW + kk;
 #pragma unroll
-    for (int st = 0; st < KB / 4; ++st) {
+    for (int st = s0; st < s1; ++st) {
       T a[TM], b[TN];
 #pragma unroll
       for (int u = 0; u < TM; ++u) a[u] = Aw[16 * u * KW + 4 * st];
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
         for (int v = 0; v < TN; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
     }
   };
+  auto compute = [&](int buf) __attribute__((always_inline)) { compute_steps(buf, 0, KB / 4); };
   if (k0 < k1) fetch(k0);
   if constexpr (DB) {
     if (k0 < k1) {
@@ -130,12 +132,14 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
     __syncthreads();
     int buf = 0;
     for (int64_t kb = k0; kb < k1; kb += KB) {
-      compute(buf);
-      // the other buffer was last read in the previous step, before its barrier
-      if (kb + KB < k1) {
-        stage(kb + KB, buf ^ 1);
-        if (kb + 2 * KB < k1) fetch(kb + 2 * KB);
-      }
+      // the other buffer was last read in the previous step, before its
+      // barrier: its LDS writes and the next global loads go out between the
+      // two halves of this step's MFMAs
+      const bool more = kb + KB < k1;
+      compute_steps(buf, 0, KB / 8);
+      if (more) stage(kb + KB, buf ^ 1);
+      compute_steps(buf, KB / 8, KB / 4);
+      if (more && kb + 2 * KB < k1) fetch(kb + 2 * KB);
       __syncthreads();
       buf ^= 1;
     }
@@ -225,11 +229,12 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
     for (int p = 0; p < LP; ++p)
       Ps[pa_ * KW + pq + RP * p] = aok && q0 + pq + RP * p < n_proj ? rp[p] : T(0);
   };
-  auto compute = [&](int buf) __attribute__((always_inline)) {
+  // k-steps [s0, s1) of the staged tiles in buffer `buf`
+  auto compute_steps = [&](int buf, int s0, int s1) __attribute__((always_inline)) {
     const T* Aw = lds + buf * STAGE + (wm * 16 * TN + c16) * KW + kk;
     const T* Bw = lds + buf * STAGE + BM * KW + (wn * 16 * TM + c16) * KW + kk;
 #pragma unroll
-    for (int st = 0; st < KB / 4; ++st) {
+    for (int st = s0; st < s1; ++st) {
       T a[TN], b[TM];
 #pragma unroll
       for (int u = 0; u < TN; ++u) a[u] = Aw[16 * u * KW + 4 * st];
@@ -241,6 +246,7 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
         for (int v = 0; v < TM; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
     }
   };
+  auto compute = [&](int buf) __attribute__((always_inline)) { compute_steps(buf, 0, KB / 4); };
   fetch(0);
   if constexpr (DB) {
     stage(0, 0);
@@ -248,11 +254,13 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
     __syncthreads();
     int buf = 0;
     for (int q0 = 0; q0 < n_proj; q0 += KB) {
-      compute(buf);
-      if (q0 + KB < n_proj) {
-        stage(q0 + KB, buf ^ 1);
-        if (q0 + 2 * KB < n_proj) fetch(q0 + 2 * KB);
-      }
+      // the other buffer's LDS writes and the next global loads go out
+      // between the two halves of this step's MFMAs (see k_kb_gemm)
+      const bool more = q0 + KB < n_proj;
+      compute_steps(buf, 0, KB / 8);
+      if (more) stage(q0 + KB, buf ^ 1);
+      compute_steps(buf, KB / 8, KB / 4);
+      if (more && q0 + 2 * KB < n_proj) fetch(q0 + 2 * KB);
       __syncthreads();
       buf ^= 1;
     }
