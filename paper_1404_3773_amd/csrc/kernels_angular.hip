@@ -985,8 +985,13 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
         k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
       }
     };
-    if (kp <= 32) return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
-    return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
+    // 16-column tiles per workgroup: four for FP32 one-tile waves on wide
+    // blocks (147 atoms: 1.95 against 2.13 ms with two), else two (309
+    // atoms: FP32 two-tile waves 12.4 against 12.6 ms with four, FP64 19.9
+    // against 24.1 ms: more waves resident)
+    if (sizeof(T) == 4 && !jt2 && kp > 32)
+      return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
+    return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
   }
   // two column tiles when the block is narrow (no idle MFMA columns), else four
   // (K loops of up to 8 k-steps, L <= 32, load all their operands at once;
