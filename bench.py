@@ -773,7 +773,7 @@ def main():
                     help="workload of --pmc-run (fcc309kb_L81_N150 or mackay147_L61_N120)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
+        print(f"bench.py runs on one GPU only (the library has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
     if args.pmc_run:
