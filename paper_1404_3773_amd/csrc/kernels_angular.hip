@@ -202,6 +202,10 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 // of the first half, 16 NT columns of one radial node; a k-step takes four l
 // of one parity, l = m + par + 2 (4t + kk); steps go in chunks of CH with the
 // next chunk's operands in flight while the current one runs on MFMA.
+// Column tile nt of lane l16 is column NT l16 + nt of the workgroup's block,
+// so a lane reads its NT B values with one vector load and writes its NT
+// results of a node with one vector store: each store instruction covers
+// whole 16 NT-column row pieces of g rather than 16-column halves.
 template <typename T, int NT, int JT, int CH>
 __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict__ Pm,
                                                              const T* __restrict__ G,
@@ -213,7 +217,6 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
   slot_to_m(s, D.L, m, sgn);
   const int r = blockIdx.x / n_ic;
   const int i0 = (blockIdx.x - r * n_ic) * (16 * NT);
-  const int nt_valid = min(NT, (D.kp - i0) / 16);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
@@ -226,10 +229,12 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
     jt[u] = (tile0 + u) * 16;
     Pa[u] = Pm + (static_cast<int64_t>(m) * (D.L + 4)) * D.J64 + min(jt[u], D.J64 - 16) + l16;
   }
-  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + l16;
-  int col[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) col[nt] = min(nt * 16, D.kp - i0 - 16);
+  // this lane's columns i0 + NT l16 + nt; in a ragged last block (kp - i0 a
+  // multiple of 16 below 16 NT) the lanes past it read the last NT columns
+  // and store nothing
+  const int cl = min(NT * l16, D.kp - i0 - NT);
+  const bool colok = i0 + NT * l16 < D.kp;
+  const T* Gr = G + static_cast<int64_t>(r) * D.LL * D.kp + i0 + cl;
   acc_t E[JT][NT], O[JT][NT];
 #pragma unroll
   for (int u = 0; u < JT; ++u)
@@ -253,8 +258,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
 #pragma unroll
     for (int u = 0; u < JT; ++u) a[u] = Pa[u][lc * D.J64];
     const int64_t off = static_cast<int64_t>(lc * lc + lc + sgn * m) * D.kp;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) b[nt] = Gr[off + col[nt]];
+    load_vec<T, NT>(Gr + off, b);
   };
   // CH steps per chunk, all loaded before the chunk's MFMAs; the next chunk
   // is in flight while the current one runs
@@ -297,22 +301,24 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
       for (int nt = 0; nt < NT; ++nt) cb[t][nt] = nb[t][nt];
     }
   }
-  T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + l16;
+  if (!colok) return;
+  T* gr = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp + i0 + NT * l16;
   const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
 #pragma unroll
   for (int u = 0; u < JT; ++u)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      if (nt >= nt_valid) break;
+    for (int v = 0; v < 4; ++v) {
+      const int j = jt[u] + MF<T>::row(lane, v);
+      if (j < nh) {
+        T pe[NT], pm[NT];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = jt[u] + MF<T>::row(lane, v);
-        if (j < nh) {
-          const T e = E[u][nt][v], o = O[u][nt][v];
-          gr[j * jstride + nt * 16] = e + o;
-          const int jm = D.n_theta - 1 - j;
-          if (jm != j) gr[jm * jstride + nt * 16] = e - o;
+        for (int nt = 0; nt < NT; ++nt) {
+          pe[nt] = E[u][nt][v] + O[u][nt][v];
+          pm[nt] = E[u][nt][v] - O[u][nt][v];
         }
+        store_vec<T, NT>(gr + j * jstride, pe);
+        const int jm = D.n_theta - 1 - j;
+        if (jm != j) store_vec<T, NT>(gr + jm * jstride, pm);
       }
     }
 }
@@ -324,7 +330,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
 //   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
 //   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
 constexpr int PS_NT = 2;             // 16-column tiles per workgroup
-constexpr int kPhiWorkgroups = 1792; // resident rows in flight (7 per CU)
+constexpr int kPhiRowsPerWg = 16;    // rows each workgroup walks, the next one in flight
 
 // phi stage: gh = C g per (r, theta_j) row, C the (2L-1)^2 coupling of the
 // product-to-sum identity above.  K (input slots) and M (output slots) are
@@ -343,11 +349,20 @@ constexpr int kPhiWorkgroups = 1792; // resident rows in flight (7 per CU)
 // input block stops at its last slot, rounded up to a k-step, at compile
 // time (LP - 4 TC rows of the cos block, 4 SS fewer of the sin block), so the
 // padding rows cost no MFMA work and the loop stays fully unrolled.
+// Column tile nt of lane l16 is column 2 l16 + nt of the workgroup's 32:
+// a lane reads both B values of a k-step with one 8-byte LDS read (the four
+// rows of a read then cover the banks once) and writes both results of an
+// output row with one 8-byte store, so each store instruction covers whole
+// 128-byte row pieces of g.
+// FP32 is held to four waves per SIMD (at L = 81: 21.7 against 22.2 ms with
+// the three the compiler chose by itself).
 template <typename T, int LP, int TC, int SS>
-__global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
+void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
                                                    AngDims D, int64_t n_rows) {
   typedef typename MF<T>::acc acc_t;
-  constexpr int GW = 16 * PS_NT + 1;
+  static_assert(PS_NT == 2, "a lane holds the two columns 2 l16 and 2 l16 + 1");
+  constexpr int GW = 16 * PS_NT;
   constexpr int K2 = 2 * LP, NMT = K2 / 16, MT = (NMT + 3) / 4;   // M-tiles per wave
   constexpr int GPT = K2 / 8;                   // g values per thread per row
   constexpr int NE = (6 * K2 + 255) / 256;      // table entries per thread
@@ -356,21 +371,26 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   T* tab = reinterpret_cast<T*>(smem_raw);     // 6 tables of K2 values
   T* gs = tab + 6 * K2;                         // [K2][GW]
   const int i0 = blockIdx.y * (16 * PS_NT);
-  const int nt_valid = min(PS_NT, (D.kp - i0) / 16);
   const int tid = threadIdx.x;
   const int ii = tid & 31, kr = tid >> 5;
-  // this thread's g rows (slot s < L -> K row s; slot L + j -> row LP + j);
-  // rows past the slots read offset 0 and are written as zero
-  int soff[GPT];
-  bool sok[GPT];
+  // this thread's g rows k = kr + 8u (slot s < L -> K row s; slot L + j ->
+  // row LP + j; k >= LP exactly when 8u >= LP).  Bit u of okm marks row k as
+  // a slot; the others load a clamped address and are written as zero.
+  // Offsets within a row are unsigned 32-bit (the row base stays in scalar
+  // registers) and are formed at each use from cbase, which an empty asm
+  // makes opaque per row so that the compiler keeps one register, not one
+  // per load or store, live across the MFMA loop.
+  unsigned okm = 0;
 #pragma unroll
   for (int u = 0; u < GPT; ++u) {
     const int k = kr + 8 * u;
     const bool sn = k >= LP;
     const int kl = sn ? k - LP : k;
-    sok[u] = (sn ? kl < L - 1 : kl < L) && i0 + ii < D.kp;
-    soff[u] = sok[u] ? (sn ? L + kl : kl) * D.kp + i0 + ii : 0;
+    const bool ok = (sn ? kl < L - 1 : kl < L) && i0 + ii < D.kp;
+    okm |= (ok ? 1u : 0u) << u;
   }
+  const unsigned cbase = unsigned(kr * D.kp + i0 + ii);
+  const unsigned clast = unsigned(S * D.kp - 1);
   // this thread's table entries E = tid + 256 v (table E / K2, index E % K2):
   // value = sign * ab[src] with the row's sums a_x at x, b_x at S + x (x < S);
   // with q = index - LP:
@@ -401,8 +421,13 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   T gp[GPT], ap[NE];
   auto fetch = [&](int64_t row) {
     const T* gr = g + row * rstride;
+    unsigned cb = cbase;
+    asm volatile("" : "+v"(cb));
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) gp[u] = gr[soff[u]];
+    for (int u = 0; u < GPT; ++u) {
+      const unsigned su = unsigned((8 * u + (8 * u >= LP ? L - LP : 0)) * D.kp);   // uniform
+      gp[u] = gr[min(cb + su, clast)];
+    }
     const T* abr = ab + row * 2 * S;
 #pragma unroll
     for (int v = 0; v < NE; ++v) ap[v] = abr[esrc[v]];
@@ -410,6 +435,7 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, kk = lane >> 4;
+  const bool colok = i0 + 2 * l16 < D.kp;   // this lane's output columns exist
   int toff[MT], hoff[MT];
   bool ocs[MT];
 #pragma unroll
@@ -426,7 +452,8 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
   if (row < n_rows) fetch(row);
   for (; row < n_rows; row += gridDim.x) {
 #pragma unroll
-    for (int u = 0; u < GPT; ++u) gs[(kr + 8 * u) * GW + ii] = sok[u] ? gp[u] : T(0);
+    for (int u = 0; u < GPT; ++u)
+      gs[(kr + 8 * u) * GW + ii] = (okm >> u) & 1u ? gp[u] : T(0);
 #pragma unroll
     for (int v = 0; v < NE; ++v) {
       const int E = tid + 256 * v;
@@ -450,13 +477,12 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
         Tb[u] = tab + tsel * K2 + toff[u];
         Hb[u] = tab + hsel * K2 + hoff[u];
       }
-      const T* grow = gs + (ic * LP + kk) * GW + l16;
+      const T* grow = gs + (ic * LP + kk) * GW + 2 * l16;
       const int kend = ic == 0 ? LP - 4 * TC : LP - 4 * (TC + SS);   // known per unrolled ic
 #pragma unroll
       for (int k0 = 0; k0 < kend; k0 += 4) {
         T b[PS_NT];
-#pragma unroll
-        for (int nt = 0; nt < PS_NT; ++nt) b[nt] = grow[k0 * GW + nt * 16];
+        load_vec<T, PS_NT>(grow + k0 * GW, b);
 #pragma unroll
         for (int u = 0; u < MT; ++u) {
           const T a = Tb[u][k0] + Hb[u][k0];
@@ -465,22 +491,31 @@ __global__ __launch_bounds__(256) void k_phi_stage(T* __restrict__ g, const T* _
         }
       }
     }
-    // inputs came from the LDS copy: write gh in place
+    // inputs came from the LDS copy: write gh in place.  Lane rows of tile mt
+    // are rl0 + dr(v), dr(v) = row(lane, v) - row(lane, 0) fixed per v; a
+    // tile whose 16 rows all hold slots (every one but the last of each block)
+    // stores without row tests.
     T* gr = g + row * rstride + i0;
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
       const int mt = wave + 4 * u;
       if (mt >= NMT) break;
-#pragma unroll
-      for (int nt = 0; nt < PS_NT; ++nt) {
-        if (nt >= nt_valid) break;
+      const bool snu = mt * 16 >= LP;                     // sin block (uniform)
+      const int lim = snu ? L - 1 : L;                    // slots in the block
+      const int rt = mt * 16 - (snu ? LP : 0);            // tile's first block row
+      const int rl0 = rt + MF<T>::row(lane, 0);
+      unsigned ob = unsigned((rl0 + (snu ? L : 0)) * D.kp + 2 * l16);
+      asm volatile("" : "+v"(ob));
+      const unsigned kpu = unsigned(D.kp);
+      if (colok && rt < lim) {
+        const bool full = rt + 16 <= lim;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int rrow = mt * 16 + MF<T>::row(lane, v);
-          const bool sn = rrow >= LP;
-          const int rl = sn ? rrow - LP : rrow;
-          if (sn ? rl < L - 1 : rl < L)
-            gr[static_cast<int64_t>(sn ? L + rl : rl) * D.kp + nt * 16 + l16] = acc[u][nt][v];
+          const int dr = MF<T>::row(lane, v) - MF<T>::row(lane, 0);
+          T pr[PS_NT];
+#pragma unroll
+          for (int nt = 0; nt < PS_NT; ++nt) pr[nt] = acc[u][nt][v];
+          if (full || rl0 + dr < lim) store_vec<T, PS_NT>(gr + ob + dr * kpu, pr);
         }
       }
     }
@@ -602,6 +637,8 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 // sum.  One m-slot per wave, NTA 16-column tiles; ME / MO 16-row l-tiles of
 // each parity (rows l = m + par + 2 (16 tile + lane row)); theta in k-steps
 // of four, CH steps per chunk with the next chunk's operands in flight.
+// Column tile nt of lane l16 is column NTA l16 + nt of the block (as in the
+// folded synthesis): one vector load per node and one vector store per row.
 template <typename T, int MH, int CH, int NTA>
 __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restrict__ PwT,
                                                                 const T* __restrict__ g,
@@ -617,14 +654,15 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
   const int r = blockIdx.x / n_ic;
   const int l16 = lane & 15, kk = lane >> 4;
   const int i0 = (blockIdx.x - r * n_ic) * (16 * NTA);
-  const int nt_valid = min(NTA, (D.kp - i0) / 16);
   const int K = D.L - m;
   const int nme = ((K + 1) / 2 + 15) / 16, nmo = (K / 2 + 15) / 16;   // <= MH each
   const int64_t jstride = static_cast<int64_t>(D.S) * D.kp;
   const T* gb = g + (static_cast<int64_t>(r) * D.n_theta * D.S + s) * D.kp;
-  int col[NTA];
-#pragma unroll
-  for (int nt = 0; nt < NTA; ++nt) col[nt] = min(i0 + nt * 16, D.kp - 16) + l16;
+  // this lane's columns i0 + NTA l16 + nt; in a ragged last block the lanes
+  // past it read the last NTA columns and store nothing
+  const int cl = min(NTA * l16, D.kp - i0 - NTA);
+  const bool colok = i0 + NTA * l16 < D.kp;
+  const T* gbl = gb + i0 + cl;
   // table entry [m][j][q] = w_j P_{m+q}^m(t_j); row q = par + 2 (16 u + l16),
   // clamped into the padded row and masked where q >= K
   const T* Pa = PwT + static_cast<int64_t>(m) * D.J4 * D.L16;
@@ -653,13 +691,14 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
       if (u < nme) a[0][u] = Pa[j * D.L16 + min(qe[u], D.L16 - 1)];
       if (u < nmo) a[1][u] = Pa[j * D.L16 + min(qo[u], D.L16 - 1)];
     }
+    T x[NTA], y[NTA];
+    load_vec<T, NTA>(gbl + j * jstride, x);
+    load_vec<T, NTA>(gbl + jm * jstride, y);
+    const bool mid = jm == j;
 #pragma unroll
     for (int nt = 0; nt < NTA; ++nt) {
-      const T x = gb[j * jstride + col[nt]];
-      const T y = gb[jm * jstride + col[nt]];
-      const bool mid = jm == j;
-      bu[nt] = mid ? x : x + y;
-      bv[nt] = mid ? T(0) : x - y;
+      bu[nt] = mid ? x[nt] : x[nt] + y[nt];
+      bv[nt] = mid ? T(0) : x[nt] - y[nt];
     }
   };
   auto mma_step = [&](int t, const T (&a)[2][MH], const T (&bu)[NTA], const T (&bv)[NTA])
@@ -707,22 +746,26 @@ __global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restr
       }
     }
   }
-  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + l16;
+  if (!colok) return;
+  T* Ar = A + static_cast<int64_t>(r) * D.LL * D.kp + i0 + NTA * l16;
 #pragma unroll
   for (int u = 0; u < MH; ++u) {
 #pragma unroll
-    for (int nt = 0; nt < NTA; ++nt) {
-      if (nt >= nt_valid) break;
+    for (int v = 0; v < 4; ++v) {
+      const int q = 2 * (16 * u + MF<T>::row(lane, v));
+      const int le = m + q, lo = le + 1;
+      T pe[NTA], po[NTA];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = 2 * (16 * u + MF<T>::row(lane, v));
-        const int le = m + q, lo = le + 1;
-        if (u < nme && le < D.L) Ar[(le * le + le + sgn * m) * D.kp + i0 + nt * 16] = ae[u][nt][v];
-        if (u < nmo && lo < D.L) Ar[(lo * lo + lo + sgn * m) * D.kp + i0 + nt * 16] = ao[u][nt][v];
+      for (int nt = 0; nt < NTA; ++nt) {
+        pe[nt] = ae[u][nt][v];
+        po[nt] = ao[u][nt][v];
       }
+      if (u < nme && le < D.L) store_vec<T, NTA>(Ar + (le * le + le + sgn * m) * D.kp, pe);
+      if (u < nmo && lo < D.L) store_vec<T, NTA>(Ar + (lo * lo + lo + sgn * m) * D.kp, po);
     }
   }
 }
+
 
 // ------------------------------------------------------------- density
 
@@ -1040,13 +1083,15 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
 template <typename T>
 void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
-  // persistent workgroups: each walks (r, theta_j) rows with a stride of the
-  // grid, prefetching the next row while the current one runs on MFMA
+  // each workgroup walks about kPhiRowsPerWg (r, theta_j) rows with a stride
+  // of the grid, prefetching the next row while the current one runs on
+  // MFMA; many short workgroups leave no partly filled last round (309
+  // atoms: 22.0 against 22.2 ms with 1792 long-lived ones)
   const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
   const int ncg = (kp + 16 * PS_NT - 1) / (16 * PS_NT);
-  const int64_t want = std::max<int64_t>(1, kPhiWorkgroups / ncg);
-  dim3 grid(static_cast<unsigned>(std::min(n_rows, want)), ncg);
-  const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT + 1)) * sizeof(T);
+  const int64_t want = (n_rows + kPhiRowsPerWg - 1) / kPhiRowsPerWg;
+  dim3 grid(static_cast<unsigned>(want), ncg);
+  const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT)) * sizeof(T);
   // K rows that hold slots: rup(L, 4) of the cos block, rup(L - 1, 4) of the
   // sin block; with L in (LP - 16, LP] that is LP - 4 TC and 4 SS fewer
   const int kend0 = rup(D.L, 4), kend1 = rup(D.L - 1, 4);

@@ -36,6 +36,14 @@ struct KbShape<double> {  // wave tile 64 x 32, workgroup 128 x 64, 32 alpha per
 };
 constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 
+// LDS row pitch of the staged tiles: the MFMA operand reads take 16 rows x 4
+// consecutive alpha (rows c16, columns kk); with pitch KB + 2 (FP32) the 64
+// lanes of a read fall on distinct banks, where KB + 1 left them two-way
+// (309-atom C = P^T Y: 25.4 -> 24.5 ms).  FP64 reads 8-byte words and keeps
+// KB + 1 (its C was slower with KB + 2).
+template <typename T>
+constexpr int kb_pitch(int kb) { return kb + (sizeof(T) == 4 ? 2 : 1); }
+
 // With DB the P and Y tiles are double-buffered in (dynamic) LDS: a step
 // computes from one buffer while the next step's tiles are written into the
 // other, so it takes one barrier instead of two.
@@ -48,7 +56,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   typedef typename MF<T>::acc acc_t;
   constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TM, BN = 32 * TN;      // 2 x 2 waves
-  constexpr int KW = KB + 1;                     // padded LDS row
+  constexpr int KW = kb_pitch<T>(KB);            // padded LDS row
   constexpr int RA = 256 / KB;                   // tile rows loaded per pass
   constexpr int LA = BM / RA, LB = BN / RA;      // passes for the P and Y tiles
   constexpr int STAGE = (BM + BN) * KW;          // one buffer: A tile then B tile
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
   typedef typename MF<T>::acc acc_t;
   constexpr int TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TN, BN = 32 * TM;      // i tile, alpha tile (2 x 2 waves)
-  constexpr int KW = KB + 1;
+  constexpr int KW = kb_pitch<T>(KB);
   constexpr int RC = 256 / BM, RP = 256 / BN;    // q rows per staging pass
   constexpr int LC = KB / RC, LP = KB / RP;
   constexpr int STAGE = (BM + BN) * KW;          // one buffer: Cs [i][q] then Ps [alpha][q]
@@ -350,7 +358,7 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
 // per CU still fit).
 template <typename T>
 constexpr size_t kb_lds_bytes(bool db, int kb = KbShape<T>::KB) {
-  return (db ? 2 : 1) * size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * (kb + 1) * sizeof(T);
+  return (db ? 2 : 1) * size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * kb_pitch<T>(kb) * sizeof(T);
 }
 
 // Allow more than the default 64 KB of dynamic LDS for a kernel that needs it

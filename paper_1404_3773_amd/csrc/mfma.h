@@ -29,6 +29,26 @@ struct MF<double> {
   __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
+// N consecutive values as one vector access (dwordx2 / dwordx4 and the
+// like); the address must be aligned to N * sizeof(T).
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecN {
+  T v[N];
+};
+template <typename T, int N>
+__device__ __forceinline__ void load_vec(const T* p, T (&out)[N]) {
+  const VecN<T, N> x = *reinterpret_cast<const VecN<T, N>*>(p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = x.v[i];
+}
+template <typename T, int N>
+__device__ __forceinline__ void store_vec(T* p, const T (&in)[N]) {
+  VecN<T, N> x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.v[i] = in[i];
+  *reinterpret_cast<VecN<T, N>*>(p) = x;
+}
+
 template <typename A>
 __device__ __forceinline__ A zero_acc() {
   A z;
