@@ -36,7 +36,9 @@ __host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 // 16-row tiles each; tiles past the last repeat it and are not stored).  The
 // X tile (N rows x 32 columns, zero-padded to a multiple of 16 rows) is staged
 // in LDS; the table operand is read in chunks of four k-steps, the next chunk
-// in flight while the current one runs.
+// in flight while the current one runs.  Column tile nt of lane l16 is column
+// 2 l16 + nt of the 32: a lane reads both B values of a k-step with one
+// 8-byte LDS read and writes both results of a row with one 8-byte store.
 template <typename T, int MT, int CK, bool ONE>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
@@ -45,7 +47,8 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
                                                              int L, int N, int n_r, int k,
                                                              int kp) {
   typedef typename MF<T>::acc acc_t;
-  constexpr int CW = 16 * RI_NT, XW = CW + 1;
+  static_assert(RI_NT == 2, "a lane holds the two columns 2 l16 and 2 l16 + 1");
+  constexpr int CW = 16 * RI_NT, XW = CW + 2;   // even pitch: 8-byte aligned pairs
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Xs = reinterpret_cast<T*>(smem_raw);  // [N16][XW]  X[n][i]
   const int N4 = rup(N, 4), R16 = rup(n_r, 16);
@@ -106,8 +109,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
     for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
   auto step = [&](int n, const T* a) {
     T b[RI_NT];
-#pragma unroll
-    for (int nt = 0; nt < RI_NT; ++nt) b[nt] = Xs[n * XW + nt * 16 + l16];
+    load_vec<T, RI_NT>(Xs + n * XW + 2 * l16, b);
     const bool ok = n < N4;                       // table rows N..N4-1 are zero
 #pragma unroll
     for (int u = 0; u < MT; ++u) {
@@ -139,20 +141,20 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
         for (int u = 0; u < MT; ++u) ca[t][u] = na[t][u];
     }
   }
+  if (i0 + 2 * l16 >= kp) return;   // this lane's columns lie past the block
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
-  T* Gb = G + static_cast<int64_t>(lm) * kp + i0 + l16;
+  T* Gb = G + static_cast<int64_t>(lm) * kp + i0 + 2 * l16;
 #pragma unroll
   for (int u = 0; u < MT; ++u) {
     const int mt = wave + 4 * u;
     if (mt >= nmt) break;
 #pragma unroll
-    for (int nt = 0; nt < RI_NT; ++nt) {
-      if (i0 + nt * 16 >= kp) break;
+    for (int v = 0; v < 4; ++v) {
+      const int r = mt * 16 + MF<T>::row(lane, v);
+      T pr[RI_NT];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = mt * 16 + MF<T>::row(lane, v);
-        if (r < n_r) Gb[r * rstride + nt * 16] = acc[u][nt][v];
-      }
+      for (int nt = 0; nt < RI_NT; ++nt) pr[nt] = acc[u][nt][v];
+      if (r < n_r) store_vec<T, RI_NT>(Gb + r * rstride, pr);
     }
   }
 }
@@ -161,6 +163,9 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
 // each, repeated past the last and not stored); K = n_r in chunks of four
 // k-steps with the next chunk's operands in flight.  The projector term
 // (column-major d x k, ld d) is added in the epilogue when Zkb is given.
+// Column tile nt of lane l16 is column 2 l16 + nt of the 32 (one 8-byte load
+// of the streamed operand per k-step), so result row q of tile nt is column
+// 2 q + nt.
 template <typename T, int MT, int CK, bool ONE>
 __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     const T* __restrict__ RfT, const T* __restrict__ A, const T* __restrict__ lamh,
@@ -184,17 +189,16 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
   int mrow[MT];
 #pragma unroll
   for (int u = 0; u < MT; ++u) mrow[u] = min(wave + 4 * u, nmt - 1) * 16;
-  // column of each N-tile clamped into the block (tiles past kp are not stored)
-  int col[RI_NT];
-#pragma unroll
-  for (int nt = 0; nt < RI_NT; ++nt) col[nt] = min(nt * 16, kp - i0 - 16);
+  // this lane's column pair, clamped into the block (a ragged last block's
+  // lanes past it load the last pair; their columns are >= kp and not stored)
+  const int cl = min(2 * l16, kp - i0 - 2);
   acc_t acc[MT][RI_NT];
 #pragma unroll
   for (int u = 0; u < MT; ++u)
 #pragma unroll
     for (int nt = 0; nt < RI_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
   const T* Rl = RfT + static_cast<int64_t>(l) * R4 * N16 + l16;
-  const T* Ab = A + static_cast<int64_t>(lm) * kp + i0 + l16;
+  const T* Ab = A + static_cast<int64_t>(lm) * kp + i0 + cl;
   const int64_t rstride = static_cast<int64_t>(L) * L * kp;
   // operands in chunks of CK k-steps (4 CK radial nodes)
   auto load = [&](int chunk, T (*a)[MT], T (*b)[RI_NT]) __attribute__((always_inline)) {
@@ -207,8 +211,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
       const int64_t roff = static_cast<int64_t>(min(r, n_r - 1)) * rstride;
 #pragma unroll
       for (int u = 0; u < MT; ++u) a[t][u] = Rl[static_cast<int64_t>(rt) * N16 + mrow[u]];
-#pragma unroll
-      for (int nt = 0; nt < RI_NT; ++nt) b[t][nt] = Ab[roff + col[nt]];
+      load_vec<T, RI_NT>(Ab + roff, b[t]);
     }
   };
   // transposed product Z^T = A^T Rf: the streamed A block is the MFMA A
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
       for (int nt = 0; nt < RI_NT; ++nt)
 #pragma unroll
         for (int v = 0; v < 4 * EPR; ++v)
-          y[u][nt][v] = Y[min(i0 + nt * 16 + MF<T>::row(lane, v), k - 1) * ld + row];
+          y[u][nt][v] = Y[min(i0 + 2 * MF<T>::row(lane, v) + nt, k - 1) * ld + row];
     }
   };
   auto zkb_load = [&]() __attribute__((always_inline)) {
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
       for (int nt = 0; nt < RI_NT; ++nt)
 #pragma unroll
         for (int v = 0; v < 4 * ZP; ++v)
-          zk[u][nt][v] = Zkb[static_cast<int64_t>(min(i0 + nt * 16 + MF<T>::row(lane, v), k - 1)) * d + row];
+          zk[u][nt][v] = Zkb[static_cast<int64_t>(min(i0 + 2 * MF<T>::row(lane, v) + nt, k - 1)) * d + row];
     }
   };
   if constexpr (ONE) {
@@ -307,9 +310,9 @@ __global__ __launch_bounds__(256) void k_radial_forward_mfma(
     for (int nt = 0; nt < RI_NT; ++nt) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        // columns of a tile past kp were clamped onto valid data: skip them
-        const int i = i0 + nt * 16 + MF<T>::row(lane, v);
-        if (i >= k || i0 + nt * 16 >= kp) continue;
+        // columns past k (among them any clamped onto valid data) are skipped
+        const int i = i0 + 2 * MF<T>::row(lane, v) + nt;
+        if (i >= k) continue;
         T z = acc[u][nt][v];
         if (Zkb) z += ZP ? zk[u][nt][v * ZP] : Zkb[static_cast<int64_t>(i) * d + row];
         if (kinetic)
@@ -333,7 +336,7 @@ template <typename T, int CK, bool ONE>
 void radial_inverse_ck(const Basis& b, const DevTables<T>& tb, const T* X, int64_t ldx, T* G,
                        int k, int kp, hipStream_t s) {
   dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
-  const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 1) * sizeof(T);
+  const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 2) * sizeof(T);
   const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
   switch (mt) {
     case 1: k_radial_inverse_mfma<T, 1, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
