@@ -448,6 +448,14 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
     toff[u] = LP - rl + kk;
     hoff[u] = rl + kk;
   }
+  // this wave's last tile holds no slot when it lies past NMT (a repeat, when
+  // NMT is not a multiple of 4) or past the block's slots (the last sin tile
+  // when L = 1 mod 16, which is TC = 3, SS = 1): its MFMAs are skipped (its
+  // results are never stored).  Other shapes compile the full loop alone.
+  constexpr bool CAN_SKIP = MT > 1 && ((TC == 3 && SS == 1) || NMT % 4 != 0);
+  const int lastmt = wave + 4 * (MT - 1);
+  const bool last_ok =
+      lastmt < NMT && (lastmt * 16 < LP ? lastmt * 16 < L : lastmt * 16 - LP < L - 1);
   int64_t row = blockIdx.x;
   if (row < n_rows) fetch(row);
   for (; row < n_rows; row += gridDim.x) {
@@ -466,30 +474,42 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
     for (int u = 0; u < MT; ++u)
 #pragma unroll
       for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = zero_acc<acc_t>();
+    // the first MTE of this wave's tiles
+    auto mfma_rows = [&](auto mte_tag) __attribute__((always_inline)) {
+      constexpr int MTE = decltype(mte_tag)::value;
 #pragma unroll
-    for (int ic = 0; ic < 2; ++ic) {
-      const T* Tb[MT];
-      const T* Hb[MT];
+      for (int ic = 0; ic < 2; ++ic) {
+        const T* Tb[MTE];
+        const T* Hb[MTE];
 #pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const int tsel = ocs[u] == (ic == 1) ? 0 : (ic == 1 ? 1 : 2);
-        const int hsel = ic == 0 ? (ocs[u] ? 4 : 3) : (ocs[u] ? 5 : 4);
-        Tb[u] = tab + tsel * K2 + toff[u];
-        Hb[u] = tab + hsel * K2 + hoff[u];
-      }
-      const T* grow = gs + (ic * LP + kk) * GW + 2 * l16;
-      const int kend = ic == 0 ? LP - 4 * TC : LP - 4 * (TC + SS);   // known per unrolled ic
+        for (int u = 0; u < MTE; ++u) {
+          const int tsel = ocs[u] == (ic == 1) ? 0 : (ic == 1 ? 1 : 2);
+          const int hsel = ic == 0 ? (ocs[u] ? 4 : 3) : (ocs[u] ? 5 : 4);
+          Tb[u] = tab + tsel * K2 + toff[u];
+          Hb[u] = tab + hsel * K2 + hoff[u];
+        }
+        const T* grow = gs + (ic * LP + kk) * GW + 2 * l16;
+        const int kend = ic == 0 ? LP - 4 * TC : LP - 4 * (TC + SS);   // known per unrolled ic
 #pragma unroll
-      for (int k0 = 0; k0 < kend; k0 += 4) {
-        T b[PS_NT];
-        load_vec<T, PS_NT>(grow + k0 * GW, b);
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+          T b[PS_NT];
+          load_vec<T, PS_NT>(grow + k0 * GW, b);
 #pragma unroll
-        for (int u = 0; u < MT; ++u) {
-          const T a = Tb[u][k0] + Hb[u][k0];
+          for (int u = 0; u < MTE; ++u) {
+            const T a = Tb[u][k0] + Hb[u][k0];
 #pragma unroll
-          for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+            for (int nt = 0; nt < PS_NT; ++nt) acc[u][nt] = MF<T>::mma(a, b[nt], acc[u][nt]);
+          }
         }
       }
+    };
+    if constexpr (CAN_SKIP) {
+      if (last_ok)
+        mfma_rows(std::integral_constant<int, MT>());
+      else
+        mfma_rows(std::integral_constant<int, (MT > 1 ? MT - 1 : 1)>());
+    } else {
+      mfma_rows(std::integral_constant<int, MT>());
     }
     // inputs came from the LDS copy: write gh in place.  Lane rows of tile mt
     // are rl0 + dr(v), dr(v) = row(lane, v) - row(lane, 0) fixed per v; a
@@ -1028,11 +1048,12 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
         k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
       }
     };
-    // 16-column tiles per workgroup: four for FP32 one-tile waves on wide
-    // blocks (147 atoms: 1.95 against 2.13 ms with two), else two (309
-    // atoms: FP32 two-tile waves 12.4 against 12.6 ms with four, FP64 19.9
-    // against 24.1 ms: more waves resident)
-    if (sizeof(T) == 4 && !jt2 && kp > 32)
+    // 16-column tiles per workgroup: four in FP32 on wide blocks (147 atoms:
+    // 1.95 against 2.13 ms with two; 309 atoms, two theta tiles per wave,
+    // with each lane's four columns read and written as one vector: 10.7
+    // against 11.5 ms), else two (FP64 at 309 atoms: 19.9 against 24.1 ms,
+    // more waves resident)
+    if (sizeof(T) == 4 && kp > 32)
       return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
     return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
   }
