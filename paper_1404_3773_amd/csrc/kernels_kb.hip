@@ -11,9 +11,11 @@
 // in registers while the current one runs on 16x16x4 MFMA (2 x 2 waves, TM x
 // TN fragments each).  K is split into chunks whose partial products go to a
 // buffer; a second kernel sums them in a fixed order and applies h.
-// Workgroups that share projector rows (same chunk and M tile) are placed on
-// one XCD (workgroup ids are dealt round-robin over the 8 XCDs) so that its
-// L2 serves their common loads.
+// Workgroup ids are dealt round-robin over the 8 XCDs; every workgroup of a
+// chunk (all its M and N tiles) is placed on XCD chunk mod 8, in M-tile
+// order, so the workgroups in flight on an XCD walk the same chunk's alpha
+// steps together: its L2 serves the Y steps they share (all M tiles) and the
+// P steps (all N tiles of an M tile), and each is fetched from HBM about once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
                                                  int64_t ldp, const T* __restrict__ Y,
                                                  int64_t ldy,
                                                  T* __restrict__ part, int n_proj, int k, int kp,
-                                                 int64_t kchunk, int nM, int nN, int n_groups) {
+                                                 int64_t kchunk, int nM, int nN, int nchunk) {
   typedef typename MF<T>::acc acc_t;
   constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TM, BN = 32 * TN;      // 2 x 2 waves
@@ -62,12 +64,14 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   constexpr int STAGE = (BM + BN) * KW;          // one buffer: A tile then B tile
   extern __shared__ __align__(16) unsigned char kb_smem[];
   T* const lds = reinterpret_cast<T*>(kb_smem);
-  // workgroup id -> (XCD x, position j on it) -> (group g = chunk and M tile, N tile)
+  // workgroup id -> (XCD x, position j on it) -> (t-th group of XCD x, N tile)
+  // -> (chunk x + 8 (t / nM), M tile t % nM)
   const int id = blockIdx.x;
   const int x = id & 7, j = id >> 3;
-  const int g = x + 8 * (j / nN), ntb = j - (j / nN) * nN;
-  if (g >= n_groups) return;
-  const int chunk = g / nM, mtb = g - chunk * nM;
+  const int t = j / nN, ntb = j - t * nN;
+  const int cx = t / nM, mtb = t - cx * nM;
+  const int chunk = x + 8 * cx;
+  if (chunk >= nchunk) return;
   const int64_t k0 = static_cast<int64_t>(chunk) * kchunk;
   const int64_t k1 = k0 + kchunk < d ? k0 + kchunk : d;
   const int tid = threadIdx.x;
@@ -311,9 +315,15 @@ __global__ void k_kb_reduce(const T* __restrict__ part, int nchunk, const T* __r
 
 template <typename T>
 struct KbGrid {
-  int nM, nN, nchunk, n_groups;
+  int nM, nN, nchunk;
   int64_t kchunk;
 };
+
+// Workgroups of a split-K grid with nchunk chunks (XCD x takes chunks x,
+// x + 8, ...): 8 XCDs x their largest group count x nN.
+inline unsigned kb_workgroups(int nchunk, int nM, int nN) {
+  return static_cast<unsigned>(8 * ((nchunk + 7) / 8) * nM * nN);
+}
 
 template <typename T>
 KbGrid<T> kb_grid(int n_proj, int k, int64_t d) {
@@ -321,16 +331,26 @@ KbGrid<T> kb_grid(int n_proj, int k, int64_t d) {
   KbGrid<T> gr;
   gr.nM = (n_proj + 32 * KbShape<T>::TM - 1) / (32 * KbShape<T>::TM);
   gr.nN = (k + 32 * KbShape<T>::TN - 1) / (32 * KbShape<T>::TN);
-  // groups (chunk, M tile) of nN workgroups each are dealt to the 8 XCDs; as
-  // many chunks as keep every XCD's groups resident at once (one round), with
-  // chunks of at least 16 steps
-  const int groups_per_xcd = std::max(1, kKbPerXcd / gr.nN);
-  int want = std::max(1, 8 * groups_per_xcd / gr.nM);
-  const int64_t maxc = std::max<int64_t>(1, (d + 16 * KB - 1) / (16 * KB));
-  want = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({int64_t(want), maxc, 64})));
+  // 8 c chunks (c per XCD, each XCD's workgroups c nM nN), c <= 4 chosen so
+  // that those workgroups fill whole rounds of kKbPerXcd resident ones as
+  // nearly as possible (309 atoms, FP32: nM = 10, nN = 8, c = 4: 5 full
+  // rounds); chunks of at least 16 steps
+  const int64_t steps = (d + KB - 1) / KB;
+  int c_best = 1;
+  double waste_best = 2.0;
+  for (int c = 1; c <= 4; ++c) {
+    if (c > 1 && steps < int64_t(8 * c) * 16) break;
+    const int64_t wg = int64_t(c) * gr.nM * gr.nN;
+    const int64_t rounds = (wg + kKbPerXcd - 1) / kKbPerXcd;
+    const double waste = double(rounds * kKbPerXcd - wg) / double(rounds * kKbPerXcd);
+    if (waste < waste_best - 1e-9) {
+      waste_best = waste;
+      c_best = c;
+    }
+  }
+  const int want = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8 * c_best, steps)));
   gr.kchunk = round_up((d + want - 1) / want, KB);
   gr.nchunk = static_cast<int>((d + gr.kchunk - 1) / gr.kchunk);
-  gr.n_groups = gr.nchunk * gr.nM;
   return gr;
 }
 
@@ -374,13 +394,12 @@ template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
                     int n_proj, int k, int kp, hipStream_t s) {
   const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
-  const int per_xcd = (gr.n_groups + 7) / 8;   // groups per XCD (the last ones idle)
-  const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
+  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN);
   constexpr bool DB = sizeof(T) == 4;
   constexpr size_t lds = kb_lds_bytes<T>(DB);
   allow_lds(&k_kb_gemm<T, DB>, lds);
   k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
-                                         gr.nN, gr.n_groups);
+                                         gr.nN, gr.nchunk);
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
   k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
@@ -396,12 +415,10 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
     constexpr int KB = KbShape<double>::KB;
     gr.kchunk = round_up((rows + maxc - 1) / maxc, KB);
     gr.nchunk = static_cast<int>((rows + gr.kchunk - 1) / gr.kchunk);
-    gr.n_groups = gr.nchunk * gr.nM;
   }
-  const int per_xcd = (gr.n_groups + 7) / 8;
-  const unsigned nwg = static_cast<unsigned>(8 * per_xcd * gr.nN);
+  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN);
   k_kb_gemm<double, false><<<nwg, 256, kb_lds_bytes<double>(false), s>>>(
-      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.n_groups);
+      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk);
   return gr.nchunk;
 }
 

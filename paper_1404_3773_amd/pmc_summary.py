@@ -168,8 +168,12 @@ def main(argv=None):
     ap.add_argument("--copy-bytes", type=float, required=True)
     ap.add_argument("--copy-match", default="elementwise")
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--sources", nargs="+", default=["kernels_angular.hip#k_phi_stage", "mfma.h"],
-                    help="sources the summary is valid for: files in csrc/, or file#kernel")
+    ap.add_argument("--sources", nargs="+",
+                    default=["kernels_angular.hip", "kernels_radial.hip", "kernels_kb.hip",
+                             "mfma.h"],
+                    help="sources the summary is valid for: files in csrc/, or file#kernel "
+                         "(by default every H*X stage kernel's source: the summary carries "
+                         "the counters of all of them)")
     ap.add_argument("--json", required=True)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
