@@ -370,7 +370,7 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
   const int S = D.S, L = D.L;
   T* tab = reinterpret_cast<T*>(smem_raw);     // 6 tables of K2 values
   T* gs = tab + 6 * K2;                         // [K2][GW]
-  const int i0 = blockIdx.y * (16 * PS_NT);
+  const int i0 = blockIdx.x * (16 * PS_NT);
   const int tid = threadIdx.x;
   const int ii = tid & 31, kr = tid >> 5;
   // this thread's g rows k = kr + 8u (slot s < L -> K row s; slot L + j ->
@@ -456,9 +456,9 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
   const int lastmt = wave + 4 * (MT - 1);
   const bool last_ok =
       lastmt < NMT && (lastmt * 16 < LP ? lastmt * 16 < L : lastmt * 16 - LP < L - 1);
-  int64_t row = blockIdx.x;
+  int64_t row = blockIdx.y;
   if (row < n_rows) fetch(row);
-  for (; row < n_rows; row += gridDim.x) {
+  for (; row < n_rows; row += gridDim.y) {
 #pragma unroll
     for (int u = 0; u < GPT; ++u)
       gs[(kr + 8 * u) * GW + ii] = (okm >> u) & 1u ? gp[u] : T(0);
@@ -468,7 +468,7 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
       if (E < 6 * K2) tab[E] = esgn[v] * ap[v];
     }
     __syncthreads();
-    if (row + gridDim.x < n_rows) fetch(row + gridDim.x);     // next row, in flight
+    if (row + gridDim.y < n_rows) fetch(row + gridDim.y);     // next row, in flight
     acc_t acc[MT][PS_NT];
 #pragma unroll
     for (int u = 0; u < MT; ++u)
@@ -1032,27 +1032,20 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
     // folded in theta: JT 16-row tiles of the first half of the nodes per wave
     const int nh = (b.n_theta + 1) / 2;
     const int ntile = (nh + 15) / 16;
-    // FP32 with more than four tiles: two theta tiles per wave share each G
-    // fragment (309 atoms, six tiles: 13.3 -> 12.4 ms; with four tiles, as
-    // at 147 atoms, it would idle half of each workgroup's waves); FP64
-    // keeps one for its registers
+    // one theta tile per wave: with a lane's columns read as one vector,
+    // two tiles per wave sharing each G fragment no longer pay for the
+    // occupancy they cost (309 atoms, six tiles: 10.3 ms with one against
+    // 10.8 with two, at two and five waves per SIMD)
     constexpr int CH = 4;
-    const bool jt2 = sizeof(T) == 4 && ntile > 4;
     auto go = [&](auto nt_tag, int n_ic) {
       constexpr int NT = decltype(nt_tag)::value;
-      if (jt2) {
-        dim3 grid(b.n_r * n_ic, (ntile + 7) / 8, D.S);
-        k_legendre_synth_fold<T, NT, 2, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
-      } else {
-        dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
-        k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
-      }
+      dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
+      k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
     };
     // 16-column tiles per workgroup: four in FP32 on wide blocks (147 atoms:
-    // 1.95 against 2.13 ms with two; 309 atoms, two theta tiles per wave,
-    // with each lane's four columns read and written as one vector: 10.7
-    // against 11.5 ms), else two (FP64 at 309 atoms: 19.9 against 24.1 ms,
-    // more waves resident)
+    // 1.95 against 2.13 ms with two; 309 atoms, with each lane's four
+    // columns read and written as one vector: 10.7 against 11.5 ms), else
+    // two (FP64 at 309 atoms: 19.9 against 24.1 ms, more waves resident)
     if (sizeof(T) == 4 && kp > 32)
       return go(std::integral_constant<int, 4>(), (kp + 63) / 64);
     return go(std::integral_constant<int, 2>(), (kp + 31) / 32);
@@ -1107,11 +1100,13 @@ void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t 
   // each workgroup walks about kPhiRowsPerWg (r, theta_j) rows with a stride
   // of the grid, prefetching the next row while the current one runs on
   // MFMA; many short workgroups leave no partly filled last round (309
-  // atoms: 22.0 against 22.2 ms with 1792 long-lived ones)
+  // atoms: 22.0 against 22.2 ms with 1792 long-lived ones).  The column
+  // block is the fast grid index, so the workgroups dispatched together
+  // cover whole rows of g (147 atoms: 3.04 -> 2.82 ms; 309: 20.4 -> 20.1)
   const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
   const int ncg = (kp + 16 * PS_NT - 1) / (16 * PS_NT);
   const int64_t want = (n_rows + kPhiRowsPerWg - 1) / kPhiRowsPerWg;
-  dim3 grid(static_cast<unsigned>(want), ncg);
+  dim3 grid(ncg, static_cast<unsigned>(std::min<int64_t>(want, 65535)));
   const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT)) * sizeof(T);
   // K rows that hold slots: rup(L, 4) of the cos block, rup(L - 1, 4) of the
   // sin block; with L in (LP - 16, LP] that is LP - 4 TC and 4 SS fewer
