@@ -11,11 +11,14 @@
 // in registers while the current one runs on 16x16x4 MFMA (2 x 2 waves, TM x
 // TN fragments each).  K is split into chunks whose partial products go to a
 // buffer; a second kernel sums them in a fixed order and applies h.
-// Workgroup ids are dealt round-robin over the 8 XCDs; every workgroup of a
-// chunk (all its M and N tiles) is placed on XCD chunk mod 8, in M-tile
-// order, so the workgroups in flight on an XCD walk the same chunk's alpha
-// steps together: its L2 serves the Y steps they share (all M tiles) and the
-// P steps (all N tiles of an M tile), and each is fetched from HBM about once.
+// Workgroup ids are dealt round-robin over the 8 XCDs.  With xcd_chunk set
+// (a chunk count that is a multiple of 8) every workgroup of a chunk (all
+// its M and N tiles) is placed on XCD chunk mod 8, in M-tile order, so the
+// workgroups in flight on an XCD walk the same chunk's alpha steps together:
+// its L2 serves the Y steps they share (all M tiles) and the P steps (all N
+// tiles of an M tile), and each is fetched from HBM about once.  Otherwise
+// the groups (chunk, M tile) of nN workgroups are dealt round-robin over the
+// XCDs, which keeps all of them busy for any chunk count.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,7 +57,8 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
                                                  int64_t ldp, const T* __restrict__ Y,
                                                  int64_t ldy,
                                                  T* __restrict__ part, int n_proj, int k, int kp,
-                                                 int64_t kchunk, int nM, int nN, int nchunk) {
+                                                 int64_t kchunk, int nM, int nN, int nchunk,
+                                                 int xcd_chunk) {
   typedef typename MF<T>::acc acc_t;
   constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TM, BN = 32 * TN;      // 2 x 2 waves
@@ -65,12 +69,20 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   extern __shared__ __align__(16) unsigned char kb_smem[];
   T* const lds = reinterpret_cast<T*>(kb_smem);
   // workgroup id -> (XCD x, position j on it) -> (t-th group of XCD x, N tile)
-  // -> (chunk x + 8 (t / nM), M tile t % nM)
+  // -> (chunk x + 8 (t / nM), M tile t % nM), or group x + 8 t = (chunk, M tile)
   const int id = blockIdx.x;
   const int x = id & 7, j = id >> 3;
   const int t = j / nN, ntb = j - t * nN;
-  const int cx = t / nM, mtb = t - cx * nM;
-  const int chunk = x + 8 * cx;
+  int chunk, mtb;
+  if (xcd_chunk) {
+    const int cx = t / nM;
+    mtb = t - cx * nM;
+    chunk = x + 8 * cx;
+  } else {
+    const int g = x + 8 * t;
+    chunk = g / nM;
+    mtb = g - chunk * nM;
+  }
   if (chunk >= nchunk) return;
   const int64_t k0 = static_cast<int64_t>(chunk) * kchunk;
   const int64_t k1 = k0 + kchunk < d ? k0 + kchunk : d;
@@ -319,10 +331,12 @@ struct KbGrid {
   int64_t kchunk;
 };
 
-// Workgroups of a split-K grid with nchunk chunks (XCD x takes chunks x,
-// x + 8, ...): 8 XCDs x their largest group count x nN.
-inline unsigned kb_workgroups(int nchunk, int nM, int nN) {
-  return static_cast<unsigned>(8 * ((nchunk + 7) / 8) * nM * nN);
+// Workgroups of a split-K grid with nchunk chunks: 8 XCDs x their largest
+// group count x nN, with whole chunks per XCD (xcd_chunk) or groups dealt
+// round-robin.
+inline unsigned kb_workgroups(int nchunk, int nM, int nN, bool xcd_chunk) {
+  const int per_xcd = xcd_chunk ? (nchunk + 7) / 8 * nM : (nchunk * nM + 7) / 8;
+  return static_cast<unsigned>(8 * per_xcd * nN);
 }
 
 template <typename T>
@@ -394,12 +408,13 @@ template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
                     int n_proj, int k, int kp, hipStream_t s) {
   const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
-  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN);
+  const bool xc = gr.nchunk % 8 == 0;
+  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
   constexpr bool DB = sizeof(T) == 4;
   constexpr size_t lds = kb_lds_bytes<T>(DB);
   allow_lds(&k_kb_gemm<T, DB>, lds);
   k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
-                                         gr.nN, gr.nchunk);
+                                         gr.nN, gr.nchunk, xc ? 1 : 0);
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
   k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
@@ -416,9 +431,10 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
     gr.kchunk = round_up((rows + maxc - 1) / maxc, KB);
     gr.nchunk = static_cast<int>((rows + gr.kchunk - 1) / gr.kchunk);
   }
-  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN);
+  const bool xc = gr.nchunk % 8 == 0;
+  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
   k_kb_gemm<double, false><<<nwg, 256, kb_lds_bytes<double>(false), s>>>(
-      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk);
+      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk, xc ? 1 : 0);
   return gr.nchunk;
 }
 
