@@ -659,8 +659,12 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 // of four, CH steps per chunk with the next chunk's operands in flight.
 // Column tile nt of lane l16 is column NTA l16 + nt of the block (as in the
 // folded synthesis): one vector load per node and one vector store per row.
+// FP32 with three l-tiles per parity is held to three waves per SIMD, which
+// its two-step chunks fit without spills (309 atoms: 7.3 -> 7.1 ms).
 template <typename T, int MH, int CH, int NTA>
-__global__ __launch_bounds__(256) void k_legendre_analysis_fold(const T* __restrict__ PwT,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MH == 3 ? 3 : 1, 8)))
+void k_legendre_analysis_fold(const T* __restrict__ PwT,
                                                                 const T* __restrict__ g,
                                                                 T* __restrict__ A, AngDims D,
                                                                 int n_ic, int nh) {
@@ -1155,8 +1159,8 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
         k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
                                                                                n_icf, nh);
       else
-        k_legendre_analysis_fold<T, 3, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
-                                                                               n_icf, nh);
+        k_legendre_analysis_fold<T, 3, 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_icf,
+                                                                     nh);
     };
     if (f32 && kp >= 512)
       go(std::integral_constant<int, 4>());
