@@ -347,8 +347,8 @@ Layout layout_for(Ham& h, int k, int prec) {
   L.B2 = take(size_t(b.d) * k * sizeof(double));
   L.V3 = take(v3);
   if (prec == CES_PREC_MIXED) {
-    L.F0 = take(size_t(b.d) * L.kp * sizeof(float));
-    L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
+    L.F0 = take(size_t(f32_ld(b.d)) * L.kp * sizeof(float));
+    L.F1 = take(size_t(f32_ld(b.d)) * L.kp * sizeof(float));
   }
   L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * sizeof(double));
   L.Cpart = take(kb_partial_bytes(h.n_proj, k, b.d));
@@ -386,8 +386,8 @@ Layout hx_layout(const Ham& h, int k, int prec) {
   L.A = take(size_t(b.n_r) * LL * L.kp * e);
   L.gbuf = take(size_t(b.n_r) * b.n_theta * (2 * size_t(b.L) - 1) * L.kp * e);
   if (prec == CES_PREC_MIXED) {
-    L.F0 = take(size_t(b.d) * L.kp * sizeof(float));
-    L.F1 = take(size_t(b.d) * L.kp * sizeof(float));
+    L.F0 = take(size_t(f32_ld(b.d)) * L.kp * sizeof(float));
+    L.F1 = take(size_t(f32_ld(b.d)) * L.kp * sizeof(float));
   }
   L.C = take(size_t(std::max(h.n_proj, 1)) * L.kp * e);
   L.Cpart = take(kb_partial_bytes(h.n_proj, k, b.d));
@@ -431,14 +431,15 @@ ces_status h_step_block(Ham& h, const Layout& ly, void* work, int k, const T* Yi
     // C = diag(h) P^T Yin (n_proj x kp, row-major), then Zkb = P C (d x k)
     const T* Pd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.proj64 : (const void*)h.proj32);
     const T* hd = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h.hproj64 : (const void*)h.hproj32);
+    const int64_t ldp = sizeof(T) == 8 ? b.d : f32_ld(b.d);   // P row stride
     {
       StageTimer t(stage_id<T>(ST_KB_C), s);
-      launch_kb_gemm<T>(Pd, b.d, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k, kp,
-                        s);
+      launch_kb_gemm<T>(Pd, b.d, ldp, Yin, ldin, hd, C, Ptr<T>::at(work, ly.Cpart), h.n_proj, k,
+                        kp, s);
     }
     Zkb = Ptr<T>::at(work, ly.Zkb);
     StageTimer t(stage_id<T>(ST_KB_Z), s);
-    launch_kb_apply<T>(Pd, b.d, C, Zkb, h.n_proj, k, kp, s);
+    launch_kb_apply<T>(Pd, b.d, ldp, C, Zkb, h.n_proj, k, kp, s);
   }
   T* gbuf = Ptr<T>::at(work, ly.gbuf);
   {
@@ -500,9 +501,10 @@ ces_status apply_H_impl(Ham& h, const Layout& ly, void* work, int k, const doubl
     return h_step<double>(h, ly, work, k, X, ldx, nullptr, 0, Y, ldy, 1.0, 0.0, 0.0, s);
   float* F0 = Ptr<float>::at(work, ly.F0);
   float* F1 = Ptr<float>::at(work, ly.F1);
-  launch_convert<double, float>(X, ldx, F0, d, d, k, s);
-  CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
-  launch_convert<float, double>(F1, d, Y, ldy, d, k, s);
+  const int64_t ldf = f32_ld(d);
+  launch_convert<double, float>(X, ldx, F0, ldf, d, k, s);
+  CES_TRY(h_step<float>(h, ly, work, k, F0, ldf, nullptr, 0, F1, ldf, 1.0f, 0.0f, 0.0f, s));
+  launch_convert<float, double>(F1, ldf, Y, ldy, d, k, s);
   CES_HIP(hipGetLastError());
   return CES_OK;
 }
@@ -701,9 +703,10 @@ ces_status rr_locked(Ham& h, const Layout& ly, void* work, int k, double* X, int
     } else {
       float* F0 = Ptr<float>::at(work, ly.F0);
       float* F1 = Ptr<float>::at(work, ly.F1);
-      launch_convert<double, float>(X, ldx, F0, d, d, k, s);
-      CES_TRY(h_step<float>(h, ly, work, k, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
-      launch_convert<float, double>(F1, d, HQ, ldhq, d, k, s);
+      const int64_t ldf = f32_ld(d);
+      launch_convert<double, float>(X, ldx, F0, ldf, d, k, s);
+      CES_TRY(h_step<float>(h, ly, work, k, F0, ldf, nullptr, 0, F1, ldf, 1.0f, 0.0f, 0.0f, s));
+      launch_convert<float, double>(F1, ldf, HQ, ldhq, d, k, s);
     }
     // Hs = Q^T H Q, eigen-decomposition (ascending)
     launch_gram(X, ldx, HQ, ldhq, S1, part, d, k, s, true);
@@ -988,7 +991,7 @@ ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const 
   const size_t nab = size_t(b.n_r) * b.n_theta * 2 * S;
   const size_t sz_v = align256(size_t(b.n_grid) * 8), sz_ab64 = align256(nab * 8),
                sz_ab32 = align256(nab * 4), sz_p64 = align256(size_t(b.d) * n_proj * 8),
-               sz_p32 = align256(size_t(b.d) * n_proj * 4), sz_h = align256(size_t(n_proj) * 8) + align256(size_t(n_proj) * 4);
+               sz_p32 = align256(size_t(f32_ld(b.d)) * n_proj * 4), sz_h = align256(size_t(n_proj) * 8) + align256(size_t(n_proj) * 4);
   void* blk = nullptr;
   if (hipMalloc(&blk, sz_v + sz_ab64 + sz_ab32 + sz_p64 + sz_p32 + sz_h) != hipSuccess) {
     delete hh;
@@ -1027,7 +1030,10 @@ ces_status ces_ham_create(ces_basis bb, const double* d_veff, int n_proj, const 
     if (hipMemcpyAsync(h.proj64, d_proj, size_t(b.d) * n_proj * 8, hipMemcpyDeviceToDevice, s) !=
         hipSuccess)
       return cleanup(fail(CES_ERR_DEVICE, "copy of projectors failed"));
-    launch_convert<double, float>(h.proj64, b.d, h.proj32, b.d, b.d, n_proj, s);
+    // FP32 rows padded to f32_ld(d) with zeros
+    if (hipMemsetAsync(h.proj32, 0, size_t(f32_ld(b.d)) * n_proj * 4, s) != hipSuccess)
+      return cleanup(fail(CES_ERR_DEVICE, "clearing the FP32 projectors failed"));
+    launch_convert<double, float>(h.proj64, b.d, h.proj32, f32_ld(b.d), b.d, n_proj, s);
     std::vector<float> e32(n_proj);
     for (int q = 0; q < n_proj; ++q) e32[q] = static_cast<float>(h_proj_energy[q]);
     if (hipMemcpyAsync(h.hproj64, h_proj_energy, size_t(n_proj) * 8, hipMemcpyHostToDevice, s) !=
@@ -1106,10 +1112,11 @@ ces_status ces_cheb_filter(ces_ham hh, int k, double* d_X, int64_t ldx, int degr
   } else {
     float* F0 = Ptr<float>::at(d_work, ly.F0);
     float* F1 = Ptr<float>::at(d_work, ly.F1);
-    launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
+    const int64_t ldf = f32_ld(d);
+    launch_convert<double, float>(d_X, ldx, F0, ldf, d, k, s);
     float* res = nullptr;
     int64_t ldr = 0;
-    CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, d, F1, d, degree, a, b, a0, s, &res, &ldr));
+    CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, ldf, F1, ldf, degree, a, b, a0, s, &res, &ldr));
     launch_convert<float, double>(res, ldr, d_X, ldx, d, k, s);
   }
   CES_HIP(hipGetLastError());
@@ -1217,10 +1224,12 @@ ces_status ces_chefsi(ces_ham hh, int k, double* d_X, int64_t ldx, int degree, d
     } else {
       float* F0 = Ptr<float>::at(d_work, ly.F0);
       float* F1 = Ptr<float>::at(d_work, ly.F1);
-      launch_convert<double, float>(d_X, ldx, F0, d, d, k, s);
+      const int64_t ldf = f32_ld(d);
+      launch_convert<double, float>(d_X, ldx, F0, ldf, d, k, s);
       float* out = nullptr;
       int64_t ldr = 0;
-      CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, d, F1, d, degree, a, b, a0u, s, &out, &ldr));
+      CES_TRY(cheb_run<float>(h, ly, d_work, k, F0, ldf, F1, ldf, degree, a, b, a0u, s, &out,
+                              &ldr));
       launch_convert<float, double>(out, ldr, d_X, ldx, d, k, s);
     }
     theta_old = theta;
@@ -1312,8 +1321,8 @@ ces_status ces_density(ces_ham hh, int k, const double* d_X, int64_t ldx, const 
     float* F0 = Ptr<float>::at(d_work, ly.F0);
     float* G = Ptr<float>::at(d_work, ly.G);
     float* gbuf = Ptr<float>::at(d_work, ly.gbuf);
-    launch_convert<double, float>(d_X, ldx, F0, b.d, b.d, k, s);
-    launch_radial_inverse<float>(b, b.t32, F0, b.d, G, k, kp, s);
+    launch_convert<double, float>(d_X, ldx, F0, f32_ld(b.d), b.d, k, s);
+    launch_radial_inverse<float>(b, b.t32, F0, f32_ld(b.d), G, k, kp, s);
     launch_legendre_synth<float>(b, b.t32, G, gbuf, kp, s);
     launch_density_phi<float>(b, gbuf, d_occ, d_rho_grid, k, kp, s);
   }

@@ -212,23 +212,29 @@ void launch_convert(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t
                     int cols, hipStream_t s);
 
 // C[q][i] *= h[q] for q < rows, i < ld.
+// Leading dimension of the library's FP32 blocks of d-vectors (the mixed
+// precision's copies of X and H X, and the FP32 projectors): d rounded up to
+// 32, so every column starts on a 128-byte line and a 32-float segment of it
+// (one staged step of the projector products) is one line.
+inline int64_t f32_ld(int64_t d) { return (d + 31) / 32 * 32; }
 // C[q][i] = h_q sum_alpha P[q][alpha] Y[alpha][i] (projector product; P n_proj x d
-// row-major, Y column-major d x k, C row-major n_proj x kp with zeros for i >= k);
-// part: kb_partial_bytes(n_proj, k, d) bytes of scratch.
+// row-major with row stride ldp, Y column-major d x k, C row-major n_proj x kp
+// with zeros for i >= k); part: kb_partial_bytes(n_proj, k, d) bytes of scratch.
 size_t kb_partial_bytes(int n_proj, int k, int64_t d);
 template <typename T>
-void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
-                    int n_proj, int k, int kp, hipStream_t s);
+void launch_kb_gemm(const T* P, int64_t d, int64_t ldp, const T* Y, int64_t ldy, const T* h,
+                    T* C, T* part, int n_proj, int k, int kp, hipStream_t s);
 // part[c][q][i] (row-major k x kp per chunk c of the rows) = the chunk's share
 // of (A^T B)[q][i] for column-major rows x k blocks A, B, on FP64 MFMA with
 // the projector product's kernel; at most part_cap doubles of part are used.
 // Returns the number of chunks.
 int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ldb, double* part,
                        int64_t part_cap, int64_t rows, int k, int kp, hipStream_t s);
-// Z[alpha][i] = sum_q P[q][alpha] C[q][i] (Z column-major d x k, ld d).
+// Z[alpha][i] = sum_q P[q][alpha] C[q][i] (P row stride ldp; Z column-major d x k,
+// ld d).
 template <typename T>
-void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,
-                     hipStream_t s);
+void launch_kb_apply(const T* P, int64_t d, int64_t ldp, const T* C, T* Z, int n_proj, int k,
+                     int kp, hipStream_t s);
 
 // Phi transforms of k grid functions (column i at f + i ldf, [r][j][p]) to /
 // from the Legendre stages' layout g[r][j][s][c] with kp columns (columns k ..

@@ -197,8 +197,9 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 // an XCD.
 template <typename T, bool DB, int KB>
 __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64_t d,
-                                                  const T* __restrict__ C, int n_proj, int k,
-                                                  int kp, T* __restrict__ Z, int nI, int nA) {
+                                                  int64_t ldp, const T* __restrict__ C,
+                                                  int n_proj, int k, int kp, T* __restrict__ Z,
+                                                  int nI, int nA) {
   typedef typename MF<T>::acc acc_t;
   constexpr int TM = KbShape<T>::TM, TN = KbShape<T>::TN;
   constexpr int BM = 32 * TN, BN = 32 * TM;      // i tile, alpha tile (2 x 2 waves)
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64
 #pragma unroll
     for (int p = 0; p < LP; ++p) {
       const int q = q0 + pq + RP * p;
-      rp[p] = pbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * d];
+      rp[p] = pbase[static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * ldp];
     }
   };
   acc_t acc[TN][TM];
@@ -405,15 +406,15 @@ void allow_lds(K kern, size_t bytes) {
 }
 
 template <typename T>
-void launch_kb_gemm(const T* P, int64_t d, const T* Y, int64_t ldy, const T* h, T* C, T* part,
-                    int n_proj, int k, int kp, hipStream_t s) {
+void launch_kb_gemm(const T* P, int64_t d, int64_t ldp, const T* Y, int64_t ldy, const T* h,
+                    T* C, T* part, int n_proj, int k, int kp, hipStream_t s) {
   const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
   const bool xc = gr.nchunk % 8 == 0;
   const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
   constexpr bool DB = sizeof(T) == 4;
   constexpr size_t lds = kb_lds_bytes<T>(DB);
   allow_lds(&k_kb_gemm<T, DB>, lds);
-  k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, d, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
+  k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, ldp, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
                                          gr.nN, gr.nchunk, xc ? 1 : 0);
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
@@ -439,8 +440,8 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
 }
 
 template <typename T>
-void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k, int kp,
-                     hipStream_t s) {
+void launch_kb_apply(const T* P, int64_t d, int64_t ldp, const T* C, T* Z, int n_proj, int k,
+                     int kp, hipStream_t s) {
   constexpr int BM = 32 * KbShape<T>::TN, BN = 32 * KbShape<T>::TM;
   const int nI = (k + BM - 1) / BM;
   const int nA = static_cast<int>((d + BN - 1) / BN);
@@ -448,16 +449,16 @@ void launch_kb_apply(const T* P, int64_t d, const T* C, T* Z, int n_proj, int k,
   constexpr int KBA = KbShape<T>::KB;   // projectors per staged step
   constexpr size_t lds = kb_lds_bytes<T>(false, KBA);
   allow_lds(&k_kb_apply<T, false, KBA>, lds);
-  k_kb_apply<T, false, KBA><<<nwg, 256, lds, s>>>(P, d, C, n_proj, k, kp, Z, nI, nA);
+  k_kb_apply<T, false, KBA><<<nwg, 256, lds, s>>>(P, d, ldp, C, n_proj, k, kp, Z, nI, nA);
 }
 
-template void launch_kb_apply<float>(const float*, int64_t, const float*, float*, int, int, int,
-                                     hipStream_t);
-template void launch_kb_apply<double>(const double*, int64_t, const double*, double*, int, int,
-                                      int, hipStream_t);
-template void launch_kb_gemm<float>(const float*, int64_t, const float*, int64_t, const float*,
-                                    float*, float*, int, int, int, hipStream_t);
-template void launch_kb_gemm<double>(const double*, int64_t, const double*, int64_t,
+template void launch_kb_apply<float>(const float*, int64_t, int64_t, const float*, float*, int,
+                                     int, int, hipStream_t);
+template void launch_kb_apply<double>(const double*, int64_t, int64_t, const double*, double*,
+                                      int, int, int, hipStream_t);
+template void launch_kb_gemm<float>(const float*, int64_t, int64_t, const float*, int64_t,
+                                    const float*, float*, float*, int, int, int, hipStream_t);
+template void launch_kb_gemm<double>(const double*, int64_t, int64_t, const double*, int64_t,
                                      const double*, double*, double*, int, int, int, hipStream_t);
 
 }  // namespace ces

@@ -250,9 +250,10 @@ ces_status ces_lobpcg(ces_ham hh, int k, double* d_X, int64_t ldx, int n_lock, c
       return h_step<double>(h, lw, d_work, n, V, d, nullptr, 0, AV, d, 1.0, 0.0, 0.0, s);
     float* F0 = Ptr<float>::at(d_work, lw.F0);
     float* F1 = Ptr<float>::at(d_work, lw.F1);
-    launch_convert<double, float>(V, d, F0, d, d, n, s);
-    CES_TRY(h_step<float>(h, lw, d_work, n, F0, d, nullptr, 0, F1, d, 1.0f, 0.0f, 0.0f, s));
-    launch_convert<float, double>(F1, d, AV, d, d, n, s);
+    const int64_t ldf = f32_ld(d);
+    launch_convert<double, float>(V, d, F0, ldf, d, n, s);
+    CES_TRY(h_step<float>(h, lw, d_work, n, F0, ldf, nullptr, 0, F1, ldf, 1.0f, 0.0f, 0.0f, s));
+    launch_convert<float, double>(F1, ldf, AV, d, d, n, s);
     return CES_OK;
   };
 
