@@ -64,6 +64,20 @@ inline AngDims ang_dims(const Basis& b, int kp) {
   return a;
 }
 
+// Streaming stores for an output of `elems` values of T (see store_vec).
+template <typename T>
+bool stream_stores(size_t elems) {
+  return elems * sizeof(T) > kStreamStoreBytes;
+}
+// f(std::true_type()) or f(std::false_type()) as `on` is set
+template <typename F>
+void with_nts(bool on, F&& f) {
+  if (on)
+    f(std::true_type());
+  else
+    f(std::false_type());
+}
+
 // ------------------------------------------------------- legendre_synth
 
 // Workgroup: one m-slot, JT groups of 64 theta nodes (one 16-row tile of each
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(256) void k_legendre_synth(const T* __restrict__ Pm
 // so a lane reads its NT B values with one vector load and writes its NT
 // results of a node with one vector store: each store instruction covers
 // whole 16 NT-column row pieces of g rather than 16-column halves.
-template <typename T, int NT, int JT, int CH>
+template <typename T, int NT, int JT, int CH, bool NTS>
 __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict__ Pm,
                                                              const T* __restrict__ G,
                                                              T* __restrict__ g, AngDims D,
@@ -316,9 +330,9 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
           pe[nt] = E[u][nt][v] + O[u][nt][v];
           pm[nt] = E[u][nt][v] - O[u][nt][v];
         }
-        store_vec<T, NT>(gr + j * jstride, pe);
+        store_vec<T, NT, NTS>(gr + j * jstride, pe);
         const int jm = D.n_theta - 1 - j;
-        if (jm != j) store_vec<T, NT>(gr + jm * jstride, pm);
+        if (jm != j) store_vec<T, NT, NTS>(gr + jm * jstride, pm);
       }
     }
 }
@@ -330,7 +344,8 @@ __global__ __launch_bounds__(256) void k_legendre_synth_fold(const T* __restrict
 //   cos <- cos  ha_|m-m'| + ha_{m+m'}      sin <- sin  ha_|m-m'| - ha_{m+m'}
 //   cos <- sin  hb_{m+m'} + hb_{m-m'}      sin <- cos  hb_{m+m'} - hb_{m-m'}
 constexpr int PS_NT = 2;             // 16-column tiles per workgroup
-constexpr int kPhiRowsPerWg = 16;    // rows each workgroup walks, the next one in flight
+constexpr int kPhiRowsPerWg = 16;    // most rows each workgroup walks, the next one in flight
+constexpr int64_t kPhiMinWgs = 2048; // fewer rows per workgroup below this many workgroups
 
 // phi stage: gh = C g per (r, theta_j) row, C the (2L-1)^2 coupling of the
 // product-to-sum identity above.  K (input slots) and M (output slots) are
@@ -356,7 +371,7 @@ constexpr int kPhiRowsPerWg = 16;    // rows each workgroup walks, the next one 
 // 128-byte row pieces of g.
 // FP32 is held to four waves per SIMD (at L = 81: 21.7 against 22.2 ms with
 // the three the compiler chose by itself).
-template <typename T, int LP, int TC, int SS>
+template <typename T, int LP, int TC, int SS, bool NTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
 void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
                                                    AngDims D, int64_t n_rows) {
@@ -535,7 +550,7 @@ void k_phi_stage(T* __restrict__ g, const T* __restrict__ ab,
           T pr[PS_NT];
 #pragma unroll
           for (int nt = 0; nt < PS_NT; ++nt) pr[nt] = acc[u][nt][v];
-          if (full || rl0 + dr < lim) store_vec<T, PS_NT>(gr + ob + dr * kpu, pr);
+          if (full || rl0 + dr < lim) store_vec<T, PS_NT, NTS>(gr + ob + dr * kpu, pr);
         }
       }
     }
@@ -661,7 +676,7 @@ __global__ __launch_bounds__(256) void k_legendre_analysis(const T* __restrict__
 // folded synthesis): one vector load per node and one vector store per row.
 // FP32 with three l-tiles per parity is held to three waves per SIMD, which
 // its two-step chunks fit without spills (309 atoms: 7.3 -> 7.1 ms).
-template <typename T, int MH, int CH, int NTA>
+template <typename T, int MH, int CH, int NTA, bool NTS>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MH == 3 ? 3 : 1, 8)))
 void k_legendre_analysis_fold(const T* __restrict__ PwT,
@@ -784,8 +799,8 @@ void k_legendre_analysis_fold(const T* __restrict__ PwT,
         pe[nt] = ae[u][nt][v];
         po[nt] = ao[u][nt][v];
       }
-      if (u < nme && le < D.L) store_vec<T, NTA>(Ar + (le * le + le + sgn * m) * D.kp, pe);
-      if (u < nmo && lo < D.L) store_vec<T, NTA>(Ar + (lo * lo + lo + sgn * m) * D.kp, po);
+      if (u < nme && le < D.L) store_vec<T, NTA, NTS>(Ar + (le * le + le + sgn * m) * D.kp, pe);
+      if (u < nmo && lo < D.L) store_vec<T, NTA, NTS>(Ar + (lo * lo + lo + sgn * m) * D.kp, po);
     }
   }
 }
@@ -1041,10 +1056,14 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
     // occupancy they cost (309 atoms, six tiles: 10.3 ms with one against
     // 10.8 with two, at two and five waves per SIMD)
     constexpr int CH = 4;
+    const bool nts = stream_stores<T>(size_t(b.n_r) * b.n_theta * D.S * kp);
     auto go = [&](auto nt_tag, int n_ic) {
       constexpr int NT = decltype(nt_tag)::value;
       dim3 grid(b.n_r * n_ic, (ntile + 3) / 4, D.S);
-      k_legendre_synth_fold<T, NT, 1, CH><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      with_nts(nts, [&](auto nts_tag) {
+        constexpr bool NTS = decltype(nts_tag)::value;
+        k_legendre_synth_fold<T, NT, 1, CH, NTS><<<grid, 256, 0, s>>>(tb.Pm, G, gbuf, D, n_ic, nh);
+      });
     };
     // 16-column tiles per workgroup: four in FP32 on wide blocks (147 atoms:
     // 1.95 against 2.13 ms with two; 309 atoms, with each lane's four
@@ -1101,6 +1120,7 @@ void launch_legendre_synth(const Basis& b, const DevTables<T>& tb, const T* G, T
 template <typename T>
 void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
+  const bool nts = stream_stores<T>(size_t(b.n_r) * b.n_theta * D.S * kp);
   // each workgroup walks about kPhiRowsPerWg (r, theta_j) rows with a stride
   // of the grid, prefetching the next row while the current one runs on
   // MFMA; many short workgroups leave no partly filled last round (309
@@ -1109,7 +1129,12 @@ void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t 
   // cover whole rows of g (147 atoms: 3.04 -> 2.82 ms; 309: 20.4 -> 20.1)
   const int64_t n_rows = int64_t(b.n_r) * b.n_theta;
   const int ncg = (kp + 16 * PS_NT - 1) / (16 * PS_NT);
-  const int64_t want = (n_rows + kPhiRowsPerWg - 1) / kPhiRowsPerWg;
+  // rows per workgroup: up to kPhiRowsPerWg while the grid keeps at least
+  // kPhiMinWgs workgroups (13 atoms, one column block: 2 rows, 2790
+  // workgroups; with 16 rows its 349 workgroups left most CUs idle)
+  const int64_t rpw = std::max<int64_t>(
+      1, std::min<int64_t>(kPhiRowsPerWg, n_rows * ncg / kPhiMinWgs));
+  const int64_t want = (n_rows + rpw - 1) / rpw;
   dim3 grid(ncg, static_cast<unsigned>(std::min<int64_t>(want, 65535)));
   const size_t lds = (6 * size_t(2 * D.L16) + size_t(2 * D.L16) * (16 * PS_NT)) * sizeof(T);
   // K rows that hold slots: rup(L, 4) of the cos block, rup(L - 1, 4) of the
@@ -1118,16 +1143,19 @@ void launch_phi_stage(const Basis& b, const T* ab, T* gbuf, int kp, hipStream_t 
   const int tc = (D.L16 - kend0) / 4, ss = (kend0 - kend1) / 4;
   auto go = [&](auto lp_tag) {
     constexpr int LP = decltype(lp_tag)::value;
-    switch (tc * 2 + ss) {
-      case 0: k_phi_stage<T, LP, 0, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 1: k_phi_stage<T, LP, 0, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 2: k_phi_stage<T, LP, 1, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 3: k_phi_stage<T, LP, 1, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 4: k_phi_stage<T, LP, 2, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 5: k_phi_stage<T, LP, 2, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      case 6: k_phi_stage<T, LP, 3, 0><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-      default: k_phi_stage<T, LP, 3, 1><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
-    }
+    with_nts(nts, [&](auto nts_tag) {
+      constexpr bool NTS = decltype(nts_tag)::value;
+      switch (tc * 2 + ss) {
+        case 0: k_phi_stage<T, LP, 0, 0, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 1: k_phi_stage<T, LP, 0, 1, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 2: k_phi_stage<T, LP, 1, 0, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 3: k_phi_stage<T, LP, 1, 1, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 4: k_phi_stage<T, LP, 2, 0, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 5: k_phi_stage<T, LP, 2, 1, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        case 6: k_phi_stage<T, LP, 3, 0, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+        default: k_phi_stage<T, LP, 3, 1, NTS><<<grid, 256, lds, s>>>(gbuf, ab, D, n_rows); break;
+      }
+    });
   };
   switch (D.L16) {   // L <= 96 (checked at basis creation)
     case 16: go(std::integral_constant<int, 16>()); break;
@@ -1143,6 +1171,7 @@ template <typename T>
 void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* gbuf, T* A,
                               int kp, hipStream_t s) {
   const AngDims D = ang_dims(b, kp);
+  const bool nts = stream_stores<T>(size_t(b.n_r) * D.LL * kp);
   const int n_ic = (kp + 16 * LA_NT - 1) / (16 * LA_NT);
   dim3 grid(b.n_r * n_ic, (D.S + LA_SW - 1) / LA_SW);
   constexpr bool f32 = sizeof(T) == 4;
@@ -1155,12 +1184,15 @@ void launch_legendre_analysis(const Basis& b, const DevTables<T>& tb, const T* g
       constexpr int NTA = decltype(nta_tag)::value;
       const int n_icf = (kp + 16 * NTA - 1) / (16 * NTA);
       dim3 gridf(b.n_r * n_icf, (D.S + LA_SW - 1) / LA_SW);
-      if (b.L <= 64)
-        k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
-                                                                               n_icf, nh);
-      else
-        k_legendre_analysis_fold<T, 3, 2, NTA><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D, n_icf,
-                                                                     nh);
+      with_nts(nts, [&](auto nts_tag) {
+        constexpr bool NTS = decltype(nts_tag)::value;
+        if (b.L <= 64)
+          k_legendre_analysis_fold<T, 2, f32 ? 4 : 2, NTA, NTS><<<gridf, 256, 0, s>>>(
+              tb.PwT, gbuf, A, D, n_icf, nh);
+        else
+          k_legendre_analysis_fold<T, 3, 2, NTA, NTS><<<gridf, 256, 0, s>>>(tb.PwT, gbuf, A, D,
+                                                                            n_icf, nh);
+      });
     };
     if (f32 && kp >= 512)
       go(std::integral_constant<int, 4>());

@@ -12,6 +12,8 @@
 //   step of the scaled Chebyshev recurrence.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ces_internal.h"
 #include "mfma.h"
 
@@ -39,7 +41,7 @@ __host__ __device__ inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 // in flight while the current one runs.  Column tile nt of lane l16 is column
 // 2 l16 + nt of the 32: a lane reads both B values of a k-step with one
 // 8-byte LDS read and writes both results of a row with one 8-byte store.
-template <typename T, int MT, int CK, bool ONE>
+template <typename T, int MT, int CK, bool ONE, bool NTS>
 __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict__ RiT,
                                                              const T* __restrict__ X,
                                                              int64_t ldx, T* __restrict__ G,
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_radial_inverse_mfma(const T* __restrict
       T pr[RI_NT];
 #pragma unroll
       for (int nt = 0; nt < RI_NT; ++nt) pr[nt] = acc[u][nt][v];
-      if (r < n_r) store_vec<T, RI_NT>(Gb + r * rstride, pr);
+      if (r < n_r) store_vec<T, RI_NT, NTS>(Gb + r * rstride, pr);
     }
   }
 }
@@ -350,12 +352,21 @@ void radial_inverse_ck(const Basis& b, const DevTables<T>& tb, const T* X, int64
   dim3 grid((kp + 16 * RI_NT - 1) / (16 * RI_NT), b.L * b.L);
   const size_t lds = size_t(rup(b.N, 16)) * (16 * RI_NT + 2) * sizeof(T);
   const int mt = (rup(b.n_r, 16) / 16 + 3) / 4;   // n_r <= 256: at most 4 tiles per wave
-  switch (mt) {
-    case 1: k_radial_inverse_mfma<T, 1, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
-    case 2: k_radial_inverse_mfma<T, 2, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
-    case 3: k_radial_inverse_mfma<T, 3, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
-    default: k_radial_inverse_mfma<T, 4, CK, ONE><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
-  }
+  // streaming stores when G exceeds the last-level cache (see store_vec)
+  const bool nts = size_t(b.n_r) * b.L * b.L * kp * sizeof(T) > kStreamStoreBytes;
+  auto go = [&](auto nts_tag) {
+    constexpr bool NTS = decltype(nts_tag)::value;
+    switch (mt) {
+      case 1: k_radial_inverse_mfma<T, 1, CK, ONE, NTS><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+      case 2: k_radial_inverse_mfma<T, 2, CK, ONE, NTS><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+      case 3: k_radial_inverse_mfma<T, 3, CK, ONE, NTS><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+      default: k_radial_inverse_mfma<T, 4, CK, ONE, NTS><<<grid, 256, lds, s>>>(tb.RiT, X, ldx, G, b.dev_lay, b.L, b.N, b.n_r, k, kp); break;
+    }
+  };
+  if (nts)
+    go(std::true_type());
+  else
+    go(std::false_type());
 }
 
 template <typename T>

@@ -41,19 +41,27 @@ __device__ __forceinline__ void load_vec(const T* p, T (&out)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) out[i] = x.v[i];
 }
-// Stores of the transform stages' outputs (global memory): each is written
-// once and read back by the next stage only after gigabytes of other
-// traffic, so they go out as non-temporal (streaming) stores (309 atoms,
-// FP32 Legendre synthesis: 10.3 -> 9.3 ms).  Measured slower, so not used:
+// Stores of the transform stages' outputs (global memory).  With NTS (an
+// output larger than the last-level cache, so the next stage reads it back
+// from HBM anyway) they go out as non-temporal (streaming) stores (309
+// atoms, FP32 Legendre synthesis: 10.3 -> 9.3 ms); a smaller output is
+// stored normally and stays cached for its reader (13 atoms: the synthesis
+// read G 30 % slower after streaming stores).  The choice is a template
+// parameter of the kernels: as a runtime branch the compiler merged the two
+// stores into one plain store.  Measured slower, so not used:
 // non-temporal loads of the stages' inputs, and non-temporal scalar stores
 // of the radial forward and projector outputs.
-template <typename T, int N>
+constexpr size_t kStreamStoreBytes = size_t(256) << 20;   // MI355X last-level cache
+template <typename T, int N, bool NTS>
 __device__ __forceinline__ void store_vec(T* p, const T (&in)[N]) {
   typedef T vt __attribute__((ext_vector_type(N)));
   vt x;
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = in[i];
-  __builtin_nontemporal_store(x, reinterpret_cast<vt*>(p));
+  if constexpr (NTS)
+    __builtin_nontemporal_store(x, reinterpret_cast<vt*>(p));
+  else
+    *reinterpret_cast<vt*>(p) = x;
 }
 
 template <typename A>
