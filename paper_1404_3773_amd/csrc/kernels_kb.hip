@@ -194,9 +194,12 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 // along i, P rows along alpha), the next step's tiles in registers.  The
 // result lane holds 16 consecutive alpha of one column, so stores are
 // coalesced.  Workgroups that read the same P tile (same alpha tile) share
-// an XCD.
+// an XCD.  FP32 is held to four waves per SIMD (309 atoms: 23.1 -> 22.7 ms;
+// three VGPRs spill, outside the K loop), FP64 to three (51.7 -> 46.7 ms,
+// no spills).
 template <typename T, bool DB, int KB>
-__global__ __launch_bounds__(256) void k_kb_apply(const T* __restrict__ P, int64_t d,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8)))
+void k_kb_apply(const T* __restrict__ P, int64_t d,
                                                   int64_t ldp, const T* __restrict__ C,
                                                   int n_proj, int k, int kp, T* __restrict__ Z,
                                                   int nI, int nA) {
