@@ -53,7 +53,7 @@ STAGE_KERNEL = {"radial_inverse": ("k_radial_inverse_mfma<float",),
                 "legendre_analysis": ("k_legendre_analysis<float",
                                       "k_legendre_analysis_fold<float"),
                 "radial_forward": ("k_radial_forward_mfma<float",),
-                "kb_project": ("k_kb_gemm<float",), "kb_apply": ("k_kb_apply<float",)}
+                "kb_project": ("k_kb_gemm<float",), "kb_apply": ("k_kb_apply_wide<", "k_kb_apply<float")}
 
 
 def algorithmic_flops(w, k, n_proj=0):

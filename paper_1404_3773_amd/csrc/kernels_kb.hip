@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "ces_internal.h"
 #include "mfma.h"
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   const int wm = wave >> 1, wn = wave & 1;
   const int c16 = lane & 15, kk = lane >> 4;
   // staging: thread -> (tile row r0 + RA p, alpha offset kc); row addresses
-  // are formed per load (keeps the register count at three waves per SIMD)
+  // are formed per load (fewer address registers held)
   const int kc = tid % KB, r0 = tid / KB;
   const int arow0 = mtb * BM + r0, bcol0 = ntb * BN + r0;
   // loads read clamped addresses and are masked when stored to LDS (a
@@ -194,9 +195,10 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
 // along i, P rows along alpha), the next step's tiles in registers.  The
 // result lane holds 16 consecutive alpha of one column, so stores are
 // coalesced.  Workgroups that read the same P tile (same alpha tile) share
-// an XCD.  FP32 is held to four waves per SIMD (309 atoms: 23.1 -> 22.7 ms;
-// three VGPRs spill, outside the K loop), FP64 to three (51.7 -> 46.7 ms,
-// no spills).
+// an XCD.  It serves FP64 and FP32 operands that the wide-tile kernel below
+// cannot load as 16-byte vectors.  FP32 is held to four waves per SIMD (309
+// atoms: 23.1 -> 22.7 ms; three VGPRs spill, outside the K loop), FP64 to
+// three (51.7 -> 46.7 ms, no spills).
 template <typename T, bool DB, int KB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8)))
 void k_kb_apply(const T* __restrict__ P, int64_t d,
@@ -309,6 +311,146 @@ void k_kb_apply(const T* __restrict__ P, int64_t d,
       for (int r = 0; r < 4; ++r) {
         const int i = itb * BM + wm * 16 * TN + 16 * u + MF<T>::row(lane, r);
         const int64_t a = static_cast<int64_t>(ga) * BN + wn * 16 * TM + 16 * v + c16;
+        if (i < k && a < d) Z[static_cast<int64_t>(i) * d + a] = acc[u][v][r];
+      }
+}
+
+// kb_apply, FP32, wide tiles: workgroup tile 128 columns i x 256 rows alpha,
+// 2 x 2 waves of 64 x 128 (4 x 8 MFMA fragments, 128 accumulators per lane),
+// so each staged operand value feeds twice the MFMAs of the 64 x 64 wave
+// tile.  The projector steps (KA per step) are staged in LDS row-major by
+// projector (C rows along i, P rows along alpha) from 16-byte loads and
+// 16-byte LDS writes; the MFMA operand reads take 16 consecutive columns of 4
+// projector rows whose starts lie 16 banks apart (row pitch = width + 16
+// words).  Column loads are clamped into the arrays (rows are padded to a
+// multiple of 4): a clamped column only feeds outputs of columns i >= kp or
+// alpha >= ldp, which are not stored.  Projector rows past n_proj are
+// clamped on load and zeroed in the C tile.  309 atoms (k = 1000, 1236
+// projectors): 22.8 ms with the 64 x 64 wave tiles, 19.5 ms here (the same
+// result bits: each accumulator takes the projectors in the same order);
+// 8, 16 and 32 projectors per step (32 single-buffered) time alike, 32
+// double-buffered (one workgroup per CU) 26.3 ms.  Measured and not kept:
+// lanes owning 4 adjacent columns so that the operands come as 16-byte LDS
+// reads (3 instead of 12 per 4 projectors: 19.5 ms as well), and the same
+// wave tile for C = P^T Y (128 x 64, 16 alpha per step from 16-byte loads:
+// 22.7 ms single-buffered, 25.2 double-buffered, against 22.7).
+constexpr int kApI = 128, kApA = 256;                 // workgroup tile: i, alpha
+constexpr int kApPI = kApI + 16, kApPA = kApA + 16;   // LDS row pitch (floats)
+constexpr int kApKA = 16;                             // projectors per staged step
+constexpr bool kApDB = true;                          // double-buffered LDS
+
+template <int KA, bool DB>
+constexpr size_t kb_apply_wide_lds() {
+  return (DB ? 2 : 1) * size_t(KA) * (kApPI + kApPA) * sizeof(float);
+}
+
+template <int KA, bool DB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_kb_apply_wide(const float* __restrict__ P, int64_t d, int64_t ldp,
+                     const float* __restrict__ C, int n_proj, int k, int kp,
+                     float* __restrict__ Z, int nI, int nA) {
+  typedef MF<float>::acc acc_t;
+  constexpr int STAGE = KA * (kApPI + kApPA);
+  constexpr int CV = KA * kApI / (4 * 256);     // 16-byte C loads per thread per step
+  constexpr int PV = KA * kApA / (4 * 256);     // 16-byte P loads per thread per step
+  constexpr int CR = 256 / (kApI / 4), PR = 256 / (kApA / 4);   // rows per pass
+  static_assert(CV >= 1 && PV >= 1, "step too short for the staging passes");
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  float* const lds = reinterpret_cast<float*>(kb_smem);
+  const int id = blockIdx.x;
+  const int x = id & 7, j = id >> 3;
+  const int ga = x + 8 * (j / nI), itb = j - (j / nI) * nI;
+  if (ga >= nA) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wa = wave & 1;
+  const int c16 = lane & 15, kk = lane >> 4;
+  const int cr = tid / (kApI / 4), cc = 4 * (tid % (kApI / 4));
+  const int pr = tid / (kApA / 4), pc = 4 * (tid % (kApA / 4));
+  const int ic = min(itb * kApI + cc, kp - 4);
+  const int64_t ac = min(static_cast<int64_t>(ga) * kApA + pc, ldp - 4);
+  const float* cbase = C + ic;
+  const float* pbase = P + ac;
+  float rc[CV][4], rp[PV][4];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int p = 0; p < CV; ++p) {
+      const int q = q0 + cr + CR * p;
+      load_vec<float, 4>(cbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp, rc[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < PV; ++p) {
+      const int q = q0 + pr + PR * p;
+      load_vec<float, 4>(pbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * ldp, rp[p]);
+    }
+  };
+  acc_t acc[4][8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[u][v] = zero_acc<acc_t>();
+  auto stage = [&](int q0, int buf) __attribute__((always_inline)) {
+    float* Cs = lds + buf * STAGE;
+    float* Ps = Cs + KA * kApPI;
+#pragma unroll
+    for (int p = 0; p < CV; ++p) {
+      const bool ok = q0 + cr + CR * p < n_proj;
+      float w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = ok ? rc[p][e] : 0.f;
+      store_vec<float, 4, false>(Cs + (cr + CR * p) * kApPI + cc, w);
+    }
+#pragma unroll
+    for (int p = 0; p < PV; ++p) store_vec<float, 4, false>(Ps + (pr + PR * p) * kApPA + pc, rp[p]);
+  };
+  auto compute_steps = [&](int buf, int s0, int s1) __attribute__((always_inline)) {
+    const float* Aw = lds + buf * STAGE + kk * kApPI + wi * 64 + c16;
+    const float* Bw = lds + buf * STAGE + KA * kApPI + kk * kApPA + wa * 128 + c16;
+#pragma unroll
+    for (int st = s0; st < s1; ++st) {
+      float a[4], b[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Aw[4 * st * kApPI + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) b[v] = Bw[4 * st * kApPA + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = MF<float>::mma(a[u], b[v], acc[u][v]);
+    }
+  };
+  fetch(0);
+  if constexpr (DB) {
+    stage(0, 0);
+    if (KA < n_proj) fetch(KA);
+    __syncthreads();
+    int buf = 0;
+    for (int q0 = 0; q0 < n_proj; q0 += KA) {
+      const bool more = q0 + KA < n_proj;
+      compute_steps(buf, 0, KA / 8);
+      if (more) stage(q0 + KA, buf ^ 1);
+      compute_steps(buf, KA / 8, KA / 4);
+      if (more && q0 + 2 * KA < n_proj) fetch(q0 + 2 * KA);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    for (int q0 = 0; q0 < n_proj; q0 += KA) {
+      stage(q0, 0);
+      __syncthreads();
+      if (q0 + KA < n_proj) fetch(q0 + KA);
+      compute_steps(0, 0, KA / 4);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = itb * kApI + wi * 64 + 16 * u + MF<float>::row(lane, r);
+        const int64_t a = static_cast<int64_t>(ga) * kApA + wa * 128 + 16 * v + c16;
         if (i < k && a < d) Z[static_cast<int64_t>(i) * d + a] = acc[u][v][r];
       }
 }
@@ -445,6 +587,19 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
 template <typename T>
 void launch_kb_apply(const T* P, int64_t d, int64_t ldp, const T* C, T* Z, int n_proj, int k,
                      int kp, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    // wide tiles when the 16-byte column loads stay aligned
+    if (ldp % 4 == 0 && kp % 4 == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(C) % 16 == 0) {
+      const int nI = (k + kApI - 1) / kApI;
+      const int nA = static_cast<int>((d + kApA - 1) / kApA);
+      const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
+      constexpr size_t lds = kb_apply_wide_lds<kApKA, kApDB>();
+      allow_lds(&k_kb_apply_wide<kApKA, kApDB>, lds);
+      k_kb_apply_wide<kApKA, kApDB><<<nwg, 256, lds, s>>>(P, d, ldp, C, n_proj, k, kp, Z, nI, nA);
+      return;
+    }
+  }
   constexpr int BM = 32 * KbShape<T>::TN, BN = 32 * KbShape<T>::TM;
   const int nI = (k + BM - 1) / BM;
   const int nA = static_cast<int>((d + BN - 1) / BN);

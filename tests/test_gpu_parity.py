@@ -147,23 +147,27 @@ def test_apply_H_kb_projectors():
         assert rel_err(host(Yt, s.B.d), Z) < tol, prec
 
 
-def test_apply_H_many_projectors_several_tiles_and_chunks():
-    # 40 atoms -> 160 projectors, k = 140, d = 1200: the projector product runs
-    # on 2 x 2 (FP32) / 2 x 3 (FP64) output tiles with ragged edges and splits
-    # the contraction over d into 2 / 3 chunks
-    w = si.small(10, 12, R=12.0, k=140, name="kb_tiles")
-    _say(f"case apply_H KB tiles {w.name} k={w.k}")
+@pytest.mark.parametrize("n_atoms,k", [(40, 140), (37, 131)], ids=["p160_k140", "p148_k131"])
+def test_apply_H_many_projectors_several_tiles_and_chunks(n_atoms, k):
+    # 40 atoms -> 160 projectors, k = 140, d = 1200: C = diag(h) P^T Y runs on
+    # 2 x 2 (FP32) / 2 x 3 (FP64) output tiles with ragged edges and splits
+    # the contraction over d into 2 / 3 chunks; Zkb = P C on 2 x 5 (FP32, 128
+    # columns x 256 rows, the last rows past the padded row length) / 2 x 10
+    # (FP64) tiles.  37 atoms -> 148 projectors, a partial last step of the
+    # projector contraction, with k = 131.
+    w = si.small(10, 12, R=12.0, k=k, name="kb_tiles")
+    _say(f"case apply_H KB tiles {w.name} atoms={n_atoms} k={w.k}")
     B = ces.Basis.for_workload(w)
     r, wr, th, wt, ph = B.grid()
     bs = ob.basis_for(w)
     V = si.potential_on_grid(w, r, th, ph)
     Vo = si.potential_on_grid(w, bs.r, bs.theta, bs.phi)
     rng = np.random.default_rng(41)
-    atoms = rng.uniform(-5.0, 5.0, size=(40, 3))
+    atoms = rng.uniform(-5.0, 5.0, size=(n_atoms, 3))
     pts = si.spherical_to_cartesian(bs.r, bs.theta, bs.phi)
     pg, h = si.kb_projector_values(pts, atoms)
     P = oh.kb_projectors(bs, pg.reshape(*Vo.shape, -1))
-    assert P.shape == (B.d, 160)
+    assert P.shape == (B.d, 4 * n_atoms)
     H = ces.Ham(B, torch.from_numpy(V.reshape(-1)).cuda(),
                 proj=torch.from_numpy(np.ascontiguousarray(P.T)).cuda(), energies=h)
     X = si.random_block(B.d, w.k, 43)
