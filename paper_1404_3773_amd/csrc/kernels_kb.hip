@@ -18,11 +18,17 @@
 // its L2 serves the Y steps they share (all M tiles) and the P steps (all N
 // tiles of an M tile), and each is fetched from HBM about once.  Otherwise
 // the groups (chunk, M tile) of nN workgroups are dealt round-robin over the
-// XCDs, which keeps all of them busy for any chunk count.
+// XCDs, which keeps all of them busy for any chunk count.  FP32 operands with
+// 16-byte aligned rows are staged 64 alpha per step from 16-byte loads into
+// one LDS buffer (309 atoms: 22.9 -> 20.8 ms against 32 alpha per step from
+// 4-byte loads, double-buffered; 32 per step from 16-byte loads,
+// double-buffered, 22.1 ms; wave tiles of 128 x 64 with 16 or 32 alpha per
+// step, 22.7 ms or slower).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "ces_internal.h"
 #include "mfma.h"
@@ -40,6 +46,13 @@ template <>
 struct KbShape<double> {  // wave tile 64 x 32, workgroup 128 x 64, 32 alpha per step
   static constexpr int KB = 32, TM = 4, TN = 2;
 };
+// C = P^T Y, FP32 with 16-byte aligned rows: the same 128 x 128 workgroup
+// tiles, 64 alpha per step staged from 16-byte loads (each row's segment of
+// a step is two whole 128-byte lines) into one LDS buffer (69.6 KB, two
+// workgroups per CU).
+struct KgVec {
+  static constexpr int KB = 64, TM = 4, TN = 4;
+};
 constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 
 // LDS row pitch of the staged tiles: the MFMA operand reads take 16 rows x 4
@@ -47,24 +60,31 @@ constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 // lanes of a read fall on distinct banks, where KB + 1 left them two-way
 // (309-atom C = P^T Y: 25.4 -> 24.5 ms).  FP64 reads 8-byte words and keeps
 // KB + 1 (its C was slower with KB + 2).
+// Rows staged from 16-byte loads (vw = 4) take pitch KB + 4, a multiple of 4
+// that spreads the operand reads the same way (16 or 32 alpha per step).
 template <typename T>
-constexpr int kb_pitch(int kb) { return kb + (sizeof(T) == 4 ? 2 : 1); }
+constexpr int kb_pitch(int kb, int vw = 1) {
+  return kb + (sizeof(T) == 4 ? (vw > 1 || kb == 16 ? 4 : 2) : 1);
+}
 
 // With DB the P and Y tiles are double-buffered in (dynamic) LDS: a step
 // computes from one buffer while the next step's tiles are written into the
 // other, so it takes one barrier instead of two.
-template <typename T, bool DB>
-__global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_t d,
-                                                 int64_t ldp, const T* __restrict__ Y,
-                                                 int64_t ldy,
-                                                 T* __restrict__ part, int n_proj, int k, int kp,
-                                                 int64_t kchunk, int nM, int nN, int nchunk,
-                                                 int xcd_chunk) {
+// S: KB alpha per step, TM x TN fragments per wave; VW: alpha per staging
+// load (1, or 4 with 16-byte aligned rows: fewer row addresses to hold).
+template <typename T, bool DB, typename S, int VW>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(VW == 4 ? 2 : 1, 8)))
+void k_kb_gemm(const T* __restrict__ P, int64_t d, int64_t ldp, const T* __restrict__ Y,
+               int64_t ldy, T* __restrict__ part, int n_proj, int k, int kp, int64_t kchunk,
+               int nM, int nN, int nchunk, int xcd_chunk) {
   typedef typename MF<T>::acc acc_t;
-  constexpr int KB = KbShape<T>::KB, TM = KbShape<T>::TM, TN = KbShape<T>::TN;
+  constexpr int KB = S::KB, TM = S::TM, TN = S::TN;
   constexpr int BM = 32 * TM, BN = 32 * TN;      // 2 x 2 waves
-  constexpr int KW = kb_pitch<T>(KB);            // padded LDS row
-  constexpr int RA = 256 / KB;                   // tile rows loaded per pass
+  constexpr int KW = kb_pitch<T>(KB, VW);        // padded LDS row
+  static_assert(KW % VW == 0, "vector LDS writes need an aligned row pitch");
+  constexpr int KV = KB / VW;                    // threads per tile row
+  constexpr int RA = 256 / KV;                   // tile rows loaded per pass
   constexpr int LA = BM / RA, LB = BN / RA;      // passes for the P and Y tiles
   constexpr int STAGE = (BM + BN) * KW;          // one buffer: A tile then B tile
   extern __shared__ __align__(16) unsigned char kb_smem[];
@@ -91,26 +111,27 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int c16 = lane & 15, kk = lane >> 4;
-  // staging: thread -> (tile row r0 + RA p, alpha offset kc); row addresses
-  // are formed per load (fewer address registers held)
-  const int kc = tid % KB, r0 = tid / KB;
+  // staging: thread -> (tile row r0 + RA p, alpha offset kc .. kc + VW - 1);
+  // row addresses are formed per load (fewer registers held)
+  const int kc = VW * (tid % KV), r0 = tid / KV;
   const int arow0 = mtb * BM + r0, bcol0 = ntb * BN + r0;
   // loads read clamped addresses and are masked when stored to LDS (a
   // select on a load makes the wave wait for it, which would serialise the
-  // next step's loads)
-  T ra[LA], rb[LB];
+  // next step's loads); a vector past k1 is clamped to the last aligned one
+  // (inside the rows, whose lengths are multiples of VW)
+  T ra[LA][VW], rb[LB][VW];
   auto fetch = [&](int64_t kb) {
     const int64_t kx = kb + kc;
-    const int64_t kcl = kx < k1 ? kx : k1 - 1;
+    const int64_t kcl = kx < k1 ? kx : (k1 - 1) / VW * VW;
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
       const int row = arow0 + RA * p;
-      ra[p] = P[static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * ldp + kcl];
+      load_vec<T, VW>(P + static_cast<int64_t>(row < n_proj ? row : n_proj - 1) * ldp + kcl, ra[p]);
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
       const int col = bcol0 + RA * p;
-      rb[p] = Y[static_cast<int64_t>(col < k ? col : k - 1) * ldy + kcl];
+      load_vec<T, VW>(Y + static_cast<int64_t>(col < k ? col : k - 1) * ldy + kcl, rb[p]);
     }
   };
   acc_t acc[TM][TN];
@@ -122,13 +143,28 @@ __global__ __launch_bounds__(256) void k_kb_gemm(const T* __restrict__ P, int64_
   auto stage = [&](int64_t kb, int buf) __attribute__((always_inline)) {
     T* As = lds + buf * STAGE;
     T* Bs = As + BM * KW;
-    const bool okk = kb + kc < k1;
 #pragma unroll
-    for (int p = 0; p < LA; ++p)
-      As[(r0 + RA * p) * KW + kc] = okk && arow0 + RA * p < n_proj ? ra[p] : T(0);
+    for (int p = 0; p < LA; ++p) {
+      const bool okr = arow0 + RA * p < n_proj;
+      T w[VW];
 #pragma unroll
-    for (int p = 0; p < LB; ++p)
-      Bs[(r0 + RA * p) * KW + kc] = okk && bcol0 + RA * p < k ? rb[p] : T(0);
+      for (int e = 0; e < VW; ++e) w[e] = okr && kb + kc + e < k1 ? ra[p][e] : T(0);
+      if constexpr (VW == 1)
+        As[(r0 + RA * p) * KW + kc] = w[0];
+      else
+        store_vec<T, VW, false>(As + (r0 + RA * p) * KW + kc, w);
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+      const bool okr = bcol0 + RA * p < k;
+      T w[VW];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) w[e] = okr && kb + kc + e < k1 ? rb[p][e] : T(0);
+      if constexpr (VW == 1)
+        Bs[(r0 + RA * p) * KW + kc] = w[0];
+      else
+        store_vec<T, VW, false>(Bs + (r0 + RA * p) * KW + kc, w);
+    }
   };
   // k-steps [s0, s1) of the staged tiles in buffer `buf`
   auto compute_steps = [&](int buf, int s0, int s1) __attribute__((always_inline)) {
@@ -331,9 +367,7 @@ void k_kb_apply(const T* __restrict__ P, int64_t d,
 // 8, 16 and 32 projectors per step (32 single-buffered) time alike, 32
 // double-buffered (one workgroup per CU) 26.3 ms.  Measured and not kept:
 // lanes owning 4 adjacent columns so that the operands come as 16-byte LDS
-// reads (3 instead of 12 per 4 projectors: 19.5 ms as well), and the same
-// wave tile for C = P^T Y (128 x 64, 16 alpha per step from 16-byte loads:
-// 22.7 ms single-buffered, 25.2 double-buffered, against 22.7).
+// reads (3 instead of 12 per 4 projectors: 19.5 ms as well).
 constexpr int kApI = 128, kApA = 256;                 // workgroup tile: i, alpha
 constexpr int kApPI = kApI + 16, kApPA = kApA + 16;   // LDS row pitch (floats)
 constexpr int kApKA = 16;                             // projectors per staged step
@@ -471,7 +505,6 @@ __global__ void k_kb_reduce(const T* __restrict__ part, int nchunk, const T* __r
   }
 }
 
-template <typename T>
 struct KbGrid {
   int nM, nN, nchunk;
   int64_t kchunk;
@@ -485,12 +518,12 @@ inline unsigned kb_workgroups(int nchunk, int nM, int nN, bool xcd_chunk) {
   return static_cast<unsigned>(8 * per_xcd * nN);
 }
 
-template <typename T>
-KbGrid<T> kb_grid(int n_proj, int k, int64_t d) {
-  constexpr int KB = KbShape<T>::KB;
-  KbGrid<T> gr;
-  gr.nM = (n_proj + 32 * KbShape<T>::TM - 1) / (32 * KbShape<T>::TM);
-  gr.nN = (k + 32 * KbShape<T>::TN - 1) / (32 * KbShape<T>::TN);
+template <typename S>
+KbGrid kb_grid(int n_proj, int k, int64_t d) {
+  constexpr int KB = S::KB;
+  KbGrid gr;
+  gr.nM = (n_proj + 32 * S::TM - 1) / (32 * S::TM);
+  gr.nN = (k + 32 * S::TN - 1) / (32 * S::TN);
   // 8 c chunks (c per XCD, each XCD's workgroups c nM nN), c <= 4 chosen so
   // that those workgroups fill whole rounds of kKbPerXcd resident ones as
   // nearly as possible (309 atoms, FP32: nM = 10, nN = 8, c = 4: 5 full
@@ -524,21 +557,28 @@ size_t kb_partial_bytes(int n_proj, int k, int64_t d) {
   size_t most = 0;
   for (int kc = 1; kc <= k; ++kc) {
     const size_t kp = size_t(round_up(kc, kColPad));
-    const size_t c32 = size_t(kb_grid<float>(n_proj, kc, d).nchunk) * sizeof(float);
-    const size_t c64 = size_t(kb_grid<double>(n_proj, kc, d).nchunk) * sizeof(double);
+    const size_t c32 = size_t(std::max(kb_grid<KgVec>(n_proj, kc, d).nchunk,
+                                       kb_grid<KbShape<float>>(n_proj, kc, d).nchunk)) *
+                       sizeof(float);
+    const size_t c64 = size_t(kb_grid<KbShape<double>>(n_proj, kc, d).nchunk) * sizeof(double);
     most = std::max(most, std::max(c32, c64) * size_t(n_proj) * kp);
   }
   return most;
 }
 
 // LDS bytes of the projector kernels: one (A tile + B tile) stage, or two when
-// double-buffered.  Measured on MI355X (309-atom shape): double buffering
-// takes the FP32 C = P^T Y product from 28.3 to 25.4 ms and makes P C slower
+// double-buffered.  Measured on MI355X (309-atom shape, 32 alpha per step
+// from 4-byte loads): double buffering took the FP32 C = P^T Y product from
+// 28.3 to 25.4 ms and made P C slower
 // (22.3 -> 24.3 ms), so only the former uses it (2 x 33.8 KB, two workgroups
 // per CU still fit).
 template <typename T>
 constexpr size_t kb_lds_bytes(bool db, int kb = KbShape<T>::KB) {
   return (db ? 2 : 1) * size_t(32 * KbShape<T>::TM + 32 * KbShape<T>::TN) * kb_pitch<T>(kb) * sizeof(T);
+}
+template <typename T, typename S>
+constexpr size_t kg_lds_bytes(bool db, int vw) {
+  return (db ? 2 : 1) * size_t(32 * S::TM + 32 * S::TN) * kb_pitch<T>(S::KB, vw) * sizeof(T);
 }
 
 // Allow more than the default 64 KB of dynamic LDS for a kernel that needs it
@@ -553,23 +593,38 @@ void allow_lds(K kern, size_t bytes) {
 template <typename T>
 void launch_kb_gemm(const T* P, int64_t d, int64_t ldp, const T* Y, int64_t ldy, const T* h,
                     T* C, T* part, int n_proj, int k, int kp, hipStream_t s) {
-  const KbGrid<T> gr = kb_grid<T>(n_proj, k, d);
-  const bool xc = gr.nchunk % 8 == 0;
-  const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
-  constexpr bool DB = sizeof(T) == 4;
-  constexpr size_t lds = kb_lds_bytes<T>(DB);
-  allow_lds(&k_kb_gemm<T, DB>, lds);
-  k_kb_gemm<T, DB><<<nwg, 256, lds, s>>>(P, d, ldp, Y, ldy, part, n_proj, k, kp, gr.kchunk, gr.nM,
-                                         gr.nN, gr.nchunk, xc ? 1 : 0);
+  int nchunk = 0;
+  auto go = [&](auto shape, auto db, auto vw) {
+    typedef decltype(shape) S;
+    constexpr bool DB = decltype(db)::value;
+    constexpr int VW = decltype(vw)::value;
+    const KbGrid gr = kb_grid<S>(n_proj, k, d);
+    const bool xc = gr.nchunk % 8 == 0;
+    const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
+    constexpr size_t lds = kg_lds_bytes<T, S>(DB, VW);
+    allow_lds(&k_kb_gemm<T, DB, S, VW>, lds);
+    k_kb_gemm<T, DB, S, VW><<<nwg, 256, lds, s>>>(P, d, ldp, Y, ldy, part, n_proj, k, kp,
+                                                   gr.kchunk, gr.nM, gr.nN, gr.nchunk, xc ? 1 : 0);
+    nchunk = gr.nchunk;
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (ldp % 4 == 0 && ldy % 4 == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(Y) % 16 == 0)
+      go(KgVec{}, std::false_type{}, std::integral_constant<int, 4>{});
+    else
+      go(KbShape<float>{}, std::true_type{}, std::integral_constant<int, 1>{});
+  } else {
+    go(KbShape<double>{}, std::false_type{}, std::integral_constant<int, 1>{});
+  }
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
-  k_kb_reduce<T><<<rb, 256, 0, s>>>(part, gr.nchunk, h, C, n_proj, k, kp);
+  k_kb_reduce<T><<<rb, 256, 0, s>>>(part, nchunk, h, C, n_proj, k, kp);
 }
 
 int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ldb, double* part,
                        int64_t part_cap, int64_t rows, int k, int kp, hipStream_t s) {
   // the projector product's split-K grid, with no more chunks than `part` holds
-  KbGrid<double> gr = kb_grid<double>(k, k, rows);
+  KbGrid gr = kb_grid<KbShape<double>>(k, k, rows);
   const int64_t per_chunk = static_cast<int64_t>(k) * kp;
   const int64_t maxc = std::max<int64_t>(1, part_cap / per_chunk);
   if (gr.nchunk > maxc) {
@@ -579,7 +634,7 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
   }
   const bool xc = gr.nchunk % 8 == 0;
   const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
-  k_kb_gemm<double, false><<<nwg, 256, kb_lds_bytes<double>(false), s>>>(
+  k_kb_gemm<double, false, KbShape<double>, 1><<<nwg, 256, kg_lds_bytes<double, KbShape<double>>(false, 1), s>>>(
       A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk, xc ? 1 : 0);
   return gr.nchunk;
 }
