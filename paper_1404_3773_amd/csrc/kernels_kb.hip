@@ -23,7 +23,9 @@
 // one LDS buffer (309 atoms: 22.9 -> 20.8 ms against 32 alpha per step from
 // 4-byte loads, double-buffered; 32 per step from 16-byte loads,
 // double-buffered, 22.1 ms; wave tiles of 128 x 64 with 16 or 32 alpha per
-// step, 22.7 ms or slower).
+// step, 22.7 ms or slower).  FP64 operands with even leading dimensions and
+// 16-byte aligned bases are staged from 16-byte loads (2 doubles; 309 atoms:
+// 48.9 -> 45.4 ms), the Gram products of Cholesky-QR and Rayleigh-Ritz too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,11 +62,12 @@ constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 // lanes of a read fall on distinct banks, where KB + 1 left them two-way
 // (309-atom C = P^T Y: 25.4 -> 24.5 ms).  FP64 reads 8-byte words and keeps
 // KB + 1 (its C was slower with KB + 2).
-// Rows staged from 16-byte loads (vw = 4) take pitch KB + 4, a multiple of 4
-// that spreads the operand reads the same way (16 or 32 alpha per step).
+// Rows staged from 16-byte loads take an aligned pitch: FP32 (vw = 4) KB + 4,
+// which spreads the operand reads the same way (16 to 64 alpha per step);
+// FP64 (vw = 2) KB + 2.
 template <typename T>
 constexpr int kb_pitch(int kb, int vw = 1) {
-  return kb + (sizeof(T) == 4 ? (vw > 1 || kb == 16 ? 4 : 2) : 1);
+  return kb + (sizeof(T) == 4 ? (vw > 1 || kb == 16 ? 4 : 2) : (vw > 1 ? 2 : 1));
 }
 
 // With DB the P and Y tiles are double-buffered in (dynamic) LDS: a step
@@ -614,7 +617,11 @@ void launch_kb_gemm(const T* P, int64_t d, int64_t ldp, const T* Y, int64_t ldy,
     else
       go(KbShape<float>{}, std::true_type{}, std::integral_constant<int, 1>{});
   } else {
-    go(KbShape<double>{}, std::false_type{}, std::integral_constant<int, 1>{});
+    if (ldp % 2 == 0 && ldy % 2 == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(Y) % 16 == 0)
+      go(KbShape<double>{}, std::false_type{}, std::integral_constant<int, 2>{});
+    else
+      go(KbShape<double>{}, std::false_type{}, std::integral_constant<int, 1>{});
   }
   const int64_t n = int64_t(n_proj) * kp;
   const unsigned rb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
@@ -634,8 +641,17 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
   }
   const bool xc = gr.nchunk % 8 == 0;
   const unsigned nwg = kb_workgroups(gr.nchunk, gr.nM, gr.nN, xc);
-  k_kb_gemm<double, false, KbShape<double>, 1><<<nwg, 256, kg_lds_bytes<double, KbShape<double>>(false, 1), s>>>(
-      A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk, xc ? 1 : 0);
+  auto run = [&](auto vw) {
+    constexpr int VW = decltype(vw)::value;
+    k_kb_gemm<double, false, KbShape<double>, VW>
+        <<<nwg, 256, kg_lds_bytes<double, KbShape<double>>(false, VW), s>>>(
+            A, rows, lda, B, ldb, part, k, k, kp, gr.kchunk, gr.nM, gr.nN, gr.nchunk, xc ? 1 : 0);
+  };
+  if (lda % 2 == 0 && ldb % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(B) % 16 == 0)
+    run(std::integral_constant<int, 2>{});
+  else
+    run(std::integral_constant<int, 1>{});
   return gr.nchunk;
 }
 

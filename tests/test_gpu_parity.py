@@ -315,11 +315,14 @@ def test_rayleigh_ritz_block_sizes_match_oracle(k):
             assert np.max(np.abs(HXg - s.oracle_apply(Xg))) < 1e-10 * scale
 
 
-def test_rayleigh_ritz_large_k_gram_over_row_chunks():
-    """k = 120 on a 630-row basis: the split-K Gram sums two row chunks."""
+@pytest.mark.parametrize("pad", [5, 6], ids=["ld_odd", "ld_even"])
+def test_rayleigh_ritz_large_k_gram_over_row_chunks(pad):
+    """k = 120 on a 630-row basis: the split-K Gram sums two row chunks.  An
+    odd leading dimension stages the Gram operands from 8-byte loads, an even
+    one from 16-byte loads."""
     w = LONG_RADIAL
     k = 120
-    _say(f"case rayleigh_ritz {w.name} k={k}")
+    _say(f"case rayleigh_ritz {w.name} k={k} ld=d+{pad}")
     s = setup(w)
     X = si.random_block(s.B.d, k, 77) * np.linspace(0.5, 3.0, k)
     theta_ref, Xr, HXr, res_ref = oe.rayleigh_ritz(s.oracle_apply, X)
@@ -327,7 +330,7 @@ def test_rayleigh_ritz_large_k_gram_over_row_chunks():
     work = s.H.workspace(k, FP64)
     ev = torch.empty(k, dtype=torch.float64, device="cuda")
     rs = torch.empty(k, dtype=torch.float64, device="cuda")
-    Xt = dev(X, ld=s.B.d + 5)
+    Xt = dev(X, ld=s.B.d + pad)
     s.H.rayleigh_ritz(Xt, ev, rs, work)
     Xg = host(Xt, s.B.d)
     assert np.max(np.abs(ev.cpu().numpy() - theta_ref)) < 1e-11 * scale
