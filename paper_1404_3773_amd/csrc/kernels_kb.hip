@@ -22,8 +22,9 @@
 // 16-byte aligned rows are staged 64 alpha per step from 16-byte loads into
 // one LDS buffer (309 atoms: 22.9 -> 20.8 ms against 32 alpha per step from
 // 4-byte loads, double-buffered; 32 per step from 16-byte loads,
-// double-buffered, 22.1 ms; wave tiles of 128 x 64 with 16 or 32 alpha per
-// step, 22.7 ms or slower).  FP64 operands with even leading dimensions and
+// double-buffered, 22.1 ms; 32 per step single-buffered at three waves per
+// SIMD, 21.4 ms; wave tiles of 128 x 64 with 16 or 32 alpha per step, 22.7
+// ms or slower).  FP64 operands with even leading dimensions and
 // 16-byte aligned bases are staged from 16-byte loads (2 doubles; 309 atoms:
 // 48.9 -> 45.4 ms), the Gram products of Cholesky-QR and Rayleigh-Ritz too.
 #include <hip/hip_runtime.h>
@@ -63,11 +64,12 @@ constexpr int kKbPerXcd = 64;   // resident workgroups per XCD (32 CUs, 2 each)
 // (309-atom C = P^T Y: 25.4 -> 24.5 ms).  FP64 reads 8-byte words and keeps
 // KB + 1 (its C was slower with KB + 2).
 // Rows staged from 16-byte loads take an aligned pitch: FP32 (vw = 4) KB + 4,
-// which spreads the operand reads the same way (16 to 64 alpha per step);
-// FP64 (vw = 2) KB + 2.
+// which spreads the operand reads the same way (64 alpha per step: rows c16
+// start 4 c16 banks apart); FP64 (vw = 2) KB + 2, where the faster staging
+// outweighs the slower reads.
 template <typename T>
 constexpr int kb_pitch(int kb, int vw = 1) {
-  return kb + (sizeof(T) == 4 ? (vw > 1 || kb == 16 ? 4 : 2) : (vw > 1 ? 2 : 1));
+  return kb + (sizeof(T) == 4 ? (vw > 1 ? 4 : 2) : (vw > 1 ? 2 : 1));
 }
 
 // With DB the P and Y tiles are double-buffered in (dynamic) LDS: a step
