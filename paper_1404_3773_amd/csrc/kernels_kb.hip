@@ -236,10 +236,11 @@ void k_kb_gemm(const T* __restrict__ P, int64_t d, int64_t ldp, const T* __restr
 // along i, P rows along alpha), the next step's tiles in registers.  The
 // result lane holds 16 consecutive alpha of one column, so stores are
 // coalesced.  Workgroups that read the same P tile (same alpha tile) share
-// an XCD.  It serves FP64 and FP32 operands that the wide-tile kernel below
-// cannot load as 16-byte vectors.  FP32 is held to four waves per SIMD (309
-// atoms: 23.1 -> 22.7 ms; three VGPRs spill, outside the K loop), FP64 to
-// three (51.7 -> 46.7 ms, no spills).
+// an XCD.  It serves the operands that the wide-tile kernel below cannot
+// load as 16-byte vectors (FP64 projector rows of odd length d).  FP32 is held
+// to four waves per SIMD (309 atoms, before the wide tiles: 23.1 -> 22.7 ms;
+// three VGPRs spill, outside the K loop), FP64 to three (51.7 -> 46.7 ms, no
+// spills).
 template <typename T, bool DB, int KB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8)))
 void k_kb_apply(const T* __restrict__ P, int64_t d,
@@ -373,29 +374,46 @@ void k_kb_apply(const T* __restrict__ P, int64_t d,
 // double-buffered (one workgroup per CU) 26.3 ms.  Measured and not kept:
 // lanes owning 4 adjacent columns so that the operands come as 16-byte LDS
 // reads (3 instead of 12 per 4 projectors: 19.5 ms as well).
-constexpr int kApI = 128, kApA = 256;                 // workgroup tile: i, alpha
-constexpr int kApPI = kApI + 16, kApPA = kApA + 16;   // LDS row pitch (floats)
-constexpr int kApKA = 16;                             // projectors per staged step
-constexpr bool kApDB = true;                          // double-buffered LDS
+// FP64 (operands with even rows): 2 x 2 waves of 64 x 64 (4 x 4 fragments),
+// 128 x 128 workgroup tiles, 2 doubles per 16-byte access, row pitch width +
+// 16 doubles (the 4 projector rows of an operand read start 128 bytes apart
+// modulo 256); 309 atoms: 46.5 -> 39.2 ms, the same result bits.
+template <typename T>
+struct ApShape;
+template <>
+struct ApShape<float> {
+  static constexpr int TI = 4, TA = 8, KA = 16;
+};
+template <>
+struct ApShape<double> {
+  static constexpr int TI = 4, TA = 4, KA = 16;
+};
+constexpr bool kApDB = true;   // double-buffered LDS
 
-template <int KA, bool DB>
+template <typename T>
 constexpr size_t kb_apply_wide_lds() {
-  return (DB ? 2 : 1) * size_t(KA) * (kApPI + kApPA) * sizeof(float);
+  typedef ApShape<T> S;
+  return (kApDB ? 2 : 1) * size_t(S::KA) * (32 * S::TI + 16 + 32 * S::TA + 16) * sizeof(T);
 }
 
-template <int KA, bool DB>
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
-void k_kb_apply_wide(const float* __restrict__ P, int64_t d, int64_t ldp,
-                     const float* __restrict__ C, int n_proj, int k, int kp,
-                     float* __restrict__ Z, int nI, int nA) {
-  typedef MF<float>::acc acc_t;
-  constexpr int STAGE = KA * (kApPI + kApPA);
-  constexpr int CV = KA * kApI / (4 * 256);     // 16-byte C loads per thread per step
-  constexpr int PV = KA * kApA / (4 * 256);     // 16-byte P loads per thread per step
-  constexpr int CR = 256 / (kApI / 4), PR = 256 / (kApA / 4);   // rows per pass
+void k_kb_apply_wide(const T* __restrict__ P, int64_t d, int64_t ldp, const T* __restrict__ C,
+                     int n_proj, int k, int kp, T* __restrict__ Z, int nI, int nA) {
+  typedef typename MF<T>::acc acc_t;
+  typedef ApShape<T> S;
+  constexpr int TI = S::TI, TA = S::TA, KA = S::KA;
+  constexpr bool DB = kApDB;
+  constexpr int BI = 32 * TI, BA = 32 * TA;     // workgroup tile: i, alpha
+  constexpr int PI = BI + 16, PA = BA + 16;     // LDS row pitch (elements)
+  constexpr int VW = 16 / static_cast<int>(sizeof(T));   // elements per 16-byte access
+  constexpr int STAGE = KA * (PI + PA);
+  constexpr int CV = KA * BI / (VW * 256);      // 16-byte C loads per thread per step
+  constexpr int PV = KA * BA / (VW * 256);      // 16-byte P loads per thread per step
+  constexpr int CR = 256 / (BI / VW), PR = 256 / (BA / VW);   // rows per pass
   static_assert(CV >= 1 && PV >= 1, "step too short for the staging passes");
   extern __shared__ __align__(16) unsigned char kb_smem[];
-  float* const lds = reinterpret_cast<float*>(kb_smem);
+  T* const lds = reinterpret_cast<T*>(kb_smem);
   const int id = blockIdx.x;
   const int x = id & 7, j = id >> 3;
   const int ga = x + 8 * (j / nI), itb = j - (j / nI) * nI;
@@ -404,58 +422,58 @@ void k_kb_apply_wide(const float* __restrict__ P, int64_t d, int64_t ldp,
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wa = wave & 1;
   const int c16 = lane & 15, kk = lane >> 4;
-  const int cr = tid / (kApI / 4), cc = 4 * (tid % (kApI / 4));
-  const int pr = tid / (kApA / 4), pc = 4 * (tid % (kApA / 4));
-  const int ic = min(itb * kApI + cc, kp - 4);
-  const int64_t ac = min(static_cast<int64_t>(ga) * kApA + pc, ldp - 4);
-  const float* cbase = C + ic;
-  const float* pbase = P + ac;
-  float rc[CV][4], rp[PV][4];
+  const int cr = tid / (BI / VW), cc = VW * (tid % (BI / VW));
+  const int pr = tid / (BA / VW), pc = VW * (tid % (BA / VW));
+  const int ic = min(itb * BI + cc, kp - VW);
+  const int64_t ac = min(static_cast<int64_t>(ga) * BA + pc, ldp - VW);
+  const T* cbase = C + ic;
+  const T* pbase = P + ac;
+  T rc[CV][VW], rp[PV][VW];
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int p = 0; p < CV; ++p) {
       const int q = q0 + cr + CR * p;
-      load_vec<float, 4>(cbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp, rc[p]);
+      load_vec<T, VW>(cbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * kp, rc[p]);
     }
 #pragma unroll
     for (int p = 0; p < PV; ++p) {
       const int q = q0 + pr + PR * p;
-      load_vec<float, 4>(pbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * ldp, rp[p]);
+      load_vec<T, VW>(pbase + static_cast<int64_t>(q < n_proj ? q : n_proj - 1) * ldp, rp[p]);
     }
   };
-  acc_t acc[4][8];
+  acc_t acc[TI][TA];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < TI; ++u)
 #pragma unroll
-    for (int v = 0; v < 8; ++v) acc[u][v] = zero_acc<acc_t>();
+    for (int v = 0; v < TA; ++v) acc[u][v] = zero_acc<acc_t>();
   auto stage = [&](int q0, int buf) __attribute__((always_inline)) {
-    float* Cs = lds + buf * STAGE;
-    float* Ps = Cs + KA * kApPI;
+    T* Cs = lds + buf * STAGE;
+    T* Ps = Cs + KA * PI;
 #pragma unroll
     for (int p = 0; p < CV; ++p) {
       const bool ok = q0 + cr + CR * p < n_proj;
-      float w[4];
+      T w[VW];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) w[e] = ok ? rc[p][e] : 0.f;
-      store_vec<float, 4, false>(Cs + (cr + CR * p) * kApPI + cc, w);
+      for (int e = 0; e < VW; ++e) w[e] = ok ? rc[p][e] : T(0);
+      store_vec<T, VW, false>(Cs + (cr + CR * p) * PI + cc, w);
     }
 #pragma unroll
-    for (int p = 0; p < PV; ++p) store_vec<float, 4, false>(Ps + (pr + PR * p) * kApPA + pc, rp[p]);
+    for (int p = 0; p < PV; ++p) store_vec<T, VW, false>(Ps + (pr + PR * p) * PA + pc, rp[p]);
   };
   auto compute_steps = [&](int buf, int s0, int s1) __attribute__((always_inline)) {
-    const float* Aw = lds + buf * STAGE + kk * kApPI + wi * 64 + c16;
-    const float* Bw = lds + buf * STAGE + KA * kApPI + kk * kApPA + wa * 128 + c16;
+    const T* Aw = lds + buf * STAGE + kk * PI + wi * 16 * TI + c16;
+    const T* Bw = lds + buf * STAGE + KA * PI + kk * PA + wa * 16 * TA + c16;
 #pragma unroll
     for (int st = s0; st < s1; ++st) {
-      float a[4], b[8];
+      T a[TI], b[TA];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = Aw[4 * st * kApPI + 16 * u];
+      for (int u = 0; u < TI; ++u) a[u] = Aw[4 * st * PI + 16 * u];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) b[v] = Bw[4 * st * kApPA + 16 * v];
+      for (int v = 0; v < TA; ++v) b[v] = Bw[4 * st * PA + 16 * v];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < TI; ++u)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u][v] = MF<float>::mma(a[u], b[v], acc[u][v]);
+        for (int v = 0; v < TA; ++v) acc[u][v] = MF<T>::mma(a[u], b[v], acc[u][v]);
     }
   };
   fetch(0);
@@ -483,13 +501,13 @@ void k_kb_apply_wide(const float* __restrict__ P, int64_t d, int64_t ldp,
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < TI; ++u)
 #pragma unroll
-    for (int v = 0; v < 8; ++v)
+    for (int v = 0; v < TA; ++v)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = itb * kApI + wi * 64 + 16 * u + MF<float>::row(lane, r);
-        const int64_t a = static_cast<int64_t>(ga) * kApA + wa * 128 + 16 * v + c16;
+        const int i = itb * BI + wi * 16 * TI + 16 * u + MF<T>::row(lane, r);
+        const int64_t a = static_cast<int64_t>(ga) * BA + wa * 16 * TA + 16 * v + c16;
         if (i < k && a < d) Z[static_cast<int64_t>(i) * d + a] = acc[u][v][r];
       }
 }
@@ -660,18 +678,18 @@ int launch_atb_partial(const double* A, int64_t lda, const double* B, int64_t ld
 template <typename T>
 void launch_kb_apply(const T* P, int64_t d, int64_t ldp, const T* C, T* Z, int n_proj, int k,
                      int kp, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-    // wide tiles when the 16-byte column loads stay aligned
-    if (ldp % 4 == 0 && kp % 4 == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0 &&
-        reinterpret_cast<uintptr_t>(C) % 16 == 0) {
-      const int nI = (k + kApI - 1) / kApI;
-      const int nA = static_cast<int>((d + kApA - 1) / kApA);
-      const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
-      constexpr size_t lds = kb_apply_wide_lds<kApKA, kApDB>();
-      allow_lds(&k_kb_apply_wide<kApKA, kApDB>, lds);
-      k_kb_apply_wide<kApKA, kApDB><<<nwg, 256, lds, s>>>(P, d, ldp, C, n_proj, k, kp, Z, nI, nA);
-      return;
-    }
+  // wide tiles when the 16-byte column loads stay aligned
+  constexpr int VW = 16 / static_cast<int>(sizeof(T));
+  if (ldp % VW == 0 && kp % VW == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(C) % 16 == 0) {
+    constexpr int BI = 32 * ApShape<T>::TI, BA = 32 * ApShape<T>::TA;
+    const int nI = (k + BI - 1) / BI;
+    const int nA = static_cast<int>((d + BA - 1) / BA);
+    const unsigned nwg = static_cast<unsigned>(8 * ((nA + 7) / 8) * nI);
+    constexpr size_t lds = kb_apply_wide_lds<T>();
+    allow_lds(&k_kb_apply_wide<T>, lds);
+    k_kb_apply_wide<T><<<nwg, 256, lds, s>>>(P, d, ldp, C, n_proj, k, kp, Z, nI, nA);
+    return;
   }
   constexpr int BM = 32 * KbShape<T>::TN, BN = 32 * KbShape<T>::TM;
   const int nI = (k + BM - 1) / BM;

@@ -147,15 +147,17 @@ def test_apply_H_kb_projectors():
         assert rel_err(host(Yt, s.B.d), Z) < tol, prec
 
 
-@pytest.mark.parametrize("n_atoms,k", [(40, 140), (37, 131)], ids=["p160_k140", "p148_k131"])
-def test_apply_H_many_projectors_several_tiles_and_chunks(n_atoms, k):
+@pytest.mark.parametrize("L,N,n_atoms,k", [(10, 12, 40, 140), (10, 12, 37, 131), (9, 11, 20, 40)],
+                         ids=["p160_k140", "p148_k131", "odd_d891_p80_k40"])
+def test_apply_H_many_projectors_several_tiles_and_chunks(L, N, n_atoms, k):
     # 40 atoms -> 160 projectors, k = 140, d = 1200: C = diag(h) P^T Y runs on
     # 2 x 2 (FP32) / 2 x 3 (FP64) output tiles with ragged edges and splits
     # the contraction over d into 2 / 3 chunks; Zkb = P C on 2 x 5 (FP32, 128
     # columns x 256 rows, the last rows past the padded row length) / 2 x 10
     # (FP64) tiles.  37 atoms -> 148 projectors, a partial last step of the
-    # projector contraction, with k = 131.
-    w = si.small(10, 12, R=12.0, k=k, name="kb_tiles")
+    # projector contraction, with k = 131.  L = 9, N = 11: d = 891 is odd, so
+    # the FP64 products take their 4- and 8-byte staging forms.
+    w = si.small(L, N, R=12.0, k=k, name="kb_tiles")
     _say(f"case apply_H KB tiles {w.name} atoms={n_atoms} k={w.k}")
     B = ces.Basis.for_workload(w)
     r, wr, th, wt, ph = B.grid()
