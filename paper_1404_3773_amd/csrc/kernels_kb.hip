@@ -357,7 +357,7 @@ void k_kb_apply(const T* __restrict__ P, int64_t d,
       }
 }
 
-// kb_apply, FP32, wide tiles: workgroup tile 128 columns i x 256 rows alpha,
+// kb_apply, wide tiles.  FP32: workgroup tile 128 columns i x 256 rows alpha,
 // 2 x 2 waves of 64 x 128 (4 x 8 MFMA fragments, 128 accumulators per lane),
 // so each staged operand value feeds twice the MFMAs of the 64 x 64 wave
 // tile.  The projector steps (KA per step) are staged in LDS row-major by
@@ -373,7 +373,9 @@ void k_kb_apply(const T* __restrict__ P, int64_t d,
 // 8, 16 and 32 projectors per step (32 single-buffered) time alike, 32
 // double-buffered (one workgroup per CU) 26.3 ms.  Measured and not kept:
 // lanes owning 4 adjacent columns so that the operands come as 16-byte LDS
-// reads (3 instead of 12 per 4 projectors: 19.5 ms as well).
+// reads (3 instead of 12 per 4 projectors: 19.5 ms as well), and a raised
+// wave priority around the MFMA sections (19.4 -> 19.2 ms here, but C =
+// P^T Y 20.6 -> 20.9 and both FP64 products slower).
 // FP64 (operands with even rows): 2 x 2 waves of 64 x 64 (4 x 4 fragments),
 // 128 x 128 workgroup tiles, 2 doubles per 16-byte access, row pitch width +
 // 16 doubles (the 4 projector rows of an operand read start 128 bytes apart
